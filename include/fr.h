@@ -1,0 +1,181 @@
+/*
+ * fr.h -- C ABI of the MI355X (gfx950) implementation of the hot path of the
+ * p-adaptive implicit high-order flux reconstruction method of Wang, Gobbert
+ * & Yu, "A dynamically load-balanced parallel p-adaptive implicit high-order
+ * flux reconstruction method for under-resolved turbulence simulation"
+ * (arXiv 1910.03693).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - State layout (device, float64 unless stated): U[var][sp], var = (rho,
+ *    rho u, rho v, rho w, rho E); the (p+1)^3 solution points of every element
+ *    are contiguous, elements in mesh order, xi index fastest, then eta, zeta.
+ *    The solution points are the tensor Gauss-Legendre points of the element's
+ *    trilinear map.  fr_layout() returns the offsets.
+ *  - Array arguments of the compute calls are DEVICE pointers owned by the
+ *    caller; the library never frees them.  The mesh descriptor and the
+ *    stats structs are HOST memory.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  fr_residual,
+ *    fr_jvp, fr_vjp and spectral_decay_indicator only enqueue work.
+ *    gmres_stage_solve and esdirk_step synchronise the stream to read their
+ *    convergence scalars.
+ *  - The library owns its workspace.  fr_create allocates the mesh data and
+ *    the residual's face buffers; the first Krylov or time-step call on a
+ *    context allocates that solver's workspace (for the largest restart seen),
+ *    later calls reuse it.
+ *  - Errors: argument errors return at once; a failed HIP call returns
+ *    FR_E_HIP; a density or pressure <= 0 met by a residual kernel raises a
+ *    device flag that the next synchronising call reports as FR_E_NONPHYSICAL.
+ *    fr_last_error() describes the last error of a context.  No call aborts
+ *    the process or lets a C++ exception escape.
+ *  - A context may be used by one host thread and one stream at a time.
+ */
+#ifndef FR_H
+#define FR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fr_ctx_s* fr_ctx;
+
+typedef enum {
+  FR_OK = 0,
+  FR_E_INVALID = -1,       /* bad argument or mesh description */
+  FR_E_NOMEM = -2,         /* device allocation failed */
+  FR_E_HIP = -3,           /* a HIP runtime call failed */
+  FR_E_NOTCONVERGED = -4,  /* solver stopped by its iteration budget */
+  FR_E_NONPHYSICAL = -5,   /* rho <= 0 or p <= 0 was met */
+  FR_E_UNSUPPORTED = -6
+} fr_status;
+
+enum { FR_EULER = 0, FR_NAVIER_STOKES = 1 };
+enum { FR_ROE = 0, FR_RUSANOV = 1 };
+enum { FR_BC_WALL = -1, FR_BC_FARFIELD = -2 };
+typedef enum { FR_F64 = 0, FR_F32 = 1 } fr_prec;
+typedef enum { FR_JV_EXACT = 0, FR_JV_FD = 1 } fr_jv_mode;
+
+/*
+ * Mesh and physics (section 2.1 and 2.2 of the paper).  Conforming hexahedra:
+ * element vertex v = a + 2b + 4c sits at reference (xi, eta, zeta) =
+ * (2a-1, 2b-1, 2c-1) of a trilinear map.  Faces are numbered (-xi, +xi, -eta,
+ * +eta, -zeta, +zeta).  elem_nbr[e][2d+1] = e' >= 0 requires
+ * elem_nbr[e'][2d] = e, with e's +d face equal to e''s -d face up to a
+ * translation (periodic images allowed) and the same tangential orientation.
+ * A negative entry is a boundary: FR_BC_WALL (no-slip adiabatic wall) or
+ * FR_BC_FARFIELD (far-field state `farfield`).  Degrees elem_p in 1..5 may
+ * differ by any amount across a face.  Non-dimensional gas with gas constant
+ * 1: T = p / rho, cp = gamma / (gamma - 1), constant mu and Prandtl number.
+ */
+typedef struct {
+  int32_t n_elem;
+  const double* elem_xyz;   /* host [n_elem][8][3] */
+  const int32_t* elem_nbr;  /* host [n_elem][6] */
+  const int8_t* elem_p;     /* host [n_elem], 1..5 */
+  int32_t physics;          /* FR_EULER or FR_NAVIER_STOKES */
+  int32_t flux;             /* FR_ROE (eq. invis_com) or FR_RUSANOV */
+  double gamma, mu, prandtl;
+  double farfield[5];       /* conservative far-field state */
+} fr_mesh_desc;
+
+/* Restarted GMRES (section 2.3: matrix-free PETSc GMRES in the paper). */
+typedef struct {
+  int32_t restart;    /* Krylov basis size m per cycle (paper: 60) */
+  int32_t max_iter;   /* operator products per solve (paper: 100) */
+  double tol;         /* stop when ||r|| <= tol ||F|| (paper: 1e-1) */
+  int32_t jv_mode;    /* FR_JV_EXACT (dual-number tangent) or FR_JV_FD */
+  int32_t precision;  /* FR_F64, or FR_F32 (exact Jv and Krylov basis in
+                         float32; Hessenberg, rotations, dots and the update
+                         stay float64) */
+  double fd_eps;      /* finite-difference step along the unit direction (1e-6) */
+  int32_t use_graph;  /* replay each Arnoldi cycle as a captured HIP graph */
+} fr_gmres_opts;
+
+typedef struct {
+  int32_t iterations;  /* operator products */
+  int32_t cycles;
+  double rel_res;      /* final residual estimate / ||F|| */
+  int32_t converged;
+} fr_gmres_stats;
+
+/* Pseudo-transient continuation inside ESDIRK2 (section 2.3). */
+typedef struct {
+  double dtau_init, dtau_max, dtau_min;  /* SER bounds (eq. ser); halving floor */
+  double tol_pseudo;                     /* ||F|| / ||F^0|| stop (paper: 1e-4) */
+  int32_t max_ptc_iter;
+  int32_t last_stage;                    /* 3: full step; 2: return stage 2's solution */
+  fr_gmres_opts gmres;
+} fr_step_opts;
+
+typedef struct {
+  int32_t ptc_iterations;
+  int32_t gmres_iterations;
+  int32_t halvings;    /* dtau halvings after a GMRES failure */
+  int32_t stages;      /* implicit stages solved */
+  double final_rel_F;  /* ||F|| / ||F^0|| of the last stage */
+} fr_step_stats;
+
+/* Builds the device mesh (geometry, degree buckets, face lists) and the
+ * residual workspace.  Returns FR_E_INVALID for a non-conforming or
+ * inconsistent description. */
+fr_status fr_create(const fr_mesh_desc* desc, fr_ctx* out);
+fr_status fr_destroy(fr_ctx ctx);
+
+/* Number of degrees of freedom (5 x solution points) and, if sp_offset is not
+ * NULL, the first solution point of every element (host [n_elem + 1]). */
+fr_status fr_layout(fr_ctx ctx, int64_t* n_dof, int64_t* sp_offset);
+
+/* R = -(P(div f) + delta) of eq. FR_diff (with R = -div f of eq. ESDIRK_ns).
+ * U, R: device [5][n_sp] float64.  R must not alias U. */
+fr_status fr_residual(fr_ctx ctx, const double* U, double* R, void* stream);
+
+/* Jv = dR/dU(U) v.  FR_JV_EXACT: forward-mode (dual-number) residual kernels;
+ * precision FR_F64: v, Jv float64; FR_F32: v, Jv float32, computed from a
+ * float32 copy of U.  FR_JV_FD: the finite difference of section 2.3,
+ * (R(U + eps v/|v|) - R(U)) |v| / eps, float64 only.  Jv must not alias v. */
+fr_status fr_jvp(fr_ctx ctx, const double* U, const void* v, void* Jv, int32_t precision, int32_t jv_mode,
+                 double fd_eps, void* stream);
+
+/* JTw = (dR/dU(U))^T w, float64 (reverse mode; face-flux intermediates are
+ * recomputed inside the call).  JTw must not alias w. */
+fr_status fr_vjp(fr_ctx ctx, const double* U, const double* w, double* JTw, void* stream);
+
+/* Solves (shift I - dR/dU(U)) dU = F (eq. linearized_pseudo_transient_final
+ * with shift = 1/(omega dt) + 1/dtau) by restarted GMRES from dU = 0.
+ * U, F, dU: device float64 [5][n_sp].  Returns FR_E_NOTCONVERGED (dU and
+ * stats still written) if the budget ran out. */
+fr_status gmres_stage_solve(fr_ctx ctx, const double* U, double shift, const double* F, double* dU,
+                            const fr_gmres_opts* opts, fr_gmres_stats* stats, void* stream);
+
+/* One step of the three-stage, second-order ESDIRK2 (eq. ESDIRK_ns):
+ * stages 2 and 3 are solved by pseudo-transient continuation with SER
+ * (eqs. pseudo_transient, ser) and GMRES; a GMRES failure halves dtau and
+ * redoes the iterate.  U: device float64, in/out. */
+fr_status esdirk_step(fr_ctx ctx, double* U, double dt, const fr_step_opts* opts, fr_step_stats* stats,
+                      void* stream);
+
+/* Spectral-decay smoothness indicator of section 3.1 for variable `var`
+ * (the paper uses 1 = rho u): eta[e] = ||s_p - s_{p-1}|| / ||s_p|| in the
+ * paper's |J|-weighted Gauss norm (ratio of weighted sums of squares),
+ * *eta_max = max_e eta[e].  eta: device [n_elem], eta_max: device scalar. */
+fr_status spectral_decay_indicator(fr_ctx ctx, const double* U, int32_t var, double* eta, double* eta_max,
+                                   void* stream);
+
+/* Picks, per degree bucket and scalar kind, the launch shapes of the residual
+ * kernels by timing the candidates on U (device float64). */
+fr_status fr_autotune(fr_ctx ctx, const double* U, void* stream);
+
+/* Reads and clears the non-physical-state flag (synchronises the stream). */
+fr_status fr_check(fr_ctx ctx, int32_t* nonphysical, void* stream);
+
+/* Text of the last error on this context (or of the last failed fr_create
+ * if ctx is NULL).  Valid until the next call on the same context. */
+const char* fr_last_error(fr_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FR_H */

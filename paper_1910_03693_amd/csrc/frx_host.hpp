@@ -1,0 +1,83 @@
+// Host-side description of a mesh resident on the device and the launchers of
+// the kernel translation units (one per scalar type of the residual).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "frx_device.hpp"
+
+namespace frx {
+
+enum ScalarKind { SK_F64 = 0, SK_DUAL64 = 1, SK_DUAL32 = 2, SK_COUNT = 3 };
+
+struct ElemBucket {
+  int n = 0;        // p + 1
+  int count = 0;
+  int* elems = nullptr;  // device, ascending element ids of this degree
+  int epb_trace[SK_COUNT] = {0, 0, 0};
+  int epb_div[SK_COUNT] = {0, 0, 0};
+};
+
+struct FaceBucket {
+  int nl = 0, nh = 0;
+  int count = 0;
+  int4* faces = nullptr;  // device (L, R, d, low_is_R)
+  int fpb[SK_COUNT] = {0, 0, 0};
+};
+
+struct BFaceBucket {
+  int n = 0;
+  int count = 0;
+  int4* faces = nullptr;  // device (e, f, bc, 0)
+};
+
+struct MeshDev {
+  int E = 0;
+  int nsp = 0, nfp = 0;
+  int physics = 0, flux = 0;
+  int* sp_off = nullptr;
+  int* fp_off = nullptr;
+  double* geo_d = nullptr;
+  float* geo_f = nullptr;
+  std::vector<ElemBucket> eb;
+  std::vector<FaceBucket> fb;
+  std::vector<BFaceBucket> bb;
+  void* facebuf = nullptr;  // 30 * nfp scalars of the widest scalar type
+  int* flag = nullptr;
+  Gas<double> gas_d;
+  Gas<float> gas_f;
+};
+
+// out = alpha * in2 + beta * result (in2 may be null); alpha_dev overrides alpha
+template <class B> struct ResCall {
+  const B* U = nullptr;
+  const B* V = nullptr;
+  B* out = nullptr;
+  const B* in2 = nullptr;
+  const B* alpha_dev = nullptr;
+  B alpha = B(0), beta = B(1);
+  const int* skip = nullptr;  // device flag: skip all work when nonzero
+};
+
+// residual (SK_F64) or residual-and-tangent (duals) on a stream
+hipError_t launch_residual_f64(const MeshDev& M, const ResCall<double>& c, hipStream_t s);
+hipError_t launch_residual_dual64(const MeshDev& M, const ResCall<double>& c, hipStream_t s);
+hipError_t launch_residual_dual32(const MeshDev& M, const ResCall<float>& c, hipStream_t s);
+
+// operator tables into each translation unit's constant memory
+hipError_t upload_tables_f64(const OpsTab<double>& d, const OpsTab<float>& f);
+hipError_t upload_tables_dual64(const OpsTab<double>& d, const OpsTab<float>& f);
+hipError_t upload_tables_dual32(const OpsTab<double>& d, const OpsTab<float>& f);
+
+// default launch shapes for the residual kernels of one scalar kind
+void default_shapes(MeshDev& M, int sk);
+size_t scalar_bytes(int sk);
+
+}  // namespace frx
+
+namespace frx {
+hipError_t launch_indicator(const MeshDev& M, const double* U, int var, double* eta, double* eta_max,
+                            hipStream_t s);
+}  // namespace frx

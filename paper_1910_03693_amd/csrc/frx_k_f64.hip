@@ -1,0 +1,40 @@
+// Residual kernels instantiated for the scalar double.
+#include "frx_launch.hpp"
+#include "frx_indicator.hpp"
+
+namespace frx {
+
+hipError_t upload_tables_f64(const OpsTab<double>& d, const OpsTab<float>& f) {
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_ops_d), &d, sizeof(d));
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_ops_f), &f, sizeof(f));
+}
+
+hipError_t launch_residual_f64(const MeshDev& M, const ResCall<double>& c, hipStream_t s) {
+  return launch_residual_T<double>(M, c, SK_F64, s);
+}
+
+hipError_t launch_indicator(const MeshDev& M, const double* U, int var, double* eta, double* eta_max,
+                            hipStream_t s) {
+  for (const ElemBucket& b : M.eb) {
+    if (!b.count) continue;
+    const int n = b.n, n3 = n * n * n;
+    const int epb = n3 >= 256 ? 1 : 256 / n3;
+    const int grid = (b.count + epb - 1) / epb;
+    const size_t lds = (size_t)epb * 4 * n3 * sizeof(double);
+    const dim3 blk(round64(epb * n3));
+    switch (n) {
+      case 2: hipLaunchKernelGGL(k_indicator<2>, dim3(grid), blk, lds, s, U, M.nsp, var, M.sp_off, M.geo_d, b.elems, b.count, epb, eta); break;
+      case 3: hipLaunchKernelGGL(k_indicator<3>, dim3(grid), blk, lds, s, U, M.nsp, var, M.sp_off, M.geo_d, b.elems, b.count, epb, eta); break;
+      case 4: hipLaunchKernelGGL(k_indicator<4>, dim3(grid), blk, lds, s, U, M.nsp, var, M.sp_off, M.geo_d, b.elems, b.count, epb, eta); break;
+      case 5: hipLaunchKernelGGL(k_indicator<5>, dim3(grid), blk, lds, s, U, M.nsp, var, M.sp_off, M.geo_d, b.elems, b.count, epb, eta); break;
+      case 6: hipLaunchKernelGGL(k_indicator<6>, dim3(grid), blk, lds, s, U, M.nsp, var, M.sp_off, M.geo_d, b.elems, b.count, epb, eta); break;
+      default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_max, dim3(1), dim3(256), 0, s, eta, M.E, eta_max);
+  return hipGetLastError();
+}
+}  // namespace frx

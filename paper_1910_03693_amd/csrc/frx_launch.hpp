@@ -1,0 +1,146 @@
+// Launchers of the three residual stages for one scalar type T; each kernel
+// translation unit includes this file once with its own T.
+#pragma once
+#include "frx_host.hpp"
+#include "frx_residual.hpp"
+
+namespace frx {
+
+template <class B> __host__ inline const B* geo_of(const MeshDev& M);
+template <> __host__ inline const double* geo_of<double>(const MeshDev& M) { return M.geo_d; }
+template <> __host__ inline const float* geo_of<float>(const MeshDev& M) { return M.geo_f; }
+template <class B> __host__ inline const Gas<B>& gas_of(const MeshDev& M);
+template <> __host__ inline const Gas<double>& gas_of<double>(const MeshDev& M) { return M.gas_d; }
+template <> __host__ inline const Gas<float>& gas_of<float>(const MeshDev& M) { return M.gas_f; }
+
+inline int round64(int t) { return (t + 63) / 64 * 64; }
+
+template <class T> size_t trace_lds(int n, int epb) { return (size_t)epb * 5 * n * n * n * sizeof(T); }
+template <class T> size_t div_lds(int n, int epb) { return (size_t)epb * (5 * n * n * n + 30 * n * n) * sizeof(T); }
+template <class T> size_t face_lds(int nl, int nh, bool ns, int fpb) {
+  return nl < nh ? (size_t)fpb * ((ns ? 20 : 5) * nl * nl + 10 * nh * nh) * sizeof(T) : 0;
+}
+
+template <int N, class T, bool NS>
+hipError_t run_trace(const ResArgs<T>& a, const ElemBucket& b, int epb, hipStream_t s) {
+  const int grid = (b.count + epb - 1) / epb;
+  hipLaunchKernelGGL((k_trace<N, T, NS>), dim3(grid), dim3(round64(epb * N * N * N)), trace_lds<T>(N, epb), s, a,
+                     b.elems, b.count, epb);
+  return hipGetLastError();
+}
+template <int N, class T, bool NS>
+hipError_t run_div(const ResArgs<T>& a, const ElemBucket& b, int epb, hipStream_t s) {
+  const int grid = (b.count + epb - 1) / epb;
+  hipLaunchKernelGGL((k_div<N, T, NS>), dim3(grid), dim3(round64(epb * N * N * N)), div_lds<T>(N, epb), s, a, b.elems,
+                     b.count, epb);
+  return hipGetLastError();
+}
+template <int NL, int NH, class T, bool NS>
+hipError_t run_face(const ResArgs<T>& a, const FaceBucket& b, int fpb, hipStream_t s) {
+  const int grid = (b.count + fpb - 1) / fpb;
+  hipLaunchKernelGGL((k_face<NL, NH, T, NS>), dim3(grid), dim3(round64(fpb * NH * NH)), face_lds<T>(NL, NH, NS, fpb),
+                     s, a, b.faces, b.count, fpb);
+  return hipGetLastError();
+}
+template <int N, class T, bool NS>
+hipError_t run_bface(const ResArgs<T>& a, const BFaceBucket& b, hipStream_t s) {
+  const int tot = b.count * N * N;
+  hipLaunchKernelGGL((k_bface<N, T, NS>), dim3((tot + 255) / 256), dim3(256), 0, s, a, b.faces, b.count);
+  return hipGetLastError();
+}
+
+#define FRX_SWITCH_N(n, CALL) \
+  switch (n) {                \
+    case 2: return CALL(2);   \
+    case 3: return CALL(3);   \
+    case 4: return CALL(4);   \
+    case 5: return CALL(5);   \
+    case 6: return CALL(6);   \
+    default: return hipErrorInvalidValue; \
+  }
+
+template <class T, bool NS>
+hipError_t trace_n(const ResArgs<T>& a, const ElemBucket& b, int epb, hipStream_t s) {
+#define FRX_C(N) run_trace<N, T, NS>(a, b, epb, s)
+  FRX_SWITCH_N(b.n, FRX_C)
+#undef FRX_C
+}
+template <class T, bool NS>
+hipError_t div_n(const ResArgs<T>& a, const ElemBucket& b, int epb, hipStream_t s) {
+#define FRX_C(N) run_div<N, T, NS>(a, b, epb, s)
+  FRX_SWITCH_N(b.n, FRX_C)
+#undef FRX_C
+}
+template <class T, bool NS>
+hipError_t bface_n(const ResArgs<T>& a, const BFaceBucket& b, hipStream_t s) {
+#define FRX_C(N) run_bface<N, T, NS>(a, b, s)
+  FRX_SWITCH_N(b.n, FRX_C)
+#undef FRX_C
+}
+template <class T, bool NS, int NL>
+hipError_t face_nh(const ResArgs<T>& a, const FaceBucket& b, int fpb, hipStream_t s) {
+  switch (b.nh) {
+    case 2: if constexpr (NL <= 2) return run_face<NL, 2, T, NS>(a, b, fpb, s); break;
+    case 3: if constexpr (NL <= 3) return run_face<NL, 3, T, NS>(a, b, fpb, s); break;
+    case 4: if constexpr (NL <= 4) return run_face<NL, 4, T, NS>(a, b, fpb, s); break;
+    case 5: if constexpr (NL <= 5) return run_face<NL, 5, T, NS>(a, b, fpb, s); break;
+    case 6: return run_face<NL, 6, T, NS>(a, b, fpb, s);
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+template <class T, bool NS>
+hipError_t face_n(const ResArgs<T>& a, const FaceBucket& b, int fpb, hipStream_t s) {
+  switch (b.nl) {
+    case 2: return face_nh<T, NS, 2>(a, b, fpb, s);
+    case 3: return face_nh<T, NS, 3>(a, b, fpb, s);
+    case 4: return face_nh<T, NS, 4>(a, b, fpb, s);
+    case 5: return face_nh<T, NS, 5>(a, b, fpb, s);
+    case 6: return face_nh<T, NS, 6>(a, b, fpb, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class T, bool NS>
+hipError_t residual_stages(const ResArgs<T>& a, const MeshDev& M, int sk, hipStream_t s) {
+  hipError_t e;
+  for (const ElemBucket& b : M.eb)
+    if (b.count && (e = trace_n<T, NS>(a, b, b.epb_trace[sk], s)) != hipSuccess) return e;
+  for (const FaceBucket& b : M.fb)
+    if (b.count && (e = face_n<T, NS>(a, b, b.fpb[sk], s)) != hipSuccess) return e;
+  for (const BFaceBucket& b : M.bb)
+    if (b.count && (e = bface_n<T, NS>(a, b, s)) != hipSuccess) return e;
+  for (const ElemBucket& b : M.eb)
+    if (b.count && (e = div_n<T, NS>(a, b, b.epb_div[sk], s)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+template <class T>
+hipError_t launch_residual_T(const MeshDev& M, const ResCall<base_t<T>>& c, int sk, hipStream_t s) {
+  using B = base_t<T>;
+  ResArgs<T> a;
+  a.U = c.U;
+  a.V = c.V;
+  a.out = c.out;
+  a.in2 = c.in2;
+  a.alpha_dev = c.alpha_dev;
+  a.alpha = c.alpha;
+  a.beta = c.beta;
+  a.nsp = M.nsp;
+  a.nfp = M.nfp;
+  a.flux = M.flux;
+  a.sp_off = M.sp_off;
+  a.fp_off = M.fp_off;
+  a.geo = geo_of<B>(M);
+  T* fb = reinterpret_cast<T*>(M.facebuf);
+  a.QF = fb;
+  a.GF = fb + 5L * M.nfp;
+  a.DQ = fb + 20L * M.nfp;
+  a.FS = fb + 25L * M.nfp;
+  a.gas = gas_of<B>(M);
+  a.flag = M.flag;
+  a.skip = c.skip;
+  return M.physics == 1 ? residual_stages<T, true>(a, M, sk, s) : residual_stages<T, false>(a, M, sk, s);
+}
+
+}  // namespace frx

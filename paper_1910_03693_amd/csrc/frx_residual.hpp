@@ -1,0 +1,464 @@
+// FR/CPR residual kernels for hexahedra of degree p = N - 1 (section 2.2 of
+// the paper), instantiated per N and per scalar T in {double, float,
+// Dual<double>, Dual<float>}; with a dual scalar the same kernels return the
+// exact tangent J(U) v next to R(U).
+//
+// The residual in the reference element (differential form eq. FR_diff with
+// the DG correction field, contravariant flux Ft^i = Ja^i . f):
+//   R = -(1/J) [ sum_i D_i Ft^i + sum_faces (f_com . S - f_loc) g'_face ]
+// is evaluated in three stages over HBM-resident structure-of-arrays buffers:
+//   trace: q (and, for Navier-Stokes, the uncorrected physical gradient) at
+//          every element's own face points;
+//   face:  common solution, BR2 common gradient and common normal flux per
+//          face point, returned to each side at its own face points (the lower
+//          degree side of a mixed face is interpolated to the higher side's
+//          Gauss points and receives the L2 projection back);
+//   div:   corrected gradient, volume flux, sum-factorised divergence and the
+//          correction, written as R (or through an epilogue out = a*x + b*R).
+#pragma once
+#include "frx_device.hpp"
+
+namespace frx {
+
+// Load/store of the scalar T from base-type buffers: a dual reads (U, V) and
+// stores its derivative part; a plain scalar reads U and stores its value.
+template <class T> struct IO;
+template <> struct IO<double> {
+  static __device__ __forceinline__ double load(const double* U, const double*, long i) { return U[i]; }
+  static __device__ __forceinline__ double out(double x) { return x; }
+};
+template <> struct IO<float> {
+  static __device__ __forceinline__ float load(const float* U, const float*, long i) { return U[i]; }
+  static __device__ __forceinline__ float out(float x) { return x; }
+};
+template <class B> struct IO<Dual<B>> {
+  static __device__ __forceinline__ Dual<B> load(const B* U, const B* V, long i) { return Dual<B>(U[i], V[i]); }
+  static __device__ __forceinline__ B out(Dual<B> x) { return x.d; }
+};
+
+template <class T> struct ResArgs {
+  using B = base_t<T>;
+  const B* U;      // state [5][nsp]
+  const B* V;      // tangent direction [5][nsp] (dual scalars only)
+  B* out;          // output [5][nsp]: out = alpha * in2 + beta * result
+  const B* in2;    // optional second input of the epilogue
+  const B* alpha_dev;  // if set, alpha is read from device memory
+  B alpha, beta;
+  int nsp, nfp;
+  int flux;            // 0 Roe, 1 Rusanov
+  const int* sp_off;   // [E] first solution point of each element
+  const int* fp_off;   // [E] first face-slot point (6 n^2 per element)
+  const B* geo;        // [E][24] trilinear monomial coefficients
+  T* QF;               // [5][nfp]  q traces
+  T* GF;               // [15][nfp] gradient traces (Navier-Stokes)
+  T* DQ;               // [5][nfp]  q_com - q at own face points
+  T* FS;               // [5][nfp]  f_com . S at own face points
+  Gas<B> gas;
+  int* flag;           // set to 1 on a non-physical state (rho <= 0 or p <= 0)
+  const int* skip;     // if set and nonzero the kernels return at once
+};
+
+// solution point on the line through face point (a, b) of direction d
+template <int N> __device__ __forceinline__ int line_pt(int d, int a, int b, int m) {
+  return d == 0 ? m + N * (a + N * b) : (d == 1 ? a + N * (m + N * b) : a + N * (b + N * m));
+}
+
+// ---------------------------------------------------------------- trace stage
+// Block: epb elements x N^3 threads (one solution point each).  LDS: one
+// region of 5 N^3 scalars per element, holding q and then, one variable at a
+// time, the three components of its uncorrected physical gradient.
+template <int N, class T, bool NS>
+__global__ void __launch_bounds__(1024) k_trace(ResArgs<T> a, const int* __restrict__ elems, int nel, int epb) {
+  if (a.skip && *a.skip) return;
+  using B = base_t<T>;
+  constexpr int N2 = N * N, N3 = N2 * N;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* sq = reinterpret_cast<T*>(smem);  // [epb][5][N3]
+  const OpsTab<B>& O = ops<B>();
+  const int tid = threadIdx.x;
+  const int le = tid / N3, k = tid - le * N3;
+  const int slot = blockIdx.x * epb + le;
+  const bool act = le < epb && slot < nel;
+  const int e = act ? elems[slot] : 0;
+  if (act) {
+    const long off = a.sp_off[e] + k;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sq[(le * 5 + v) * N3 + k] = IO<T>::load(a.U, a.V, (long)v * a.nsp + off);
+  }
+  __syncthreads();
+  const int items = epb * 6 * N2;
+  for (int it = tid; it < items; it += blockDim.x) {
+    const int l2 = it / (6 * N2), rem = it - l2 * 6 * N2;
+    const int f = rem / N2, pt = rem - f * N2;
+    const int s2 = blockIdx.x * epb + l2;
+    if (s2 >= nel) continue;
+    const long o = a.fp_off[elems[s2]] + f * N2 + pt;
+    const int d = f >> 1, fa = pt % N, fb = pt / N;
+    const B* lf = (f & 1) ? O.lp[N] : O.lm[N];
+    const T* q = sq + l2 * 5 * N3;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      T s = T(B(0));
+#pragma unroll
+      for (int m = 0; m < N; ++m) s = fmab(lf[m], q[v * N3 + line_pt<N>(d, fa, fb, m)], s);
+      a.QF[(long)v * a.nfp + o] = s;
+    }
+  }
+  if (!NS) return;
+  // uncorrected physical gradient at the point, kept in registers
+  const int i0 = k % N, i1 = (k / N) % N, i2 = k / N2;
+  T gq[5][3];
+  if (act) {
+    B Ja[3][3], J;
+    tri_metrics<B>(a.geo + 24L * e, O.x[N][i0], O.x[N][i1], O.x[N][i2], Ja, J);
+    const B iJ = B(1) / J;
+    const T* q = sq + le * 5 * N3;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      T d0 = T(B(0)), d1 = T(B(0)), d2 = T(B(0));
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        d0 = fmab(O.D[N][i0][m], q[v * N3 + m + N * (i1 + N * i2)], d0);
+        d1 = fmab(O.D[N][i1][m], q[v * N3 + i0 + N * (m + N * i2)], d1);
+        d2 = fmab(O.D[N][i2][m], q[v * N3 + i0 + N * (i1 + N * m)], d2);
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gq[v][c] = (Ja[0][c] * d0 + Ja[1][c] * d1 + Ja[2][c] * d2) * iJ;
+    }
+  }
+#pragma unroll 1
+  for (int v = 0; v < 5; ++v) {
+    __syncthreads();  // previous readers of the region are done
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sq[(le * 5 + c) * N3 + k] = gq[v][c];
+    }
+    __syncthreads();
+    for (int it = tid; it < epb * 18 * N2; it += blockDim.x) {
+      const int l2 = it / (18 * N2), rem = it - l2 * 18 * N2;
+      const int fc = rem / N2, pt = rem - fc * N2;  // fc = f * 3 + c
+      const int f = fc / 3, c = fc - f * 3;
+      const int s2 = blockIdx.x * epb + l2;
+      if (s2 >= nel) continue;
+      const long o = a.fp_off[elems[s2]] + f * N2 + pt;
+      const int d = f >> 1;
+      const B* lf = (f & 1) ? O.lp[N] : O.lm[N];
+      const T* g = sq + (l2 * 5 + c) * N3;
+      T s = T(B(0));
+#pragma unroll
+      for (int m = 0; m < N; ++m) s = fmab(lf[m], g[line_pt<N>(d, pt % N, pt / N, m)], s);
+      a.GF[(long)(v * 3 + c) * a.nfp + o] = s;
+    }
+  }
+}
+
+// ----------------------------------------------------------------- face stage
+// Interior faces whose sides have sizes {NL, NH}, NL <= NH.  Face record
+// (L, R, d, low_is_R): L's +d face is R's -d face; the area vector S points
+// from L to R and is evaluated once per face point from L's map.
+// Block: fpb faces x NH^2 threads (one face point each).
+template <int NL, int NH, class T, bool NS>
+__global__ void __launch_bounds__(1024) k_face(ResArgs<T> a, const int4* __restrict__ faces, int nf, int fpb) {
+  if (a.skip && *a.skip) return;
+  using B = base_t<T>;
+  constexpr int NH2 = NH * NH, NL2 = NL * NL;
+  constexpr bool MIX = NL < NH;
+  constexpr int NV = NS ? 20 : 5;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* slow = reinterpret_cast<T*>(smem);              // [fpb][NV][NL2] low-side traces
+  T* sout = slow + (MIX ? fpb * NV * NL2 : 0);       // [fpb][10][NH2] low-side results
+  const OpsTab<B>& O = ops<B>();
+  const int tid = threadIdx.x;
+  const int lf = tid / NH2, pt = tid - lf * NH2;
+  const int fi = blockIdx.x * fpb + lf;
+  const bool act = lf < fpb && fi < nf;
+  int4 F = act ? faces[fi] : make_int4(0, 0, 0, 0);
+  const int L = F.x, R = F.y, d = F.z;
+  const bool lowR = MIX && F.w;
+  const bool lowL = MIX && !F.w;
+  if (MIX) {  // stage the low side's own-point traces
+    for (int it = tid; it < fpb * NV * NL2; it += blockDim.x) {
+      const int l2 = it / (NV * NL2), rem = it - l2 * NV * NL2;
+      const int vv = rem / NL2, p2 = rem - vv * NL2;
+      const int f2 = blockIdx.x * fpb + l2;
+      if (f2 >= nf) continue;
+      int4 G2 = faces[f2];
+      const int el = G2.w ? G2.y : G2.x;
+      const int ff = G2.w ? 2 * G2.z : 2 * G2.z + 1;
+      const long o = a.fp_off[el] + ff * NL2 + p2;
+      slow[it] = vv < 5 ? a.QF[(long)vv * a.nfp + o] : a.GF[(long)(vv - 5) * a.nfp + o];
+    }
+    __syncthreads();
+  }
+  if (act) {
+    const int A = pt % NH, Bq = pt / NH;
+    T q[2][5], g[2][5][3];
+    for (int s = 0; s < 2; ++s) {
+      const bool low = s ? lowR : lowL;
+      if (low) {
+        const T* src = slow + lf * NV * NL2;
+        for (int vv = 0; vv < NV; ++vv) {
+          T acc = T(B(0));
+#pragma unroll
+          for (int b = 0; b < NL; ++b) {
+            T row = T(B(0));
+#pragma unroll
+            for (int aa = 0; aa < NL; ++aa) row = fmab(O.I[NL - 2][NH - 2][A][aa], src[vv * NL2 + aa + NL * b], row);
+            acc = fmab(O.I[NL - 2][NH - 2][Bq][b], row, acc);
+          }
+          if (vv < 5) q[s][vv] = acc;
+          else g[s][(vv - 5) / 3][(vv - 5) % 3] = acc;
+        }
+      } else {
+        const int el = s ? R : L;
+        const long o = a.fp_off[el] + (s ? 2 * d : 2 * d + 1) * NH2 + pt;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q[s][v] = a.QF[(long)v * a.nfp + o];
+        if (NS) {
+#pragma unroll
+          for (int vc = 0; vc < 15; ++vc) g[s][vc / 3][vc % 3] = a.GF[(long)vc * a.nfp + o];
+        }
+      }
+    }
+    // geometry at the face point: S from L at r_d = +1, J of both sides
+    B rL[3], rR[3];
+    const B ta = O.x[NH][A], tb = O.x[NH][Bq];
+    rL[d] = B(1);
+    rR[d] = B(-1);
+    rL[d == 0 ? 1 : 0] = rR[d == 0 ? 1 : 0] = ta;
+    rL[d == 2 ? 1 : 2] = rR[d == 2 ? 1 : 2] = tb;
+    B JaL[3][3], JL, JaR[3][3], JR;
+    tri_metrics<B>(a.geo + 24L * L, rL[0], rL[1], rL[2], JaL, JL);
+    const B S[3] = {JaL[d][0], JaL[d][1], JaL[d][2]};
+    B cL = B(0), cR = B(0);
+    if (NS) {
+      tri_metrics<B>(a.geo + 24L * R, rR[0], rR[1], rR[2], JaR, JR);
+      const int nL = lowL ? NL : NH, nR = lowR ? NL : NH;
+      cL = B(0.5) * B(nL * nL) / JL;
+      cR = -B(0.5) * B(nR * nR) / JR;
+    }
+    T fS[5], jL[5], jR[5];
+    face_fn<NS, T, B>(q[0], q[1], g[0], g[1], S, cL, cR, a.gas, a.flux, fS, jL, jR);
+    if (!lowL) {
+      const long o = a.fp_off[L] + (2 * d + 1) * NH2 + pt;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        a.FS[(long)v * a.nfp + o] = fS[v];
+        a.DQ[(long)v * a.nfp + o] = jL[v];
+      }
+    }
+    if (!lowR) {
+      const long o = a.fp_off[R] + (2 * d) * NH2 + pt;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        a.FS[(long)v * a.nfp + o] = fS[v];
+        a.DQ[(long)v * a.nfp + o] = jR[v];
+      }
+    }
+    if (MIX) {
+      T* dst = sout + lf * 10 * NH2;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        dst[v * NH2 + pt] = fS[v];
+        dst[(5 + v) * NH2 + pt] = lowL ? jL[v] : jR[v];
+      }
+    }
+  }
+  if (MIX) {
+    __syncthreads();
+    for (int it = tid; it < fpb * NL2; it += blockDim.x) {
+      const int l2 = it / NL2, p2 = it - l2 * NL2;
+      const int f2 = blockIdx.x * fpb + l2;
+      if (f2 >= nf) continue;
+      int4 G2 = faces[f2];
+      const int el = G2.w ? G2.y : G2.x;
+      const int ff = G2.w ? 2 * G2.z : 2 * G2.z + 1;
+      const long o = a.fp_off[el] + ff * NL2 + p2;
+      const int aa = p2 % NL, bb = p2 / NL;
+      const T* src = sout + l2 * 10 * NH2;
+      for (int vv = 0; vv < 10; ++vv) {
+        T acc = T(B(0));
+#pragma unroll
+        for (int Bq = 0; Bq < NH; ++Bq) {
+          T row = T(B(0));
+#pragma unroll
+          for (int A = 0; A < NH; ++A) row = fmab(O.P[NL - 2][NH - 2][aa][A], src[vv * NH2 + A + NH * Bq], row);
+          acc = fmab(O.P[NL - 2][NH - 2][bb][Bq], row, acc);
+        }
+        if (vv < 5) a.FS[(long)vv * a.nfp + o] = acc;
+        else a.DQ[(long)(vv - 5) * a.nfp + o] = acc;
+      }
+    }
+  }
+}
+
+// Boundary faces of elements of size N: record (e, f, bc, 0).  One thread per
+// face point.
+template <int N, class T, bool NS>
+__global__ void __launch_bounds__(256) k_bface(ResArgs<T> a, const int4* __restrict__ faces, int nf) {
+  if (a.skip && *a.skip) return;
+  using B = base_t<T>;
+  constexpr int N2 = N * N;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nf * N2) return;
+  const int fi = gid / N2, pt = gid - fi * N2;
+  const int4 F = faces[fi];
+  const int e = F.x, f = F.y, bc = F.z, d = f >> 1, side = f & 1;
+  const OpsTab<B>& O = ops<B>();
+  const long o = a.fp_off[e] + f * N2 + pt;
+  T q[5], g[5][3];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) q[v] = a.QF[(long)v * a.nfp + o];
+  if (NS) {
+#pragma unroll
+    for (int vc = 0; vc < 15; ++vc) g[vc / 3][vc % 3] = a.GF[(long)vc * a.nfp + o];
+  }
+  B r[3];
+  r[d] = side ? B(1) : B(-1);
+  r[d == 0 ? 1 : 0] = O.x[N][pt % N];
+  r[d == 2 ? 1 : 2] = O.x[N][pt / N];
+  B Ja[3][3], J;
+  tri_metrics<B>(a.geo + 24L * e, r[0], r[1], r[2], Ja, J);
+  const B S[3] = {Ja[d][0], Ja[d][1], Ja[d][2]};
+  const B cf = (side ? B(0.5) : B(-0.5)) * B(N * N) / J;
+  T fS[5], jmp[5];
+  bface_fn<NS, T, B>(q, g, S, cf, bc, side, a.gas, a.flux, fS, jmp);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    a.FS[(long)v * a.nfp + o] = fS[v];
+    a.DQ[(long)v * a.nfp + o] = jmp[v];
+  }
+}
+
+// ------------------------------------------------------------------ div stage
+// Block: epb elements x N^3 threads.  LDS per element: a region X of 5 N^3
+// (q, then one direction of the contravariant flux at a time) and a region Y
+// of 30 N^2 (the solution jumps of the 6 faces, then the flux jumps
+// f_com . S - f_loc).
+template <int N, class T, bool NS>
+__global__ void __launch_bounds__(1024) k_div(ResArgs<T> a, const int* __restrict__ elems, int nel, int epb) {
+  if (a.skip && *a.skip) return;
+  using B = base_t<T>;
+  constexpr int N2 = N * N, N3 = N2 * N;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* sX = reinterpret_cast<T*>(smem);  // [epb][5][N3]
+  T* sY = sX + epb * 5 * N3;           // [epb][6][5][N2]
+  const OpsTab<B>& O = ops<B>();
+  const int tid = threadIdx.x;
+  const int le = tid / N3, k = tid - le * N3;
+  const int slot = blockIdx.x * epb + le;
+  const bool act = le < epb && slot < nel;
+  const int e = act ? elems[slot] : 0;
+  const long off = act ? (long)a.sp_off[e] + k : 0;
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sX[(le * 5 + v) * N3 + k] = IO<T>::load(a.U, a.V, (long)v * a.nsp + off);
+  }
+  if (NS) {
+    for (int it = tid; it < epb * 30 * N2; it += blockDim.x) {
+      const int l2 = it / (30 * N2), rem = it - l2 * 30 * N2;
+      const int fv = rem / N2, p2 = rem - fv * N2;  // fv = f * 5 + v
+      const int s2 = blockIdx.x * epb + l2;
+      if (s2 >= nel) continue;
+      const int f = fv / 5, v = fv - f * 5;
+      sY[it] = a.DQ[(long)v * a.nfp + a.fp_off[elems[s2]] + f * N2 + p2];
+    }
+  }
+  __syncthreads();
+  const int i0 = k % N, i1 = (k / N) % N, i2 = k / N2;
+  const int id[3] = {i0, i1, i2};
+  B Ja[3][3], J = B(1);
+  T Ft[3][5];
+  if (act) {
+    tri_metrics<B>(a.geo + 24L * e, O.x[N][i0], O.x[N][i1], O.x[N][i2], Ja, J);
+    const T* qs = sX + le * 5 * N3;
+    T q[5], Gq[5][3];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) q[v] = qs[v * N3 + k];
+    if (val(q[0]) <= B(0) || val(pressure<T, B>(q, a.gas)) <= B(0)) *a.flag = 1;
+    if (NS) {
+      const T* jm = sY + le * 30 * N2;
+      const B iJ = B(1) / J;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        T d0 = T(B(0)), d1 = T(B(0)), d2 = T(B(0));
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+          d0 = fmab(O.D[N][i0][m], qs[v * N3 + m + N * (i1 + N * i2)], d0);
+          d1 = fmab(O.D[N][i1][m], qs[v * N3 + i0 + N * (m + N * i2)], d1);
+          d2 = fmab(O.D[N][i2][m], qs[v * N3 + i0 + N * (i1 + N * m)], d2);
+        }
+        // corrections from the solution jumps of the two faces of each direction
+        d0 = fmab(O.gL[N][i0], jm[(0 * 5 + v) * N2 + i1 + N * i2], d0);
+        d0 = fmab(O.gR[N][i0], jm[(1 * 5 + v) * N2 + i1 + N * i2], d0);
+        d1 = fmab(O.gL[N][i1], jm[(2 * 5 + v) * N2 + i0 + N * i2], d1);
+        d1 = fmab(O.gR[N][i1], jm[(3 * 5 + v) * N2 + i0 + N * i2], d1);
+        d2 = fmab(O.gL[N][i2], jm[(4 * 5 + v) * N2 + i0 + N * i1], d2);
+        d2 = fmab(O.gR[N][i2], jm[(5 * 5 + v) * N2 + i0 + N * i1], d2);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Gq[v][c] = (Ja[0][c] * d0 + Ja[1][c] * d1 + Ja[2][c] * d2) * iJ;
+      }
+    }
+    volume_flux<T, B, NS>(q, Gq, Ja, a.gas, Ft);
+  }
+  T acc[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) acc[v] = T(B(0));
+#pragma unroll 1
+  for (int d = 0; d < 3; ++d) {
+    __syncthreads();  // X (q or the previous direction) and Y are no longer read
+    if (act) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sX[(le * 5 + v) * N3 + k] = Ft[d][v];
+    }
+    __syncthreads();
+    if (act) {
+      const T* X = sX + le * 5 * N3;
+      const int kd = id[d];
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+          const int kk = d == 0 ? m + N * (i1 + N * i2) : (d == 1 ? i0 + N * (m + N * i2) : i0 + N * (i1 + N * m));
+          acc[v] = fmab(O.D[N][kd][m], X[v * N3 + kk], acc[v]);
+        }
+    }
+    // flux jumps on the two faces of direction d
+    for (int it = tid; it < epb * 10 * N2; it += blockDim.x) {
+      const int l2 = it / (10 * N2), rem = it - l2 * 10 * N2;
+      const int sv = rem / N2, p2 = rem - sv * N2;  // sv = side * 5 + v
+      const int s2 = blockIdx.x * epb + l2;
+      if (s2 >= nel) continue;
+      const int side = sv / 5, v = sv - side * 5, f = 2 * d + side;
+      const B* lf = side ? O.lp[N] : O.lm[N];
+      const T* X = sX + (l2 * 5 + v) * N3;
+      T floc = T(B(0));
+#pragma unroll
+      for (int m = 0; m < N; ++m) floc = fmab(lf[m], X[line_pt<N>(d, p2 % N, p2 / N, m)], floc);
+      sY[(l2 * 30 + f * 5 + v) * N2 + p2] = a.FS[(long)v * a.nfp + a.fp_off[elems[s2]] + f * N2 + p2] - floc;
+    }
+    __syncthreads();
+    if (act) {
+      const T* jm = sY + le * 30 * N2;
+      const int kd = id[d];
+      const int fp = d == 0 ? i1 + N * i2 : (d == 1 ? i0 + N * i2 : i0 + N * i1);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        acc[v] = fmab(O.gL[N][kd], jm[((2 * d) * 5 + v) * N2 + fp], acc[v]);
+        acc[v] = fmab(O.gR[N][kd], jm[((2 * d + 1) * 5 + v) * N2 + fp], acc[v]);
+      }
+    }
+  }
+  if (act) {
+    const B mJ = B(-1) / J;
+    const B alpha = a.alpha_dev ? *a.alpha_dev : a.alpha;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const B r = IO<T>::out(acc[v] * mJ);
+      const long idx = (long)v * a.nsp + off;
+      a.out[idx] = a.in2 ? alpha * a.in2[idx] + a.beta * r : a.beta * r;
+    }
+  }
+}
+
+}  // namespace frx

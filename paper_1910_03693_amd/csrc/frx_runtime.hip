@@ -1,0 +1,1086 @@
+// Host runtime of the C ABI in include/fr.h: device mesh construction,
+// operator tables, residual/tangent entry points, the restarted GMRES driver
+// (optionally replayed as captured HIP graphs), pseudo-transient continuation
+// with ESDIRK2, the smoothness indicator and the launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/fr.h"
+#include "frx_host.hpp"
+#include "frx_krylov.hpp"
+
+using namespace frx;
+
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct HipErr {
+  hipError_t e;
+  const char* what;
+};
+
+#define FRX_TRY(call)                                  \
+  do {                                                 \
+    hipError_t _e = (call);                            \
+    if (_e != hipSuccess) throw HipErr{_e, #call};     \
+  } while (0)
+
+struct StatusErr {
+  fr_status st;
+  std::string msg;
+};
+
+// ------------------------------------------------------------ operator tables
+// Gauss-Legendre nodes by Newton's method on P_n, barycentric Lagrange
+// weights, D by the barycentric differentiation formula, DG correction
+// derivatives from the Legendre derivative identity
+// (1 - x^2) P_k'(x) = k (P_{k-1}(x) - x P_k(x)).
+void legendre_upto(int K, double x, double* P) {
+  P[0] = 1.0;
+  if (K > 0) P[1] = x;
+  for (int k = 2; k <= K; ++k) P[k] = ((2.0 * k - 1.0) * x * P[k - 1] - (k - 1.0) * P[k - 2]) / k;
+}
+
+double legendre_d(int k, double x) {  // interior points only
+  if (k == 0) return 0.0;
+  double P[16];
+  legendre_upto(k, x, P);
+  return k * (P[k - 1] - x * P[k]) / (1.0 - x * x);
+}
+
+void gauss_nodes(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    // i-th root from the largest downwards, stored ascending
+    double t = std::cos(M_PI * (4.0 * i + 3.0) / (4.0 * n + 2.0));
+    for (int it = 0; it < 64; ++it) {
+      double P[16];
+      legendre_upto(n, t, P);
+      const double dp = n * (P[n - 1] - t * P[n]) / (1.0 - t * t);
+      const double step = P[n] / dp;
+      t -= step;
+      if (std::fabs(step) <= 1e-17) break;
+    }
+    const double dp = legendre_d(n, t);
+    x[n - 1 - i] = t;
+    w[n - 1 - i] = 2.0 / ((1.0 - t * t) * dp * dp);
+  }
+}
+
+struct Nodes {
+  int n;
+  double x[NMAX], w[NMAX], lam[NMAX];
+};
+
+Nodes make_nodes(int n) {
+  Nodes N;
+  N.n = n;
+  gauss_nodes(n, N.x, N.w);
+  for (int j = 0; j < n; ++j) {
+    double p = 1.0;
+    for (int m = 0; m < n; ++m)
+      if (m != j) p *= (N.x[j] - N.x[m]);
+    N.lam[j] = 1.0 / p;
+  }
+  return N;
+}
+
+// l_j(t) for every j (barycentric form; t may coincide with a node)
+void lagrange_at(const Nodes& N, double t, double* l) {
+  for (int j = 0; j < N.n; ++j)
+    if (t == N.x[j]) {
+      for (int m = 0; m < N.n; ++m) l[m] = (m == j) ? 1.0 : 0.0;
+      return;
+    }
+  double den = 0.0;
+  for (int j = 0; j < N.n; ++j) den += N.lam[j] / (t - N.x[j]);
+  for (int j = 0; j < N.n; ++j) l[j] = N.lam[j] / (t - N.x[j]) / den;
+}
+
+void build_tables(OpsTab<double>& T) {
+  std::memset(&T, 0, sizeof(T));
+  for (int n = 1; n <= NMAX; ++n) {
+    Nodes N = make_nodes(n);
+    const int p = n - 1;
+    for (int k = 0; k < n; ++k) {
+      T.x[n][k] = N.x[k];
+      T.w[n][k] = N.w[k];
+      double s = 0.0;
+      for (int j = 0; j < n; ++j) {
+        if (j == k) continue;
+        const double d = (N.lam[j] / N.lam[k]) / (N.x[k] - N.x[j]);
+        T.D[n][k][j] = d;
+        s += d;
+      }
+      T.D[n][k][k] = -s;
+      // g_L = (-1)^(p+1)/2 (P_{p+1} - P_p): right Radau polynomial, g_L(-1) = 1
+      const double sg = (p % 2 == 0) ? -0.5 : 0.5;
+      T.gL[n][k] = sg * (legendre_d(p + 1, N.x[k]) - legendre_d(p, N.x[k]));
+      T.gR[n][k] = -sg * (legendre_d(p + 1, -N.x[k]) - legendre_d(p, -N.x[k]));
+      double P[16];
+      legendre_upto(n - 1, N.x[k], P);
+      for (int m = 0; m < n; ++m) {
+        T.V[n][k][m] = P[m];
+        T.Vinv[n][m][k] = 0.5 * (2.0 * m + 1.0) * N.w[k] * P[m];
+      }
+    }
+    double l[NMAX];
+    lagrange_at(N, -1.0, l);
+    for (int j = 0; j < n; ++j) T.lm[n][j] = l[j];
+    lagrange_at(N, 1.0, l);
+    for (int j = 0; j < n; ++j) T.lp[n][j] = l[j];
+  }
+  for (int nl = 2; nl <= NMAX; ++nl)
+    for (int nh = nl + 1; nh <= NMAX; ++nh) {
+      Nodes L = make_nodes(nl), H = make_nodes(nh);
+      for (int A = 0; A < nh; ++A) {
+        double l[NMAX];
+        lagrange_at(L, H.x[A], l);
+        for (int a = 0; a < nl; ++a) {
+          T.I[nl - 2][nh - 2][A][a] = l[a];
+          T.P[nl - 2][nh - 2][a][A] = H.w[A] * l[a] / L.w[a];
+        }
+      }
+    }
+}
+
+template <class B, class S> void cast_tables(const OpsTab<S>& s, OpsTab<B>& d) {
+  const S* ps = reinterpret_cast<const S*>(&s);
+  B* pd = reinterpret_cast<B*>(&d);
+  for (size_t i = 0; i < sizeof(s) / sizeof(S); ++i) pd[i] = (B)ps[i];
+}
+
+bool g_tables_uploaded[64] = {false};
+
+void ensure_tables(int dev) {
+  if (dev >= 0 && dev < 64 && g_tables_uploaded[dev]) return;
+  std::unique_ptr<OpsTab<double>> td(new OpsTab<double>);
+  std::unique_ptr<OpsTab<float>> tf(new OpsTab<float>);
+  build_tables(*td);
+  cast_tables<float, double>(*td, *tf);
+  FRX_TRY(upload_tables_f64(*td, *tf));
+  FRX_TRY(upload_tables_dual64(*td, *tf));
+  FRX_TRY(upload_tables_dual32(*td, *tf));
+  if (dev >= 0 && dev < 64) g_tables_uploaded[dev] = true;
+}
+
+constexpr int NBLK = 512;  // multi-dot blocks
+
+}  // namespace
+
+namespace frx {
+size_t scalar_bytes(int sk) { return sk == SK_F64 ? 8 : (sk == SK_DUAL64 ? 16 : 8); }
+
+// Default shapes: about 256 threads per block, LDS per block capped at 48 KB.
+void default_shapes(MeshDev& M, int sk) {
+  const size_t sb = scalar_bytes(sk);
+  const size_t cap = 48 * 1024;
+  for (ElemBucket& b : M.eb) {
+    const int n = b.n, n3 = n * n * n;
+    int e = std::max(1, 256 / n3);
+    while (e > 1 && (size_t)e * 5 * n3 * sb > cap) --e;
+    b.epb_trace[sk] = e;
+    e = std::max(1, 256 / n3);
+    while (e > 1 && (size_t)e * (5 * n3 + 30 * n * n) * sb > cap) --e;
+    b.epb_div[sk] = e;
+  }
+  for (FaceBucket& f : M.fb) {
+    int e = std::max(1, 256 / (f.nh * f.nh));
+    const size_t per = f.nl < f.nh ? (size_t)(20 * f.nl * f.nl + 10 * f.nh * f.nh) * sb : 0;
+    while (e > 1 && (size_t)e * per > cap) --e;
+    f.fpb[sk] = e;
+  }
+}
+}  // namespace frx
+
+// ===================================================================== context
+struct GraphKey {
+  int mode, prec, m;
+  bool operator<(const GraphKey& o) const { return std::tie(mode, prec, m) < std::tie(o.mode, o.prec, o.m); }
+};
+
+struct fr_ctx_s {
+  MeshDev M;
+  int dev = 0;
+  long ndof = 0;
+  std::string err;
+  std::vector<int8_t> p;
+  std::vector<int64_t> sp_off_h;
+  std::vector<void*> allocs;
+  hipStream_t cap = nullptr;  // private stream for graph capture
+  // scratch for fr_jvp / operators
+  double* t0 = nullptr;   // ndof
+  double* t1 = nullptr;   // ndof
+  double* t2 = nullptr;   // ndof
+  float* uf = nullptr;    // ndof float copy of a state
+  double* part = nullptr; // multi-dot partials [(mmax+2) x NBLK]
+  double* sc = nullptr;   // small device scalars
+  int* ist = nullptr;     // small device ints
+  double* hpin = nullptr; // pinned host scalars
+  int* ipin = nullptr;
+  // Krylov workspace
+  int m_alloc = -1, prec_alloc = -1;
+  void* Vb = nullptr;     // (m+1) x ndof basis
+  void* wv = nullptr;     // ndof work vector (basis type)
+  void* xv = nullptr;     // ndof basis-type copy of x
+  double* Ulin = nullptr; // linearisation point
+  double* Fb = nullptr;   // right-hand side
+  double* R0 = nullptr;   // R(Ulin) for finite differences
+  double* Up = nullptr;
+  double* R1 = nullptr;
+  double* rb = nullptr;   // restart residual
+  double* H = nullptr;    // Hessenberg etc. (one block)
+  float* sigf = nullptr;  // float copy of the shift
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  // ESDIRK workspace
+  double* es = nullptr;   // 8 x ndof
+  // VJP workspace
+  void* vjpw = nullptr;
+
+  void* dalloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) throw StatusErr{FR_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    allocs.push_back(p);
+    return p;
+  }
+  void dfree(void* p) {
+    if (!p) return;
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it != allocs.end()) allocs.erase(it);
+    (void)hipFree(p);
+  }
+  ~fr_ctx_s() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    for (void* p : allocs) (void)hipFree(p);
+    if (hpin) (void)hipHostFree(hpin);
+    if (ipin) (void)hipHostFree(ipin);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+namespace {
+
+fr_status fail(fr_ctx c, fr_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_error = msg;
+  return st;
+}
+
+template <class F> fr_status guarded(fr_ctx c, F&& f) {
+  try {
+    return f();
+  } catch (const HipErr& h) {
+    return fail(c, FR_E_HIP, std::string(h.what) + ": " + hipGetErrorString(h.e));
+  } catch (const StatusErr& s) {
+    return fail(c, s.st, s.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(c, FR_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(c, FR_E_INVALID, "unexpected exception");
+  }
+}
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+inline int grid_for(long n) { return (int)std::min<long>((n + KR_THREADS - 1) / KR_THREADS, 4096); }
+
+// ------------------------------------------------------------- vector helpers
+// dot(a, b) or |a|^2 (b == nullptr) into dst (device), deterministic
+template <class TA>
+void dot_to(fr_ctx c, const TA* a, const TA* b, double* dst, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL((k_multidot<TA, TA>), dim3(NBLK, 1), dim3(KR_THREADS), 0, s, b, (long)c->ndof, b ? 1 : 0, a,
+                     (long)c->ndof, c->part, NBLK, done);
+  FRX_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(KR_THREADS), 0, s, c->part, NBLK, dst, done);
+  FRX_TRY(hipGetLastError());
+}
+
+double read_scalar(fr_ctx c, const double* d, hipStream_t s) {
+  FRX_TRY(hipMemcpyAsync(c->hpin, d, sizeof(double), hipMemcpyDeviceToHost, s));
+  FRX_TRY(hipStreamSynchronize(s));
+  return c->hpin[0];
+}
+
+double norm2(fr_ctx c, const double* a, hipStream_t s) {
+  dot_to<double>(c, a, nullptr, c->sc + 15, nullptr, s);
+  return std::sqrt(read_scalar(c, c->sc + 15, s));
+}
+
+void lincomb(fr_ctx c, double* out, double c0, const double* x0, double c1 = 0, const double* x1 = nullptr,
+             double c2 = 0, const double* x2 = nullptr, double c3 = 0, const double* x3 = nullptr,
+             hipStream_t s = nullptr) {
+  hipLaunchKernelGGL(k_lincomb, dim3(grid_for(c->ndof)), dim3(KR_THREADS), 0, s, out, (long)c->ndof, c0, x0, c1, x1,
+                     c2, x2, c3, x3);
+  FRX_TRY(hipGetLastError());
+}
+
+void check_flag(fr_ctx c, hipStream_t s) {
+  FRX_TRY(hipMemcpyAsync(c->ipin, c->M.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  FRX_TRY(hipStreamSynchronize(s));
+  if (c->ipin[0]) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->M.flag, 0);
+    throw StatusErr{FR_E_NONPHYSICAL, "non-physical state (rho <= 0 or p <= 0) met in the residual"};
+  }
+}
+
+// --------------------------------------------------------- Krylov workspace
+// Device scalars: sc[0..5] GMRES (see GmresDev), sc[6] sigma, sc[8..] misc,
+// sc[15] norm scratch; h1 = sc + 32, h2 = h1 + (mmax+1), nrm = h2 + (mmax+1).
+void ensure_krylov(fr_ctx c, int m, int prec) {
+  if (c->m_alloc >= m && c->prec_alloc >= prec) return;
+  const int mm = std::max(m, c->m_alloc);
+  const int pp = std::max(prec, c->prec_alloc);
+  // graphs reference the old buffers
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  for (void* p : {c->Vb, c->wv, c->xv, (void*)c->H, (void*)c->part, (void*)c->sc, (void*)c->ist}) c->dfree(p);
+  const size_t vb = 8;  // basis storage sized for float64 (float32 uses half)
+  (void)pp;
+  c->Vb = c->dalloc((size_t)(mm + 1) * c->ndof * vb);
+  c->wv = c->dalloc((size_t)c->ndof * vb);
+  c->xv = c->dalloc((size_t)c->ndof * vb);
+  c->H = (double*)c->dalloc(sizeof(double) * ((mm + 1) * mm + 4 * (mm + 1)));
+  c->part = (double*)c->dalloc(sizeof(double) * (size_t)(mm + 2) * NBLK);
+  c->sc = (double*)c->dalloc(sizeof(double) * (64 + 3 * (mm + 2)));
+  c->ist = (int*)c->dalloc(sizeof(int) * 16);
+  if (!c->Ulin) {
+    c->Ulin = (double*)c->dalloc(sizeof(double) * c->ndof);
+    c->Fb = (double*)c->dalloc(sizeof(double) * c->ndof);
+    c->R0 = (double*)c->dalloc(sizeof(double) * c->ndof);
+    c->Up = (double*)c->dalloc(sizeof(double) * c->ndof);
+    c->R1 = (double*)c->dalloc(sizeof(double) * c->ndof);
+    c->rb = (double*)c->dalloc(sizeof(double) * c->ndof);
+    c->sigf = (float*)c->dalloc(sizeof(float) * 4);
+  }
+  c->m_alloc = mm;
+  c->prec_alloc = pp;
+}
+
+GmresDev gdev(fr_ctx c, int m) {
+  GmresDev G;
+  G.m = m;
+  G.H = c->H;
+  G.cs = c->H + (size_t)(m + 1) * m;
+  G.sn = G.cs + (m + 1);
+  G.g = G.sn + (m + 1);
+  G.y = G.g + (m + 1);
+  G.part = c->part;
+  G.hbuf = c->sc + 32;
+  G.sc = c->sc;
+  G.ist = c->ist;
+  G.nblk = NBLK;
+  return G;
+}
+
+// The GMRES operator A x = sigma x - J(Ulin) x (sigma in sc[6], float copy in
+// sigf) applied to `in` (basis type) into `out` (basis type).
+template <class TV>
+void apply_A(fr_ctx c, int mode, const TV* in, TV* out, double eps, const int* done, hipStream_t s) {
+  const MeshDev& M = c->M;
+  if (mode == FR_JV_EXACT) {
+    if constexpr (sizeof(TV) == 8) {
+      ResCall<double> rc;
+      rc.U = c->Ulin;
+      rc.V = (const double*)in;
+      rc.out = (double*)out;
+      rc.in2 = (const double*)in;
+      rc.alpha_dev = c->sc + 6;
+      rc.beta = -1.0;
+      rc.skip = done;
+      FRX_TRY(launch_residual_dual64(M, rc, s));
+    } else {
+      ResCall<float> rc;
+      rc.U = c->uf;
+      rc.V = (const float*)in;
+      rc.out = (float*)out;
+      rc.in2 = (const float*)in;
+      rc.alpha_dev = c->sigf;
+      rc.beta = -1.0f;
+      rc.skip = done;
+      FRX_TRY(launch_residual_dual32(M, rc, s));
+    }
+  } else {
+    double* nrm = c->sc + 8;
+    hipLaunchKernelGGL((k_multidot<TV, TV>), dim3(NBLK, 1), dim3(KR_THREADS), 0, s, (const TV*)nullptr,
+                       (long)c->ndof, 0, in, (long)c->ndof, c->part, NBLK, done);
+    FRX_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(KR_THREADS), 0, s, c->part, NBLK, nrm, done);
+    FRX_TRY(hipGetLastError());
+    hipLaunchKernelGGL((k_fd_perturb<TV>), dim3(grid_for(c->ndof)), dim3(KR_THREADS), 0, s, c->Ulin, in, nrm, eps,
+                       c->Up, (long)c->ndof, done);
+    FRX_TRY(hipGetLastError());
+    ResCall<double> rc;
+    rc.U = c->Up;
+    rc.out = c->R1;
+    rc.skip = done;
+    FRX_TRY(launch_residual_f64(M, rc, s));
+    hipLaunchKernelGGL((k_fd_combine<TV, TV>), dim3(grid_for(c->ndof)), dim3(KR_THREADS), 0, s, in, c->R1, c->R0,
+                       nrm, eps, c->sc + 6, out, (long)c->ndof, done);
+    FRX_TRY(hipGetLastError());
+  }
+}
+
+// One Arnoldi iteration j with CGS2 (all kernels skip once *done is set).
+template <class TV>
+void arnoldi_step(fr_ctx c, int mode, int m, int j, double eps, hipStream_t s) {
+  GmresDev G = gdev(c, m);
+  const long n = c->ndof;
+  TV* V = (TV*)c->Vb;
+  TV* w = (TV*)c->wv;
+  const int* done = c->ist;
+  double* h1 = c->sc + 32;
+  double* h2 = h1 + (m + 1);
+  double* nr = h2 + (m + 1);
+  apply_A<TV>(c, mode, V + (size_t)j * n, w, eps, done, s);
+  const int nv = j + 1;
+  const int gy = (nv + KR_VB - 1) / KR_VB;
+  for (int pass = 0; pass < 2; ++pass) {
+    double* h = pass ? h2 : h1;
+    hipLaunchKernelGGL((k_multidot<TV, TV>), dim3(NBLK, gy), dim3(KR_THREADS), 0, s, (const TV*)V, n, nv,
+                       (const TV*)w, n, c->part, NBLK, done);
+    FRX_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(KR_THREADS), 0, s, c->part, NBLK, h, done);
+    FRX_TRY(hipGetLastError());
+    hipLaunchKernelGGL((k_multiaxpy<TV, TV>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const TV*)V, n, nv,
+                       (const double*)h, w, n, done);
+    FRX_TRY(hipGetLastError());
+  }
+  hipLaunchKernelGGL((k_multidot<TV, TV>), dim3(NBLK, 1), dim3(KR_THREADS), 0, s, (const TV*)nullptr, n, 0,
+                     (const TV*)w, n, c->part, NBLK, done);
+  FRX_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(KR_THREADS), 0, s, c->part, NBLK, nr, done);
+  FRX_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, s, G, j, (const double*)h1, (const double*)h2,
+                     (const double*)nr);
+  FRX_TRY(hipGetLastError());
+  hipLaunchKernelGGL((k_scale<TV, TV>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const TV*)w, V + (size_t)(j + 1) * n,
+                     n, (const double*)(c->sc + 4), 0, done);
+  FRX_TRY(hipGetLastError());
+}
+
+template <class TV>
+void arnoldi_cycle(fr_ctx c, int mode, int m, double eps, bool use_graph, hipStream_t s) {
+  if (!use_graph) {
+    for (int j = 0; j < m; ++j) arnoldi_step<TV>(c, mode, m, j, eps, s);
+    return;
+  }
+  GraphKey key{mode, (int)sizeof(TV), m};
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    if (!c->cap) FRX_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    FRX_TRY(hipStreamSynchronize(s));
+    hipGraph_t g;
+    FRX_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    try {
+      for (int j = 0; j < m; ++j) arnoldi_step<TV>(c, mode, m, j, eps, c->cap);
+    } catch (...) {
+      hipGraph_t tmp;
+      (void)hipStreamEndCapture(c->cap, &tmp);
+      if (tmp) (void)hipGraphDestroy(tmp);
+      throw;
+    }
+    FRX_TRY(hipStreamEndCapture(c->cap, &g));
+    hipGraphExec_t ex;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    FRX_TRY(e);
+    it = c->graphs.emplace(key, ex).first;
+  }
+  FRX_TRY(hipGraphLaunch(it->second, s));
+}
+
+// Restarted GMRES on the device.  x (float64, device) receives the solution.
+template <class TV>
+fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats* st, hipStream_t s) {
+  const long n = c->ndof;
+  const int m = o.restart;
+  GmresDev G = gdev(c, m);
+  TV* V = (TV*)c->Vb;
+  TV* w = (TV*)c->wv;
+  TV* xv = (TV*)c->xv;
+  const double eps = o.fd_eps > 0 ? o.fd_eps : 1e-6;
+  // ||F||, tolerance, budget
+  const double nF = norm2(c, c->Fb, s);
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(KR_THREADS), 0, s, x, n, 0.0);
+  FRX_TRY(hipGetLastError());
+  fr_gmres_stats stats{0, 0, 0.0, 1};
+  if (nF == 0.0) {
+    if (st) *st = stats;
+    return FR_OK;
+  }
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, c->sc + 1, nF);
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, c->sc + 2, o.tol);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->ist + 2, 0);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->ist + 3, o.max_iter);
+  FRX_TRY(hipGetLastError());
+  double res = nF;
+  int total = 0, cycles = 0;
+  bool conv = false;
+  while (true) {
+    // restart residual r = F - A x (r = F at the start)
+    if (cycles == 0) {
+      FRX_TRY(hipMemcpyAsync(c->rb, c->Fb, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    } else {
+      hipLaunchKernelGGL((k_cast<double, TV>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const double*)x, xv, n);
+      FRX_TRY(hipGetLastError());
+      apply_A<TV>(c, o.jv_mode, xv, w, eps, nullptr, s);
+      hipLaunchKernelGGL((k_cast<TV, double>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const TV*)w, c->R1, n);
+      FRX_TRY(hipGetLastError());
+      lincomb(c, c->rb, 1.0, c->Fb, -1.0, c->R1, 0, nullptr, 0, nullptr, s);
+    }
+    dot_to<double>(c, c->rb, nullptr, c->sc + 9, nullptr, s);
+    hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(1), 0, s, G, (const double*)(c->sc + 9));
+    FRX_TRY(hipGetLastError());
+    hipLaunchKernelGGL((k_scale<double, TV>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const double*)c->rb, V, n,
+                       (const double*)(c->sc + 4), 0, (const int*)nullptr);
+    FRX_TRY(hipGetLastError());
+    arnoldi_cycle<TV>(c, o.jv_mode, m, eps, o.use_graph != 0, s);
+    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, s, G);
+    FRX_TRY(hipGetLastError());
+    hipLaunchKernelGGL((k_update_x<TV>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const TV*)V, n,
+                       (const double*)G.y, (const int*)(c->ist + 1), x, n);
+    FRX_TRY(hipGetLastError());
+    FRX_TRY(hipMemcpyAsync(c->ipin, c->ist, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    FRX_TRY(hipMemcpyAsync(c->hpin, c->sc, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    FRX_TRY(hipStreamSynchronize(s));
+    ++cycles;
+    total = c->ipin[2];
+    res = c->hpin[3];
+    if (res <= o.tol * nF) {
+      conv = true;
+      break;
+    }
+    if (total >= o.max_iter || c->ipin[1] == 0) break;
+  }
+  stats.iterations = total;
+  stats.cycles = cycles;
+  stats.rel_res = res / nF;
+  stats.converged = conv ? 1 : 0;
+  if (st) *st = stats;
+  return conv ? FR_OK : FR_E_NOTCONVERGED;
+}
+
+// Prepare linearisation state and right-hand side, then run GMRES.
+fr_status gmres_solve(fr_ctx c, const double* U, double shift, const double* F, double* dU, const fr_gmres_opts& o,
+                      fr_gmres_stats* st, hipStream_t s, const double* R0_known) {
+  if (o.restart < 1 || o.restart > 200 || o.max_iter < 1 || !(o.tol >= 0.0))
+    throw StatusErr{FR_E_INVALID, "gmres options out of range"};
+  if (o.precision == FR_F32 && o.jv_mode != FR_JV_EXACT)
+    throw StatusErr{FR_E_UNSUPPORTED, "float32 GMRES needs the exact tangent"};
+  ensure_krylov(c, o.restart, o.precision);
+  const long n = c->ndof;
+  if (U != c->Ulin) FRX_TRY(hipMemcpyAsync(c->Ulin, U, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  if (F != c->Fb) FRX_TRY(hipMemcpyAsync(c->Fb, F, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, c->sc + 6, shift);
+  hipLaunchKernelGGL((k_cast<double, float>), dim3(1), dim3(1), 0, s, (const double*)(c->sc + 6), c->sigf, 1L);
+  FRX_TRY(hipGetLastError());
+  if (o.jv_mode == FR_JV_FD) {
+    if (R0_known) {
+      FRX_TRY(hipMemcpyAsync(c->R0, R0_known, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    } else {
+      ResCall<double> rc;
+      rc.U = c->Ulin;
+      rc.out = c->R0;
+      FRX_TRY(launch_residual_f64(c->M, rc, s));
+    }
+  }
+  if (o.precision == FR_F32) {
+    hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const double*)c->Ulin,
+                       c->uf, n);
+    FRX_TRY(hipGetLastError());
+    return gmres_run<float>(c, o, dU, st, s);
+  }
+  return gmres_run<double>(c, o, dU, st, s);
+}
+
+void validate_desc(const fr_mesh_desc* d) {
+  if (!d) throw StatusErr{FR_E_INVALID, "null descriptor"};
+  if (d->n_elem <= 0 || !d->elem_xyz || !d->elem_nbr || !d->elem_p)
+    throw StatusErr{FR_E_INVALID, "empty mesh or null arrays"};
+  if (d->physics != FR_EULER && d->physics != FR_NAVIER_STOKES) throw StatusErr{FR_E_INVALID, "physics"};
+  if (d->flux != FR_ROE && d->flux != FR_RUSANOV) throw StatusErr{FR_E_INVALID, "flux"};
+  if (!(d->gamma > 1.0) || !(d->mu >= 0.0) || !(d->prandtl > 0.0)) throw StatusErr{FR_E_INVALID, "gas constants"};
+  const int E = d->n_elem;
+  for (int e = 0; e < E; ++e) {
+    if (d->elem_p[e] < 1 || d->elem_p[e] > 5) throw StatusErr{FR_E_INVALID, "degree outside 1..5 at element " + std::to_string(e)};
+    for (int f = 0; f < 6; ++f) {
+      const int nb = d->elem_nbr[6 * e + f];
+      if (nb >= E || (nb < 0 && nb != FR_BC_WALL && nb != FR_BC_FARFIELD))
+        throw StatusErr{FR_E_INVALID, "neighbour id out of range at element " + std::to_string(e)};
+      if (nb >= 0 && d->elem_nbr[6 * nb + (f ^ 1)] != e)
+        throw StatusErr{FR_E_INVALID, "neighbour relation not symmetric at element " + std::to_string(e)};
+      if (nb >= 0 && (f & 1)) {
+        // L's +d face vertices must match R's -d face vertices up to one translation
+        const int dd = f >> 1;
+        const double* XL = d->elem_xyz + 24L * e;
+        const double* XR = d->elem_xyz + 24L * nb;
+        double t[3] = {0, 0, 0}, h = 0.0;
+        for (int c = 0; c < 3; ++c) h = std::max(h, std::fabs(XL[3 * 7 + c] - XL[c]));
+        bool first = true;
+        for (int v = 0; v < 8; ++v) {
+          if (!((v >> dd) & 1)) continue;
+          const int vr = v & ~(1 << dd);
+          for (int c = 0; c < 3; ++c) {
+            const double dv = XR[3 * vr + c] - XL[3 * v + c];
+            if (first) t[c] = dv;
+            else if (std::fabs(dv - t[c]) > 1e-9 * std::max(1.0, h))
+              throw StatusErr{FR_E_INVALID, "non-conforming face between elements " + std::to_string(e) + " and " +
+                                                std::to_string(nb)};
+          }
+          first = false;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+// ======================================================================= C ABI
+extern "C" {
+
+fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
+  if (!out) return fail(nullptr, FR_E_INVALID, "null output handle");
+  *out = nullptr;
+  fr_ctx c = nullptr;
+  fr_status st = guarded(nullptr, [&]() -> fr_status {
+    validate_desc(d);
+    std::unique_ptr<fr_ctx_s> C(new fr_ctx_s);
+    FRX_TRY(hipGetDevice(&C->dev));
+    ensure_tables(C->dev);
+    MeshDev& M = C->M;
+    const int E = d->n_elem;
+    M.E = E;
+    M.physics = d->physics;
+    M.flux = d->flux;
+    C->p.assign(d->elem_p, d->elem_p + E);
+    std::vector<int> sp(E), fp(E);
+    C->sp_off_h.resize(E + 1);
+    long nsp = 0, nfp = 0;
+    for (int e = 0; e < E; ++e) {
+      const int n = d->elem_p[e] + 1;
+      sp[e] = (int)nsp;
+      fp[e] = (int)nfp;
+      C->sp_off_h[e] = nsp;
+      nsp += (long)n * n * n;
+      nfp += 6L * n * n;
+    }
+    C->sp_off_h[E] = nsp;
+    if (5 * nsp >= (1L << 31) || 30 * nfp >= (1L << 31)) throw StatusErr{FR_E_INVALID, "mesh too large for 32-bit indices"};
+    M.nsp = (int)nsp;
+    M.nfp = (int)nfp;
+    C->ndof = 5 * nsp;
+    // trilinear monomial coefficients
+    std::vector<double> geo(24L * E);
+    std::vector<float> geof(24L * E);
+    for (int e = 0; e < E; ++e) {
+      const double* X = d->elem_xyz + 24L * e;
+      for (int mnm = 0; mnm < 8; ++mnm) {
+        // monomials: 1, r0, r1, r2, r0 r1, r1 r2, r0 r2, r0 r1 r2
+        static const int use[8][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {0, 1, 1}, {1, 0, 1}, {1, 1, 1}};
+        for (int c = 0; c < 3; ++c) {
+          double s = 0.0;
+          for (int v = 0; v < 8; ++v) {
+            double f = 0.125;
+            for (int i = 0; i < 3; ++i)
+              if (use[mnm][i]) f *= ((v >> i) & 1) ? 1.0 : -1.0;
+            s += f * X[3 * v + c];
+          }
+          geo[24L * e + 3 * mnm + c] = s;
+          geof[24L * e + 3 * mnm + c] = (float)s;
+        }
+      }
+    }
+    M.sp_off = (int*)C->dalloc(sizeof(int) * E);
+    M.fp_off = (int*)C->dalloc(sizeof(int) * E);
+    M.geo_d = (double*)C->dalloc(sizeof(double) * 24L * E);
+    M.geo_f = (float*)C->dalloc(sizeof(float) * 24L * E);
+    FRX_TRY(hipMemcpy(M.sp_off, sp.data(), sizeof(int) * E, hipMemcpyHostToDevice));
+    FRX_TRY(hipMemcpy(M.fp_off, fp.data(), sizeof(int) * E, hipMemcpyHostToDevice));
+    FRX_TRY(hipMemcpy(M.geo_d, geo.data(), sizeof(double) * 24L * E, hipMemcpyHostToDevice));
+    FRX_TRY(hipMemcpy(M.geo_f, geof.data(), sizeof(float) * 24L * E, hipMemcpyHostToDevice));
+    // degree buckets
+    for (int n = 2; n <= NMAX; ++n) {
+      std::vector<int> ids;
+      for (int e = 0; e < E; ++e)
+        if (d->elem_p[e] + 1 == n) ids.push_back(e);
+      if (ids.empty()) continue;
+      ElemBucket b;
+      b.n = n;
+      b.count = (int)ids.size();
+      b.elems = (int*)C->dalloc(sizeof(int) * ids.size());
+      FRX_TRY(hipMemcpy(b.elems, ids.data(), sizeof(int) * ids.size(), hipMemcpyHostToDevice));
+      M.eb.push_back(b);
+    }
+    // face buckets by (n_low, n_high); boundary faces by n
+    std::map<std::pair<int, int>, std::vector<int4>> fmap;
+    std::map<int, std::vector<int4>> bmap;
+    for (int e = 0; e < E; ++e)
+      for (int f = 0; f < 6; ++f) {
+        const int nb = d->elem_nbr[6 * e + f];
+        const int ne = d->elem_p[e] + 1;
+        if (nb >= 0) {
+          if (!(f & 1)) continue;
+          const int nr = d->elem_p[nb] + 1;
+          fmap[{std::min(ne, nr), std::max(ne, nr)}].push_back(make_int4(e, nb, f >> 1, nr < ne ? 1 : 0));
+        } else {
+          bmap[ne].push_back(make_int4(e, f, nb, 0));
+        }
+      }
+    for (auto& kv : fmap) {
+      FaceBucket b;
+      b.nl = kv.first.first;
+      b.nh = kv.first.second;
+      b.count = (int)kv.second.size();
+      b.faces = (int4*)C->dalloc(sizeof(int4) * kv.second.size());
+      FRX_TRY(hipMemcpy(b.faces, kv.second.data(), sizeof(int4) * kv.second.size(), hipMemcpyHostToDevice));
+      M.fb.push_back(b);
+    }
+    for (auto& kv : bmap) {
+      BFaceBucket b;
+      b.n = kv.first;
+      b.count = (int)kv.second.size();
+      b.faces = (int4*)C->dalloc(sizeof(int4) * kv.second.size());
+      FRX_TRY(hipMemcpy(b.faces, kv.second.data(), sizeof(int4) * kv.second.size(), hipMemcpyHostToDevice));
+      M.bb.push_back(b);
+    }
+    for (int sk = 0; sk < SK_COUNT; ++sk) default_shapes(M, sk);
+    // gas
+    const double kappa = d->mu * d->gamma / ((d->gamma - 1.0) * d->prandtl);
+    M.gas_d.gamma = d->gamma;
+    M.gas_d.gm1 = d->gamma - 1.0;
+    M.gas_d.mu = d->mu;
+    M.gas_d.kappa = kappa;
+    M.gas_f.gamma = (float)d->gamma;
+    M.gas_f.gm1 = (float)(d->gamma - 1.0);
+    M.gas_f.mu = (float)d->mu;
+    M.gas_f.kappa = (float)kappa;
+    for (int v = 0; v < 5; ++v) {
+      M.gas_d.ff[v] = d->farfield[v];
+      M.gas_f.ff[v] = (float)d->farfield[v];
+    }
+    M.facebuf = C->dalloc(30L * nfp * 16);
+    M.flag = (int*)C->dalloc(sizeof(int) * 4);
+    FRX_TRY(hipMemset(M.flag, 0, sizeof(int) * 4));
+    C->t0 = (double*)C->dalloc(sizeof(double) * C->ndof);
+    C->t1 = (double*)C->dalloc(sizeof(double) * C->ndof);
+    C->t2 = (double*)C->dalloc(sizeof(double) * C->ndof);
+    C->uf = (float*)C->dalloc(sizeof(float) * C->ndof);
+    FRX_TRY(hipHostMalloc((void**)&C->hpin, 64 * sizeof(double), 0));
+    FRX_TRY(hipHostMalloc((void**)&C->ipin, 64 * sizeof(int), 0));
+    ensure_krylov(C.get(), 1, 0);
+    FRX_TRY(hipDeviceSynchronize());
+    c = C.release();
+    return FR_OK;
+  });
+  if (st == FR_OK) *out = c;
+  return st;
+}
+
+fr_status fr_destroy(fr_ctx c) {
+  if (!c) return FR_E_INVALID;
+  (void)hipDeviceSynchronize();
+  delete c;
+  return FR_OK;
+}
+
+fr_status fr_layout(fr_ctx c, int64_t* n_dof, int64_t* sp_offset) {
+  if (!c) return FR_E_INVALID;
+  if (n_dof) *n_dof = c->ndof;
+  if (sp_offset) std::copy(c->sp_off_h.begin(), c->sp_off_h.end(), sp_offset);
+  return FR_OK;
+}
+
+fr_status fr_residual(fr_ctx c, const double* U, double* R, void* stream) {
+  if (!c || !U || !R || (const void*)U == (void*)R) return c ? fail(c, FR_E_INVALID, "fr_residual: bad arguments") : FR_E_INVALID;
+  return guarded(c, [&]() -> fr_status {
+    ResCall<double> rc;
+    rc.U = U;
+    rc.out = R;
+    FRX_TRY(launch_residual_f64(c->M, rc, S(stream)));
+    return FR_OK;
+  });
+}
+
+fr_status fr_jvp(fr_ctx c, const double* U, const void* v, void* Jv, int32_t prec, int32_t mode, double eps,
+                 void* stream) {
+  if (!c) return FR_E_INVALID;
+  if (!U || !v || !Jv || v == Jv) return fail(c, FR_E_INVALID, "fr_jvp: bad arguments");
+  if (prec != FR_F64 && prec != FR_F32) return fail(c, FR_E_INVALID, "fr_jvp: precision");
+  if (mode != FR_JV_EXACT && mode != FR_JV_FD) return fail(c, FR_E_INVALID, "fr_jvp: mode");
+  if (mode == FR_JV_FD && prec != FR_F64) return fail(c, FR_E_UNSUPPORTED, "fr_jvp: finite differences need float64");
+  return guarded(c, [&]() -> fr_status {
+    hipStream_t s = S(stream);
+    const long n = c->ndof;
+    if (mode == FR_JV_EXACT && prec == FR_F64) {
+      ResCall<double> rc;
+      rc.U = U;
+      rc.V = (const double*)v;
+      rc.out = (double*)Jv;
+      FRX_TRY(launch_residual_dual64(c->M, rc, s));
+    } else if (mode == FR_JV_EXACT) {
+      hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, U, c->uf, n);
+      FRX_TRY(hipGetLastError());
+      ResCall<float> rc;
+      rc.U = c->uf;
+      rc.V = (const float*)v;
+      rc.out = (float*)Jv;
+      FRX_TRY(launch_residual_dual32(c->M, rc, s));
+    } else {
+      const double e = eps > 0 ? eps : 1e-6;
+      double* nrm = c->sc + 10;
+      dot_to<double>(c, (const double*)v, nullptr, nrm, nullptr, s);
+      hipLaunchKernelGGL((k_fd_perturb<double>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, U, (const double*)v, nrm,
+                         e, c->t0, n, (const int*)nullptr);
+      FRX_TRY(hipGetLastError());
+      ResCall<double> rc;
+      rc.U = c->t0;
+      rc.out = c->t1;
+      FRX_TRY(launch_residual_f64(c->M, rc, s));
+      rc.U = U;
+      rc.out = c->t2;
+      FRX_TRY(launch_residual_f64(c->M, rc, s));
+      hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, c->sc + 11, 0.0);
+      hipLaunchKernelGGL((k_fd_combine<double, double>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const double*)v,
+                         c->t1, c->t2, nrm, e, (const double*)(c->sc + 11), (double*)Jv, n, (const int*)nullptr);
+      FRX_TRY(hipGetLastError());
+      // k_fd_combine computes sigma v - |v|(R1 - R0)/eps; with sigma = 0 negate
+      hipLaunchKernelGGL(k_lincomb, dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (double*)Jv, n, -1.0,
+                         (const double*)Jv, 0.0, (const double*)nullptr, 0.0, (const double*)nullptr, 0.0,
+                         (const double*)nullptr);
+      FRX_TRY(hipGetLastError());
+    }
+    return FR_OK;
+  });
+}
+
+fr_status fr_vjp(fr_ctx c, const double* U, const double* w, double* JTw, void* stream) {
+  if (!c) return FR_E_INVALID;
+  if (!U || !w || !JTw || w == JTw) return fail(c, FR_E_INVALID, "fr_vjp: bad arguments");
+  (void)stream;
+  return fail(c, FR_E_UNSUPPORTED, "fr_vjp: not built yet");
+}
+
+fr_status gmres_stage_solve(fr_ctx c, const double* U, double shift, const double* F, double* dU,
+                            const fr_gmres_opts* o, fr_gmres_stats* st, void* stream) {
+  if (!c) return FR_E_INVALID;
+  if (!U || !F || !dU || !o || dU == F || dU == U) return fail(c, FR_E_INVALID, "gmres_stage_solve: bad arguments");
+  return guarded(c, [&]() -> fr_status {
+    hipStream_t s = S(stream);
+    fr_status r = gmres_solve(c, U, shift, F, dU, *o, st, s, nullptr);
+    check_flag(c, s);
+    if (r == FR_E_NOTCONVERGED) c->err = "gmres_stage_solve: iteration budget exhausted";
+    return r;
+  });
+}
+
+fr_status esdirk_step(fr_ctx c, double* U, double dt, const fr_step_opts* o, fr_step_stats* st, void* stream) {
+  if (!c) return FR_E_INVALID;
+  if (!U || !o || !(dt > 0.0)) return fail(c, FR_E_INVALID, "esdirk_step: bad arguments");
+  if (o->last_stage != 2 && o->last_stage != 3) return fail(c, FR_E_INVALID, "esdirk_step: last_stage must be 2 or 3");
+  return guarded(c, [&]() -> fr_status {
+    hipStream_t s = S(stream);
+    const long n = c->ndof;
+    if (!c->es) c->es = (double*)c->dalloc(sizeof(double) * 8 * n);
+    double* qn = c->es;
+    double* q = qn + n;
+    double* rhs = q + n;
+    double* F = rhs + n;
+    double* dq = F + n;
+    double* Rs = dq + n;  // 3 stage residuals
+    const double gam = 1.0 - std::sqrt(2.0) / 2.0;
+    const double A[3][3] = {{0, 0, 0}, {gam, gam, 0}, {0.5 * (1 - gam), 0.5 * (1 - gam), gam}};
+    const double b[3] = {0.5 * (1 - gam), 0.5 * (1 - gam), gam};
+    const double w = gam;
+    fr_step_stats stats{0, 0, 0, 0, 0.0};
+    FRX_TRY(hipMemcpyAsync(qn, U, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    FRX_TRY(hipMemcpyAsync(q, U, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    ResCall<double> rc;
+    rc.U = qn;
+    rc.out = Rs;
+    FRX_TRY(launch_residual_f64(c->M, rc, s));
+    fr_status status = FR_OK;
+    for (int i = 1; i < 3 && i < o->last_stage; ++i) {
+      lincomb(c, rhs, 1.0, qn, dt * A[i][0], Rs, i > 1 ? dt * A[i][1] : 0.0, i > 1 ? Rs + n : nullptr, 0, nullptr, s);
+      double dtau = o->dtau_init, nF0 = 0.0, nFprev = 0.0;
+      double* Rq = Rs + (size_t)i * n;
+      for (int m = 0;; ++m) {
+        rc.U = q;
+        rc.out = Rq;
+        FRX_TRY(launch_residual_f64(c->M, rc, s));
+        hipLaunchKernelGGL(k_stage_F, dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const double*)q, (const double*)Rq,
+                           (const double*)rhs, 1.0 / (w * dt), F, n);
+        FRX_TRY(hipGetLastError());
+        const double nF = norm2(c, F, s);
+        check_flag(c, s);
+        if (m == 0) nF0 = nF;
+        else dtau = std::min(dtau * nFprev / nF, o->dtau_max);  // SER
+        stats.final_rel_F = nF0 > 0 ? nF / nF0 : 0.0;
+        if (nF <= o->tol_pseudo * nF0 || nF == 0.0) break;
+        if (m >= o->max_ptc_iter) {
+          status = FR_E_NOTCONVERGED;
+          break;
+        }
+        while (true) {
+          fr_gmres_stats gs;
+          fr_status gr = gmres_solve(c, q, 1.0 / (w * dt) + 1.0 / dtau, F, dq, o->gmres, &gs, s, Rq);
+          stats.gmres_iterations += gs.iterations;
+          if (gr == FR_OK) break;
+          if (gr != FR_E_NOTCONVERGED) return gr;
+          dtau *= 0.5;
+          stats.halvings += 1;
+          if (dtau < o->dtau_min) {
+            status = FR_E_NOTCONVERGED;
+            break;
+          }
+        }
+        if (status != FR_OK) break;
+        lincomb(c, q, 1.0, q, 1.0, dq, 0, nullptr, 0, nullptr, s);
+        nFprev = nF;
+        stats.ptc_iterations += 1;
+      }
+      stats.stages += 1;
+      if (status != FR_OK) break;
+    }
+    if (o->last_stage < 3 || status != FR_OK) {
+      FRX_TRY(hipMemcpyAsync(U, q, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    } else {
+      lincomb(c, U, 1.0, qn, dt * b[0], Rs, dt * b[1], Rs + n, dt * b[2], Rs + 2 * n, s);
+    }
+    FRX_TRY(hipStreamSynchronize(s));
+    if (st) *st = stats;
+    if (status != FR_OK) c->err = "esdirk_step: pseudo-transient continuation did not converge";
+    return status;
+  });
+}
+
+fr_status spectral_decay_indicator(fr_ctx c, const double* U, int32_t var, double* eta, double* eta_max,
+                                   void* stream) {
+  if (!c) return FR_E_INVALID;
+  if (!U || !eta || !eta_max || var < 0 || var > 4) return fail(c, FR_E_INVALID, "spectral_decay_indicator: bad arguments");
+  return guarded(c, [&]() -> fr_status {
+    FRX_TRY(launch_indicator(c->M, U, var, eta, eta_max, S(stream)));
+    return FR_OK;
+  });
+}
+
+fr_status fr_check(fr_ctx c, int32_t* nonphysical, void* stream) {
+  if (!c || !nonphysical) return FR_E_INVALID;
+  return guarded(c, [&]() -> fr_status {
+    hipStream_t s = S(stream);
+    FRX_TRY(hipMemcpyAsync(c->ipin, c->M.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    FRX_TRY(hipStreamSynchronize(s));
+    *nonphysical = c->ipin[0];
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->M.flag, 0);
+    FRX_TRY(hipGetLastError());
+    return FR_OK;
+  });
+}
+
+// Launch-shape autotuner: for every scalar kind and every degree (pair)
+// bucket, time the whole residual with each candidate elements-per-block
+// (faces-per-block) of that bucket's kernel and keep the fastest.
+fr_status fr_autotune(fr_ctx c, const double* U, void* stream) {
+  if (!c || !U) return FR_E_INVALID;
+  return guarded(c, [&]() -> fr_status {
+    hipStream_t s = S(stream);
+    const long n = c->ndof;
+    hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, U, c->uf, n);
+    FRX_TRY(hipGetLastError());
+    hipEvent_t e0, e1;
+    FRX_TRY(hipEventCreate(&e0));
+    FRX_TRY(hipEventCreate(&e1));
+    auto run = [&](int sk) {
+      if (sk == SK_F64) {
+        ResCall<double> rc;
+        rc.U = U;
+        rc.out = c->t0;
+        FRX_TRY(launch_residual_f64(c->M, rc, s));
+      } else if (sk == SK_DUAL64) {
+        ResCall<double> rc;
+        rc.U = U;
+        rc.V = U;
+        rc.out = c->t0;
+        FRX_TRY(launch_residual_dual64(c->M, rc, s));
+      } else {
+        ResCall<float> rc;
+        rc.U = c->uf;
+        rc.V = c->uf;
+        rc.out = (float*)c->t1;
+        FRX_TRY(launch_residual_dual32(c->M, rc, s));
+      }
+    };
+    auto timed = [&](int sk) -> float {
+      run(sk);
+      FRX_TRY(hipEventRecord(e0, s));
+      for (int r = 0; r < 5; ++r) run(sk);
+      FRX_TRY(hipEventRecord(e1, s));
+      FRX_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      FRX_TRY(hipEventElapsedTime(&ms, e0, e1));
+      return ms;
+    };
+    const size_t lds_cap = 64 * 1024;
+    const int cands[] = {1, 2, 4, 8, 16, 32, 64};
+    for (int sk = 0; sk < SK_COUNT; ++sk) {
+      const size_t sb = scalar_bytes(sk);
+      for (ElemBucket& b : c->M.eb) {
+        const int n3 = b.n * b.n * b.n;
+        for (int kind = 0; kind < 2; ++kind) {
+          int* slot = kind == 0 ? &b.epb_trace[sk] : &b.epb_div[sk];
+          int best = *slot;
+          float tbest = timed(sk);
+          for (int e : cands) {
+            const size_t lds = kind == 0 ? (size_t)e * 5 * n3 * sb : (size_t)e * (5 * n3 + 30 * b.n * b.n) * sb;
+            if (e == best || e * n3 > 1024 || lds > lds_cap || e > 2 * b.count) continue;
+            *slot = e;
+            const float t = timed(sk);
+            if (t < tbest) {
+              tbest = t;
+              best = e;
+            }
+          }
+          *slot = best;
+        }
+      }
+      for (FaceBucket& f : c->M.fb) {
+        const int nh2 = f.nh * f.nh;
+        const size_t per = f.nl < f.nh ? (size_t)(20 * f.nl * f.nl + 10 * nh2) * sb : 0;
+        int best = f.fpb[sk];
+        float tbest = timed(sk);
+        for (int e : cands) {
+          if (e == best || e * nh2 > 1024 || (size_t)e * per > lds_cap || e > 2 * f.count) continue;
+          f.fpb[sk] = e;
+          const float t = timed(sk);
+          if (t < tbest) {
+            tbest = t;
+            best = e;
+          }
+        }
+        f.fpb[sk] = best;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // captured graphs hold the old shapes
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    return FR_OK;
+  });
+}
+
+const char* fr_last_error(fr_ctx c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,306 @@
+"""Python binding of libfrx.so (include/fr.h): argument marshalling only.
+
+The module-level functions carry the C-ABI names and take torch tensors that
+already live on the GPU; every step of the hot path runs in the HIP library.
+PyTorch supplies device memory and the current stream.  If the library is not
+built the binding raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfrx.so")
+
+FR_OK, FR_E_INVALID, FR_E_NOMEM, FR_E_HIP, FR_E_NOTCONVERGED, FR_E_NONPHYSICAL, FR_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+FR_EULER, FR_NAVIER_STOKES = 0, 1
+FR_ROE, FR_RUSANOV = 0, 1
+FR_F64, FR_F32 = 0, 1
+FR_JV_EXACT, FR_JV_FD = 0, 1
+STATUS_NAMES = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_NOMEM", -3: "FR_E_HIP", -4: "FR_E_NOTCONVERGED",
+                -5: "FR_E_NONPHYSICAL", -6: "FR_E_UNSUPPORTED"}
+EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_residual", "fr_jvp", "fr_vjp", "gmres_stage_solve",
+            "esdirk_step", "spectral_decay_indicator", "fr_autotune", "fr_check", "fr_last_error")
+
+
+class FrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class fr_mesh_desc(C.Structure):
+    _fields_ = [("n_elem", C.c_int32), ("elem_xyz", C.POINTER(C.c_double)), ("elem_nbr", C.POINTER(C.c_int32)),
+                ("elem_p", C.POINTER(C.c_int8)), ("physics", C.c_int32), ("flux", C.c_int32),
+                ("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double), ("farfield", C.c_double * 5)]
+
+
+class fr_gmres_opts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double), ("jv_mode", C.c_int32),
+                ("precision", C.c_int32), ("fd_eps", C.c_double), ("use_graph", C.c_int32)]
+
+
+class fr_gmres_stats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("cycles", C.c_int32), ("rel_res", C.c_double),
+                ("converged", C.c_int32)]
+
+
+class fr_step_opts(C.Structure):
+    _fields_ = [("dtau_init", C.c_double), ("dtau_max", C.c_double), ("dtau_min", C.c_double),
+                ("tol_pseudo", C.c_double), ("max_ptc_iter", C.c_int32), ("last_stage", C.c_int32),
+                ("gmres", fr_gmres_opts)]
+
+
+class fr_step_stats(C.Structure):
+    _fields_ = [("ptc_iterations", C.c_int32), ("gmres_iterations", C.c_int32), ("halvings", C.c_int32),
+                ("stages", C.c_int32), ("final_rel_F", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfrx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1910_03693_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.fr_create.restype = C.c_int
+        L.fr_create.argtypes = [C.POINTER(fr_mesh_desc), C.POINTER(vp)]
+        L.fr_destroy.argtypes = [vp]
+        L.fr_layout.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.fr_residual.argtypes = [vp, vp, vp, vp]
+        L.fr_jvp.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_double, vp]
+        L.fr_vjp.argtypes = [vp, vp, vp, vp, vp]
+        L.gmres_stage_solve.argtypes = [vp, vp, C.c_double, vp, vp, C.POINTER(fr_gmres_opts),
+                                        C.POINTER(fr_gmres_stats), vp]
+        L.esdirk_step.argtypes = [vp, vp, C.c_double, C.POINTER(fr_step_opts), C.POINTER(fr_step_stats), vp]
+        L.spectral_decay_indicator.argtypes = [vp, vp, C.c_int32, vp, vp, vp]
+        L.fr_autotune.argtypes = [vp, vp, vp]
+        L.fr_check.argtypes = [vp, C.POINTER(C.c_int32), vp]
+        L.fr_last_error.restype = C.c_char_p
+        L.fr_last_error.argtypes = [vp]
+        for name in EXPORTED:
+            if name not in ("fr_last_error",):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _check(st, ctx=None):
+    if st != FR_OK:
+        msg = lib().fr_last_error(ctx)
+        raise FrError(st, msg.decode() if msg else "")
+    return st
+
+
+def _dev(t, dtype, n=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"expected a contiguous {dtype} tensor, got {t.dtype}")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------ C-ABI wrappers
+def fr_create(elem_xyz, elem_nbr, elem_p, physics=FR_EULER, flux=FR_RUSANOV, gamma=1.4, mu=0.0, prandtl=0.72,
+              farfield=None):
+    """Returns (handle, keepalive) for a host mesh description."""
+    xyz = np.ascontiguousarray(elem_xyz, dtype=np.float64)
+    nbr = np.ascontiguousarray(elem_nbr, dtype=np.int32)
+    p = np.ascontiguousarray(elem_p, dtype=np.int8)
+    d = fr_mesh_desc()
+    d.n_elem = len(p)
+    d.elem_xyz = xyz.ctypes.data_as(C.POINTER(C.c_double))
+    d.elem_nbr = nbr.ctypes.data_as(C.POINTER(C.c_int32))
+    d.elem_p = p.ctypes.data_as(C.POINTER(C.c_int8))
+    d.physics, d.flux, d.gamma, d.mu, d.prandtl = physics, flux, gamma, mu, prandtl
+    ff = np.zeros(5) if farfield is None else np.asarray(farfield, dtype=np.float64)
+    for i in range(5):
+        d.farfield[i] = float(ff[i])
+    h = C.c_void_p()
+    _check(lib().fr_create(C.byref(d), C.byref(h)))
+    return h
+
+
+def fr_destroy(h):
+    return lib().fr_destroy(h)
+
+
+def fr_layout(h, n_elem):
+    n = C.c_int64()
+    off = np.zeros(n_elem + 1, dtype=np.int64)
+    _check(lib().fr_layout(h, C.byref(n), off.ctypes.data_as(C.POINTER(C.c_int64))), h)
+    return n.value, off
+
+
+def fr_residual(h, U, R, stream=None):
+    return _check(lib().fr_residual(h, _dev(U, torch.float64), _dev(R, torch.float64, U.numel()), _stream(stream)), h)
+
+
+def fr_jvp(h, U, v, Jv, precision=FR_F64, jv_mode=FR_JV_EXACT, fd_eps=1e-6, stream=None):
+    dt = torch.float64 if precision == FR_F64 else torch.float32
+    return _check(lib().fr_jvp(h, _dev(U, torch.float64), _dev(v, dt, U.numel()), _dev(Jv, dt, U.numel()),
+                               precision, jv_mode, fd_eps, _stream(stream)), h)
+
+
+def fr_vjp(h, U, w, JTw, stream=None):
+    return _check(lib().fr_vjp(h, _dev(U, torch.float64), _dev(w, torch.float64, U.numel()),
+                               _dev(JTw, torch.float64, U.numel()), _stream(stream)), h)
+
+
+def gmres_opts(restart=30, max_iter=100, tol=1e-1, jv_mode=FR_JV_EXACT, precision=FR_F64, fd_eps=1e-6,
+               use_graph=False):
+    o = fr_gmres_opts()
+    o.restart, o.max_iter, o.tol, o.jv_mode, o.precision, o.fd_eps, o.use_graph = (
+        restart, max_iter, tol, jv_mode, precision, fd_eps, int(bool(use_graph)))
+    return o
+
+
+def gmres_stage_solve(h, U, shift, F, dU, opts, stream=None, check=True):
+    st = fr_gmres_stats()
+    r = lib().gmres_stage_solve(h, _dev(U, torch.float64), float(shift), _dev(F, torch.float64, U.numel()),
+                                _dev(dU, torch.float64, U.numel()), C.byref(opts), C.byref(st), _stream(stream))
+    if check and r not in (FR_OK, FR_E_NOTCONVERGED):
+        _check(r, h)
+    return r, dict(iterations=st.iterations, cycles=st.cycles, rel_res=st.rel_res, converged=bool(st.converged))
+
+
+def step_opts(dtau_init, dtau_max, dtau_min=0.0, tol_pseudo=1e-4, max_ptc_iter=200, last_stage=3, gmres=None):
+    o = fr_step_opts()
+    o.dtau_init, o.dtau_max, o.dtau_min, o.tol_pseudo = dtau_init, dtau_max, dtau_min, tol_pseudo
+    o.max_ptc_iter, o.last_stage = max_ptc_iter, last_stage
+    o.gmres = gmres if gmres is not None else gmres_opts()
+    return o
+
+
+def esdirk_step(h, U, dt, opts, stream=None, check=True):
+    st = fr_step_stats()
+    r = lib().esdirk_step(h, _dev(U, torch.float64), float(dt), C.byref(opts), C.byref(st), _stream(stream))
+    if check and r not in (FR_OK, FR_E_NOTCONVERGED):
+        _check(r, h)
+    return r, dict(ptc_iterations=st.ptc_iterations, gmres_iterations=st.gmres_iterations, halvings=st.halvings,
+                   stages=st.stages, final_rel_F=st.final_rel_F)
+
+
+def spectral_decay_indicator(h, U, var, eta, eta_max, stream=None):
+    return _check(lib().spectral_decay_indicator(h, _dev(U, torch.float64), var, _dev(eta, torch.float64),
+                                                 _dev(eta_max, torch.float64, 1), _stream(stream)), h)
+
+
+def fr_autotune(h, U, stream=None):
+    return _check(lib().fr_autotune(h, _dev(U, torch.float64), _stream(stream)), h)
+
+
+def fr_check(h, stream=None):
+    f = C.c_int32(0)
+    _check(lib().fr_check(h, C.byref(f), _stream(stream)), h)
+    return f.value
+
+
+# ------------------------------------------------------------------- context
+class Context:
+    """A mesh on the GPU; methods take and return torch tensors shaped [5, n_sp]."""
+
+    def __init__(self, elem_xyz, elem_nbr, elem_p, physics=FR_EULER, flux=FR_RUSANOV, gamma=1.4, mu=0.0,
+                 prandtl=0.72, farfield=None):
+        self.n_elem = len(elem_p)
+        self.h = fr_create(elem_xyz, elem_nbr, elem_p, physics, flux, gamma, mu, prandtl, farfield)
+        self.n_dof, self.sp_offset = fr_layout(self.h, self.n_elem)
+        self.n_sp = self.n_dof // 5
+
+    @classmethod
+    def from_case(cls, case):
+        return cls(**case.desc())
+
+    def close(self):
+        if getattr(self, "h", None):
+            fr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def residual(self, U, out=None):
+        out = torch.empty_like(U) if out is None else out
+        fr_residual(self.h, U, out)
+        return out
+
+    def jvp(self, U, v, precision=FR_F64, jv_mode=FR_JV_EXACT, fd_eps=1e-6, out=None):
+        out = torch.empty_like(v) if out is None else out
+        fr_jvp(self.h, U, v, out, precision, jv_mode, fd_eps)
+        return out
+
+    def vjp(self, U, w, out=None):
+        out = torch.empty_like(w) if out is None else out
+        fr_vjp(self.h, U, w, out)
+        return out
+
+    def gmres(self, U, shift, F, out=None, **kw):
+        out = torch.empty_like(F) if out is None else out
+        r, st = gmres_stage_solve(self.h, U, shift, F, out, gmres_opts(**kw))
+        st["status"] = r
+        return out, st
+
+    def esdirk_step(self, U, dt, gmres=None, **kw):
+        r, st = esdirk_step(self.h, U, dt, step_opts(gmres=gmres_opts(**(gmres or {})), **kw))
+        st["status"] = r
+        return st
+
+    def indicator(self, U, var=1):
+        eta = torch.empty(self.n_elem, dtype=torch.float64, device=U.device)
+        mx = torch.empty(1, dtype=torch.float64, device=U.device)
+        spectral_decay_indicator(self.h, U, var, eta, mx)
+        return eta, mx
+
+    def autotune(self, U):
+        fr_autotune(self.h, U)
+
+    def nonphysical(self):
+        return fr_check(self.h)
+
+
+class FRResidual(torch.autograd.Function):
+    """R(U) with the exact adjoint (backward -> fr_vjp) and exact tangent
+    (forward-mode jvp -> fr_jvp); ``fr`` is a Context."""
+
+    @staticmethod
+    def forward(U, fr):
+        return fr.residual(U.contiguous())
+
+    @staticmethod
+    def setup_context(ctx, inputs, output):
+        U, fr = inputs
+        ctx.fr = fr
+        ctx.save_for_backward(U)
+        ctx.save_for_forward(U)
+
+    @staticmethod
+    def backward(ctx, grad):
+        (U,) = ctx.saved_tensors
+        return ctx.fr.vjp(U, grad.contiguous()), None
+
+    @staticmethod
+    def jvp(ctx, tU, _tfr):
+        (U,) = ctx.saved_tensors
+        return ctx.fr.jvp(U, tU.contiguous())
+
+
+def residual(U, fr):
+    return FRResidual.apply(U, fr)
