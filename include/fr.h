@@ -167,6 +167,29 @@ fr_status spectral_decay_indicator(fr_ctx ctx, const double* U, int32_t var, dou
  * kernels by timing the candidates on U (device float64). */
 fr_status fr_autotune(fr_ctx ctx, const double* U, void* stream);
 
+/* Per-launch timing of one operator's kernels (op 0: residual float64,
+ * 1: exact tangent float64, 2: exact tangent float32; U doubles as the
+ * direction).  Each launch is bracketed by HIP events on `stream`; out[i]
+ * receives the stage ("k_trace", "k_face", "k_bface", "k_div"), the degree
+ * sizes n = p + 1 of its bucket, the elements or faces it processes and the
+ * average duration over `reps` runs.  Synchronises the stream. */
+typedef struct {
+  char stage[16];
+  int32_t n_lo, n_hi;
+  int64_t units;
+  double ms;
+} fr_kernel_time;
+fr_status fr_profile(fr_ctx ctx, const double* U, int32_t op, int32_t reps, fr_kernel_time* out, int32_t max_out,
+                     int32_t* n_out, void* stream);
+
+/* Launch mode of the residual, tangent and Krylov operators of a context.
+ * FR_LAUNCH_PER_BUCKET (default): each stage (traces, faces, divergence) is
+ * launched once per degree bucket (per degree pair for faces).
+ * FR_LAUNCH_FUSED: each stage is one launch over all buckets, its blocks
+ * ordered by decreasing work (the degree-bucketed work queue). */
+enum { FR_LAUNCH_PER_BUCKET = 0, FR_LAUNCH_FUSED = 1 };
+fr_status fr_set_launch(fr_ctx ctx, int32_t mode);
+
 /* Reads and clears the non-physical-state flag (synchronises the stream). */
 fr_status fr_check(fr_ctx ctx, int32_t* nonphysical, void* stream);
 

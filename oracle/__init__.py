@@ -47,7 +47,7 @@ def lib():
         L.oracle_destroy.argtypes = [C.c_void_p]
         L.oracle_nsp.restype = C.c_long
         L.oracle_nsp.argtypes = [C.c_void_p]
-        for name in ("oracle_residual",):
+        for name in ("oracle_residual", "oracle_residual_ld"):
             getattr(L, name).argtypes = [C.c_void_p, dp, dp]
         L.oracle_jvp_cs.argtypes = [C.c_void_p, dp, dp, dp]
         L.oracle_jvp_fd.argtypes = [C.c_void_p, dp, dp, C.c_double, dp]
@@ -166,6 +166,13 @@ class Oracle:
         U = self._vec(U)
         R = np.zeros(self.shape)
         lib().oracle_residual(self.h, _p(U), _p(R))
+        return R
+
+    def residual_ld(self, U):
+        """The residual evaluated in extended precision (rounding reference)."""
+        U = self._vec(U)
+        R = np.zeros(self.shape)
+        lib().oracle_residual_ld(self.h, _p(U), _p(R))
         return R
 
     def jvp(self, U, v):

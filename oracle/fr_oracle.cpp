@@ -40,16 +40,18 @@ using cplx = std::complex<double>;
 
 // ------------------------------------------------------------ scalar helpers
 inline double re(double x) { return x; }
+inline double re(long double x) { return (double)x; }
 inline double re(const cplx& x) { return x.real(); }
 // |x| and max() choose by the real part, which makes them complex-step safe
 template <class S> S sabs(const S& x) { return re(x) < 0 ? S(-x) : x; }
 template <class S> S smax(const S& a, const S& b) { return re(a) >= re(b) ? a : b; }
 inline double ssqrt(double x) { return std::sqrt(x); }
+inline long double ssqrt(long double x) { return std::sqrt(x); }
 inline cplx ssqrt(const cplx& x) { return std::sqrt(x); }
 
 // ------------------------------------------------------- 1-D polynomial tools
 // Legendre P_k(x) and P_k'(x) for k = 0..K by the three-term recurrence.
-static void legendre(int K, double x, double* P, double* dP) {
+template <class R> static void legendre(int K, R x, R* P, R* dP) {
   P[0] = 1.0;
   dP[0] = 0.0;
   if (K >= 1) { P[1] = x; dP[1] = 1.0; }
@@ -59,27 +61,31 @@ static void legendre(int K, double x, double* P, double* dP) {
   }
 }
 
-struct Ops1D {
+// Operators in the real type R: double for the double and complex-step
+// residuals, long double for the extended-precision reference used to size
+// rounding errors.
+template <class R> struct Ops1DT {
   int n = 0;
-  std::vector<double> x, w;  // Gauss-Legendre nodes (ascending) and weights
-  std::vector<double> D;     // D[k*n + j] = l_j'(x_k)
-  std::vector<double> lm, lp;  // l_j(-1), l_j(+1)
-  std::vector<double> gLp, gRp;  // g_L'(x_k), g_R'(x_k)
-  std::vector<double> V;       // V[k*n + m] = P_m(x_k)  (Legendre Vandermonde)
+  std::vector<R> x, w;  // Gauss-Legendre nodes (ascending) and weights
+  std::vector<R> D;     // D[k*n + j] = l_j'(x_k)
+  std::vector<R> lm, lp;  // l_j(-1), l_j(+1)
+  std::vector<R> gLp, gRp;  // g_L'(x_k), g_R'(x_k)
+  std::vector<R> V;       // V[k*n + m] = P_m(x_k)  (Legendre Vandermonde)
 };
+using Ops1D = Ops1DT<double>;
 
-static double lagrange(const std::vector<double>& x, int j, double t) {
-  double v = 1.0;
+template <class R> static R lagrange(const std::vector<R>& x, int j, R t) {
+  R v = 1.0;
   for (size_t m = 0; m < x.size(); ++m)
     if ((int)m != j) v *= (t - x[m]) / (x[j] - x[m]);
   return v;
 }
 
-static double lagrange_d(const std::vector<double>& x, int j, double t) {
-  double s = 0.0;
+template <class R> static R lagrange_d(const std::vector<R>& x, int j, R t) {
+  R s = 0.0;
   for (size_t l = 0; l < x.size(); ++l) {
     if ((int)l == j) continue;
-    double prod = 1.0 / (x[j] - x[l]);
+    R prod = R(1.0) / (x[j] - x[l]);
     for (size_t m = 0; m < x.size(); ++m)
       if ((int)m != j && m != l) prod *= (t - x[m]) / (x[j] - x[m]);
     s += prod;
@@ -89,30 +95,30 @@ static double lagrange_d(const std::vector<double>& x, int j, double t) {
 
 // DG correction function g_L = right Radau polynomial of degree p+1:
 // g_L(x) = (-1)^(p+1)/2 (P_{p+1}(x) - P_p(x)); g_L(-1) = 1, g_L(+1) = 0.
-static double radau_gL_d(int p, double x) {
-  double P[16], dP[16];
-  legendre(p + 1, x, P, dP);
-  double sgn = ((p + 1) % 2 == 0) ? 1.0 : -1.0;
+template <class R> static R radau_gL_d(int p, R x) {
+  R P[16], dP[16];
+  legendre<R>(p + 1, x, P, dP);
+  R sgn = ((p + 1) % 2 == 0) ? 1.0 : -1.0;
   return 0.5 * sgn * (dP[p + 1] - dP[p]);
 }
 
-static Ops1D make_ops(int n) {
-  Ops1D o;
+template <class R> static Ops1DT<R> make_ops(int n) {
+  Ops1DT<R> o;
   o.n = n;
   o.x.resize(n);
   o.w.resize(n);
-  double P[16], dP[16];
+  R P[16], dP[16];
   for (int i = 0; i < n; ++i) {  // Newton on P_n from the usual cosine guess
-    double t = -std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    R t = -std::cos(R(M_PI) * (i + R(0.75)) / (n + R(0.5)));
     for (int it = 0; it < 100; ++it) {
-      legendre(n, t, P, dP);
-      double dt = P[n] / dP[n];
+      legendre<R>(n, t, P, dP);
+      R dt = P[n] / dP[n];
       t -= dt;
-      if (std::fabs(dt) < 1e-16) break;
+      if (std::fabs(dt) < R(1e-19)) break;
     }
-    legendre(n, t, P, dP);
+    legendre<R>(n, t, P, dP);
     o.x[i] = t;
-    o.w[i] = 2.0 / ((1.0 - t * t) * dP[n] * dP[n]);
+    o.w[i] = R(2.0) / ((R(1.0) - t * t) * dP[n] * dP[n]);
   }
   o.D.resize(n * n);
   o.lm.resize(n);
@@ -122,22 +128,22 @@ static Ops1D make_ops(int n) {
   o.V.resize(n * n);
   int p = n - 1;
   for (int k = 0; k < n; ++k) {
-    for (int j = 0; j < n; ++j) o.D[k * n + j] = lagrange_d(o.x, j, o.x[k]);
-    o.lm[k] = lagrange(o.x, k, -1.0);
-    o.lp[k] = lagrange(o.x, k, 1.0);
-    o.gLp[k] = radau_gL_d(p, o.x[k]);
-    o.gRp[k] = -radau_gL_d(p, -o.x[k]);  // g_R(x) = g_L(-x)
-    legendre(n - 1, o.x[k], P, dP);
+    for (int j = 0; j < n; ++j) o.D[k * n + j] = lagrange_d<R>(o.x, j, o.x[k]);
+    o.lm[k] = lagrange<R>(o.x, k, R(-1.0));
+    o.lp[k] = lagrange<R>(o.x, k, R(1.0));
+    o.gLp[k] = radau_gL_d<R>(p, o.x[k]);
+    o.gRp[k] = -radau_gL_d<R>(p, -o.x[k]);  // g_R(x) = g_L(-x)
+    legendre<R>(n - 1, o.x[k], P, dP);
     for (int m = 0; m < n; ++m) o.V[k * n + m] = P[m];
   }
   return o;
 }
 
-static const Ops1D& ops(int n) {
-  static Ops1D table[8];
+template <class R = double> static const Ops1DT<R>& ops(int n) {
+  static Ops1DT<R> table[8];
   static bool init = false;
   if (!init) {
-    for (int m = 1; m < 8; ++m) table[m] = make_ops(m);
+    for (int m = 1; m < 8; ++m) table[m] = make_ops<R>(m);
     init = true;
   }
   return table[n];
@@ -145,40 +151,40 @@ static const Ops1D& ops(int n) {
 
 // Interpolation from the n_from Gauss points to the n_to Gauss points:
 // I[a*n_from + b] = l^{from}_b(x^{to}_a).
-static std::vector<double> interp_matrix(int n_from, int n_to) {
-  const Ops1D& f = ops(n_from);
-  const Ops1D& t = ops(n_to);
-  std::vector<double> I(n_to * n_from);
+template <class R = double> static std::vector<R> interp_matrix(int n_from, int n_to) {
+  const Ops1DT<R>& f = ops<R>(n_from);
+  const Ops1DT<R>& t = ops<R>(n_to);
+  std::vector<R> I(n_to * n_from);
   for (int a = 0; a < n_to; ++a)
-    for (int b = 0; b < n_from; ++b) I[a * n_from + b] = lagrange(f.x, b, t.x[a]);
+    for (int b = 0; b < n_from; ++b) I[a * n_from + b] = lagrange<R>(f.x, b, t.x[a]);
   return I;
 }
 
 // L2 projection onto degree n_lo-1 of values at the n_hi Gauss points, returned
 // at the n_lo Gauss points; the n_lo-point rule makes the mass matrix diagonal:
 // Pr[k*n_hi + m] = w^hi_m l^lo_k(x^hi_m) / w^lo_k.
-static std::vector<double> project_matrix(int n_hi, int n_lo) {
-  const Ops1D& h = ops(n_hi);
-  const Ops1D& l = ops(n_lo);
-  std::vector<double> Pr(n_lo * n_hi);
+template <class R = double> static std::vector<R> project_matrix(int n_hi, int n_lo) {
+  const Ops1DT<R>& h = ops<R>(n_hi);
+  const Ops1DT<R>& l = ops<R>(n_lo);
+  std::vector<R> Pr(n_lo * n_hi);
   for (int k = 0; k < n_lo; ++k)
-    for (int m = 0; m < n_hi; ++m) Pr[k * n_hi + m] = h.w[m] * lagrange(l.x, k, h.x[m]) / l.w[k];
+    for (int m = 0; m < n_hi; ++m) Pr[k * n_hi + m] = h.w[m] * lagrange<R>(l.x, k, h.x[m]) / l.w[k];
   return Pr;
 }
 
 // ------------------------------------------------------------------ geometry
 // Trilinear map of a hexahedron; vertex v = a + 2b + 4c sits at reference
 // (2a-1, 2b-1, 2c-1).  dx[i][c] = d x_c / d xi^i.
-static void trilinear(const double* X, const double r[3], double x[3], double dx[3][3]) {
+template <class R> static void trilinear(const double* X, const R r[3], R x[3], R dx[3][3]) {
   for (int c = 0; c < 3; ++c) {
     x[c] = 0;
     for (int i = 0; i < 3; ++i) dx[i][c] = 0;
   }
   for (int v = 0; v < 8; ++v) {
-    double s[3] = {(v & 1) ? 1.0 : -1.0, (v & 2) ? 1.0 : -1.0, (v & 4) ? 1.0 : -1.0};
-    double f[3] = {1 + s[0] * r[0], 1 + s[1] * r[1], 1 + s[2] * r[2]};
-    double N = 0.125 * f[0] * f[1] * f[2];
-    double dN[3] = {0.125 * s[0] * f[1] * f[2], 0.125 * f[0] * s[1] * f[2], 0.125 * f[0] * f[1] * s[2]};
+    R s[3] = {(v & 1) ? R(1.0) : R(-1.0), (v & 2) ? R(1.0) : R(-1.0), (v & 4) ? R(1.0) : R(-1.0)};
+    R f[3] = {1 + s[0] * r[0], 1 + s[1] * r[1], 1 + s[2] * r[2]};
+    R N = R(0.125) * f[0] * f[1] * f[2];
+    R dN[3] = {R(0.125) * s[0] * f[1] * f[2], R(0.125) * f[0] * s[1] * f[2], R(0.125) * f[0] * f[1] * s[2]};
     for (int c = 0; c < 3; ++c) {
       x[c] += N * X[3 * v + c];
       for (int i = 0; i < 3; ++i) dx[i][c] += dN[i] * X[3 * v + c];
@@ -186,16 +192,16 @@ static void trilinear(const double* X, const double r[3], double x[3], double dx
   }
 }
 
-static void cross(const double a[3], const double b[3], double o[3]) {
+template <class R> static void cross(const R a[3], const R b[3], R o[3]) {
   o[0] = a[1] * b[2] - a[2] * b[1];
   o[1] = a[2] * b[0] - a[0] * b[2];
   o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
 // Metric cofactors Ja^i = x_{xi^(i+1)} x x_{xi^(i+2)} and J = det(dx/dxi) at r.
-static void metrics(const double* X, const double r[3], double Ja[3][3], double* J) {
-  double x[3], dx[3][3];
-  trilinear(X, r, x, dx);
+template <class R> static void metrics(const double* X, const R r[3], R Ja[3][3], R* J) {
+  R x[3], dx[3][3];
+  trilinear<R>(X, r, x, dx);
   for (int i = 0; i < 3; ++i) cross(dx[(i + 1) % 3], dx[(i + 2) % 3], Ja[i]);
   *J = dx[0][0] * Ja[0][0] + dx[0][1] * Ja[0][1] + dx[0][2] * Ja[0][2];
 }
@@ -206,7 +212,17 @@ struct Elem {
   long off;          // first solution point
   const double* X;   // 8 vertices
   std::vector<double> J, Ja;  // per solution point: J, Ja[i][c]
+  std::vector<long double> Jl, Jal;  // the same in extended precision
+  template <class R> const R* Jp() const;
+  template <class R> const R* Jap() const;
 };
+template <> const double* Elem::Jp<double>() const { return J.data(); }
+template <> const long double* Elem::Jp<long double>() const { return Jl.data(); }
+template <> const double* Elem::Jap<double>() const { return Ja.data(); }
+template <> const long double* Elem::Jap<long double>() const { return Jal.data(); }
+
+template <class S> struct real_of { using type = double; };
+template <> struct real_of<long double> { using type = long double; };
 
 struct IFace { int L, R, d; };        // L's +d face is R's -d face
 struct BFace { int e, f, bc; };       // element face f = 2d + s, bc -1 wall, -2 far field
@@ -236,8 +252,8 @@ static inline int line_idx(int n, int d, int a, int b, int m) {
 }
 
 // Reference coordinates of face point (a, b) of the n-point rule on face (d, side).
-static void face_point(int n, int d, int side, int a, int b, double r[3]) {
-  const Ops1D& o = ops(n);
+template <class R> static void face_point(int n, int d, int side, int a, int b, R r[3]) {
+  const Ops1DT<R>& o = ops<R>(n);
   r[d] = side ? 1.0 : -1.0;
   r[d == 0 ? 1 : 0] = o.x[a];
   r[d == 2 ? 1 : 2] = o.x[b];
@@ -284,9 +300,9 @@ template <class S> struct Phys {
     }
   }
   // common inviscid flux dotted with the (unnormalised) area vector Sv.
-  void roe(const S* qL, const S* qR, const double* Sv, S* out) const {
-    double area = std::sqrt(Sv[0] * Sv[0] + Sv[1] * Sv[1] + Sv[2] * Sv[2]);
-    double nv[3] = {Sv[0] / area, Sv[1] / area, Sv[2] / area};
+  template <class R> void roe(const S* qL, const S* qR, const R* Sv, S* out) const {
+    R area = std::sqrt(Sv[0] * Sv[0] + Sv[1] * Sv[1] + Sv[2] * Sv[2]);
+    R nv[3] = {Sv[0] / area, Sv[1] / area, Sv[2] / area};
     S fL[5], fR[5];
     for (int v = 0; v < 5; ++v) fL[v] = fR[v] = 0.0;
     for (int c = 0; c < 3; ++c) {
@@ -329,9 +345,9 @@ template <class S> struct Phys {
     diss[4] = l1 * a1 * (Ht - un * ct) + l2 * (a2 * 0.5 * q2 + rhot * (udu - un * dun)) + l5 * a5 * (Ht + un * ct);
     for (int v = 0; v < 5; ++v) out[v] = area * (0.5 * (fL[v] + fR[v]) - 0.5 * diss[v]);
   }
-  void rusanov(const S* qL, const S* qR, const double* Sv, S* out) const {
-    double area = std::sqrt(Sv[0] * Sv[0] + Sv[1] * Sv[1] + Sv[2] * Sv[2]);
-    double nv[3] = {Sv[0] / area, Sv[1] / area, Sv[2] / area};
+  template <class R> void rusanov(const S* qL, const S* qR, const R* Sv, S* out) const {
+    R area = std::sqrt(Sv[0] * Sv[0] + Sv[1] * Sv[1] + Sv[2] * Sv[2]);
+    R nv[3] = {Sv[0] / area, Sv[1] / area, Sv[2] / area};
     S fL[5], fR[5];
     for (int v = 0; v < 5; ++v) fL[v] = fR[v] = 0.0;
     for (int c = 0; c < 3; ++c) {
@@ -361,7 +377,8 @@ template <class S> struct Work {
 };
 
 template <class S>
-static void residual(const Mesh& M, const S* U, S* R, double* bflux = nullptr) {
+static void residual(const Mesh& M, const S* U, S* Rout, double* bflux = nullptr) {
+  using R = typename real_of<S>::type;
   Phys<S> ph{M.gamma, M.mu, M.prandtl};
   const bool ns = M.physics == 1;
   if (bflux)
@@ -381,11 +398,13 @@ static void residual(const Mesh& M, const S* U, S* R, double* bflux = nullptr) {
   for (int e = 0; e < E; ++e) {
     const Elem& el = M.el[e];
     int n = el.n, n2 = n * n, n3 = n2 * n;
-    const Ops1D& o = ops(n);
+    const Ops1DT<R>& o = ops<R>(n);
+    const R* eJ = el.Jp<R>();
+    const R* eJa = el.Jap<R>();
     W.qf[e].assign(6 * 5 * n2, S(0.0));
     for (int f = 0; f < 6; ++f) {
       int d = f / 2;
-      const std::vector<double>& l = (f % 2) ? o.lp : o.lm;
+      const std::vector<R>& l = (f % 2) ? o.lp : o.lm;
       for (int v = 0; v < 5; ++v)
         for (int b = 0; b < n; ++b)
           for (int a = 0; a < n; ++a) {
@@ -410,15 +429,15 @@ static void residual(const Mesh& M, const S* U, S* R, double* bflux = nullptr) {
         }
         for (int c = 0; c < 3; ++c) {
           S s = 0.0;
-          for (int i = 0; i < 3; ++i) s += el.Ja[k * 9 + i * 3 + c] * dxi[i];
-          gphys[e][k * 15 + v * 3 + c] = s / el.J[k];
+          for (int i = 0; i < 3; ++i) s += eJa[k * 9 + i * 3 + c] * dxi[i];
+          gphys[e][k * 15 + v * 3 + c] = s / eJ[k];
         }
       }
     }
     W.gf[e].assign(6 * 15 * n2, S(0.0));
     for (int f = 0; f < 6; ++f) {
       int d = f / 2;
-      const std::vector<double>& l = (f % 2) ? o.lp : o.lm;
+      const std::vector<R>& l = (f % 2) ? o.lp : o.lm;
       for (int vc = 0; vc < 15; ++vc)
         for (int b = 0; b < n; ++b)
           for (int a = 0; a < n; ++a) {
@@ -438,7 +457,7 @@ static void residual(const Mesh& M, const S* U, S* R, double* bflux = nullptr) {
   // values of side (e, f) at the face's nh x nh points (tensor interpolation)
   auto to_face = [&](const std::vector<S>& src, int e, int f, int nvals, int nh, std::vector<S>& dst) {
     int n = M.el[e].n, n2 = n * n;
-    std::vector<double> I = interp_matrix(n, nh);
+    std::vector<R> I = interp_matrix<R>(n, nh);
     dst.assign(nvals * nh * nh, S(0.0));
     for (int v = 0; v < nvals; ++v)
       for (int B = 0; B < nh; ++B)
@@ -453,7 +472,7 @@ static void residual(const Mesh& M, const S* U, S* R, double* bflux = nullptr) {
   // onto the side's own degree
   auto from_face = [&](const std::vector<S>& src, int e, int f, int nh, std::vector<S>& dst) {
     int n = M.el[e].n, n2 = n * n;
-    std::vector<double> P = project_matrix(nh, n);
+    std::vector<R> P = project_matrix<R>(nh, n);
     for (int v = 0; v < 5; ++v)
       for (int b = 0; b < n; ++b)
         for (int a = 0; a < n; ++a) {
@@ -463,7 +482,7 @@ static void residual(const Mesh& M, const S* U, S* R, double* bflux = nullptr) {
           dst[(f * 5 + v) * n2 + a + n * b] = s;
         }
   };
-  auto common_inviscid = [&](const S* qm, const S* qp, const double* Sv, S* out) {
+  auto common_inviscid = [&](const S* qm, const S* qp, const R* Sv, S* out) {
     if (M.flux == 0) ph.roe(qm, qp, Sv, out);
     else ph.rusanov(qm, qp, Sv, out);
   };
@@ -482,11 +501,11 @@ static void residual(const Mesh& M, const S* U, S* R, double* bflux = nullptr) {
     for (int B = 0; B < nh; ++B)
       for (int A = 0; A < nh; ++A) {
         int pt = A + nh * B;
-        double rL[3], rR[3], Sv[3], JaL[3][3], JaR[3][3], JL, JR;
-        face_point(nh, F.d, 1, A, B, rL);
-        face_point(nh, F.d, 0, A, B, rR);
-        metrics(M.el[F.L].X, rL, JaL, &JL);  // area vector from the minus side
-        metrics(M.el[F.R].X, rR, JaR, &JR);
+        R rL[3], rR[3], Sv[3], JaL[3][3], JaR[3][3], JL, JR;
+        face_point<R>(nh, F.d, 1, A, B, rL);
+        face_point<R>(nh, F.d, 0, A, B, rR);
+        metrics<R>(M.el[F.L].X, rL, JaL, &JL);  // area vector from the minus side
+        metrics<R>(M.el[F.R].X, rR, JaR, &JR);
         for (int c = 0; c < 3; ++c) Sv[c] = JaL[F.d][c];
         S qm[5], qp[5], qc[5], out[5];
         for (int v = 0; v < 5; ++v) {
@@ -497,8 +516,8 @@ static void residual(const Mesh& M, const S* U, S* R, double* bflux = nullptr) {
         common_inviscid(qm, qp, Sv, out);
         if (ns) {
           // BR2 liftings of this face's jump: r = (S / J_f) (q_com - q) g'(face)
-          double cL = 0.5 * nL * nL / JL;   // g_R'(+1) = (p+1)^2/2 on L's + face
-          double cR = -0.5 * nR * nR / JR;  // g_L'(-1) = -(p+1)^2/2 on R's - face
+          R cL = R(0.5) * nL * nL / JL;   // g_R'(+1) = (p+1)^2/2 on L's + face
+          R cR = R(-0.5) * nR * nR / JR;  // g_L'(-1) = -(p+1)^2/2 on R's - face
           S Gc[5][3];
           for (int v = 0; v < 5; ++v)
             for (int c = 0; c < 3; ++c) {
@@ -528,10 +547,10 @@ static void residual(const Mesh& M, const S* U, S* R, double* bflux = nullptr) {
     for (int b = 0; b < n; ++b)
       for (int a = 0; a < n; ++a) {
         int pt = a + n * b;
-        double r[3], Ja[3][3], J;
-        face_point(n, d, side, a, b, r);
-        metrics(el.X, r, Ja, &J);
-        const double* Sv = Ja[d];
+        R r[3], Ja[3][3], J;
+        face_point<R>(n, d, side, a, b, r);
+        metrics<R>(el.X, r, Ja, &J);
+        const R* Sv = Ja[d];
         S qi[5], qb[5], out[5];
         for (int v = 0; v < 5; ++v) qi[v] = W.qf[F.e][(F.f * 5 + v) * n2 + pt];
         bool wall = F.bc == -1;
@@ -553,7 +572,7 @@ static void residual(const Mesh& M, const S* U, S* R, double* bflux = nullptr) {
           else common_inviscid(qinf, qi, Sv, out);
         }
         if (ns) {
-          double cf = (side ? 0.5 : -0.5) * n * n / J;
+          R cf = R(side ? 0.5 : -0.5) * n * n / J;
           S Gc[5][3];
           for (int v = 0; v < 5; ++v)
             for (int c = 0; c < 3; ++c)
@@ -574,7 +593,9 @@ static void residual(const Mesh& M, const S* U, S* R, double* bflux = nullptr) {
   for (int e = 0; e < E; ++e) {
     const Elem& el = M.el[e];
     int n = el.n, n2 = n * n, n3 = n2 * n;
-    const Ops1D& o = ops(n);
+    const Ops1DT<R>& o = ops<R>(n);
+    const R* eJ = el.Jp<R>();
+    const R* eJa = el.Jap<R>();
     std::vector<S> Ft(n3 * 15);  // Ft[k][i][v]
     for (int k = 0; k < n3; ++k) {
       int id[3] = {k % n, (k / n) % n, k / n2};
@@ -601,8 +622,8 @@ static void residual(const Mesh& M, const S* U, S* R, double* bflux = nullptr) {
           }
           for (int c = 0; c < 3; ++c) {
             S s = 0.0;
-            for (int i = 0; i < 3; ++i) s += el.Ja[k * 9 + i * 3 + c] * dxi[i];
-            G[v][c] = s / el.J[k];
+            for (int i = 0; i < 3; ++i) s += eJa[k * 9 + i * 3 + c] * dxi[i];
+            G[v][c] = s / eJ[k];
           }
         }
         S fv[3][5];
@@ -613,7 +634,7 @@ static void residual(const Mesh& M, const S* U, S* R, double* bflux = nullptr) {
       for (int i = 0; i < 3; ++i)
         for (int v = 0; v < 5; ++v) {
           S s = 0.0;
-          for (int c = 0; c < 3; ++c) s += el.Ja[k * 9 + i * 3 + c] * f[c][v];
+          for (int c = 0; c < 3; ++c) s += eJa[k * 9 + i * 3 + c] * f[c][v];
           Ft[k * 15 + i * 5 + v] = s;
         }
     }
@@ -621,7 +642,7 @@ static void residual(const Mesh& M, const S* U, S* R, double* bflux = nullptr) {
     std::vector<S> df(6 * 5 * n2);
     for (int f = 0; f < 6; ++f) {
       int d = f / 2;
-      const std::vector<double>& l = (f % 2) ? o.lp : o.lm;
+      const std::vector<R>& l = (f % 2) ? o.lp : o.lm;
       for (int v = 0; v < 5; ++v)
         for (int b = 0; b < n; ++b)
           for (int a = 0; a < n; ++a) {
@@ -644,7 +665,7 @@ static void residual(const Mesh& M, const S* U, S* R, double* bflux = nullptr) {
           s += df[((2 * i) * 5 + v) * n2 + a + n * b] * o.gLp[id[i]];
           s += df[((2 * i + 1) * 5 + v) * n2 + a + n * b] * o.gRp[id[i]];
         }
-        R[v * N + el.off + k] = -s / el.J[k];
+        Rout[v * N + el.off + k] = -s / eJ[k];
       }
     }
   }
@@ -683,14 +704,23 @@ void* oracle_create(int n_elem, const double* elem_xyz, const int32_t* elem_nbr,
     off += n3;
     el.J.resize(n3);
     el.Ja.resize(9 * n3);
+    el.Jl.resize(n3);
+    el.Jal.resize(9 * n3);
     const Ops1D& o = ops(n);
+    const Ops1DT<long double>& ol = ops<long double>(n);
     for (int k = 0; k < n3; ++k) {
       double r[3] = {o.x[k % n], o.x[(k / n) % n], o.x[k / (n * n)]};
       double Ja[3][3], J;
-      metrics(el.X, r, Ja, &J);
+      metrics<double>(el.X, r, Ja, &J);
       el.J[k] = J;
       for (int i = 0; i < 3; ++i)
         for (int c = 0; c < 3; ++c) el.Ja[k * 9 + i * 3 + c] = Ja[i][c];
+      long double rl[3] = {ol.x[k % n], ol.x[(k / n) % n], ol.x[k / (n * n)]};
+      long double Jal[3][3], Jl;
+      metrics<long double>(el.X, rl, Jal, &Jl);
+      el.Jl[k] = Jl;
+      for (int i = 0; i < 3; ++i)
+        for (int c = 0; c < 3; ++c) el.Jal[k * 9 + i * 3 + c] = Jal[i][c];
     }
   }
   M->n_sp = off;
@@ -710,6 +740,17 @@ void oracle_destroy(void* h) { delete (Mesh*)h; }
 long oracle_nsp(void* h) { return ((Mesh*)h)->n_sp; }
 
 void oracle_residual(void* h, const double* U, double* R) { residual<double>(*(Mesh*)h, U, R); }
+
+// The same residual evaluated in extended precision (x87 long double, 64-bit
+// significand) from the same double inputs: a reference for sizing the
+// rounding error of double-precision evaluations.
+void oracle_residual_ld(void* h, const double* U, double* R) {
+  Mesh& M = *(Mesh*)h;
+  long N = 5 * M.n_sp;
+  std::vector<long double> Ul(U, U + N), Rl(N);
+  residual<long double>(M, Ul.data(), Rl.data());
+  for (long i = 0; i < N; ++i) R[i] = (double)Rl[i];
+}
 
 // Complex-step tangent: J v = Im R(U + i h v) / h.
 void oracle_jvp_cs(void* h, const double* U, const double* v, double* Jv) {

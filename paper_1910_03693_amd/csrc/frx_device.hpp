@@ -258,14 +258,14 @@ __device__ __forceinline__ void riemann(const T qL[5], const T qR[5], const B S[
 
 // Face function at one face point of an interior face (L on the minus side of
 // S, R on the plus side): common solution (eq. com_q), BR2 common gradient
-// (eq. com_grad_q) with liftings r = S (q_com - q) g'(face) / J_f, common
+// (eq. com_grad_q) from gLR = grad q^- + grad q^+ and the liftings
+// r = S (q_com - q) g'(face) / J_f, common
 // normal flux f_com . S = Riemann(qL, qR) - f_vis(q_com, grad q_com) . S,
 // and the solution jumps q_com - q of both sides.  cL = g_R'(+1)/J_L > 0,
 // cR = g_L'(-1)/J_R < 0.
 template <bool NS, class T, class B>
-__device__ __forceinline__ void face_fn(const T qL[5], const T qR[5], const T gL[5][3], const T gR[5][3],
-                                        const B S[3], B cL, B cR, const Gas<B>& G, int flux, T fS[5], T jL[5],
-                                        T jR[5]) {
+__device__ __forceinline__ void face_fn(const T qL[5], const T qR[5], const T gLR[5][3], const B S[3], B cL, B cR,
+                                        const Gas<B>& G, int flux, T fS[5], T jL[5], T jR[5]) {
   T qc[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
@@ -280,7 +280,7 @@ __device__ __forceinline__ void face_fn(const T qL[5], const T qR[5], const T gL
     for (int v = 0; v < 5; ++v) {
       T lift = cL * jL[v] + cR * jR[v];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) Gc[v][c] = B(0.5) * (gL[v][c] + gR[v][c] + S[c] * lift);
+      for (int c = 0; c < 3; ++c) Gc[v][c] = B(0.5) * (gLR[v][c] + S[c] * lift);
     }
     T tau[3][3], e[3];
     viscous_terms<T, B>(qc, Gc, G, tau, e);

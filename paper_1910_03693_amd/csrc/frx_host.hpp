@@ -33,6 +33,33 @@ struct BFaceBucket {
   int4* faces = nullptr;  // device (e, f, bc, 0)
 };
 
+// Optional per-launch timing: every residual-stage launch is bracketed by two
+// events on its stream.
+struct ProfHook {
+  struct Rec {
+    const char* stage;
+    int nl, nh;
+    long units;  // elements or faces of the launch
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  void begin(const char* stage, int nl, int nh, long units, hipStream_t s) {
+    Rec r{stage, nl, nh, units, nullptr, nullptr};
+    (void)hipEventCreate(&r.a);
+    (void)hipEventCreate(&r.b);
+    (void)hipEventRecord(r.a, s);
+    recs.push_back(r);
+  }
+  void end(hipStream_t s) { (void)hipEventRecord(recs.back().b, s); }
+};
+
+// Tile tables of the degree-bucketed (fused) launches, per scalar kind.
+struct FusedPlan {
+  int4* tiles[3] = {nullptr, nullptr, nullptr};  // trace, face, div
+  int count[3] = {0, 0, 0};
+  size_t lds[3] = {0, 0, 0};
+};
+
 struct MeshDev {
   int E = 0;
   int nsp = 0, nfp = 0;
@@ -46,6 +73,11 @@ struct MeshDev {
   std::vector<BFaceBucket> bb;
   void* facebuf = nullptr;  // 30 * nfp scalars of the widest scalar type
   int* flag = nullptr;
+  ProfHook* prof = nullptr;
+  bool fused = false;             // one launch per stage over all buckets
+  int* all_elems = nullptr;       // concatenated bucket element lists
+  int4* all_faces = nullptr;      // concatenated interior + boundary face lists
+  FusedPlan plan[SK_COUNT];
   Gas<double> gas_d;
   Gas<float> gas_f;
 };
@@ -78,6 +110,8 @@ size_t scalar_bytes(int sk);
 }  // namespace frx
 
 namespace frx {
+hipError_t upload_tables_vjp(const OpsTab<double>& d, const OpsTab<float>& f);
+hipError_t launch_vjp(const MeshDev& M, const double* U, const double* w, double* out, hipStream_t s);
 hipError_t launch_indicator(const MeshDev& M, const double* U, int var, double* eta, double* eta_max,
                             hipStream_t s);
 }  // namespace frx

@@ -104,14 +104,52 @@ hipError_t face_n(const ResArgs<T>& a, const FaceBucket& b, int fpb, hipStream_t
 template <class T, bool NS>
 hipError_t residual_stages(const ResArgs<T>& a, const MeshDev& M, int sk, hipStream_t s) {
   hipError_t e;
-  for (const ElemBucket& b : M.eb)
-    if (b.count && (e = trace_n<T, NS>(a, b, b.epb_trace[sk], s)) != hipSuccess) return e;
-  for (const FaceBucket& b : M.fb)
-    if (b.count && (e = face_n<T, NS>(a, b, b.fpb[sk], s)) != hipSuccess) return e;
-  for (const BFaceBucket& b : M.bb)
-    if (b.count && (e = bface_n<T, NS>(a, b, s)) != hipSuccess) return e;
-  for (const ElemBucket& b : M.eb)
-    if (b.count && (e = div_n<T, NS>(a, b, b.epb_div[sk], s)) != hipSuccess) return e;
+  ProfHook* P = M.prof;
+  for (const ElemBucket& b : M.eb) {
+    if (!b.count) continue;
+    if (P) P->begin("k_trace", b.n, b.n, b.count, s);
+    if ((e = trace_n<T, NS>(a, b, b.epb_trace[sk], s)) != hipSuccess) return e;
+    if (P) P->end(s);
+  }
+  for (const FaceBucket& b : M.fb) {
+    if (!b.count) continue;
+    if (P) P->begin("k_face", b.nl, b.nh, b.count, s);
+    if ((e = face_n<T, NS>(a, b, b.fpb[sk], s)) != hipSuccess) return e;
+    if (P) P->end(s);
+  }
+  for (const BFaceBucket& b : M.bb) {
+    if (!b.count) continue;
+    if (P) P->begin("k_bface", b.n, b.n, b.count, s);
+    if ((e = bface_n<T, NS>(a, b, s)) != hipSuccess) return e;
+    if (P) P->end(s);
+  }
+  for (const ElemBucket& b : M.eb) {
+    if (!b.count) continue;
+    if (P) P->begin("k_div", b.n, b.n, b.count, s);
+    if ((e = div_n<T, NS>(a, b, b.epb_div[sk], s)) != hipSuccess) return e;
+    if (P) P->end(s);
+  }
+  return hipSuccess;
+}
+
+template <class T, bool NS>
+hipError_t residual_fused(const ResArgs<T>& a, const MeshDev& M, int sk, hipStream_t s) {
+  const FusedPlan& P = M.plan[sk];
+  ProfHook* H = M.prof;
+  const char* names[3] = {"k_trace_fused", "k_face_fused", "k_div_fused"};
+  for (int st = 0; st < 3; ++st) {
+    if (!P.count[st]) continue;
+    if (H) H->begin(names[st], 0, 0, P.count[st], s);
+    if (st == 0)
+      hipLaunchKernelGGL((k_trace_fused<T, NS>), dim3(P.count[0]), dim3(256), P.lds[0], s, a, M.all_elems, P.tiles[0]);
+    else if (st == 1)
+      hipLaunchKernelGGL((k_face_fused<T, NS>), dim3(P.count[1]), dim3(256), P.lds[1], s, a, M.all_faces, P.tiles[1]);
+    else
+      hipLaunchKernelGGL((k_div_fused<T, NS>), dim3(P.count[2]), dim3(256), P.lds[2], s, a, M.all_elems, P.tiles[2]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (H) H->end(s);
+  }
   return hipSuccess;
 }
 
@@ -140,6 +178,8 @@ hipError_t launch_residual_T(const MeshDev& M, const ResCall<base_t<T>>& c, int 
   a.gas = gas_of<B>(M);
   a.flag = M.flag;
   a.skip = c.skip;
+  if (M.fused)
+    return M.physics == 1 ? residual_fused<T, true>(a, M, sk, s) : residual_fused<T, false>(a, M, sk, s);
   return M.physics == 1 ? residual_stages<T, true>(a, M, sk, s) : residual_stages<T, false>(a, M, sk, s);
 }
 

@@ -68,16 +68,15 @@ template <int N> __device__ __forceinline__ int line_pt(int d, int a, int b, int
 // region of 5 N^3 scalars per element, holding q and then, one variable at a
 // time, the three components of its uncorrected physical gradient.
 template <int N, class T, bool NS>
-__global__ void __launch_bounds__(1024) k_trace(ResArgs<T> a, const int* __restrict__ elems, int nel, int epb) {
-  if (a.skip && *a.skip) return;
+__device__ __forceinline__ void trace_body(const ResArgs<T>& a, const int* __restrict__ elems, int nel, int epb,
+                                           int blk, unsigned char* smem) {
   using B = base_t<T>;
   constexpr int N2 = N * N, N3 = N2 * N;
-  extern __shared__ __align__(16) unsigned char smem[];
   T* sq = reinterpret_cast<T*>(smem);  // [epb][5][N3]
   const OpsTab<B>& O = ops<B>();
   const int tid = threadIdx.x;
   const int le = tid / N3, k = tid - le * N3;
-  const int slot = blockIdx.x * epb + le;
+  const int slot = blk * epb + le;
   const bool act = le < epb && slot < nel;
   const int e = act ? elems[slot] : 0;
   if (act) {
@@ -90,7 +89,7 @@ __global__ void __launch_bounds__(1024) k_trace(ResArgs<T> a, const int* __restr
   for (int it = tid; it < items; it += blockDim.x) {
     const int l2 = it / (6 * N2), rem = it - l2 * 6 * N2;
     const int f = rem / N2, pt = rem - f * N2;
-    const int s2 = blockIdx.x * epb + l2;
+    const int s2 = blk * epb + l2;
     if (s2 >= nel) continue;
     const long o = a.fp_off[elems[s2]] + f * N2 + pt;
     const int d = f >> 1, fa = pt % N, fb = pt / N;
@@ -126,7 +125,7 @@ __global__ void __launch_bounds__(1024) k_trace(ResArgs<T> a, const int* __restr
       for (int c = 0; c < 3; ++c) gq[v][c] = (Ja[0][c] * d0 + Ja[1][c] * d1 + Ja[2][c] * d2) * iJ;
     }
   }
-#pragma unroll 1
+#pragma unroll
   for (int v = 0; v < 5; ++v) {
     __syncthreads();  // previous readers of the region are done
     if (act) {
@@ -138,7 +137,7 @@ __global__ void __launch_bounds__(1024) k_trace(ResArgs<T> a, const int* __restr
       const int l2 = it / (18 * N2), rem = it - l2 * 18 * N2;
       const int fc = rem / N2, pt = rem - fc * N2;  // fc = f * 3 + c
       const int f = fc / 3, c = fc - f * 3;
-      const int s2 = blockIdx.x * epb + l2;
+      const int s2 = blk * epb + l2;
       if (s2 >= nel) continue;
       const long o = a.fp_off[elems[s2]] + f * N2 + pt;
       const int d = f >> 1;
@@ -158,19 +157,18 @@ __global__ void __launch_bounds__(1024) k_trace(ResArgs<T> a, const int* __restr
 // from L to R and is evaluated once per face point from L's map.
 // Block: fpb faces x NH^2 threads (one face point each).
 template <int NL, int NH, class T, bool NS>
-__global__ void __launch_bounds__(1024) k_face(ResArgs<T> a, const int4* __restrict__ faces, int nf, int fpb) {
-  if (a.skip && *a.skip) return;
+__device__ __forceinline__ void face_body(const ResArgs<T>& a, const int4* __restrict__ faces, int nf, int fpb,
+                                          int blk, unsigned char* smem) {
   using B = base_t<T>;
   constexpr int NH2 = NH * NH, NL2 = NL * NL;
   constexpr bool MIX = NL < NH;
   constexpr int NV = NS ? 20 : 5;
-  extern __shared__ __align__(16) unsigned char smem[];
   T* slow = reinterpret_cast<T*>(smem);              // [fpb][NV][NL2] low-side traces
   T* sout = slow + (MIX ? fpb * NV * NL2 : 0);       // [fpb][10][NH2] low-side results
   const OpsTab<B>& O = ops<B>();
   const int tid = threadIdx.x;
   const int lf = tid / NH2, pt = tid - lf * NH2;
-  const int fi = blockIdx.x * fpb + lf;
+  const int fi = blk * fpb + lf;
   const bool act = lf < fpb && fi < nf;
   int4 F = act ? faces[fi] : make_int4(0, 0, 0, 0);
   const int L = F.x, R = F.y, d = F.z;
@@ -180,7 +178,7 @@ __global__ void __launch_bounds__(1024) k_face(ResArgs<T> a, const int4* __restr
     for (int it = tid; it < fpb * NV * NL2; it += blockDim.x) {
       const int l2 = it / (NV * NL2), rem = it - l2 * NV * NL2;
       const int vv = rem / NL2, p2 = rem - vv * NL2;
-      const int f2 = blockIdx.x * fpb + l2;
+      const int f2 = blk * fpb + l2;
       if (f2 >= nf) continue;
       int4 G2 = faces[f2];
       const int el = G2.w ? G2.y : G2.x;
@@ -192,11 +190,19 @@ __global__ void __launch_bounds__(1024) k_face(ResArgs<T> a, const int4* __restr
   }
   if (act) {
     const int A = pt % NH, Bq = pt / NH;
-    T q[2][5], g[2][5][3];
+    // q of both sides and the SUM of their gradient traces (all that the
+    // BR2 common gradient needs), each side read at the face point
+    T q[2][5], g[1][5][3];
+    if (NS) {
+#pragma unroll
+      for (int vc = 0; vc < 15; ++vc) g[0][vc / 3][vc % 3] = T(B(0));
+    }
+#pragma unroll
     for (int s = 0; s < 2; ++s) {
       const bool low = s ? lowR : lowL;
       if (low) {
         const T* src = slow + lf * NV * NL2;
+#pragma unroll
         for (int vv = 0; vv < NV; ++vv) {
           T acc = T(B(0));
 #pragma unroll
@@ -207,7 +213,7 @@ __global__ void __launch_bounds__(1024) k_face(ResArgs<T> a, const int4* __restr
             acc = fmab(O.I[NL - 2][NH - 2][Bq][b], row, acc);
           }
           if (vv < 5) q[s][vv] = acc;
-          else g[s][(vv - 5) / 3][(vv - 5) % 3] = acc;
+          else g[0][(vv - 5) / 3][(vv - 5) % 3] += acc;
         }
       } else {
         const int el = s ? R : L;
@@ -216,7 +222,7 @@ __global__ void __launch_bounds__(1024) k_face(ResArgs<T> a, const int4* __restr
         for (int v = 0; v < 5; ++v) q[s][v] = a.QF[(long)v * a.nfp + o];
         if (NS) {
 #pragma unroll
-          for (int vc = 0; vc < 15; ++vc) g[s][vc / 3][vc % 3] = a.GF[(long)vc * a.nfp + o];
+          for (int vc = 0; vc < 15; ++vc) g[0][vc / 3][vc % 3] += a.GF[(long)vc * a.nfp + o];
         }
       }
     }
@@ -238,7 +244,7 @@ __global__ void __launch_bounds__(1024) k_face(ResArgs<T> a, const int4* __restr
       cR = -B(0.5) * B(nR * nR) / JR;
     }
     T fS[5], jL[5], jR[5];
-    face_fn<NS, T, B>(q[0], q[1], g[0], g[1], S, cL, cR, a.gas, a.flux, fS, jL, jR);
+    face_fn<NS, T, B>(q[0], q[1], g[0], S, cL, cR, a.gas, a.flux, fS, jL, jR);
     if (!lowL) {
       const long o = a.fp_off[L] + (2 * d + 1) * NH2 + pt;
 #pragma unroll
@@ -268,7 +274,7 @@ __global__ void __launch_bounds__(1024) k_face(ResArgs<T> a, const int4* __restr
     __syncthreads();
     for (int it = tid; it < fpb * NL2; it += blockDim.x) {
       const int l2 = it / NL2, p2 = it - l2 * NL2;
-      const int f2 = blockIdx.x * fpb + l2;
+      const int f2 = blk * fpb + l2;
       if (f2 >= nf) continue;
       int4 G2 = faces[f2];
       const int el = G2.w ? G2.y : G2.x;
@@ -295,11 +301,10 @@ __global__ void __launch_bounds__(1024) k_face(ResArgs<T> a, const int4* __restr
 // Boundary faces of elements of size N: record (e, f, bc, 0).  One thread per
 // face point.
 template <int N, class T, bool NS>
-__global__ void __launch_bounds__(256) k_bface(ResArgs<T> a, const int4* __restrict__ faces, int nf) {
-  if (a.skip && *a.skip) return;
+__device__ __forceinline__ void bface_body(const ResArgs<T>& a, const int4* __restrict__ faces, int nf, int blk) {
   using B = base_t<T>;
   constexpr int N2 = N * N;
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gid = blk * blockDim.x + threadIdx.x;
   if (gid >= nf * N2) return;
   const int fi = gid / N2, pt = gid - fi * N2;
   const int4 F = faces[fi];
@@ -336,17 +341,16 @@ __global__ void __launch_bounds__(256) k_bface(ResArgs<T> a, const int4* __restr
 // of 30 N^2 (the solution jumps of the 6 faces, then the flux jumps
 // f_com . S - f_loc).
 template <int N, class T, bool NS>
-__global__ void __launch_bounds__(1024) k_div(ResArgs<T> a, const int* __restrict__ elems, int nel, int epb) {
-  if (a.skip && *a.skip) return;
+__device__ __forceinline__ void div_body(const ResArgs<T>& a, const int* __restrict__ elems, int nel, int epb,
+                                         int blk, unsigned char* smem) {
   using B = base_t<T>;
   constexpr int N2 = N * N, N3 = N2 * N;
-  extern __shared__ __align__(16) unsigned char smem[];
   T* sX = reinterpret_cast<T*>(smem);  // [epb][5][N3]
   T* sY = sX + epb * 5 * N3;           // [epb][6][5][N2]
   const OpsTab<B>& O = ops<B>();
   const int tid = threadIdx.x;
   const int le = tid / N3, k = tid - le * N3;
-  const int slot = blockIdx.x * epb + le;
+  const int slot = blk * epb + le;
   const bool act = le < epb && slot < nel;
   const int e = act ? elems[slot] : 0;
   const long off = act ? (long)a.sp_off[e] + k : 0;
@@ -358,7 +362,7 @@ __global__ void __launch_bounds__(1024) k_div(ResArgs<T> a, const int* __restric
     for (int it = tid; it < epb * 30 * N2; it += blockDim.x) {
       const int l2 = it / (30 * N2), rem = it - l2 * 30 * N2;
       const int fv = rem / N2, p2 = rem - fv * N2;  // fv = f * 5 + v
-      const int s2 = blockIdx.x * epb + l2;
+      const int s2 = blk * epb + l2;
       if (s2 >= nel) continue;
       const int f = fv / 5, v = fv - f * 5;
       sY[it] = a.DQ[(long)v * a.nfp + a.fp_off[elems[s2]] + f * N2 + p2];
@@ -404,7 +408,7 @@ __global__ void __launch_bounds__(1024) k_div(ResArgs<T> a, const int* __restric
   T acc[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) acc[v] = T(B(0));
-#pragma unroll 1
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
     __syncthreads();  // X (q or the previous direction) and Y are no longer read
     if (act) {
@@ -427,7 +431,7 @@ __global__ void __launch_bounds__(1024) k_div(ResArgs<T> a, const int* __restric
     for (int it = tid; it < epb * 10 * N2; it += blockDim.x) {
       const int l2 = it / (10 * N2), rem = it - l2 * 10 * N2;
       const int sv = rem / N2, p2 = rem - sv * N2;  // sv = side * 5 + v
-      const int s2 = blockIdx.x * epb + l2;
+      const int s2 = blk * epb + l2;
       if (s2 >= nel) continue;
       const int side = sv / 5, v = sv - side * 5, f = 2 * d + side;
       const B* lf = side ? O.lp[N] : O.lm[N];
@@ -460,5 +464,97 @@ __global__ void __launch_bounds__(1024) k_div(ResArgs<T> a, const int* __restric
     }
   }
 }
+
+// ------------------------------------------------------ per-bucket kernels
+template <int N, class T, bool NS>
+__global__ void __launch_bounds__(256) k_trace(ResArgs<T> a, const int* __restrict__ elems, int nel, int epb) {
+  if (a.skip && *a.skip) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  trace_body<N, T, NS>(a, elems, nel, epb, blockIdx.x, smem);
+}
+template <int NL, int NH, class T, bool NS>
+__global__ void __launch_bounds__(256) k_face(ResArgs<T> a, const int4* __restrict__ faces, int nf, int fpb) {
+  if (a.skip && *a.skip) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  face_body<NL, NH, T, NS>(a, faces, nf, fpb, blockIdx.x, smem);
+}
+template <int N, class T, bool NS>
+__global__ void __launch_bounds__(256) k_bface(ResArgs<T> a, const int4* __restrict__ faces, int nf) {
+  if (a.skip && *a.skip) return;
+  bface_body<N, T, NS>(a, faces, nf, blockIdx.x);
+}
+template <int N, class T, bool NS>
+__global__ void __launch_bounds__(256) k_div(ResArgs<T> a, const int* __restrict__ elems, int nel, int epb) {
+  if (a.skip && *a.skip) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  div_body<N, T, NS>(a, elems, nel, epb, blockIdx.x, smem);
+}
+
+// ------------------------------------------------- degree-bucketed launches
+// One launch per stage over every degree bucket.  tiles[blockIdx.x] =
+// (code, first, count, per): code = n for element tiles, 8 nl + nh for
+// interior-face tiles, 64 + n for boundary-face tiles; `first` indexes the
+// concatenated element (face) list; count <= per items of one block.  The
+// host orders the tiles by decreasing work (the heavy degrees first), so the
+// hardware dispatcher hands out the long tiles before the short ones.
+#define FRX_ECASE(BODY, N) \
+  case N: BODY<N, T, NS>(a, elems + t.y, t.z, t.w, 0, smem); break;
+
+template <class T, bool NS>
+__global__ void __launch_bounds__(256) k_trace_fused(ResArgs<T> a, const int* __restrict__ elems,
+                                                     const int4* __restrict__ tiles) {
+  if (a.skip && *a.skip) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int4 t = tiles[blockIdx.x];
+  switch (t.x) {
+    FRX_ECASE(trace_body, 2)
+    FRX_ECASE(trace_body, 3)
+    FRX_ECASE(trace_body, 4)
+    FRX_ECASE(trace_body, 5)
+    FRX_ECASE(trace_body, 6)
+    default: break;
+  }
+}
+
+template <class T, bool NS>
+__global__ void __launch_bounds__(256) k_div_fused(ResArgs<T> a, const int* __restrict__ elems,
+                                                   const int4* __restrict__ tiles) {
+  if (a.skip && *a.skip) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int4 t = tiles[blockIdx.x];
+  switch (t.x) {
+    FRX_ECASE(div_body, 2)
+    FRX_ECASE(div_body, 3)
+    FRX_ECASE(div_body, 4)
+    FRX_ECASE(div_body, 5)
+    FRX_ECASE(div_body, 6)
+    default: break;
+  }
+}
+#undef FRX_ECASE
+
+#define FRX_FCASE(NL, NH) \
+  case 8 * NL + NH: face_body<NL, NH, T, NS>(a, faces + t.y, t.z, t.w, 0, smem); break;
+#define FRX_BCASE(N) \
+  case 64 + N: bface_body<N, T, NS>(a, faces + t.y, t.z, 0); break;
+
+template <class T, bool NS>
+__global__ void __launch_bounds__(256) k_face_fused(ResArgs<T> a, const int4* __restrict__ faces,
+                                                    const int4* __restrict__ tiles) {
+  if (a.skip && *a.skip) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int4 t = tiles[blockIdx.x];
+  switch (t.x) {
+    FRX_FCASE(2, 2) FRX_FCASE(2, 3) FRX_FCASE(2, 4) FRX_FCASE(2, 5) FRX_FCASE(2, 6)
+    FRX_FCASE(3, 3) FRX_FCASE(3, 4) FRX_FCASE(3, 5) FRX_FCASE(3, 6)
+    FRX_FCASE(4, 4) FRX_FCASE(4, 5) FRX_FCASE(4, 6)
+    FRX_FCASE(5, 5) FRX_FCASE(5, 6)
+    FRX_FCASE(6, 6)
+    FRX_BCASE(2) FRX_BCASE(3) FRX_BCASE(4) FRX_BCASE(5) FRX_BCASE(6)
+    default: break;
+  }
+}
+#undef FRX_FCASE
+#undef FRX_BCASE
 
 }  // namespace frx

@@ -172,6 +172,7 @@ void ensure_tables(int dev) {
   FRX_TRY(upload_tables_f64(*td, *tf));
   FRX_TRY(upload_tables_dual64(*td, *tf));
   FRX_TRY(upload_tables_dual32(*td, *tf));
+  FRX_TRY(upload_tables_vjp(*td, *tf));
   if (dev >= 0 && dev < 64) g_tables_uploaded[dev] = true;
 }
 
@@ -605,6 +606,88 @@ fr_status gmres_solve(fr_ctx c, const double* U, double shift, const double* F, 
   return gmres_run<double>(c, o, dU, st, s);
 }
 
+// Tile tables of the fused launches: every degree bucket cut into blocks of
+// 256 threads (elements or faces per block limited by the thread count and an
+// LDS cap), all tiles of a stage sorted by decreasing work.
+void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair<int, int>, std::vector<int4>>& fmap,
+                       const std::map<int, std::vector<int4>>& bmap) {
+  MeshDev& M = c->M;
+  const int E = d->n_elem;
+  std::vector<int> all;
+  std::vector<std::pair<int, int>> eb_range;  // n -> (first, count)
+  std::map<int, std::pair<int, int>> erange;
+  for (int n = NMAX; n >= 2; --n) {
+    const int first = (int)all.size();
+    for (int e = 0; e < E; ++e)
+      if (d->elem_p[e] + 1 == n) all.push_back(e);
+    if ((int)all.size() > first) erange[n] = {first, (int)all.size() - first};
+  }
+  std::vector<int4> faces;
+  std::vector<std::tuple<int, int, int, int>> frange;  // (code, first, count, nl)
+  for (auto it = fmap.rbegin(); it != fmap.rend(); ++it) {
+    frange.emplace_back(8 * it->first.first + it->first.second, (int)faces.size(), (int)it->second.size(), it->first.first);
+    faces.insert(faces.end(), it->second.begin(), it->second.end());
+  }
+  for (auto it = bmap.rbegin(); it != bmap.rend(); ++it) {
+    frange.emplace_back(64 + it->first, (int)faces.size(), (int)it->second.size(), it->first);
+    faces.insert(faces.end(), it->second.begin(), it->second.end());
+  }
+  M.all_elems = (int*)c->dalloc(sizeof(int) * std::max<size_t>(1, all.size()));
+  FRX_TRY(hipMemcpy(M.all_elems, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice));
+  M.all_faces = (int4*)c->dalloc(sizeof(int4) * std::max<size_t>(1, faces.size()));
+  if (!faces.empty())
+    FRX_TRY(hipMemcpy(M.all_faces, faces.data(), sizeof(int4) * faces.size(), hipMemcpyHostToDevice));
+  const bool ns = d->physics == FR_NAVIER_STOKES;
+  const size_t cap = 48 * 1024;
+  for (int sk = 0; sk < SK_COUNT; ++sk) {
+    const size_t sb = scalar_bytes(sk);
+    FusedPlan& P = M.plan[sk];
+    for (int st = 0; st < 3; ++st) {
+      std::vector<std::pair<double, int4>> tiles;
+      size_t lds = 0;
+      if (st != 1) {
+        for (auto& kv : erange) {
+          const int n = kv.first, n3 = n * n * n;
+          const size_t per_el = st == 0 ? (size_t)5 * n3 * sb : (size_t)(5 * n3 + 30 * n * n) * sb;
+          int epb = std::max(1, 256 / n3);
+          while (epb > 1 && epb * per_el > cap) --epb;
+          lds = std::max(lds, epb * per_el);
+          for (int i = 0; i < kv.second.second; i += epb) {
+            const int cnt = std::min(epb, kv.second.second - i);
+            tiles.push_back({(double)cnt * n3 * n, make_int4(n, kv.second.first + i, cnt, epb)});
+          }
+        }
+      } else {
+        for (auto& fr : frange) {
+          const int code = std::get<0>(fr), first = std::get<1>(fr), count = std::get<2>(fr);
+          if (code >= 64) {
+            const int n = code - 64, per = std::max(1, 256 / (n * n));
+            for (int i = 0; i < count; i += per)
+              tiles.push_back({(double)std::min(per, count - i) * n * n * 2.0, make_int4(code, first + i, std::min(per, count - i), per)});
+          } else {
+            const int nl = code / 8, nh = code % 8;
+            const size_t per_face = nl < nh ? (size_t)((ns ? 20 : 5) * nl * nl + 10 * nh * nh) * sb : 0;
+            int fpb = std::max(1, 256 / (nh * nh));
+            while (fpb > 1 && fpb * per_face > cap) --fpb;
+            lds = std::max(lds, fpb * per_face);
+            for (int i = 0; i < count; i += fpb)
+              tiles.push_back({(double)std::min(fpb, count - i) * nh * nh * (nl < nh ? 1.5 : 1.0),
+                               make_int4(code, first + i, std::min(fpb, count - i), fpb)});
+          }
+        }
+      }
+      std::stable_sort(tiles.begin(), tiles.end(),
+                       [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) { return x.first > y.first; });
+      std::vector<int4> t;
+      for (auto& x : tiles) t.push_back(x.second);
+      P.count[st] = (int)t.size();
+      P.lds[st] = lds;
+      P.tiles[st] = (int4*)c->dalloc(sizeof(int4) * std::max<size_t>(1, t.size()));
+      if (!t.empty()) FRX_TRY(hipMemcpy(P.tiles[st], t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice));
+    }
+  }
+}
+
 void validate_desc(const fr_mesh_desc* d) {
   if (!d) throw StatusErr{FR_E_INVALID, "null descriptor"};
   if (d->n_elem <= 0 || !d->elem_xyz || !d->elem_nbr || !d->elem_p)
@@ -757,6 +840,7 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
       M.bb.push_back(b);
     }
     for (int sk = 0; sk < SK_COUNT; ++sk) default_shapes(M, sk);
+    build_fused_plans(C.get(), d, fmap, bmap);
     // gas
     const double kappa = d->mu * d->gamma / ((d->gamma - 1.0) * d->prandtl);
     M.gas_d.gamma = d->gamma;
@@ -869,8 +953,10 @@ fr_status fr_jvp(fr_ctx c, const double* U, const void* v, void* Jv, int32_t pre
 fr_status fr_vjp(fr_ctx c, const double* U, const double* w, double* JTw, void* stream) {
   if (!c) return FR_E_INVALID;
   if (!U || !w || !JTw || w == JTw) return fail(c, FR_E_INVALID, "fr_vjp: bad arguments");
-  (void)stream;
-  return fail(c, FR_E_UNSUPPORTED, "fr_vjp: not built yet");
+  return guarded(c, [&]() -> fr_status {
+    FRX_TRY(launch_vjp(c->M, U, w, JTw, S(stream)));
+    return FR_OK;
+  });
 }
 
 fr_status gmres_stage_solve(fr_ctx c, const double* U, double shift, const double* F, double* dU,
@@ -976,6 +1062,16 @@ fr_status spectral_decay_indicator(fr_ctx c, const double* U, int32_t var, doubl
   });
 }
 
+fr_status fr_set_launch(fr_ctx c, int32_t mode) {
+  if (!c || (mode != FR_LAUNCH_PER_BUCKET && mode != FR_LAUNCH_FUSED)) return c ? fail(c, FR_E_INVALID, "fr_set_launch: mode") : FR_E_INVALID;
+  if (c->M.fused != (mode == FR_LAUNCH_FUSED)) {
+    c->M.fused = mode == FR_LAUNCH_FUSED;
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+  }
+  return FR_OK;
+}
+
 fr_status fr_check(fr_ctx c, int32_t* nonphysical, void* stream) {
   if (!c || !nonphysical) return FR_E_INVALID;
   return guarded(c, [&]() -> fr_status {
@@ -1077,6 +1173,70 @@ fr_status fr_autotune(fr_ctx c, const double* U, void* stream) {
     // captured graphs hold the old shapes
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
+    return FR_OK;
+  });
+}
+
+fr_status fr_profile(fr_ctx c, const double* U, int32_t op, int32_t reps, fr_kernel_time* out, int32_t max_out,
+                     int32_t* n_out, void* stream) {
+  if (!c || !U || !out || !n_out || reps < 1 || op < 0 || op > 2) return c ? fail(c, FR_E_INVALID, "fr_profile: bad arguments") : FR_E_INVALID;
+  return guarded(c, [&]() -> fr_status {
+    hipStream_t s = S(stream);
+    const long n = c->ndof;
+    hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, U, c->uf, n);
+    FRX_TRY(hipGetLastError());
+    ProfHook P;
+    auto run = [&]() {
+      if (op == 0) {
+        ResCall<double> rc;
+        rc.U = U;
+        rc.out = c->t0;
+        FRX_TRY(launch_residual_f64(c->M, rc, s));
+      } else if (op == 1) {
+        ResCall<double> rc;
+        rc.U = U;
+        rc.V = U;
+        rc.out = c->t0;
+        FRX_TRY(launch_residual_dual64(c->M, rc, s));
+      } else {
+        ResCall<float> rc;
+        rc.U = c->uf;
+        rc.V = c->uf;
+        rc.out = (float*)c->t1;
+        FRX_TRY(launch_residual_dual32(c->M, rc, s));
+      }
+    };
+    run();  // warm-up, untimed
+    c->M.prof = &P;
+    try {
+      for (int r = 0; r < reps; ++r) run();
+    } catch (...) {
+      c->M.prof = nullptr;
+      throw;
+    }
+    c->M.prof = nullptr;
+    FRX_TRY(hipStreamSynchronize(s));
+    const size_t per = P.recs.size() / reps;
+    int k = 0;
+    for (size_t i = 0; i < per && k < max_out; ++i, ++k) {
+      double tot = 0.0;
+      for (int r = 0; r < reps; ++r) {
+        float ms = 0.f;
+        FRX_TRY(hipEventElapsedTime(&ms, P.recs[r * per + i].a, P.recs[r * per + i].b));
+        tot += ms;
+      }
+      const auto& R = P.recs[i];
+      std::snprintf(out[k].stage, sizeof(out[k].stage), "%s", R.stage);
+      out[k].n_lo = R.nl;
+      out[k].n_hi = R.nh;
+      out[k].units = R.units;
+      out[k].ms = tot / reps;
+    }
+    for (auto& R : P.recs) {
+      (void)hipEventDestroy(R.a);
+      (void)hipEventDestroy(R.b);
+    }
+    *n_out = k;
     return FR_OK;
   });
 }

