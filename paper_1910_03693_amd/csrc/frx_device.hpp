@@ -11,6 +11,7 @@
 namespace frx {
 
 constexpr int NMAX = 6;  // n = p + 1 <= 6 (p <= 5)
+#define FRX_MAX_THREADS 256  // launch bound of every residual-stage kernel
 
 // ------------------------------------------------------------------ scalars
 // Forward-mode dual number: value and directional derivative.  The residual

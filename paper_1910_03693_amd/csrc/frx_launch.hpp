@@ -15,6 +15,10 @@ template <> __host__ inline const Gas<float>& gas_of<float>(const MeshDev& M) { 
 
 inline int round64(int t) { return (t + 63) / 64 * 64; }
 
+// Every residual kernel is compiled with __launch_bounds__(FRX_MAX_THREADS);
+// a wider block is refused on the host instead of being launched.
+inline bool block_ok(int threads) { return threads >= 1 && threads <= FRX_MAX_THREADS; }
+
 template <class T> size_t trace_lds(int n, int epb) { return (size_t)epb * 5 * n * n * n * sizeof(T); }
 template <class T> size_t div_lds(int n, int epb) { return (size_t)epb * (5 * n * n * n + 30 * n * n) * sizeof(T); }
 template <class T> size_t face_lds(int nl, int nh, bool ns, int fpb) {
@@ -24,6 +28,7 @@ template <class T> size_t face_lds(int nl, int nh, bool ns, int fpb) {
 template <int N, class T, bool NS>
 hipError_t run_trace(const ResArgs<T>& a, const ElemBucket& b, int epb, hipStream_t s) {
   const int grid = (b.count + epb - 1) / epb;
+  if (!block_ok(round64(epb * N * N * N))) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((k_trace<N, T, NS>), dim3(grid), dim3(round64(epb * N * N * N)), trace_lds<T>(N, epb), s, a,
                      b.elems, b.count, epb);
   return hipGetLastError();
@@ -31,6 +36,7 @@ hipError_t run_trace(const ResArgs<T>& a, const ElemBucket& b, int epb, hipStrea
 template <int N, class T, bool NS>
 hipError_t run_div(const ResArgs<T>& a, const ElemBucket& b, int epb, hipStream_t s) {
   const int grid = (b.count + epb - 1) / epb;
+  if (!block_ok(round64(epb * N * N * N))) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((k_div<N, T, NS>), dim3(grid), dim3(round64(epb * N * N * N)), div_lds<T>(N, epb), s, a, b.elems,
                      b.count, epb);
   return hipGetLastError();
@@ -38,6 +44,7 @@ hipError_t run_div(const ResArgs<T>& a, const ElemBucket& b, int epb, hipStream_
 template <int NL, int NH, class T, bool NS>
 hipError_t run_face(const ResArgs<T>& a, const FaceBucket& b, int fpb, hipStream_t s) {
   const int grid = (b.count + fpb - 1) / fpb;
+  if (!block_ok(round64(fpb * NH * NH))) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((k_face<NL, NH, T, NS>), dim3(grid), dim3(round64(fpb * NH * NH)), face_lds<T>(NL, NH, NS, fpb),
                      s, a, b.faces, b.count, fpb);
   return hipGetLastError();

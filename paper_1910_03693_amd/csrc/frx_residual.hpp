@@ -467,24 +467,24 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int* __restr
 
 // ------------------------------------------------------ per-bucket kernels
 template <int N, class T, bool NS>
-__global__ void __launch_bounds__(256) k_trace(ResArgs<T> a, const int* __restrict__ elems, int nel, int epb) {
+__global__ void __launch_bounds__(FRX_MAX_THREADS) k_trace(ResArgs<T> a, const int* __restrict__ elems, int nel, int epb) {
   if (a.skip && *a.skip) return;
   extern __shared__ __align__(16) unsigned char smem[];
   trace_body<N, T, NS>(a, elems, nel, epb, blockIdx.x, smem);
 }
 template <int NL, int NH, class T, bool NS>
-__global__ void __launch_bounds__(256) k_face(ResArgs<T> a, const int4* __restrict__ faces, int nf, int fpb) {
+__global__ void __launch_bounds__(FRX_MAX_THREADS) k_face(ResArgs<T> a, const int4* __restrict__ faces, int nf, int fpb) {
   if (a.skip && *a.skip) return;
   extern __shared__ __align__(16) unsigned char smem[];
   face_body<NL, NH, T, NS>(a, faces, nf, fpb, blockIdx.x, smem);
 }
 template <int N, class T, bool NS>
-__global__ void __launch_bounds__(256) k_bface(ResArgs<T> a, const int4* __restrict__ faces, int nf) {
+__global__ void __launch_bounds__(FRX_MAX_THREADS) k_bface(ResArgs<T> a, const int4* __restrict__ faces, int nf) {
   if (a.skip && *a.skip) return;
   bface_body<N, T, NS>(a, faces, nf, blockIdx.x);
 }
 template <int N, class T, bool NS>
-__global__ void __launch_bounds__(256) k_div(ResArgs<T> a, const int* __restrict__ elems, int nel, int epb) {
+__global__ void __launch_bounds__(FRX_MAX_THREADS) k_div(ResArgs<T> a, const int* __restrict__ elems, int nel, int epb) {
   if (a.skip && *a.skip) return;
   extern __shared__ __align__(16) unsigned char smem[];
   div_body<N, T, NS>(a, elems, nel, epb, blockIdx.x, smem);
@@ -501,7 +501,7 @@ __global__ void __launch_bounds__(256) k_div(ResArgs<T> a, const int* __restrict
   case N: BODY<N, T, NS>(a, elems + t.y, t.z, t.w, 0, smem); break;
 
 template <class T, bool NS>
-__global__ void __launch_bounds__(256) k_trace_fused(ResArgs<T> a, const int* __restrict__ elems,
+__global__ void __launch_bounds__(FRX_MAX_THREADS) k_trace_fused(ResArgs<T> a, const int* __restrict__ elems,
                                                      const int4* __restrict__ tiles) {
   if (a.skip && *a.skip) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -517,7 +517,7 @@ __global__ void __launch_bounds__(256) k_trace_fused(ResArgs<T> a, const int* __
 }
 
 template <class T, bool NS>
-__global__ void __launch_bounds__(256) k_div_fused(ResArgs<T> a, const int* __restrict__ elems,
+__global__ void __launch_bounds__(FRX_MAX_THREADS) k_div_fused(ResArgs<T> a, const int* __restrict__ elems,
                                                    const int4* __restrict__ tiles) {
   if (a.skip && *a.skip) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -539,7 +539,7 @@ __global__ void __launch_bounds__(256) k_div_fused(ResArgs<T> a, const int* __re
   case 64 + N: bface_body<N, T, NS>(a, faces + t.y, t.z, 0); break;
 
 template <class T, bool NS>
-__global__ void __launch_bounds__(256) k_face_fused(ResArgs<T> a, const int4* __restrict__ faces,
+__global__ void __launch_bounds__(FRX_MAX_THREADS) k_face_fused(ResArgs<T> a, const int4* __restrict__ faces,
                                                     const int4* __restrict__ tiles) {
   if (a.skip && *a.skip) return;
   extern __shared__ __align__(16) unsigned char smem[];

@@ -1140,7 +1140,7 @@ fr_status fr_autotune(fr_ctx c, const double* U, void* stream) {
           float tbest = timed(sk);
           for (int e : cands) {
             const size_t lds = kind == 0 ? (size_t)e * 5 * n3 * sb : (size_t)e * (5 * n3 + 30 * b.n * b.n) * sb;
-            if (e == best || e * n3 > 1024 || lds > lds_cap || e > 2 * b.count) continue;
+            if (e == best || e * n3 > FRX_MAX_THREADS || lds > lds_cap || e > 2 * b.count) continue;
             *slot = e;
             const float t = timed(sk);
             if (t < tbest) {
@@ -1157,7 +1157,7 @@ fr_status fr_autotune(fr_ctx c, const double* U, void* stream) {
         int best = f.fpb[sk];
         float tbest = timed(sk);
         for (int e : cands) {
-          if (e == best || e * nh2 > 1024 || (size_t)e * per > lds_cap || e > 2 * f.count) continue;
+          if (e == best || e * nh2 > FRX_MAX_THREADS || (size_t)e * per > lds_cap || e > 2 * f.count) continue;
           f.fpb[sk] = e;
           const float t = timed(sk);
           if (t < tbest) {
