@@ -125,6 +125,20 @@ __device__ __forceinline__ void tri_metrics(const B* __restrict__ g, B r0, B r1,
   J = d[0][0] * Ja[0][0] + d[0][1] * Ja[0][1] + d[0][2] * Ja[0][2];
 }
 
+// Area vector S = Ja^d and Jacobian J at the face point (r_d = rd, tangential
+// coordinates ta, tb in increasing direction order) of the face of direction d;
+// selects instead of indexing so that nothing is spilled to scratch.
+template <class B>
+__device__ __forceinline__ void face_geom(const B* __restrict__ g, int d, B rd, B ta, B tb, B S[3], B& J) {
+  const B r0 = d == 0 ? rd : ta;
+  const B r1 = d == 1 ? rd : (d == 0 ? ta : tb);
+  const B r2 = d == 2 ? rd : tb;
+  B Ja[3][3];
+  tri_metrics<B>(g, r0, r1, r2, Ja, J);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) S[c] = d == 0 ? Ja[0][c] : (d == 1 ? Ja[1][c] : Ja[2][c]);
+}
+
 template <class T, class B> __device__ __forceinline__ T pressure(const T q[5], const Gas<B>& G) {
   return G.gm1 * (q[4] - B(0.5) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
 }
@@ -335,3 +349,4 @@ __device__ __forceinline__ void bface_fn(const T qi[5], const T gi[5][3], const 
 }
 
 }  // namespace frx
+

@@ -19,7 +19,13 @@ inline int round64(int t) { return (t + 63) / 64 * 64; }
 // a wider block is refused on the host instead of being launched.
 inline bool block_ok(int threads) { return threads >= 1 && threads <= FRX_MAX_THREADS; }
 
-template <class T> size_t trace_lds(int n, int epb) { return (size_t)epb * 5 * n * n * n * sizeof(T); }
+// LDS scalars per element of the trace stage (see trace_in_rounds)
+inline int trace_vals_host(int n, bool ns, size_t sb) {
+  return (ns && 20 * n * n * n * sb > 65536) ? 5 : (ns ? 20 : 5);
+}
+template <class T> size_t trace_lds(int n, int epb, bool ns) {
+  return (size_t)epb * trace_vals_host(n, ns, sizeof(T)) * n * n * n * sizeof(T);
+}
 template <class T> size_t div_lds(int n, int epb) { return (size_t)epb * (5 * n * n * n + 30 * n * n) * sizeof(T); }
 template <class T> size_t face_lds(int nl, int nh, bool ns, int fpb) {
   return nl < nh ? (size_t)fpb * ((ns ? 20 : 5) * nl * nl + 10 * nh * nh) * sizeof(T) : 0;
@@ -29,7 +35,7 @@ template <int N, class T, bool NS>
 hipError_t run_trace(const ResArgs<T>& a, const ElemBucket& b, int epb, hipStream_t s) {
   const int grid = (b.count + epb - 1) / epb;
   if (!block_ok(round64(epb * N * N * N))) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_trace<N, T, NS>), dim3(grid), dim3(round64(epb * N * N * N)), trace_lds<T>(N, epb), s, a,
+  hipLaunchKernelGGL((k_trace<N, T, NS>), dim3(grid), dim3(round64(epb * N * N * N)), trace_lds<T>(N, epb, NS), s, a,
                      b.elems, b.count, epb);
   return hipGetLastError();
 }

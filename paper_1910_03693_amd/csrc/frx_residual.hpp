@@ -64,11 +64,21 @@ template <int N> __device__ __forceinline__ int line_pt(int d, int a, int b, int
 }
 
 // ---------------------------------------------------------------- trace stage
-// Block: epb elements x N^3 threads (one solution point each).  LDS: one
-// region of 5 N^3 scalars per element, holding q and then, one variable at a
-// time, the three components of its uncorrected physical gradient.
+// Block: epb elements x N^3 threads (one solution point each).  LDS per
+// element: q (5 N^3) and, for Navier-Stokes, the uncorrected physical
+// gradient (15 N^3).  After one barrier every face item (element, face,
+// point) extrapolates all of its values along the face-normal line.  Where
+// 20 N^3 scalars of one element exceed 64 KB (n = 6 with float64 duals) the
+// gradient goes through a 5 N^3 region one variable at a time instead.
+template <class T, int N, bool NS> __host__ __device__ constexpr bool trace_in_rounds() {
+  return NS && 20 * N * N * N * (int)sizeof(T) > 65536;
+}
+template <class T, int N, bool NS> __host__ __device__ constexpr int trace_vals() {
+  return trace_in_rounds<T, N, NS>() ? 5 : (NS ? 20 : 5);
+}
+
 template <int N, class T, bool NS>
-__device__ __forceinline__ void trace_body(const ResArgs<T>& a, const int* __restrict__ elems, int nel, int epb,
+__device__ __forceinline__ void trace_body_rounds(const ResArgs<T>& a, const int* __restrict__ elems, int nel, int epb,
                                            int blk, unsigned char* smem) {
   using B = base_t<T>;
   constexpr int N2 = N * N, N3 = N2 * N;
@@ -135,8 +145,8 @@ __device__ __forceinline__ void trace_body(const ResArgs<T>& a, const int* __res
     __syncthreads();
     for (int it = tid; it < epb * 18 * N2; it += blockDim.x) {
       const int l2 = it / (18 * N2), rem = it - l2 * 18 * N2;
-      const int fc = rem / N2, pt = rem - fc * N2;  // fc = f * 3 + c
-      const int f = fc / 3, c = fc - f * 3;
+      const int c = rem / (6 * N2), fp = rem - c * 6 * N2;
+      const int f = fp / N2, pt = fp - f * N2;
       const int s2 = blk * epb + l2;
       if (s2 >= nel) continue;
       const long o = a.fp_off[elems[s2]] + f * N2 + pt;
@@ -147,6 +157,81 @@ __device__ __forceinline__ void trace_body(const ResArgs<T>& a, const int* __res
 #pragma unroll
       for (int m = 0; m < N; ++m) s = fmab(lf[m], g[line_pt<N>(d, pt % N, pt / N, m)], s);
       a.GF[(long)(v * 3 + c) * a.nfp + o] = s;
+    }
+  }
+}
+
+
+template <int N, class T, bool NS>
+__device__ __forceinline__ void trace_body(const ResArgs<T>& a, const int* __restrict__ elems, int nel, int epb,
+                                           int blk, unsigned char* smem) {
+  using B = base_t<T>;
+  if constexpr (trace_in_rounds<T, N, NS>()) {
+    trace_body_rounds<N, T, NS>(a, elems, nel, epb, blk, smem);
+    return;
+  }
+  constexpr int N2 = N * N, N3 = N2 * N, NV = trace_vals<T, N, NS>();
+  T* sq = reinterpret_cast<T*>(smem);  // [epb][NV][N3]
+  const OpsTab<B>& O = ops<B>();
+  const int tid = threadIdx.x;
+  const int le = tid / N3, k = tid - le * N3;
+  const int slot = blk * epb + le;
+  const bool act = le < epb && slot < nel;
+  const int e = act ? elems[slot] : 0;
+  T* q = sq + le * NV * N3;
+  if (act) {
+    const int off = a.sp_off[e] + k;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) q[v * N3 + k] = IO<T>::load(a.U, a.V, (long)(v * a.nsp + off));
+  }
+  if (NS) {
+    __syncthreads();
+    if (act) {
+      const int i0 = k % N, i1 = (k / N) % N, i2 = k / N2;
+      B Ja[3][3], J;
+      tri_metrics<B>(a.geo + 24 * e, O.x[N][i0], O.x[N][i1], O.x[N][i2], Ja, J);
+      const B iJ = B(1) / J;
+      T g[15];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        T d0 = T(B(0)), d1 = T(B(0)), d2 = T(B(0));
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+          d0 = fmab(O.D[N][i0][m], q[v * N3 + m + N * (i1 + N * i2)], d0);
+          d1 = fmab(O.D[N][i1][m], q[v * N3 + i0 + N * (m + N * i2)], d1);
+          d2 = fmab(O.D[N][i2][m], q[v * N3 + i0 + N * (i1 + N * m)], d2);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g[v * 3 + c] = (Ja[0][c] * d0 + Ja[1][c] * d1 + Ja[2][c] * d2) * iJ;
+      }
+#pragma unroll
+      for (int vc = 0; vc < 15; ++vc) q[(5 + vc) * N3 + k] = g[vc];
+    }
+  }
+  __syncthreads();
+  // items (element, face, point): a wave covers runs of contiguous slots
+  for (int it = tid; it < epb * 6 * N2; it += blockDim.x) {
+    const int l2 = it / (6 * N2), fp = it - l2 * 6 * N2;
+    const int s2 = blk * epb + l2;
+    if (s2 >= nel) continue;
+    const int f = fp / N2, pt = fp - f * N2;
+    const int d = f >> 1, fa = pt % N, fb = pt / N;
+    const int o = a.fp_off[elems[s2]] + fp;
+    const B* lf = (f & 1) ? O.lp[N] : O.lm[N];
+    // start and stride of the normal line through (fa, fb)
+    const int base = d == 0 ? N * (fa + N * fb) : (d == 1 ? fa + N2 * fb : fa + N * fb);
+    const int stride = d == 0 ? 1 : (d == 1 ? N : N2);
+    const T* src = sq + l2 * NV * N3 + base;
+    B w[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) w[m] = lf[m];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      T s = T(B(0));
+#pragma unroll
+      for (int m = 0; m < N; ++m) s = fmab(w[m], src[v * N3 + m * stride], s);
+      if (v < 5) a.QF[v * a.nfp + o] = s;
+      else a.GF[(v - 5) * a.nfp + o] = s;
     }
   }
 }
@@ -227,18 +312,12 @@ __device__ __forceinline__ void face_body(const ResArgs<T>& a, const int4* __res
       }
     }
     // geometry at the face point: S from L at r_d = +1, J of both sides
-    B rL[3], rR[3];
     const B ta = O.x[NH][A], tb = O.x[NH][Bq];
-    rL[d] = B(1);
-    rR[d] = B(-1);
-    rL[d == 0 ? 1 : 0] = rR[d == 0 ? 1 : 0] = ta;
-    rL[d == 2 ? 1 : 2] = rR[d == 2 ? 1 : 2] = tb;
-    B JaL[3][3], JL, JaR[3][3], JR;
-    tri_metrics<B>(a.geo + 24L * L, rL[0], rL[1], rL[2], JaL, JL);
-    const B S[3] = {JaL[d][0], JaL[d][1], JaL[d][2]};
+    B S[3], JL, SR[3], JR;
+    face_geom<B>(a.geo + 24L * L, d, B(1), ta, tb, S, JL);
     B cL = B(0), cR = B(0);
     if (NS) {
-      tri_metrics<B>(a.geo + 24L * R, rR[0], rR[1], rR[2], JaR, JR);
+      face_geom<B>(a.geo + 24L * R, d, B(-1), ta, tb, SR, JR);
       const int nL = lowL ? NL : NH, nR = lowR ? NL : NH;
       cL = B(0.5) * B(nL * nL) / JL;
       cR = -B(0.5) * B(nR * nR) / JR;
@@ -318,13 +397,8 @@ __device__ __forceinline__ void bface_body(const ResArgs<T>& a, const int4* __re
 #pragma unroll
     for (int vc = 0; vc < 15; ++vc) g[vc / 3][vc % 3] = a.GF[(long)vc * a.nfp + o];
   }
-  B r[3];
-  r[d] = side ? B(1) : B(-1);
-  r[d == 0 ? 1 : 0] = O.x[N][pt % N];
-  r[d == 2 ? 1 : 2] = O.x[N][pt / N];
-  B Ja[3][3], J;
-  tri_metrics<B>(a.geo + 24L * e, r[0], r[1], r[2], Ja, J);
-  const B S[3] = {Ja[d][0], Ja[d][1], Ja[d][2]};
+  B S[3], J;
+  face_geom<B>(a.geo + 24L * e, d, side ? B(1) : B(-1), O.x[N][pt % N], O.x[N][pt / N], S, J);
   const B cf = (side ? B(0.5) : B(-0.5)) * B(N * N) / J;
   T fS[5], jmp[5];
   bface_fn<NS, T, B>(q, g, S, cf, bc, side, a.gas, a.flux, fS, jmp);
@@ -360,12 +434,13 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int* __restr
   }
   if (NS) {
     for (int it = tid; it < epb * 30 * N2; it += blockDim.x) {
+      // (element, variable, face, point): contiguous 6 n^2 runs per variable
       const int l2 = it / (30 * N2), rem = it - l2 * 30 * N2;
-      const int fv = rem / N2, p2 = rem - fv * N2;  // fv = f * 5 + v
+      const int v = rem / (6 * N2), fp = rem - v * 6 * N2;
+      const int f = fp / N2, p2 = fp - f * N2;
       const int s2 = blk * epb + l2;
       if (s2 >= nel) continue;
-      const int f = fv / 5, v = fv - f * 5;
-      sY[it] = a.DQ[(long)v * a.nfp + a.fp_off[elems[s2]] + f * N2 + p2];
+      sY[(l2 * 30 + f * 5 + v) * N2 + p2] = a.DQ[(long)v * a.nfp + a.fp_off[elems[s2]] + fp];
     }
   }
   __syncthreads();
@@ -429,11 +504,13 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int* __restr
     }
     // flux jumps on the two faces of direction d
     for (int it = tid; it < epb * 10 * N2; it += blockDim.x) {
+      // (element, variable, side, point): the two faces of direction d are
+      // contiguous slots
       const int l2 = it / (10 * N2), rem = it - l2 * 10 * N2;
-      const int sv = rem / N2, p2 = rem - sv * N2;  // sv = side * 5 + v
+      const int v = rem / (2 * N2), sp2 = rem - v * 2 * N2;
+      const int side = sp2 / N2, p2 = sp2 - side * N2, f = 2 * d + side;
       const int s2 = blk * epb + l2;
       if (s2 >= nel) continue;
-      const int side = sv / 5, v = sv - side * 5, f = 2 * d + side;
       const B* lf = side ? O.lp[N] : O.lm[N];
       const T* X = sX + (l2 * 5 + v) * N3;
       T floc = T(B(0));

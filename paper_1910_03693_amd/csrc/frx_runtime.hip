@@ -186,11 +186,12 @@ size_t scalar_bytes(int sk) { return sk == SK_F64 ? 8 : (sk == SK_DUAL64 ? 16 : 
 // Default shapes: about 256 threads per block, LDS per block capped at 48 KB.
 void default_shapes(MeshDev& M, int sk) {
   const size_t sb = scalar_bytes(sk);
-  const size_t cap = 48 * 1024;
+  const size_t cap = 64 * 1024;
   for (ElemBucket& b : M.eb) {
     const int n = b.n, n3 = n * n * n;
+    const int tv = (M.physics == 1 && 20 * n3 * sb > 65536) ? 5 : (M.physics == 1 ? 20 : 5);
     int e = std::max(1, 256 / n3);
-    while (e > 1 && (size_t)e * 5 * n3 * sb > cap) --e;
+    while (e > 1 && (size_t)e * tv * n3 * sb > cap) --e;
     b.epb_trace[sk] = e;
     e = std::max(1, 256 / n3);
     while (e > 1 && (size_t)e * (5 * n3 + 30 * n * n) * sb > cap) --e;
@@ -638,7 +639,7 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
   if (!faces.empty())
     FRX_TRY(hipMemcpy(M.all_faces, faces.data(), sizeof(int4) * faces.size(), hipMemcpyHostToDevice));
   const bool ns = d->physics == FR_NAVIER_STOKES;
-  const size_t cap = 48 * 1024;
+  const size_t cap = 64 * 1024;
   for (int sk = 0; sk < SK_COUNT; ++sk) {
     const size_t sb = scalar_bytes(sk);
     FusedPlan& P = M.plan[sk];
@@ -648,7 +649,8 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
       if (st != 1) {
         for (auto& kv : erange) {
           const int n = kv.first, n3 = n * n * n;
-          const size_t per_el = st == 0 ? (size_t)5 * n3 * sb : (size_t)(5 * n3 + 30 * n * n) * sb;
+          const int tv = (ns && 20 * n3 * sb > 65536) ? 5 : (ns ? 20 : 5);
+          const size_t per_el = st == 0 ? (size_t)tv * n3 * sb : (size_t)(5 * n3 + 30 * n * n) * sb;
           int epb = std::max(1, 256 / n3);
           while (epb > 1 && epb * per_el > cap) --epb;
           lds = std::max(lds, epb * per_el);
@@ -1139,7 +1141,8 @@ fr_status fr_autotune(fr_ctx c, const double* U, void* stream) {
           int best = *slot;
           float tbest = timed(sk);
           for (int e : cands) {
-            const size_t lds = kind == 0 ? (size_t)e * 5 * n3 * sb : (size_t)e * (5 * n3 + 30 * b.n * b.n) * sb;
+            const int tv = (c->M.physics == 1 && 20 * n3 * sb > 65536) ? 5 : (c->M.physics == 1 ? 20 : 5);
+            const size_t lds = kind == 0 ? (size_t)e * tv * n3 * sb : (size_t)e * (5 * n3 + 30 * b.n * b.n) * sb;
             if (e == best || e * n3 > FRX_MAX_THREADS || lds > lds_cap || e > 2 * b.count) continue;
             *slot = e;
             const float t = timed(sk);

@@ -401,17 +401,11 @@ __global__ void __launch_bounds__(256) k_face_rev(VjpArgs a, const int4* __restr
         }
       }
     }
-    double rL[3], rR[3];
-    rL[d] = 1.0;
-    rR[d] = -1.0;
-    rL[d == 0 ? 1 : 0] = rR[d == 0 ? 1 : 0] = O.x[NH][A];
-    rL[d == 2 ? 1 : 2] = rR[d == 2 ? 1 : 2] = O.x[NH][Bq];
-    double JaL[3][3], JL, JaR[3][3], JR;
-    tri_metrics<double>(a.geo + 24L * L, rL[0], rL[1], rL[2], JaL, JL);
-    const double S[3] = {JaL[d][0], JaL[d][1], JaL[d][2]};
+    double S[3], JL, SR[3], JR;
+    face_geom<double>(a.geo + 24L * L, d, 1.0, O.x[NH][A], O.x[NH][Bq], S, JL);
     double cL = 0.0, cR = 0.0;
     if (NS) {
-      tri_metrics<double>(a.geo + 24L * R, rR[0], rR[1], rR[2], JaR, JR);
+      face_geom<double>(a.geo + 24L * R, d, -1.0, O.x[NH][A], O.x[NH][Bq], SR, JR);
       const int nL = lowL ? NL : NH, nR = lowR ? NL : NH;
       cL = 0.5 * (double)(nL * nL) / JL;
       cR = -0.5 * (double)(nR * nR) / JR;
@@ -476,13 +470,8 @@ __global__ void __launch_bounds__(256) k_bface_rev(VjpArgs a, const int4* __rest
     jb[v] = NS ? a.DQ[(long)v * a.nfp + o] : 0.0;
   }
   for (int vc = 0; vc < 15; ++vc) g[vc / 3][vc % 3] = NS ? a.GF[(long)vc * a.nfp + o] : 0.0;
-  double r[3];
-  r[d] = side ? 1.0 : -1.0;
-  r[d == 0 ? 1 : 0] = O.x[N][pt % N];
-  r[d == 2 ? 1 : 2] = O.x[N][pt / N];
-  double Ja[3][3], J;
-  tri_metrics<double>(a.geo + 24L * e, r[0], r[1], r[2], Ja, J);
-  const double S[3] = {Ja[d][0], Ja[d][1], Ja[d][2]};
+  double S[3], J;
+  face_geom<double>(a.geo + 24L * e, d, side ? 1.0 : -1.0, O.x[N][pt % N], O.x[N][pt / N], S, J);
   const double cf = (side ? 0.5 : -0.5) * (double)(N * N) / J;
   constexpr int NI = NS ? 20 : 5;
   double qb[5], gb[5][3];
