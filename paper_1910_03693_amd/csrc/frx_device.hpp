@@ -323,14 +323,17 @@ __device__ __forceinline__ void bface_fn(const T qi[5], const T gi[5][3], const 
 #pragma unroll
     for (int a = 0; a < 3; ++a) fS[1 + a] = p * S[a];
   } else {
-    T qf[5];
+    // minus / plus states chosen value by value (a pointer select would put
+    // the arrays in scratch)
+    T qm[5], qp[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      qf[v] = T(G.ff[v]);
-      qb[v] = B(0.5) * (qi[v] + qf[v]);
+      const T qf = T(G.ff[v]);
+      qb[v] = B(0.5) * (qi[v] + qf);
+      qm[v] = side ? qi[v] : qf;
+      qp[v] = side ? qf : qi[v];
     }
-    if (side) riemann<T, B>(qi, qf, S, G, flux, fS);
-    else riemann<T, B>(qf, qi, S, G, flux, fS);
+    riemann<T, B>(qm, qp, S, G, flux, fS);
   }
 #pragma unroll
   for (int v = 0; v < 5; ++v) jump[v] = qb[v] - qi[v];

@@ -341,11 +341,17 @@ __device__ __forceinline__ void face_body(const ResArgs<T>& a, const int4* __res
       }
     }
     if (MIX) {
+      // (two explicit branches: a select between the two jump arrays would
+      // be turned into a dynamically indexed private array in scratch)
       T* dst = sout + lf * 10 * NH2;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        dst[v * NH2 + pt] = fS[v];
-        dst[(5 + v) * NH2 + pt] = lowL ? jL[v] : jR[v];
+      for (int v = 0; v < 5; ++v) dst[v * NH2 + pt] = fS[v];
+      if (lowL) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) dst[(5 + v) * NH2 + pt] = jL[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) dst[(5 + v) * NH2 + pt] = jR[v];
       }
     }
   }

@@ -180,6 +180,24 @@ def test_residual_parity_wall_32x32x8(frx, oracle_mod):
     _full_size_residual_check(R.cpu().numpy(), orc, case, "c4 residual")
 
 
+@pytest.mark.skip(reason="persistent (work-queue) launch mode withdrawn: its first GPU run faulted the GPU in the "
+                         "dual-number Navier-Stokes fused tangent and no cause was shown; the mode is not built")
+def test_persistent_queue_resets_across_calls_and_graph_replays(frx, c2):
+    """The persistent launch resets its own work-queue counters: repeated
+    calls and repeated graph-captured GMRES cycles give identical results."""
+    case, orc, ctx, U = c2
+    ctx.set_launch(True, persistent=True)
+    R1 = ctx.residual(U).clone()
+    for _ in range(3):
+        assert torch.equal(ctx.residual(U), R1)
+    ctx.set_launch(True, persistent=False)
+    assert torch.equal(ctx.residual(U), R1)
+    ctx.set_launch(True, persistent=True)
+    F = torch.tensor(I.random_direction(case.U.size, 79).reshape(case.U.shape), device="cuda")
+    xs = [ctx.gmres(U, 800.0, F, restart=6, max_iter=18, tol=0.0, use_graph=True)[0].clone() for _ in range(3)]
+    assert torch.equal(xs[0], xs[1]) and torch.equal(xs[0], xs[2])
+
+
 def test_nonphysical_flag(frx):
     case = CASES["vortex_p2_rusanov"]
     ctx = frx.Context.from_case(case)
@@ -259,7 +277,8 @@ def test_esdirk_full_step_mixed_vs_plain(frx, oracle_mod):
     Uo, so = orc.esdirk2_step(case.U, 0.05, restart=30, tol_gmres=1e-3, jv_mode=0, **kw)
     ref = np.linalg.norm(Uo)
     for g in (dict(restart=30, tol=1e-3, jv_mode=frx.FR_JV_FD),
-              dict(restart=30, tol=1e-3, jv_mode=frx.FR_JV_EXACT, precision=frx.FR_F32, use_graph=True)):
+              dict(restart=30, tol=1e-3, jv_mode=frx.FR_JV_EXACT, precision=frx.FR_F32, use_graph=True),
+              dict(restart=30, tol=1e-3, jv_mode=frx.FR_JV_EXACT, precision=frx.FR_F64, use_graph=True)):
         ctx.set_launch(g.get("use_graph", False))
         Ug = U.clone()
         sg = ctx.esdirk_step(Ug, 0.05, gmres=g, **kw)
@@ -267,3 +286,32 @@ def test_esdirk_full_step_mixed_vs_plain(frx, oracle_mod):
         print("full step", g, sg, "rel diff to oracle", err)
         assert sg["status"] == 0
         assert err <= 1e-6
+
+
+def test_indicator_degree_field_matches_oracle(frx, oracle_mod):
+    """The degree field of the vortex-street workload (at 16x16x2) chosen from
+    the GPU indicator equals the one chosen from the oracle's indicator with
+    the criteria written out again here (integer result: bit-exact)."""
+    from paper_1910_03693_amd import adapt
+
+    def make(ep):
+        return I.case_street(16, 16, 2, elem_p=ep)
+
+    p_gpu, hist = adapt.indicator_degree_field(make)
+    # the oracle side, with its own statement of the criteria and limiter
+    p = np.full(make(None).mesh["n_elem"], 5, np.int64)
+    for _ in range(4):
+        case = make(p.astype(np.int8))
+        eta, mx = oracle_mod.Oracle.from_case(case).indicator(case.U, var=1)
+        pn = np.clip(p + (eta > 0.1 * mx) - (eta < 0.001 * mx), 1, 5)
+        if np.array_equal(pn, p):
+            break
+        p = pn
+    nbr = case.mesh["elem_nbr"]
+    while True:
+        need = np.maximum(p, np.where(nbr >= 0, p[np.clip(nbr, 0, None)], 0).max(axis=1) - 1)
+        if np.array_equal(need, p):
+            break
+        p = need
+    print("degree histogram", np.bincount(p_gpu, minlength=6)[1:], hist)
+    assert np.array_equal(p_gpu.astype(np.int64), p)
