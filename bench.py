@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--no-implicit", action="store_true", help="skip the ESDIRK2 step comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB five times (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the hot path is built and "
@@ -192,7 +194,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(by / t_s / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom["stage"])
     roof["kernel"] = f"{dom['stage']}<{SK_NAME[1]},navier-stokes>" if dom["stage"].endswith("_fused") else \
         f"{dom['stage']}<n={dom['n_hi']}{'' if dom['n_lo'] == dom['n_hi'] else ',' + str(dom['n_lo'])}," \
         f"{SK_NAME[1]},navier-stokes>"
@@ -224,11 +226,69 @@ def main():
         "roofline": roof,
     }
 
+    if args.copy_calibration > 0:
+        out["copy_calibration"] = copy_calibration(torch, args.copy_calibration)
     if not args.no_implicit:
         out["implicit_step"] = implicit_steps(ctx, case, U, frx, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+# Sources that define the dominant kernel (the fused face stage of the float64
+# tangent).  Its HBM traffic is taken from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+# summary under profiles/ only while these files hash to the value recorded
+# there; after any change to them `traffic` is null until the counters are
+# taken again.
+TRAFFIC_SOURCES = ("frx_device.hpp", "frx_residual.hpp", "frx_launch.hpp", "frx_host.hpp", "frx_k_dual64.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "face_fused_dual64_ns_32x32x4_hbm_traffic.md")
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1910_03693_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (lines 'kernel: ...', 'source_sha256: ...', 'traffic_bytes: ...'),
+    or None if there is none or the kernel's sources have changed since."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            kv = dict(line.split(":", 1) for line in f if line.count(":") >= 1 and not line.startswith(("#", "|")))
+    except OSError:
+        return None
+    kv = {k.strip().strip("-* `"): v.strip().strip("`") for k, v in kv.items()}
+    if kv.get("kernel") != stage or kv.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(torch, mib):
+    """A plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
+    counters give the scale from counter units to bytes."""
+    n = mib * 1024 * 1024 // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(5):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / 5
+    return {"bytes_read": n * 8, "bytes_written": n * 8, "ms": round(ms, 4),
+            "gb_s": round(2 * n * 8 / (ms * 1e-3) / 1e9, 1)}
 
 
 def implicit_steps(ctx, case, U, frx, torch):

@@ -104,6 +104,17 @@ __global__ void __launch_bounds__(KR_THREADS) k_multiaxpy(const TV* __restrict__
   }
 }
 
+// x *= *sptr in place
+template <class TV>
+__global__ void __launch_bounds__(KR_THREADS) k_scale_inplace(TV* __restrict__ x, long n,
+                                                             const double* __restrict__ sptr,
+                                                             const int* __restrict__ done) {
+  if (done && *done) return;
+  const double s = *sptr;
+  for (long t = (long)blockIdx.x * KR_THREADS + threadIdx.x; t < n; t += (long)gridDim.x * KR_THREADS)
+    x[t] = (TV)((double)x[t] * s);
+}
+
 // x += sum_{i < k} y[i] V_i  with k read from the device
 template <class TV>
 __global__ void __launch_bounds__(KR_THREADS) k_update_x(const TV* __restrict__ V, long ldv, const double* __restrict__ y,
@@ -140,16 +151,16 @@ __global__ void k_cycle_start(GmresDev G, const double* __restrict__ dot) {
   G.ist[0] = (beta <= G.sc[2] * G.sc[1] || G.ist[2] >= G.ist[3]) ? 1 : 0;
 }
 
-// Column j of H from the two Gram-Schmidt passes (h1 + h2) and the norm of the
-// orthogonalised vector; Givens rotation; residual estimate |g_{j+1}|;
-// convergence or budget check; 1/h_{j+1,j} for the scaling of the new vector.
-__global__ void k_givens(GmresDev G, int j, const double* __restrict__ h1, const double* __restrict__ h2,
-                         const double* __restrict__ nrm2) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Column j of H from the two Gram-Schmidt passes (h1 + h2) and the squared
+// norm of the orthogonalised vector; Givens rotation; residual estimate
+// |g_{j+1}|; convergence or budget check; 1/h_{j+1,j} for the scaling of the
+// new vector.  One thread.
+__device__ __forceinline__ void givens_step(const GmresDev& G, int j, const double* __restrict__ h1,
+                                            const double* __restrict__ h2, double nrm2) {
   if (G.ist[0]) return;
   const int m = G.m;
   for (int i = 0; i <= j; ++i) G.H[i * m + j] = h1[i] + h2[i];
-  const double hn = sqrt(*nrm2);
+  const double hn = sqrt(nrm2);
   G.H[(j + 1) * m + j] = hn;
   for (int i = 0; i < j; ++i) {
     const double a = G.H[i * m + j], b = G.H[(i + 1) * m + j];
@@ -171,6 +182,119 @@ __global__ void k_givens(GmresDev G, int j, const double* __restrict__ h1, const
   G.ist[1] = j + 1;
   G.ist[2] += 1;
   if (res <= G.sc[2] * G.sc[1] || hn == 0.0 || G.ist[2] >= G.ist[3] || j + 1 == m) G.ist[0] = 1;
+}
+
+__global__ void k_givens(GmresDev G, int j, const double* __restrict__ h1, const double* __restrict__ h2,
+                         const double* __restrict__ nrm2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  givens_step(G, j, h1, h2, *nrm2);
+}
+
+// ---------------------------------------------- fused Gram-Schmidt passes
+// For NV <= 32 basis vectors (one instantiation per NV, so that no load sits
+// behind a branch) every thread keeps the partial sums of all NV dots in
+// registers, and one launch reads w and each V_i once (k_multidot splits the
+// vectors over block rows and reads w once per row).
+//  MODE 0: sums V_i . w                                     (first pass dots)
+//  MODE 1: w -= sum_i h_i V_i (stored as TV); sums V_i . w   (first pass
+//          update fused with the second pass dots)
+//  MODE 2: out = w - sum_i h_i V_i (stored as TV); sum |out|^2
+// Each block writes its partial sums to part[i * nblk + blockIdx.x];
+// k_gs_reduce adds them up in a fixed order.  (A last-block reduction inside
+// k_gs would need a device-scope fence per block, which costs an L2
+// write-back each on this chip.)
+template <class TV, int NV, int MODE>
+__global__ void __launch_bounds__(KR_THREADS) k_gs(const TV* __restrict__ V, long ldv, const double* __restrict__ h,
+                                                  TV* w, TV* __restrict__ out, long n, double* __restrict__ part,
+                                                  const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int NS = MODE == 2 ? 1 : NV;
+  __shared__ double sh[KR_THREADS / 64][NS];
+  __shared__ double hs[NV];
+  const int nblk = gridDim.x;
+  if (MODE != 0) {
+    if (threadIdx.x < NV) hs[threadIdx.x] = h[threadIdx.x];
+    __syncthreads();
+  }
+  double s[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) s[i] = 0.0;
+  // grid-stride rows, UR per trip so that the loads of all of them are in
+  // flight together; the rows are still accumulated in grid-stride order
+  constexpr int UR = NV <= 2 ? 8 : (NV <= 4 ? 4 : (NV <= 16 ? 2 : 1));
+  const long stride = (long)nblk * KR_THREADS;
+  for (long t = (long)blockIdx.x * KR_THREADS + threadIdx.x; t < n; t += UR * stride) {
+    TV v[UR][NV];
+    double a[UR];
+    bool in[UR];
+    long tr[UR];
+#pragma unroll
+    for (int r = 0; r < UR; ++r) {
+      in[r] = t + r * stride < n;
+      tr[r] = in[r] ? t + r * stride : t;  // a valid row; its values are not used
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+      for (int r = 0; r < UR; ++r) v[r][i] = V[(long)i * ldv + tr[r]];
+#pragma unroll
+    for (int r = 0; r < UR; ++r) a[r] = (double)w[tr[r]];
+    // keep the scheduler from interleaving the loads with the arithmetic, so
+    // that all of them are in flight at once
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < UR; ++r) {
+      if (MODE != 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) a[r] -= hs[i] * (double)v[r][i];
+        const TV st = (TV)a[r];
+        if (in[r]) {
+          if (MODE == 1) w[tr[r]] = st;
+          else out[tr[r]] = st;
+        }
+        a[r] = (double)st;
+      }
+      if (!in[r]) a[r] = 0.0;
+      if (MODE == 2) {
+        s[0] += a[r] * a[r];
+      } else {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) s[i] += a[r] * (double)v[r][i];
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const double r = wave_sum(s[i]);
+    if (lane == 0) sh[wv][i] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < NS) {
+    double r = 0.0;
+#pragma unroll
+    for (int k = 0; k < KR_THREADS / 64; ++k) r += sh[k][threadIdx.x];
+    part[(long)threadIdx.x * nblk + blockIdx.x] = r;
+  }
+}
+
+// Final sums of the block partials of k_gs: block i adds up entry i in a fixed
+// order; after the norm pass (givens != 0, one entry) the Givens step of
+// column j follows.
+__global__ void __launch_bounds__(KR_THREADS) k_gs_reduce(const double* __restrict__ part, int nblk,
+                                                         double* __restrict__ hout, int givens, GmresDev G, int j,
+                                                         const double* __restrict__ h1,
+                                                         const double* __restrict__ h2,
+                                                         const int* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double sh[KR_THREADS / 64];
+  double r = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += KR_THREADS) r += part[(long)blockIdx.x * nblk + b];
+  r = block_sum(r, sh);
+  if (threadIdx.x == 0) {
+    hout[blockIdx.x] = r;
+    if (givens) givens_step(G, j, h1, h2, r);
+  }
 }
 
 // y = H(0:k, 0:k)^{-1} g(0:k) by back substitution, k = iterations of the cycle

@@ -177,6 +177,7 @@ void ensure_tables(int dev) {
 }
 
 constexpr int NBLK = 512;  // multi-dot blocks
+constexpr int GS_PARTS = 65536;  // partial sums of one fused Gram-Schmidt launch
 
 }  // namespace
 
@@ -208,9 +209,15 @@ void default_shapes(MeshDev& M, int sk) {
 
 // ===================================================================== context
 struct GraphKey {
-  int mode, prec, m;
-  bool operator<(const GraphKey& o) const { return std::tie(mode, prec, m) < std::tie(o.mode, o.prec, o.m); }
+  int mode, prec, m, j0;  // Arnoldi iterations j0 .. j0 + ARNOLDI_CHUNK - 1 of a GMRES(m) cycle
+  bool operator<(const GraphKey& o) const {
+    return std::tie(mode, prec, m, j0) < std::tie(o.mode, o.prec, o.m, o.j0);
+  }
 };
+// Arnoldi iterations per captured graph.  Between two graphs the host reads
+// the device's converged flag, so a converged cycle stops within this many
+// iterations instead of replaying skipped kernels up to m.
+constexpr int ARNOLDI_CHUNK = 6;
 
 struct fr_ctx_s {
   MeshDev M;
@@ -354,9 +361,10 @@ void ensure_krylov(fr_ctx c, int m, int prec) {
   c->wv = c->dalloc((size_t)c->ndof * vb);
   c->xv = c->dalloc((size_t)c->ndof * vb);
   c->H = (double*)c->dalloc(sizeof(double) * ((mm + 1) * mm + 4 * (mm + 1)));
-  c->part = (double*)c->dalloc(sizeof(double) * (size_t)(mm + 2) * NBLK);
+  c->part = (double*)c->dalloc(sizeof(double) * std::max<size_t>((size_t)(mm + 2) * NBLK, GS_PARTS));
   c->sc = (double*)c->dalloc(sizeof(double) * (64 + 3 * (mm + 2)));
   c->ist = (int*)c->dalloc(sizeof(int) * 16);
+  FRX_TRY(hipMemset(c->ist, 0, sizeof(int) * 16));
   if (!c->Ulin) {
     c->Ulin = (double*)c->dalloc(sizeof(double) * c->ndof);
     c->Fb = (double*)c->dalloc(sizeof(double) * c->ndof);
@@ -434,6 +442,51 @@ void apply_A(fr_ctx c, int mode, const TV* in, TV* out, double eps, const int* d
   }
 }
 
+// CGS2 for nv <= 32 basis vectors with the fused kernels: dots (h1), update
+// fused with the second dots (h2), update fused with the norm and the Givens
+// step; the orthogonalised vector goes straight into its basis slot (scaled
+// afterwards by 1/h_{j+1,j}).
+template <class TV, int NV>
+void gs_fused_n(fr_ctx c, const GmresDev& G, int j, double* h1, double* h2, double* nr, TV* vnext, const int* done,
+                hipStream_t s) {
+  const long n = c->ndof;
+  const TV* V = (const TV*)c->Vb;
+  TV* w = (TV*)c->wv;
+  // blocks: 2048 (8 per CU); the update-and-dot pass keeps all NV basis values
+  // of its rows in registers and gets what stays resident of it at once
+  constexpr int nb0 = 2048, nb1 = NV <= 8 ? 2048 : (NV <= 16 ? 1024 : 512);
+  static_assert(NV * nb0 <= GS_PARTS && NV * nb1 <= GS_PARTS, "partials");
+  hipLaunchKernelGGL((k_gs<TV, NV, 0>), dim3(nb0), dim3(KR_THREADS), 0, s, V, n, (const double*)nullptr, w,
+                     (TV*)nullptr, n, c->part, done);
+  FRX_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_gs_reduce, dim3(NV), dim3(KR_THREADS), 0, s, (const double*)c->part, nb0, h1, 0, G, j,
+                     (const double*)nullptr, (const double*)nullptr, done);
+  FRX_TRY(hipGetLastError());
+  hipLaunchKernelGGL((k_gs<TV, NV, 1>), dim3(nb1), dim3(KR_THREADS), 0, s, V, n, (const double*)h1, w,
+                     (TV*)nullptr, n, c->part, done);
+  FRX_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_gs_reduce, dim3(NV), dim3(KR_THREADS), 0, s, (const double*)c->part, nb1, h2, 0, G, j,
+                     (const double*)nullptr, (const double*)nullptr, done);
+  FRX_TRY(hipGetLastError());
+  hipLaunchKernelGGL((k_gs<TV, NV, 2>), dim3(nb0), dim3(KR_THREADS), 0, s, V, n, (const double*)h2, w, vnext, n,
+                     c->part, done);
+  FRX_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_gs_reduce, dim3(1), dim3(KR_THREADS), 0, s, (const double*)c->part, nb0, nr, 1, G, j,
+                     (const double*)h1, (const double*)h2, done);
+  FRX_TRY(hipGetLastError());
+}
+
+template <class TV, int NV = 1>
+void gs_fused(fr_ctx c, const GmresDev& G, int j, double* h1, double* h2, double* nr, TV* vnext, const int* done,
+              hipStream_t s) {
+  if constexpr (NV <= 32) {
+    if (j + 1 == NV) return gs_fused_n<TV, NV>(c, G, j, h1, h2, nr, vnext, done, s);
+    return gs_fused<TV, NV + 1>(c, G, j, h1, h2, nr, vnext, done, s);
+  } else {
+    throw StatusErr{FR_E_INVALID, "fused Gram-Schmidt takes at most 32 vectors"};
+  }
+}
+
 // One Arnoldi iteration j with CGS2 (all kernels skip once *done is set).
 template <class TV>
 void arnoldi_step(fr_ctx c, int mode, int m, int j, double eps, hipStream_t s) {
@@ -447,6 +500,13 @@ void arnoldi_step(fr_ctx c, int mode, int m, int j, double eps, hipStream_t s) {
   double* nr = h2 + (m + 1);
   apply_A<TV>(c, mode, V + (size_t)j * n, w, eps, done, s);
   const int nv = j + 1;
+  if (nv <= 32) {
+    gs_fused<TV>(c, G, j, h1, h2, nr, V + (size_t)(j + 1) * n, done, s);
+    hipLaunchKernelGGL((k_scale_inplace<TV>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, V + (size_t)(j + 1) * n, n,
+                       (const double*)(c->sc + 4), done);
+    FRX_TRY(hipGetLastError());
+    return;
+  }
   const int gy = (nv + KR_VB - 1) / KR_VB;
   for (int pass = 0; pass < 2; ++pass) {
     double* h = pass ? h2 : h1;
@@ -478,29 +538,37 @@ void arnoldi_cycle(fr_ctx c, int mode, int m, double eps, bool use_graph, hipStr
     for (int j = 0; j < m; ++j) arnoldi_step<TV>(c, mode, m, j, eps, s);
     return;
   }
-  GraphKey key{mode, (int)sizeof(TV), m};
-  auto it = c->graphs.find(key);
-  if (it == c->graphs.end()) {
-    if (!c->cap) FRX_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
-    FRX_TRY(hipStreamSynchronize(s));
-    hipGraph_t g;
-    FRX_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-    try {
-      for (int j = 0; j < m; ++j) arnoldi_step<TV>(c, mode, m, j, eps, c->cap);
-    } catch (...) {
-      hipGraph_t tmp;
-      (void)hipStreamEndCapture(c->cap, &tmp);
-      if (tmp) (void)hipGraphDestroy(tmp);
-      throw;
+  for (int j0 = 0; j0 < m; j0 += ARNOLDI_CHUNK) {
+    const int j1 = std::min(m, j0 + ARNOLDI_CHUNK);
+    GraphKey key{mode, (int)sizeof(TV), m, j0};
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+      if (!c->cap) FRX_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+      FRX_TRY(hipStreamSynchronize(s));
+      hipGraph_t g;
+      FRX_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+      try {
+        for (int j = j0; j < j1; ++j) arnoldi_step<TV>(c, mode, m, j, eps, c->cap);
+      } catch (...) {
+        hipGraph_t tmp;
+        (void)hipStreamEndCapture(c->cap, &tmp);
+        if (tmp) (void)hipGraphDestroy(tmp);
+        throw;
+      }
+      FRX_TRY(hipStreamEndCapture(c->cap, &g));
+      hipGraphExec_t ex;
+      hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      FRX_TRY(e);
+      it = c->graphs.emplace(key, ex).first;
     }
-    FRX_TRY(hipStreamEndCapture(c->cap, &g));
-    hipGraphExec_t ex;
-    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    FRX_TRY(e);
-    it = c->graphs.emplace(key, ex).first;
+    FRX_TRY(hipGraphLaunch(it->second, s));
+    if (j1 < m) {
+      FRX_TRY(hipMemcpyAsync(c->ipin + 8, c->ist, sizeof(int), hipMemcpyDeviceToHost, s));
+      FRX_TRY(hipStreamSynchronize(s));
+      if (c->ipin[8]) break;
+    }
   }
-  FRX_TRY(hipGraphLaunch(it->second, s));
 }
 
 // Restarted GMRES on the device.  x (float64, device) receives the solution.

@@ -235,6 +235,25 @@ def test_gmres_fixed_iterations_parity(frx, oracle_mod):
         assert abs(sg["rel_res"] - so["rel_res"]) <= 1e-9 * max(so["rel_res"], 1e-300) + 1e-12
 
 
+def test_gmres_long_cycle_parity(frx, oracle_mod):
+    """GMRES(40), 36 iterations in one cycle: the fused Gram-Schmidt kernels
+    (up to 32 basis vectors) and the split multi-dot / multi-axpy path beyond
+    them, against the oracle's modified Gram-Schmidt."""
+    case = CASES["mixed_p1to5_ns_roe"]
+    orc, ctx, U = _pair(frx, oracle_mod, case)
+    F = I.random_direction(case.U.size, 80).reshape(case.U.shape)
+    shift = 8.0
+    xo, so = orc.gmres(case.U, shift, F, m=40, max_it=36, tol=0.0, jv_mode=0)
+    for graph in (False, True):
+        xg, sg = ctx.gmres(U, shift, torch.tensor(F, device="cuda"), restart=40, max_iter=36, tol=0.0,
+                           use_graph=graph)
+        assert sg["iterations"] == so["iterations"] == 36
+        err = np.linalg.norm(xg.cpu().numpy() - xo) / np.linalg.norm(xo)
+        print("gmres(40) 36 its rel diff", err, "rel res", sg["rel_res"], so["rel_res"], "graph", graph)
+        assert err <= 1e-8
+        assert abs(sg["rel_res"] - so["rel_res"]) <= 1e-6 * so["rel_res"] + 1e-13
+
+
 @pytest.mark.parametrize("mode", ["exact64", "fd64", "exact32", "exact64_graph", "exact32_graph"])
 def test_gmres_converged(frx, oracle_mod, mode):
     case = CASES["wall_farfield_ns_roe"]
