@@ -88,11 +88,17 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB five times (reference for the HBM byte counters)")
+    ap.add_argument("--study", choices=("c3", "c5"), default=None,
+                    help="instead of the headline: the implicit-step comparison on the 64x64x8 vortex street "
+                         "(c3, degrees from the indicator) or the 128x128x8 Re 60000 box (c5)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the hot path is built and "
               "measured on a single MI355X, with no collectives).", file=sys.stderr)
         sys.exit(2)
+    if args.study:
+        print(json.dumps(step_study(args.study)), flush=True)
+        return
 
     import torch
 
@@ -324,6 +330,54 @@ def implicit_steps(ctx, case, U, frx, torch):
     res["rel_change_of_step"] = (outs["plain_f64_fd"] - U).norm().item() / U.norm().item()
     res["speedup_mixed_vs_plain"] = round(res["plain_f64_fd"]["ms"] / res["mixed_f32_exact_graph"]["ms"], 3)
     return res
+
+
+def step_study(which):
+    """One ESDIRK2 step in the plain, FP64-exact and mixed forms on a larger
+    workload (not the headline): c3 = 64x64x8 vortex street with the degree
+    field chosen by the spectral-decay indicator; c5 = 128x128x8 box at
+    Re 60000, Mach 0.1 with the settings of the paper's SD7003 runs."""
+    import torch
+
+    from paper_1910_03693_amd import adapt, frx
+    from paper_1910_03693_amd import inputs as I
+
+    out = {"study": which}
+    if which == "c3":
+        p, hist = adapt.indicator_degree_field(lambda ep: I.case_street(elem_p=ep))
+        case = I.case_street(elem_p=p)
+        out["degree_histogram_p1_to_p5"] = np.bincount(p, minlength=6)[1:].tolist()
+        dt, common = 0.05, dict(dtau_init=0.005, dtau_max=0.05, tol_pseudo=1e-4, max_ptc_iter=50)
+        g = dict(restart=30, max_iter=100, tol=1e-1)
+    else:
+        case = I.config(5)
+        dt, common = 0.002, dict(dtau_init=2e-4, dtau_max=4e-3, tol_pseudo=1e-4, max_ptc_iter=50)
+        g = dict(restart=30, max_iter=300, tol=1e-6)
+    ctx = frx.Context.from_case(case)
+    U = torch.tensor(case.U, device="cuda")
+    out["n_dof"] = int(ctx.n_dof)
+    out["dt"] = dt
+    out["settings"] = {**common, **g}
+    variants = (("f64_exact_graph", dict(g, precision=frx.FR_F64, use_graph=True), True),
+                ("mixed_f32_exact_graph", dict(g, precision=frx.FR_F32, use_graph=True), True),
+                ("plain_f64_fd", dict(g, jv_mode=frx.FR_JV_FD, precision=frx.FR_F64, use_graph=False), False))
+    outs = {}
+    for name, gv, fused in variants:
+        ctx.set_launch(fused)
+        Uw = U.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ctx.esdirk_step(Uw, dt, gmres=gv, **common)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        outs[name] = Uw
+        out[name] = {"ms": round(ms, 1), **st, "launch": "fused" if fused else "per-bucket"}
+        print(f"[bench] {which} {name}: {ms:.1f} ms {st}", file=sys.stderr, flush=True)
+    ref = outs["f64_exact_graph"]
+    for name in ("mixed_f32_exact_graph", "plain_f64_fd"):
+        out[f"rel_diff_{name}_vs_f64_exact"] = (outs[name] - ref).norm().item() / ref.norm().item()
+    out["speedup_mixed_vs_plain"] = round(out["plain_f64_fd"]["ms"] / out["mixed_f32_exact_graph"]["ms"], 3)
+    return out
 
 
 def cpu_baseline(case, seconds):
