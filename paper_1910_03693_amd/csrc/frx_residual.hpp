@@ -63,6 +63,26 @@ template <int N> __device__ __forceinline__ int line_pt(int d, int a, int b, int
   return d == 0 ? m + N * (a + N * b) : (d == 1 ? a + N * (m + N * b) : a + N * (b + N * m));
 }
 
+// Interior-face record (L, R, oL, pack): L's +d face is R's -d face; oL and
+// oR are the first face slots of that face on L and on R, and
+// pack = oR | d << 28 | low_is_R << 30, so that a face point's slots need no
+// second dependent load.  Boundary-face record (e, f, bc, o), o the first slot
+// of face f of e.
+struct FaceRec {
+  int L, R, oL, oR, d;
+  bool low_is_R;
+};
+__device__ __forceinline__ FaceRec face_rec(const int4 F) {
+  FaceRec r;
+  r.L = F.x;
+  r.R = F.y;
+  r.oL = F.z;
+  r.oR = F.w & 0x0fffffff;
+  r.d = (F.w >> 28) & 3;
+  r.low_is_R = (F.w >> 30) & 1;
+  return r;
+}
+
 // ---------------------------------------------------------------- trace stage
 // Block: epb elements x N^3 threads (one solution point each).  LDS per
 // element: q (5 N^3) and, for Navier-Stokes, the uncorrected physical
@@ -255,20 +275,18 @@ __device__ __forceinline__ void face_body(const ResArgs<T>& a, const int4* __res
   const int lf = tid / NH2, pt = tid - lf * NH2;
   const int fi = blk * fpb + lf;
   const bool act = lf < fpb && fi < nf;
-  int4 F = act ? faces[fi] : make_int4(0, 0, 0, 0);
-  const int L = F.x, R = F.y, d = F.z;
-  const bool lowR = MIX && F.w;
-  const bool lowL = MIX && !F.w;
+  const FaceRec F = face_rec(act ? faces[fi] : make_int4(0, 0, 0, 0));
+  const int L = F.L, R = F.R, d = F.d;
+  const bool lowR = MIX && F.low_is_R;
+  const bool lowL = MIX && !F.low_is_R;
   if (MIX) {  // stage the low side's own-point traces
     for (int it = tid; it < fpb * NV * NL2; it += blockDim.x) {
       const int l2 = it / (NV * NL2), rem = it - l2 * NV * NL2;
       const int vv = rem / NL2, p2 = rem - vv * NL2;
       const int f2 = blk * fpb + l2;
       if (f2 >= nf) continue;
-      int4 G2 = faces[f2];
-      const int el = G2.w ? G2.y : G2.x;
-      const int ff = G2.w ? 2 * G2.z : 2 * G2.z + 1;
-      const long o = a.fp_off[el] + ff * NL2 + p2;
+      const FaceRec G2 = face_rec(faces[f2]);
+      const long o = (G2.low_is_R ? G2.oR : G2.oL) + p2;
       slow[it] = vv < 5 ? a.QF[(long)vv * a.nfp + o] : a.GF[(long)(vv - 5) * a.nfp + o];
     }
     __syncthreads();
@@ -301,8 +319,7 @@ __device__ __forceinline__ void face_body(const ResArgs<T>& a, const int4* __res
           else g[0][(vv - 5) / 3][(vv - 5) % 3] += acc;
         }
       } else {
-        const int el = s ? R : L;
-        const long o = a.fp_off[el] + (s ? 2 * d : 2 * d + 1) * NH2 + pt;
+        const long o = (s ? F.oR : F.oL) + pt;
 #pragma unroll
         for (int v = 0; v < 5; ++v) q[s][v] = a.QF[(long)v * a.nfp + o];
         if (NS) {
@@ -325,7 +342,7 @@ __device__ __forceinline__ void face_body(const ResArgs<T>& a, const int4* __res
     T fS[5], jL[5], jR[5];
     face_fn<NS, T, B>(q[0], q[1], g[0], S, cL, cR, a.gas, a.flux, fS, jL, jR);
     if (!lowL) {
-      const long o = a.fp_off[L] + (2 * d + 1) * NH2 + pt;
+      const long o = F.oL + pt;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         a.FS[(long)v * a.nfp + o] = fS[v];
@@ -333,7 +350,7 @@ __device__ __forceinline__ void face_body(const ResArgs<T>& a, const int4* __res
       }
     }
     if (!lowR) {
-      const long o = a.fp_off[R] + (2 * d) * NH2 + pt;
+      const long o = F.oR + pt;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         a.FS[(long)v * a.nfp + o] = fS[v];
@@ -361,10 +378,8 @@ __device__ __forceinline__ void face_body(const ResArgs<T>& a, const int4* __res
       const int l2 = it / NL2, p2 = it - l2 * NL2;
       const int f2 = blk * fpb + l2;
       if (f2 >= nf) continue;
-      int4 G2 = faces[f2];
-      const int el = G2.w ? G2.y : G2.x;
-      const int ff = G2.w ? 2 * G2.z : 2 * G2.z + 1;
-      const long o = a.fp_off[el] + ff * NL2 + p2;
+      const FaceRec G2 = face_rec(faces[f2]);
+      const long o = (G2.low_is_R ? G2.oR : G2.oL) + p2;
       const int aa = p2 % NL, bb = p2 / NL;
       const T* src = sout + l2 * 10 * NH2;
       for (int vv = 0; vv < 10; ++vv) {
@@ -395,7 +410,7 @@ __device__ __forceinline__ void bface_body(const ResArgs<T>& a, const int4* __re
   const int4 F = faces[fi];
   const int e = F.x, f = F.y, bc = F.z, d = f >> 1, side = f & 1;
   const OpsTab<B>& O = ops<B>();
-  const long o = a.fp_off[e] + f * N2 + pt;
+  const long o = F.w + pt;
   T q[5], g[5][3];
 #pragma unroll
   for (int v = 0; v < 5; ++v) q[v] = a.QF[(long)v * a.nfp + o];
@@ -489,8 +504,27 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int* __restr
   T acc[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) acc[v] = T(B(0));
+  // face items (element, variable, side, point) of one direction: at most
+  // epb 10 N^2 <= blockDim.x 10 / N of them, FIT per thread
+  constexpr int FIT = (10 + N - 1) / N;
+  const int items = epb * 10 * N2;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
+    // the common fluxes f_com . S of the two faces of direction d, loaded
+    // before the barrier so that the loads overlap the contraction below
+    T fsr[FIT];
+#pragma unroll
+    for (int q = 0; q < FIT; ++q) {
+      const int it = tid + q * (int)blockDim.x;
+      fsr[q] = T(B(0));
+      if (it < items) {
+        const int l2 = it / (10 * N2), rem = it - l2 * 10 * N2;
+        const int v = rem / (2 * N2), sp2 = rem - v * 2 * N2;
+        const int side = sp2 / N2, p2 = sp2 - side * N2, f = 2 * d + side;
+        const int s2 = blk * epb + l2;
+        if (s2 < nel) fsr[q] = a.FS[(long)v * a.nfp + a.fp_off[elems[s2]] + f * N2 + p2];
+      }
+    }
     __syncthreads();  // X (q or the previous direction) and Y are no longer read
     if (act) {
 #pragma unroll
@@ -508,10 +542,27 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int* __restr
           acc[v] = fmab(O.D[N][kd][m], X[v * N3 + kk], acc[v]);
         }
     }
-    // flux jumps on the two faces of direction d
-    for (int it = tid; it < epb * 10 * N2; it += blockDim.x) {
-      // (element, variable, side, point): the two faces of direction d are
-      // contiguous slots
+    // flux jumps f_com . S - f_loc on the two faces of direction d
+    // (element, variable, side, point): the two faces are contiguous slots
+#pragma unroll
+    for (int q = 0; q < FIT; ++q) {
+      const int it = tid + q * (int)blockDim.x;
+      if (it >= items) continue;
+      const int l2 = it / (10 * N2), rem = it - l2 * 10 * N2;
+      const int v = rem / (2 * N2), sp2 = rem - v * 2 * N2;
+      const int side = sp2 / N2, p2 = sp2 - side * N2, f = 2 * d + side;
+      const int s2 = blk * epb + l2;
+      if (s2 >= nel) continue;
+      const B* lf = side ? O.lp[N] : O.lm[N];
+      const T* X = sX + (l2 * 5 + v) * N3;
+      T floc = T(B(0));
+#pragma unroll
+      for (int m = 0; m < N; ++m) floc = fmab(lf[m], X[line_pt<N>(d, p2 % N, p2 / N, m)], floc);
+      sY[(l2 * 30 + f * 5 + v) * N2 + p2] = fsr[q] - floc;
+    }
+    // (only for block shapes with more than FIT items per thread, which the
+    // launchers do not make)
+    for (int it = tid + FIT * (int)blockDim.x; it < items; it += blockDim.x) {
       const int l2 = it / (10 * N2), rem = it - l2 * 10 * N2;
       const int v = rem / (2 * N2), sp2 = rem - v * 2 * N2;
       const int side = sp2 / N2, p2 = sp2 - side * N2, f = 2 * d + side;

@@ -831,6 +831,8 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
       nfp += 6L * n * n;
     }
     C->sp_off_h[E] = nsp;
+    // (30 nfp < 2^31 also keeps face-slot offsets below 2^28, as the packed
+    // interior-face records need)
     if (5 * nsp >= (1L << 31) || 30 * nfp >= (1L << 31)) throw StatusErr{FR_E_INVALID, "mesh too large for 32-bit indices"};
     M.nsp = (int)nsp;
     M.nfp = (int)nfp;
@@ -887,9 +889,12 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
         if (nb >= 0) {
           if (!(f & 1)) continue;
           const int nr = d->elem_p[nb] + 1;
-          fmap[{std::min(ne, nr), std::max(ne, nr)}].push_back(make_int4(e, nb, f >> 1, nr < ne ? 1 : 0));
+          // (L, R, first slot of L's +d face, first slot of R's -d face | d << 28 | low_is_R << 30)
+          const int oL = fp[e] + f * ne * ne, oR = fp[nb] + (f - 1) * nr * nr;
+          fmap[{std::min(ne, nr), std::max(ne, nr)}].push_back(
+              make_int4(e, nb, oL, oR | ((f >> 1) << 28) | ((nr < ne ? 1 : 0) << 30)));
         } else {
-          bmap[ne].push_back(make_int4(e, f, nb, 0));
+          bmap[ne].push_back(make_int4(e, f, nb, fp[e] + f * ne * ne));
         }
       }
     for (auto& kv : fmap) {

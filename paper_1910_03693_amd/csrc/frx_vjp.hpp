@@ -333,20 +333,18 @@ __global__ void __launch_bounds__(256) k_face_rev(VjpArgs a, const int4* __restr
   const int lf = tid / NH2, pt = tid - lf * NH2;
   const int fi = blockIdx.x * fpb + lf;
   const bool act = lf < fpb && fi < nf;
-  int4 F = act ? faces[fi] : make_int4(0, 0, 0, 0);
-  const int L = F.x, R = F.y, d = F.z;
-  const bool lowR = MIX && F.w;
-  const bool lowL = MIX && !F.w;
+  const FaceRec F = face_rec(act ? faces[fi] : make_int4(0, 0, 0, 0));
+  const int L = F.L, R = F.R, d = F.d;
+  const bool lowR = MIX && F.low_is_R;
+  const bool lowL = MIX && !F.low_is_R;
   if (MIX) {
     for (int it = tid; it < fpb * (NV + 10) * NL2; it += blockDim.x) {
       const int l2 = it / ((NV + 10) * NL2), rem = it - l2 * (NV + 10) * NL2;
       const int vv = rem / NL2, p2 = rem - vv * NL2;
       const int f2 = blockIdx.x * fpb + l2;
       if (f2 >= nf) continue;
-      int4 G2 = faces[f2];
-      const int el = G2.w ? G2.y : G2.x;
-      const int ff = G2.w ? 2 * G2.z : 2 * G2.z + 1;
-      const long o = a.fp_off[el] + ff * NL2 + p2;
+      const FaceRec G2 = face_rec(faces[f2]);
+      const long o = (G2.low_is_R ? G2.oR : G2.oL) + p2;
       double val;
       if (vv < 5) val = a.QF[(long)vv * a.nfp + o];
       else if (vv < NV) val = a.GF[(long)(vv - 5) * a.nfp + o];
@@ -387,8 +385,7 @@ __global__ void __launch_bounds__(256) k_face_rev(VjpArgs a, const int4* __restr
           else jb[s][w - 5] = NS ? acc : 0.0;
         }
       } else {
-        const int el = s ? R : L;
-        const long o = a.fp_off[el] + (s ? 2 * d : 2 * d + 1) * NH2 + pt;
+        const long o = (s ? F.oR : F.oL) + pt;
         for (int v = 0; v < 5; ++v) {
           q[s][v] = a.QF[(long)v * a.nfp + o];
           fSb[v] += a.FS[(long)v * a.nfp + o];
@@ -414,8 +411,7 @@ __global__ void __launch_bounds__(256) k_face_rev(VjpArgs a, const int4* __restr
     for (int s = 0; s < 2; ++s) {
       const bool low = s ? lowR : lowL;
       if (!low) {
-        const int el = s ? R : L;
-        const long o = a.fp_off[el] + (s ? 2 * d : 2 * d + 1) * NH2 + pt;
+        const long o = (s ? F.oR : F.oL) + pt;
         for (int v = 0; v < 5; ++v) a.QF[(long)v * a.nfp + o] = qb[s][v];
         if (NS)
           for (int vc = 0; vc < 15; ++vc) a.GF[(long)vc * a.nfp + o] = gb[s][vc / 3][vc % 3];
@@ -434,10 +430,8 @@ __global__ void __launch_bounds__(256) k_face_rev(VjpArgs a, const int4* __restr
       const int l2 = it / NL2, p2 = it - l2 * NL2;
       const int f2 = blockIdx.x * fpb + l2;
       if (f2 >= nf) continue;
-      int4 G2 = faces[f2];
-      const int el = G2.w ? G2.y : G2.x;
-      const int ff = G2.w ? 2 * G2.z : 2 * G2.z + 1;
-      const long o = a.fp_off[el] + ff * NL2 + p2;
+      const FaceRec G2 = face_rec(faces[f2]);
+      const long o = (G2.low_is_R ? G2.oR : G2.oL) + p2;
       const int aa = p2 % NL, bb = p2 / NL;
       const double* src = sres + l2 * NV * NH2;
       for (int vv = 0; vv < NV; ++vv) {
@@ -462,7 +456,7 @@ __global__ void __launch_bounds__(256) k_bface_rev(VjpArgs a, const int4* __rest
   const int4 F = faces[fi];
   const int e = F.x, f = F.y, bc = F.z, d = f >> 1, side = f & 1;
   const OpsTab<double>& O = ops<double>();
-  const long o = a.fp_off[e] + f * N2 + pt;
+  const long o = F.w + pt;
   double q[5], g[5][3], fSb[5], jb[5];
   for (int v = 0; v < 5; ++v) {
     q[v] = a.QF[(long)v * a.nfp + o];
