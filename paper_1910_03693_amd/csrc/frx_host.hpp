@@ -16,6 +16,7 @@ struct ElemBucket {
   int n = 0;        // p + 1
   int count = 0;
   int* elems = nullptr;  // device, ascending element ids of this degree
+  int4* recs = nullptr;  // device, the same elements as (e, first solution point, first face slot, 0)
   int epb_trace[SK_COUNT] = {0, 0, 0};
   int epb_div[SK_COUNT] = {0, 0, 0};
 };
@@ -75,7 +76,7 @@ struct MeshDev {
   int* flag = nullptr;
   ProfHook* prof = nullptr;
   bool fused = false;             // one launch per stage over all buckets
-  int* all_elems = nullptr;       // concatenated bucket element lists
+  int4* all_elems = nullptr;      // concatenated bucket element records
   int4* all_faces = nullptr;      // concatenated interior + boundary face lists
   FusedPlan plan[SK_COUNT];
   Gas<double> gas_d;

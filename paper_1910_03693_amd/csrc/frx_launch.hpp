@@ -36,14 +36,14 @@ hipError_t run_trace(const ResArgs<T>& a, const ElemBucket& b, int epb, hipStrea
   const int grid = (b.count + epb - 1) / epb;
   if (!block_ok(round64(epb * N * N * N))) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((k_trace<N, T, NS>), dim3(grid), dim3(round64(epb * N * N * N)), trace_lds<T>(N, epb, NS), s, a,
-                     b.elems, b.count, epb);
+                     b.recs, b.count, epb);
   return hipGetLastError();
 }
 template <int N, class T, bool NS>
 hipError_t run_div(const ResArgs<T>& a, const ElemBucket& b, int epb, hipStream_t s) {
   const int grid = (b.count + epb - 1) / epb;
   if (!block_ok(round64(epb * N * N * N))) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_div<N, T, NS>), dim3(grid), dim3(round64(epb * N * N * N)), div_lds<T>(N, epb), s, a, b.elems,
+  hipLaunchKernelGGL((k_div<N, T, NS>), dim3(grid), dim3(round64(epb * N * N * N)), div_lds<T>(N, epb), s, a, b.recs,
                      b.count, epb);
   return hipGetLastError();
 }

@@ -98,7 +98,7 @@ template <class T, int N, bool NS> __host__ __device__ constexpr int trace_vals(
 }
 
 template <int N, class T, bool NS>
-__device__ __forceinline__ void trace_body_rounds(const ResArgs<T>& a, const int* __restrict__ elems, int nel, int epb,
+__device__ __forceinline__ void trace_body_rounds(const ResArgs<T>& a, const int4* __restrict__ elems, int nel, int epb,
                                            int blk, unsigned char* smem) {
   using B = base_t<T>;
   constexpr int N2 = N * N, N3 = N2 * N;
@@ -108,9 +108,10 @@ __device__ __forceinline__ void trace_body_rounds(const ResArgs<T>& a, const int
   const int le = tid / N3, k = tid - le * N3;
   const int slot = blk * epb + le;
   const bool act = le < epb && slot < nel;
-  const int e = act ? elems[slot] : 0;
+  const int4 ER = act ? elems[slot] : make_int4(0, 0, 0, 0);
+  const int e = ER.x;
   if (act) {
-    const long off = a.sp_off[e] + k;
+    const long off = (long)ER.y + k;
 #pragma unroll
     for (int v = 0; v < 5; ++v) sq[(le * 5 + v) * N3 + k] = IO<T>::load(a.U, a.V, (long)v * a.nsp + off);
   }
@@ -121,7 +122,7 @@ __device__ __forceinline__ void trace_body_rounds(const ResArgs<T>& a, const int
     const int f = rem / N2, pt = rem - f * N2;
     const int s2 = blk * epb + l2;
     if (s2 >= nel) continue;
-    const long o = a.fp_off[elems[s2]] + f * N2 + pt;
+    const long o = elems[s2].z + f * N2 + pt;
     const int d = f >> 1, fa = pt % N, fb = pt / N;
     const B* lf = (f & 1) ? O.lp[N] : O.lm[N];
     const T* q = sq + l2 * 5 * N3;
@@ -169,7 +170,7 @@ __device__ __forceinline__ void trace_body_rounds(const ResArgs<T>& a, const int
       const int f = fp / N2, pt = fp - f * N2;
       const int s2 = blk * epb + l2;
       if (s2 >= nel) continue;
-      const long o = a.fp_off[elems[s2]] + f * N2 + pt;
+      const long o = elems[s2].z + f * N2 + pt;
       const int d = f >> 1;
       const B* lf = (f & 1) ? O.lp[N] : O.lm[N];
       const T* g = sq + (l2 * 5 + c) * N3;
@@ -183,7 +184,7 @@ __device__ __forceinline__ void trace_body_rounds(const ResArgs<T>& a, const int
 
 
 template <int N, class T, bool NS>
-__device__ __forceinline__ void trace_body(const ResArgs<T>& a, const int* __restrict__ elems, int nel, int epb,
+__device__ __forceinline__ void trace_body(const ResArgs<T>& a, const int4* __restrict__ elems, int nel, int epb,
                                            int blk, unsigned char* smem) {
   using B = base_t<T>;
   if constexpr (trace_in_rounds<T, N, NS>()) {
@@ -197,10 +198,11 @@ __device__ __forceinline__ void trace_body(const ResArgs<T>& a, const int* __res
   const int le = tid / N3, k = tid - le * N3;
   const int slot = blk * epb + le;
   const bool act = le < epb && slot < nel;
-  const int e = act ? elems[slot] : 0;
+  const int4 ER = act ? elems[slot] : make_int4(0, 0, 0, 0);
+  const int e = ER.x;
   T* q = sq + le * NV * N3;
   if (act) {
-    const int off = a.sp_off[e] + k;
+    const int off = ER.y + k;
 #pragma unroll
     for (int v = 0; v < 5; ++v) q[v * N3 + k] = IO<T>::load(a.U, a.V, (long)(v * a.nsp + off));
   }
@@ -236,7 +238,7 @@ __device__ __forceinline__ void trace_body(const ResArgs<T>& a, const int* __res
     if (s2 >= nel) continue;
     const int f = fp / N2, pt = fp - f * N2;
     const int d = f >> 1, fa = pt % N, fb = pt / N;
-    const int o = a.fp_off[elems[s2]] + fp;
+    const int o = elems[s2].z + fp;
     const B* lf = (f & 1) ? O.lp[N] : O.lm[N];
     // start and stride of the normal line through (fa, fb)
     const int base = d == 0 ? N * (fa + N * fb) : (d == 1 ? fa + N2 * fb : fa + N * fb);
@@ -436,7 +438,7 @@ __device__ __forceinline__ void bface_body(const ResArgs<T>& a, const int4* __re
 // of 30 N^2 (the solution jumps of the 6 faces, then the flux jumps
 // f_com . S - f_loc).
 template <int N, class T, bool NS>
-__device__ __forceinline__ void div_body(const ResArgs<T>& a, const int* __restrict__ elems, int nel, int epb,
+__device__ __forceinline__ void div_body(const ResArgs<T>& a, const int4* __restrict__ elems, int nel, int epb,
                                          int blk, unsigned char* smem) {
   using B = base_t<T>;
   constexpr int N2 = N * N, N3 = N2 * N;
@@ -447,8 +449,9 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int* __restr
   const int le = tid / N3, k = tid - le * N3;
   const int slot = blk * epb + le;
   const bool act = le < epb && slot < nel;
-  const int e = act ? elems[slot] : 0;
-  const long off = act ? (long)a.sp_off[e] + k : 0;
+  const int4 ER = act ? elems[slot] : make_int4(0, 0, 0, 0);
+  const int e = ER.x;
+  const long off = act ? (long)ER.y + k : 0;
   if (act) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) sX[(le * 5 + v) * N3 + k] = IO<T>::load(a.U, a.V, (long)v * a.nsp + off);
@@ -461,7 +464,7 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int* __restr
       const int f = fp / N2, p2 = fp - f * N2;
       const int s2 = blk * epb + l2;
       if (s2 >= nel) continue;
-      sY[(l2 * 30 + f * 5 + v) * N2 + p2] = a.DQ[(long)v * a.nfp + a.fp_off[elems[s2]] + fp];
+      sY[(l2 * 30 + f * 5 + v) * N2 + p2] = a.DQ[(long)v * a.nfp + elems[s2].z + fp];
     }
   }
   __syncthreads();
@@ -522,7 +525,7 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int* __restr
         const int v = rem / (2 * N2), sp2 = rem - v * 2 * N2;
         const int side = sp2 / N2, p2 = sp2 - side * N2, f = 2 * d + side;
         const int s2 = blk * epb + l2;
-        if (s2 < nel) fsr[q] = a.FS[(long)v * a.nfp + a.fp_off[elems[s2]] + f * N2 + p2];
+        if (s2 < nel) fsr[q] = a.FS[(long)v * a.nfp + elems[s2].z + f * N2 + p2];
       }
     }
     __syncthreads();  // X (q or the previous direction) and Y are no longer read
@@ -573,7 +576,7 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int* __restr
       T floc = T(B(0));
 #pragma unroll
       for (int m = 0; m < N; ++m) floc = fmab(lf[m], X[line_pt<N>(d, p2 % N, p2 / N, m)], floc);
-      sY[(l2 * 30 + f * 5 + v) * N2 + p2] = a.FS[(long)v * a.nfp + a.fp_off[elems[s2]] + f * N2 + p2] - floc;
+      sY[(l2 * 30 + f * 5 + v) * N2 + p2] = a.FS[(long)v * a.nfp + elems[s2].z + f * N2 + p2] - floc;
     }
     __syncthreads();
     if (act) {
@@ -601,7 +604,7 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int* __restr
 
 // ------------------------------------------------------ per-bucket kernels
 template <int N, class T, bool NS>
-__global__ void __launch_bounds__(FRX_MAX_THREADS) k_trace(ResArgs<T> a, const int* __restrict__ elems, int nel, int epb) {
+__global__ void __launch_bounds__(FRX_MAX_THREADS) k_trace(ResArgs<T> a, const int4* __restrict__ elems, int nel, int epb) {
   if (a.skip && *a.skip) return;
   extern __shared__ __align__(16) unsigned char smem[];
   trace_body<N, T, NS>(a, elems, nel, epb, blockIdx.x, smem);
@@ -618,13 +621,14 @@ __global__ void __launch_bounds__(FRX_MAX_THREADS) k_bface(ResArgs<T> a, const i
   bface_body<N, T, NS>(a, faces, nf, blockIdx.x);
 }
 template <int N, class T, bool NS>
-__global__ void __launch_bounds__(FRX_MAX_THREADS) k_div(ResArgs<T> a, const int* __restrict__ elems, int nel, int epb) {
+__global__ void __launch_bounds__(FRX_MAX_THREADS) k_div(ResArgs<T> a, const int4* __restrict__ elems, int nel, int epb) {
   if (a.skip && *a.skip) return;
   extern __shared__ __align__(16) unsigned char smem[];
   div_body<N, T, NS>(a, elems, nel, epb, blockIdx.x, smem);
 }
 
 // ------------------------------------------------- degree-bucketed launches
+// Element lists hold records (e, first solution point, first face slot, 0).
 // One launch per stage over every degree bucket.  tiles[blockIdx.x] =
 // (code, first, count, per): code = n for element tiles, 8 nl + nh for
 // interior-face tiles, 64 + n for boundary-face tiles; `first` indexes the
@@ -635,7 +639,7 @@ __global__ void __launch_bounds__(FRX_MAX_THREADS) k_div(ResArgs<T> a, const int
   case N: BODY<N, T, NS>(a, elems + t.y, t.z, t.w, 0, smem); break;
 
 template <class T, bool NS>
-__global__ void __launch_bounds__(FRX_MAX_THREADS) k_trace_fused(ResArgs<T> a, const int* __restrict__ elems,
+__global__ void __launch_bounds__(FRX_MAX_THREADS) k_trace_fused(ResArgs<T> a, const int4* __restrict__ elems,
                                                      const int4* __restrict__ tiles) {
   if (a.skip && *a.skip) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -651,7 +655,7 @@ __global__ void __launch_bounds__(FRX_MAX_THREADS) k_trace_fused(ResArgs<T> a, c
 }
 
 template <class T, bool NS>
-__global__ void __launch_bounds__(FRX_MAX_THREADS) k_div_fused(ResArgs<T> a, const int* __restrict__ elems,
+__global__ void __launch_bounds__(FRX_MAX_THREADS) k_div_fused(ResArgs<T> a, const int4* __restrict__ elems,
                                                    const int4* __restrict__ tiles) {
   if (a.skip && *a.skip) return;
   extern __shared__ __align__(16) unsigned char smem[];

@@ -226,6 +226,7 @@ struct fr_ctx_s {
   std::string err;
   std::vector<int8_t> p;
   std::vector<int64_t> sp_off_h;
+  std::vector<int> fp_off_h;      // first face slot of each element
   std::vector<void*> allocs;
   hipStream_t cap = nullptr;  // private stream for graph capture
   // scratch for fr_jvp / operators
@@ -701,8 +702,10 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
     frange.emplace_back(64 + it->first, (int)faces.size(), (int)it->second.size(), it->first);
     faces.insert(faces.end(), it->second.begin(), it->second.end());
   }
-  M.all_elems = (int*)c->dalloc(sizeof(int) * std::max<size_t>(1, all.size()));
-  FRX_TRY(hipMemcpy(M.all_elems, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice));
+  std::vector<int4> all_recs;
+  for (int e : all) all_recs.push_back(make_int4(e, (int)c->sp_off_h[e], c->fp_off_h[e], 0));
+  M.all_elems = (int4*)c->dalloc(sizeof(int4) * std::max<size_t>(1, all_recs.size()));
+  FRX_TRY(hipMemcpy(M.all_elems, all_recs.data(), sizeof(int4) * all_recs.size(), hipMemcpyHostToDevice));
   M.all_faces = (int4*)c->dalloc(sizeof(int4) * std::max<size_t>(1, faces.size()));
   if (!faces.empty())
     FRX_TRY(hipMemcpy(M.all_faces, faces.data(), sizeof(int4) * faces.size(), hipMemcpyHostToDevice));
@@ -831,6 +834,7 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
       nfp += 6L * n * n;
     }
     C->sp_off_h[E] = nsp;
+    C->fp_off_h = fp;
     // (30 nfp < 2^31 also keeps face-slot offsets below 2^28, as the packed
     // interior-face records need)
     if (5 * nsp >= (1L << 31) || 30 * nfp >= (1L << 31)) throw StatusErr{FR_E_INVALID, "mesh too large for 32-bit indices"};
@@ -877,6 +881,10 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
       b.count = (int)ids.size();
       b.elems = (int*)C->dalloc(sizeof(int) * ids.size());
       FRX_TRY(hipMemcpy(b.elems, ids.data(), sizeof(int) * ids.size(), hipMemcpyHostToDevice));
+      std::vector<int4> recs;
+      for (int e : ids) recs.push_back(make_int4(e, sp[e], fp[e], 0));
+      b.recs = (int4*)C->dalloc(sizeof(int4) * recs.size());
+      FRX_TRY(hipMemcpy(b.recs, recs.data(), sizeof(int4) * recs.size(), hipMemcpyHostToDevice));
       M.eb.push_back(b);
     }
     // face buckets by (n_low, n_high); boundary faces by n
