@@ -163,6 +163,28 @@ fr_status esdirk_step(fr_ctx ctx, double* U, double dt, const fr_step_opts* opts
 fr_status spectral_decay_indicator(fr_ctx ctx, const double* U, int32_t var, double* eta, double* eta_max,
                                    void* stream);
 
+/* Degree selection of section 3.1 on the device: the indicator of variable
+ * `var` as above, then per element p + 1 where eta > nu_max * eta_max and
+ * p - 1 where eta < nu_min * eta_max (the paper: nu_max = 0.1,
+ * nu_min = 0.001; decisions in float64), clamped to [p_min, p_max]; then
+ * the lower side of every face whose degrees differ by more than one is
+ * raised until no face does.  p_new: device int8 [n_elem], written in mesh
+ * order.  FR_E_INVALID for 1 <= p_min <= p_max <= 5 violated, var outside
+ * 0..4 or nu_max < nu_min.  To adapt, create a context for p_new and move the
+ * state with fr_project. */
+fr_status fr_select_degrees(fr_ctx ctx, const double* U, int32_t var, double nu_max, double nu_min, int32_t p_min,
+                            int32_t p_max, int8_t* p_new, void* stream);
+
+/* Moves a state between two contexts of the same mesh with different degree
+ * fields (section 3.1: a lower degree takes the projection of the solution
+ * onto the lower-degree space).  Element by element in reference coordinates:
+ * to a lower degree the L2 projection onto the tensor space of that degree
+ * (Legendre modes truncated); to an equal or higher degree the element
+ * polynomial evaluated at the new solution points (exact).  U_src: device
+ * float64 in src's layout; U_dst: device float64 in dst's layout (distinct
+ * buffers).  FR_E_INVALID if the element counts or devices differ. */
+fr_status fr_project(fr_ctx src, const double* U_src, fr_ctx dst, double* U_dst, void* stream);
+
 /* Picks, per degree bucket and scalar kind, the launch shapes of the residual
  * kernels by timing the candidates on U (device float64). */
 fr_status fr_autotune(fr_ctx ctx, const double* U, void* stream);

@@ -59,3 +59,18 @@ def indicator_degree_field(make_case, p_max=5, p_min=1, nu_max=0.1, nu_min=0.001
         p = pn
     p = limit_jumps(p, case.mesh["elem_nbr"])
     return p, hist
+
+
+def adapt_step(case, ctx, U, nu_max=0.1, nu_min=0.001, p_min=1, p_max=5, var=1):
+    """One p-adaptation on the device: degrees from the indicator, criteria and
+    face limiter (fr_select_degrees), a context for the new degree field (new
+    degree buckets and face lists), the state projected onto it (fr_project).
+    Returns (new case description, new context, new state)."""
+    import dataclasses
+
+    from . import frx
+
+    p_new = ctx.select_degrees(U, var, nu_max, nu_min, p_min, p_max).cpu().numpy()
+    new_case = dataclasses.replace(case, elem_p=p_new.astype(np.int8), U=None)
+    new_ctx = frx.Context.from_case(new_case)
+    return new_case, new_ctx, ctx.project_to(U, new_ctx)

@@ -74,6 +74,10 @@ struct MeshDev {
   std::vector<BFaceBucket> bb;
   void* facebuf = nullptr;  // 30 * nfp scalars of the widest scalar type
   int* flag = nullptr;
+  int8_t* p_dev = nullptr;        // [E] degrees
+  int* nbr = nullptr;             // [E][6] neighbours (negative: boundary)
+  double* eta_w = nullptr;        // [E + 1] indicator workspace of the degree selection
+  int8_t* psel = nullptr;         // [2 E] degree-selection ping-pong buffers
   ProfHook* prof = nullptr;
   bool fused = false;             // one launch per stage over all buckets
   int4* all_elems = nullptr;      // concatenated bucket element records
@@ -115,4 +119,7 @@ hipError_t upload_tables_vjp(const OpsTab<double>& d, const OpsTab<float>& f);
 hipError_t launch_vjp(const MeshDev& M, const double* U, const double* w, double* out, hipStream_t s);
 hipError_t launch_indicator(const MeshDev& M, const double* U, int var, double* eta, double* eta_max,
                             hipStream_t s);
+hipError_t launch_select_degrees(const MeshDev& M, const double* U, int var, double nu_max, double nu_min, int p_min,
+                                 int p_max, int8_t* p_new, hipStream_t s);
+hipError_t launch_project(const MeshDev& Ms, const double* Us, const MeshDev& Md, double* Ud, hipStream_t s);
 }  // namespace frx

@@ -102,3 +102,84 @@ __global__ void __launch_bounds__(256) k_max(const double* __restrict__ x, int n
 }
 
 }  // namespace frx
+
+namespace frx {
+
+// ------------------------------------------------------- degree selection
+// Criteria of section 3.1 from the indicator: raise p by one where
+// eta > nu_max eta_max, lower it by one where eta < nu_min eta_max, clamped to
+// [p_min, p_max] (decided in float64).  One thread per element.
+__global__ void __launch_bounds__(256) k_select(const double* __restrict__ eta, const double* __restrict__ eta_max,
+                                               const int8_t* __restrict__ p, int E, double nu_max, double nu_min,
+                                               int p_min, int p_max, int8_t* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const double m = *eta_max;
+  int q = p[e] + (eta[e] > nu_max * m ? 1 : 0) - (eta[e] < nu_min * m ? 1 : 0);
+  q = q < p_min ? p_min : (q > p_max ? p_max : q);
+  out[e] = (int8_t)q;
+}
+
+// One sweep of the face limiter: the lower side of a face whose degrees
+// differ by more than one is raised, out[e] = max(in[e], max_nb in[nb] - 1).
+// p_max - p_min sweeps reach the fixed point (a degree constraint travels one
+// element per sweep and loses one degree per element).
+__global__ void __launch_bounds__(256) k_limit(const int8_t* __restrict__ in, const int* __restrict__ nbr, int E,
+                                              int8_t* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  int q = in[e];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int nb = nbr[6 * e + f];
+    if (nb >= 0) q = max(q, (int)in[nb] - 1);
+  }
+  out[e] = (int8_t)q;
+}
+
+// Projection of a state between two degree fields of the same mesh, one block
+// per element: the element polynomial through its ns^3 Gauss points is
+// expanded in Legendre modes (Vinv), truncated to the modes below nd in every
+// direction and evaluated at the nd^3 Gauss points (V):
+//   M[i][a] = sum_{m < min(ns, nd)} P_m(x^nd_i) (2m+1)/2 w^ns_a P_m(x^ns_a),
+// applied in the three directions (the reference-space L2 projection when
+// nd < ns, exact interpolation otherwise).
+__global__ void __launch_bounds__(256) k_project(const double* __restrict__ Us, int nsp_s, const int* __restrict__ off_s,
+                                                const int8_t* __restrict__ p_s, double* __restrict__ Ud, int nsp_d,
+                                                const int* __restrict__ off_d, const int8_t* __restrict__ p_d) {
+  __shared__ double M[NMAX][NMAX];
+  __shared__ double u[5][NMAX * NMAX * NMAX];
+  const OpsTab<double>& O = ops<double>();
+  const int e = blockIdx.x;
+  const int ns = p_s[e] + 1, nd = p_d[e] + 1, ns3 = ns * ns * ns, nd3 = nd * nd * nd;
+  const int mm = min(ns, nd);
+  const int t = threadIdx.x;
+  if (t < nd * ns) {
+    const int i = t / ns, a = t - i * ns;
+    double s = 0.0;
+    for (int m = 0; m < mm; ++m) s += O.V[nd][i][m] * O.Vinv[ns][m][a];
+    M[i][a] = s;
+  }
+  for (int k = t; k < 5 * ns3; k += blockDim.x) {
+    const int v = k / ns3, q = k - v * ns3;
+    u[v][q] = Us[(long)v * nsp_s + off_s[e] + q];
+  }
+  __syncthreads();
+  if (t >= nd3) return;
+  const int i0 = t % nd, i1 = (t / nd) % nd, i2 = t / (nd * nd);
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int c = 0; c < ns; ++c)
+    for (int b = 0; b < ns; ++b) {
+      const double mbc = M[i2][c] * M[i1][b];
+      for (int a = 0; a < ns; ++a) {
+        const double w = mbc * M[i0][a];
+        const int q = a + ns * (b + ns * c);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[v] += w * u[v][q];
+      }
+    }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) Ud[(long)v * nsp_d + off_d[e] + t] = acc[v];
+}
+
+}  // namespace frx

@@ -37,4 +37,30 @@ hipError_t launch_indicator(const MeshDev& M, const double* U, int var, double* 
   hipLaunchKernelGGL(k_max, dim3(1), dim3(256), 0, s, eta, M.E, eta_max);
   return hipGetLastError();
 }
+hipError_t launch_select_degrees(const MeshDev& M, const double* U, int var, double nu_max, double nu_min, int p_min,
+                                 int p_max, int8_t* p_new, hipStream_t s) {
+  double* eta = M.eta_w;
+  double* eta_max = M.eta_w + M.E;
+  hipError_t e = launch_indicator(M, U, var, eta, eta_max, s);
+  if (e != hipSuccess) return e;
+  const int grid = (M.E + 255) / 256;
+  int8_t* a = M.psel;
+  int8_t* b = M.psel + M.E;
+  hipLaunchKernelGGL(k_select, dim3(grid), dim3(256), 0, s, (const double*)eta, (const double*)eta_max,
+                     (const int8_t*)M.p_dev, M.E, nu_max, nu_min, p_min, p_max, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int it = 0; it < p_max - p_min; ++it) {
+    hipLaunchKernelGGL(k_limit, dim3(grid), dim3(256), 0, s, (const int8_t*)a, (const int*)M.nbr, M.E, b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    std::swap(a, b);
+  }
+  return hipMemcpyAsync(p_new, a, M.E, hipMemcpyDeviceToDevice, s);
+}
+
+hipError_t launch_project(const MeshDev& Ms, const double* Us, const MeshDev& Md, double* Ud, hipStream_t s) {
+  hipLaunchKernelGGL(k_project, dim3(Ms.E), dim3(256), 0, s, Us, Ms.nsp, (const int*)Ms.sp_off,
+                     (const int8_t*)Ms.p_dev, Ud, Md.nsp, (const int*)Md.sp_off, (const int8_t*)Md.p_dev);
+  return hipGetLastError();
+}
+
 }  // namespace frx

@@ -939,6 +939,12 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
       M.gas_f.ff[v] = (float)d->farfield[v];
     }
     M.facebuf = C->dalloc(30L * nfp * 16);
+    M.p_dev = (int8_t*)C->dalloc(E);
+    FRX_TRY(hipMemcpy(M.p_dev, d->elem_p, E, hipMemcpyHostToDevice));
+    M.nbr = (int*)C->dalloc(sizeof(int) * 6L * E);
+    FRX_TRY(hipMemcpy(M.nbr, d->elem_nbr, sizeof(int) * 6L * E, hipMemcpyHostToDevice));
+    M.eta_w = (double*)C->dalloc(sizeof(double) * (E + 1));
+    M.psel = (int8_t*)C->dalloc(2L * E);
     M.flag = (int*)C->dalloc(sizeof(int) * 4);
     FRX_TRY(hipMemset(M.flag, 0, sizeof(int) * 4));
     C->t0 = (double*)C->dalloc(sizeof(double) * C->ndof);
@@ -1141,6 +1147,29 @@ fr_status spectral_decay_indicator(fr_ctx c, const double* U, int32_t var, doubl
   if (!U || !eta || !eta_max || var < 0 || var > 4) return fail(c, FR_E_INVALID, "spectral_decay_indicator: bad arguments");
   return guarded(c, [&]() -> fr_status {
     FRX_TRY(launch_indicator(c->M, U, var, eta, eta_max, S(stream)));
+    return FR_OK;
+  });
+}
+
+fr_status fr_select_degrees(fr_ctx c, const double* U, int32_t var, double nu_max, double nu_min, int32_t p_min,
+                            int32_t p_max, int8_t* p_new, void* stream) {
+  if (!c) return FR_E_INVALID;
+  if (!U || !p_new || var < 0 || var > 4 || p_min < 1 || p_max > 5 || p_min > p_max || !(nu_min >= 0.0) ||
+      !(nu_max >= nu_min))
+    return fail(c, FR_E_INVALID, "fr_select_degrees: bad arguments");
+  return guarded(c, [&]() -> fr_status {
+    FRX_TRY(launch_select_degrees(c->M, U, var, nu_max, nu_min, p_min, p_max, p_new, S(stream)));
+    return FR_OK;
+  });
+}
+
+fr_status fr_project(fr_ctx src, const double* U_src, fr_ctx dst, double* U_dst, void* stream) {
+  if (!src || !dst) return FR_E_INVALID;
+  if (!U_src || !U_dst || (const double*)U_dst == U_src) return fail(dst, FR_E_INVALID, "fr_project: bad arguments");
+  if (src->M.E != dst->M.E || src->dev != dst->dev)
+    return fail(dst, FR_E_INVALID, "fr_project: the two contexts must hold the same mesh on the same device");
+  return guarded(dst, [&]() -> fr_status {
+    FRX_TRY(launch_project(src->M, U_src, dst->M, U_dst, S(stream)));
     return FR_OK;
   });
 }

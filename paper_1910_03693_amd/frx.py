@@ -25,7 +25,8 @@ FR_LAUNCH_PER_BUCKET, FR_LAUNCH_FUSED = 0, 1
 STATUS_NAMES = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_NOMEM", -3: "FR_E_HIP", -4: "FR_E_NOTCONVERGED",
                 -5: "FR_E_NONPHYSICAL", -6: "FR_E_UNSUPPORTED"}
 EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_residual", "fr_jvp", "fr_vjp", "gmres_stage_solve",
-            "esdirk_step", "spectral_decay_indicator", "fr_autotune", "fr_profile", "fr_set_launch", "fr_check", "fr_last_error")
+            "esdirk_step", "spectral_decay_indicator", "fr_select_degrees", "fr_project", "fr_autotune", "fr_profile",
+            "fr_set_launch", "fr_check", "fr_last_error")
 
 
 class FrError(RuntimeError):
@@ -88,6 +89,8 @@ def lib():
                                         C.POINTER(fr_gmres_stats), vp]
         L.esdirk_step.argtypes = [vp, vp, C.c_double, C.POINTER(fr_step_opts), C.POINTER(fr_step_stats), vp]
         L.spectral_decay_indicator.argtypes = [vp, vp, C.c_int32, vp, vp, vp]
+        L.fr_select_degrees.argtypes = [vp, vp, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32, vp, vp]
+        L.fr_project.argtypes = [vp, vp, vp, vp, vp]
         L.fr_autotune.argtypes = [vp, vp, vp]
         L.fr_check.argtypes = [vp, C.POINTER(C.c_int32), vp]
         L.fr_set_launch.argtypes = [vp, C.c_int32]
@@ -210,6 +213,16 @@ def spectral_decay_indicator(h, U, var, eta, eta_max, stream=None):
                                                  _dev(eta_max, torch.float64, 1), _stream(stream)), h)
 
 
+def fr_select_degrees(h, U, var, nu_max, nu_min, p_min, p_max, p_new, stream=None):
+    return _check(lib().fr_select_degrees(h, _dev(U, torch.float64), var, nu_max, nu_min, p_min, p_max,
+                                          _dev(p_new, torch.int8), _stream(stream)), h)
+
+
+def fr_project(h_src, U_src, h_dst, U_dst, stream=None):
+    return _check(lib().fr_project(h_src, _dev(U_src, torch.float64), h_dst, _dev(U_dst, torch.float64),
+                                   _stream(stream)), h_dst)
+
+
 def fr_autotune(h, U, stream=None):
     return _check(lib().fr_autotune(h, _dev(U, torch.float64), _stream(stream)), h)
 
@@ -291,6 +304,19 @@ class Context:
         mx = torch.empty(1, dtype=torch.float64, device=U.device)
         spectral_decay_indicator(self.h, U, var, eta, mx)
         return eta, mx
+
+    def select_degrees(self, U, var=1, nu_max=0.1, nu_min=0.001, p_min=1, p_max=5):
+        """Device int8 tensor [n_elem] of the degrees chosen by the criteria
+        and the face limiter of section 3.1."""
+        p = torch.empty(self.n_elem, dtype=torch.int8, device=U.device)
+        fr_select_degrees(self.h, U, var, nu_max, nu_min, p_min, p_max, p)
+        return p
+
+    def project_to(self, U, dst):
+        """U (this context's layout) moved to the context `dst` (same mesh)."""
+        out = torch.empty((5, dst.n_dof // 5), dtype=torch.float64, device=U.device)
+        fr_project(self.h, U, dst.h, out)
+        return out
 
     def autotune(self, U):
         fr_autotune(self.h, U)
