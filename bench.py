@@ -88,7 +88,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB five times (reference for the HBM byte counters)")
-    ap.add_argument("--study", choices=("c3", "c5"), default=None,
+    ap.add_argument("--study", choices=("c3", "c5", "c3adapt"), default=None,
                     help="instead of the headline: the implicit-step comparison on the 64x64x8 vortex street "
                          "(c3, degrees from the indicator) or the 128x128x8 Re 60000 box (c5)")
     args = ap.parse_args()
@@ -97,7 +97,8 @@ def main():
               "measured on a single MI355X, with no collectives).", file=sys.stderr)
         sys.exit(2)
     if args.study:
-        print(json.dumps(step_study(args.study)), flush=True)
+        res = adaptive_study() if args.study == "c3adapt" else step_study(args.study)
+        print(json.dumps(res), flush=True)
         return
 
     import torch
@@ -330,6 +331,45 @@ def implicit_steps(ctx, case, U, frx, torch):
     res["rel_change_of_step"] = (outs["plain_f64_fd"] - U).norm().item() / U.norm().item()
     res["speedup_mixed_vs_plain"] = round(res["plain_f64_fd"]["ms"] / res["mixed_f32_exact_graph"]["ms"], 3)
     return res
+
+
+def adaptive_study(steps=4):
+    """The paper's loop on the 64x64x8 vortex street: starting from the
+    indicator's degree field, each time step is one implicit ESDIRK2 step
+    (mixed form) followed by one p-adaptation on the device (indicator,
+    criteria, face limiter, new degree buckets, projected state)."""
+    import torch
+
+    from paper_1910_03693_amd import adapt, frx
+    from paper_1910_03693_amd import inputs as I
+
+    p, _ = adapt.indicator_degree_field(lambda ep: I.case_street(elem_p=ep))
+    case = I.case_street(elem_p=p)
+    ctx = frx.Context.from_case(case)
+    ctx.set_launch(True)
+    U = torch.tensor(case.U, device="cuda")
+    dt = 0.05
+    common = dict(dtau_init=0.005, dtau_max=0.05, tol_pseudo=1e-4, max_ptc_iter=50)
+    g = dict(restart=30, max_iter=100, tol=1e-1, precision=frx.FR_F32, use_graph=True)
+    out = {"study": "c3adapt", "dt": dt, "settings": {**common, **g}, "steps": []}
+    for k in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ctx.esdirk_step(U, dt, gmres=g, **common)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        case, ctx2, U = adapt.adapt_step(case, ctx, U)
+        ctx2.set_launch(True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ctx.close()
+        ctx = ctx2
+        rec = {"step_ms": round((t1 - t0) * 1e3, 1), "adapt_ms": round((t2 - t1) * 1e3, 1), **st,
+               "n_dof_after": int(ctx.n_dof),
+               "degree_histogram_p1_to_p5_after": np.bincount(case.elem_p, minlength=6)[1:].tolist()}
+        out["steps"].append(rec)
+        print(f"[bench] c3adapt step {k}: {rec}", file=sys.stderr, flush=True)
+    return out
 
 
 def step_study(which):
