@@ -131,6 +131,13 @@ fr_status fr_layout(fr_ctx ctx, int64_t* n_dof, int64_t* sp_offset);
  * U, R: device [5][n_sp] float64.  R must not alias U. */
 fr_status fr_residual(fr_ctx ctx, const double* U, double* R, void* stream);
 
+/* R(U) and the exact tangent J(U) v in float64 from one forward-mode pass:
+ * the dual-number residual kernels carry the residual in their value part and
+ * the tangent in their derivative part (as a forward-mode derivative returns
+ * the primal with the tangent).  U, v, R, Jv: device [5][n_sp] float64; R and
+ * Jv must be distinct and alias neither input. */
+fr_status fr_residual_jvp(fr_ctx ctx, const double* U, const double* v, double* R, double* Jv, void* stream);
+
 /* Jv = dR/dU(U) v.  FR_JV_EXACT: forward-mode (dual-number) residual kernels;
  * precision FR_F64: v, Jv float64; FR_F32: v, Jv float32, computed from a
  * float32 copy of U.  FR_JV_FD: the finite difference of section 2.3,

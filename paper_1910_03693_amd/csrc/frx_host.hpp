@@ -92,6 +92,7 @@ template <class B> struct ResCall {
   const B* U = nullptr;
   const B* V = nullptr;
   B* out = nullptr;
+  B* out_val = nullptr;  // duals: also write the value part (the residual)
   const B* in2 = nullptr;
   const B* alpha_dev = nullptr;
   B alpha = B(0), beta = B(1);

@@ -118,6 +118,7 @@ hipError_t launch_vjp(const MeshDev& M, const double* U, const double* w, double
   fa.U = U;
   fa.V = nullptr;
   fa.out = nullptr;
+  fa.out_val = nullptr;
   fa.in2 = nullptr;
   fa.alpha_dev = nullptr;
   fa.alpha = 0.0;

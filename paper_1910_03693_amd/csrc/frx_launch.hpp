@@ -173,6 +173,7 @@ hipError_t launch_residual_T(const MeshDev& M, const ResCall<base_t<T>>& c, int 
   a.U = c.U;
   a.V = c.V;
   a.out = c.out;
+  a.out_val = c.out_val;
   a.in2 = c.in2;
   a.alpha_dev = c.alpha_dev;
   a.alpha = c.alpha;

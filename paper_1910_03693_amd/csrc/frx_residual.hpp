@@ -26,14 +26,17 @@ template <class T> struct IO;
 template <> struct IO<double> {
   static __device__ __forceinline__ double load(const double* U, const double*, long i) { return U[i]; }
   static __device__ __forceinline__ double out(double x) { return x; }
+  static __device__ __forceinline__ double value(double x) { return x; }
 };
 template <> struct IO<float> {
   static __device__ __forceinline__ float load(const float* U, const float*, long i) { return U[i]; }
   static __device__ __forceinline__ float out(float x) { return x; }
+  static __device__ __forceinline__ float value(float x) { return x; }
 };
 template <class B> struct IO<Dual<B>> {
   static __device__ __forceinline__ Dual<B> load(const B* U, const B* V, long i) { return Dual<B>(U[i], V[i]); }
   static __device__ __forceinline__ B out(Dual<B> x) { return x.d; }
+  static __device__ __forceinline__ B value(Dual<B> x) { return x.v; }
 };
 
 template <class T> struct ResArgs {
@@ -41,6 +44,7 @@ template <class T> struct ResArgs {
   const B* U;      // state [5][nsp]
   const B* V;      // tangent direction [5][nsp] (dual scalars only)
   B* out;          // output [5][nsp]: out = alpha * in2 + beta * result
+  B* out_val;      // optional (dual scalars): the value part of the result, i.e. R(U)
   const B* in2;    // optional second input of the epilogue
   const B* alpha_dev;  // if set, alpha is read from device memory
   B alpha, beta;
@@ -595,9 +599,11 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int4* __rest
     const B alpha = a.alpha_dev ? *a.alpha_dev : a.alpha;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      const B r = IO<T>::out(acc[v] * mJ);
+      const T res = acc[v] * mJ;
+      const B r = IO<T>::out(res);
       const long idx = (long)v * a.nsp + off;
       a.out[idx] = a.in2 ? alpha * a.in2[idx] + a.beta * r : a.beta * r;
+      if (a.out_val) a.out_val[idx] = IO<T>::value(res);
     }
   }
 }

@@ -987,6 +987,22 @@ fr_status fr_residual(fr_ctx c, const double* U, double* R, void* stream) {
   });
 }
 
+fr_status fr_residual_jvp(fr_ctx c, const double* U, const double* v, double* R, double* Jv, void* stream) {
+  if (!c) return FR_E_INVALID;
+  if (!U || !v || !R || !Jv || (const double*)R == U || (const double*)Jv == v || R == Jv ||
+      (const double*)R == v || (const double*)Jv == U)
+    return fail(c, FR_E_INVALID, "fr_residual_jvp: bad arguments");
+  return guarded(c, [&]() -> fr_status {
+    ResCall<double> rc;
+    rc.U = U;
+    rc.V = v;
+    rc.out = Jv;
+    rc.out_val = R;
+    FRX_TRY(launch_residual_dual64(c->M, rc, S(stream)));
+    return FR_OK;
+  });
+}
+
 fr_status fr_jvp(fr_ctx c, const double* U, const void* v, void* Jv, int32_t prec, int32_t mode, double eps,
                  void* stream) {
   if (!c) return FR_E_INVALID;

@@ -24,7 +24,7 @@ FR_JV_EXACT, FR_JV_FD = 0, 1
 FR_LAUNCH_PER_BUCKET, FR_LAUNCH_FUSED = 0, 1
 STATUS_NAMES = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_NOMEM", -3: "FR_E_HIP", -4: "FR_E_NOTCONVERGED",
                 -5: "FR_E_NONPHYSICAL", -6: "FR_E_UNSUPPORTED"}
-EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_residual", "fr_jvp", "fr_vjp", "gmres_stage_solve",
+EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_residual", "fr_residual_jvp", "fr_jvp", "fr_vjp", "gmres_stage_solve",
             "esdirk_step", "spectral_decay_indicator", "fr_select_degrees", "fr_project", "fr_autotune", "fr_profile",
             "fr_set_launch", "fr_check", "fr_last_error")
 
@@ -85,6 +85,7 @@ def lib():
         L.fr_residual.argtypes = [vp, vp, vp, vp]
         L.fr_jvp.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_double, vp]
         L.fr_vjp.argtypes = [vp, vp, vp, vp, vp]
+        L.fr_residual_jvp.argtypes = [vp, vp, vp, vp, vp, vp]
         L.gmres_stage_solve.argtypes = [vp, vp, C.c_double, vp, vp, C.POINTER(fr_gmres_opts),
                                         C.POINTER(fr_gmres_stats), vp]
         L.esdirk_step.argtypes = [vp, vp, C.c_double, C.POINTER(fr_step_opts), C.POINTER(fr_step_stats), vp]
@@ -213,6 +214,12 @@ def spectral_decay_indicator(h, U, var, eta, eta_max, stream=None):
                                                  _dev(eta_max, torch.float64, 1), _stream(stream)), h)
 
 
+def fr_residual_jvp(h, U, v, R, Jv, stream=None):
+    n = U.numel()
+    return _check(lib().fr_residual_jvp(h, _dev(U, torch.float64), _dev(v, torch.float64, n), _dev(R, torch.float64, n),
+                                        _dev(Jv, torch.float64, n), _stream(stream)), h)
+
+
 def fr_select_degrees(h, U, var, nu_max, nu_min, p_min, p_max, p_new, stream=None):
     return _check(lib().fr_select_degrees(h, _dev(U, torch.float64), var, nu_max, nu_min, p_min, p_max,
                                           _dev(p_new, torch.int8), _stream(stream)), h)
@@ -304,6 +311,13 @@ class Context:
         mx = torch.empty(1, dtype=torch.float64, device=U.device)
         spectral_decay_indicator(self.h, U, var, eta, mx)
         return eta, mx
+
+    def residual_jvp(self, U, v, R=None, Jv=None):
+        """(R(U), J(U) v) in float64 from one forward-mode pass."""
+        R = torch.empty_like(U) if R is None else R
+        Jv = torch.empty_like(U) if Jv is None else Jv
+        fr_residual_jvp(self.h, U, v, R, Jv)
+        return R, Jv
 
     def select_degrees(self, U, var=1, nu_max=0.1, nu_min=0.001, p_min=1, p_max=5):
         """Device int8 tensor [n_elem] of the degrees chosen by the criteria

@@ -114,6 +114,25 @@ def test_exact_jvp_parity_small(frx, oracle_mod, name, fused):
     assert e32 <= 1e-4
 
 
+@pytest.mark.parametrize("fused", [False, True], ids=["per_bucket", "fused"])
+@pytest.mark.parametrize("name", ["mixed_p1to5_ns_roe", "wall_farfield_ns_roe", "mixed_p1to5_euler_roe"])
+def test_residual_and_tangent_in_one_pass(frx, oracle_mod, name, fused):
+    """fr_residual_jvp: the value part of the dual-number pass is the float64
+    residual (to the oracle's tolerance, and to the separate residual call),
+    its derivative part the exact tangent."""
+    print("case", name, "fused", fused, flush=True)
+    case = CASES[name]
+    orc, ctx, U = _pair(frx, oracle_mod, case)
+    ctx.set_launch(fused)
+    v = I.random_direction(case.U.size, 4100 + len(name)).reshape(case.U.shape)
+    R, Jv = ctx.residual_jvp(U, torch.tensor(v, device="cuda"))
+    torch.cuda.synchronize()
+    _full_size_residual_check(R.cpu().numpy(), orc, case, name + " residual (one pass)")
+    assert rel_err(Jv.cpu().numpy(), orc.jvp(case.U, v)) <= 1e-12
+    R1 = ctx.residual(U).cpu().numpy()
+    assert rel_err(R.cpu().numpy(), R1) <= 1e-13
+
+
 @pytest.fixture(scope="module")
 def c2(frx, oracle_mod):
     case = I.config(2)
@@ -148,6 +167,18 @@ def test_residual_parity_ns_mixed_32x32x4(frx, c2, fused):
     R = ctx.residual(U)
     torch.cuda.synchronize()
     _full_size_residual_check(R.cpu().numpy(), orc, case, "c2 residual")
+
+
+def test_residual_and_tangent_in_one_pass_32x32x4(frx, c2):
+    case, orc, ctx, U = c2
+    ctx.set_launch(True)
+    v = I.random_direction(case.U.size, 4002).reshape(case.U.shape)
+    R, Jv = ctx.residual_jvp(U, torch.tensor(v, device="cuda"))
+    torch.cuda.synchronize()
+    _full_size_residual_check(R.cpu().numpy(), orc, case, "c2 residual (one pass)")
+    err = rel_err(Jv.cpu().numpy(), orc.jvp(case.U, v))
+    print("c2 one-pass tangent rel err", err)
+    assert err <= 1e-12
 
 
 @pytest.mark.parametrize("fused", [False, True], ids=["per_bucket", "fused"])
