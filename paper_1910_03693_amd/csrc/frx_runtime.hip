@@ -209,15 +209,17 @@ void default_shapes(MeshDev& M, int sk) {
 
 // ===================================================================== context
 struct GraphKey {
-  int mode, prec, m, j0;  // Arnoldi iterations j0 .. j0 + ARNOLDI_CHUNK - 1 of a GMRES(m) cycle
+  int mode, prec, m, j0, j1;  // Arnoldi iterations j0 .. j1 - 1 of a GMRES(m) cycle
   bool operator<(const GraphKey& o) const {
-    return std::tie(mode, prec, m, j0) < std::tie(o.mode, o.prec, o.m, o.j0);
+    return std::tie(mode, prec, m, j0, j1) < std::tie(o.mode, o.prec, o.m, o.j0, o.j1);
   }
 };
-// Arnoldi iterations per captured graph.  Between two graphs the host reads
-// the device's converged flag, so a converged cycle stops within this many
-// iterations instead of replaying skipped kernels up to m.
-constexpr int ARNOLDI_CHUNK = 6;
+// Captured Arnoldi graphs cover the first `k` iterations of a cycle, k = the
+// iterations the previous cycle of the same (mode, precision, m) needed, then
+// ARNOLDI_CHUNK iterations at a time.  Between two graphs the host reads the
+// device's converged flag, so a converged cycle stops early instead of
+// replaying skipped kernels up to m.
+constexpr int ARNOLDI_CHUNK = 3;
 
 struct fr_ctx_s {
   MeshDev M;
@@ -253,6 +255,7 @@ struct fr_ctx_s {
   double* H = nullptr;    // Hessenberg etc. (one block)
   float* sigf = nullptr;  // float copy of the shift
   std::map<GraphKey, hipGraphExec_t> graphs;
+  std::map<std::tuple<int, int, int>, int> cycle_iters;  // (mode, precision, m) -> iterations of the last cycle
   // ESDIRK workspace
   double* es = nullptr;   // 8 x ndof
   // VJP workspace
@@ -539,9 +542,12 @@ void arnoldi_cycle(fr_ctx c, int mode, int m, double eps, bool use_graph, hipStr
     for (int j = 0; j < m; ++j) arnoldi_step<TV>(c, mode, m, j, eps, s);
     return;
   }
-  for (int j0 = 0; j0 < m; j0 += ARNOLDI_CHUNK) {
-    const int j1 = std::min(m, j0 + ARNOLDI_CHUNK);
-    GraphKey key{mode, (int)sizeof(TV), m, j0};
+  const auto ck = std::make_tuple(mode, (int)sizeof(TV), m);
+  auto pit = c->cycle_iters.find(ck);
+  const int first = std::max(1, std::min(m, pit == c->cycle_iters.end() ? ARNOLDI_CHUNK : pit->second));
+  for (int j0 = 0; j0 < m;) {
+    const int j1 = std::min(m, j0 == 0 ? first : j0 + ARNOLDI_CHUNK);
+    GraphKey key{mode, (int)sizeof(TV), m, j0, j1};
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
       if (!c->cap) FRX_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
@@ -565,11 +571,18 @@ void arnoldi_cycle(fr_ctx c, int mode, int m, double eps, bool use_graph, hipStr
     }
     FRX_TRY(hipGraphLaunch(it->second, s));
     if (j1 < m) {
-      FRX_TRY(hipMemcpyAsync(c->ipin + 8, c->ist, sizeof(int), hipMemcpyDeviceToHost, s));
+      FRX_TRY(hipMemcpyAsync(c->ipin + 8, c->ist, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
       FRX_TRY(hipStreamSynchronize(s));
       if (c->ipin[8]) break;
     }
+    j0 = j1;
   }
+}
+
+// Iterations of the cycle just finished (read by gmres_run after its
+// synchronisation) sizes the first graph of the next cycle.
+void note_cycle(fr_ctx c, int mode, int prec_bytes, int m, int iters) {
+  c->cycle_iters[std::make_tuple(mode, prec_bytes, m)] = iters;
 }
 
 // Restarted GMRES on the device.  x (float64, device) receives the solution.
@@ -629,6 +642,7 @@ fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats*
     ++cycles;
     total = c->ipin[2];
     res = c->hpin[3];
+    if (o.use_graph) note_cycle(c, o.jv_mode, (int)sizeof(TV), m, c->ipin[1]);
     if (res <= o.tol * nF) {
       conv = true;
       break;
