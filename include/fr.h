@@ -217,6 +217,14 @@ fr_status fr_profile(fr_ctx ctx, const double* U, int32_t op, int32_t reps, fr_k
  * FR_LAUNCH_FUSED: each stage is one launch over all buckets, its blocks
  * ordered by decreasing work (the degree-bucketed work queue). */
 enum { FR_LAUNCH_PER_BUCKET = 0, FR_LAUNCH_FUSED = 1 };
+/* Optional flags or-ed into the mode (Navier-Stokes only; without either,
+ * the current choice for that launch mode is kept, which fr_autotune makes
+ * per scalar kind by timing):
+ * FR_LAUNCH_FACES_TWO_PASS: the interior-face stage runs as two kernels, the
+ * inviscid common flux and then the viscous correction (each needs about half
+ * the registers of the one-pass face kernel);
+ * FR_LAUNCH_FACES_ONE_PASS: one kernel for both (the default). */
+enum { FR_LAUNCH_FACES_TWO_PASS = 4, FR_LAUNCH_FACES_ONE_PASS = 8 };
 fr_status fr_set_launch(fr_ctx ctx, int32_t mode);
 
 /* Reads and clears the non-physical-state flag (synchronises the stream). */

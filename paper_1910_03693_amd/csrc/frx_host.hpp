@@ -59,6 +59,7 @@ struct FusedPlan {
   int4* tiles[3] = {nullptr, nullptr, nullptr};  // trace, face, div
   int count[3] = {0, 0, 0};
   size_t lds[3] = {0, 0, 0};
+  int n_interior = 0;  // face stage: interior-face tiles come first, boundary-face tiles after them
 };
 
 struct MeshDev {
@@ -80,6 +81,9 @@ struct MeshDev {
   int8_t* psel = nullptr;         // [2 E] degree-selection ping-pong buffers
   ProfHook* prof = nullptr;
   bool fused = false;             // one launch per stage over all buckets
+  // Navier-Stokes face stage in two passes (inviscid, then viscous correction),
+  // per launch mode [per-bucket, fused] and scalar kind; chosen by fr_autotune
+  bool split_faces[2][SK_COUNT] = {{false, false, false}, {false, false, false}};
   int4* all_elems = nullptr;      // concatenated bucket element records
   int4* all_faces = nullptr;      // concatenated interior + boundary face lists
   FusedPlan plan[SK_COUNT];

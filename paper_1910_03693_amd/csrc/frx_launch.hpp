@@ -55,6 +55,15 @@ hipError_t run_face(const ResArgs<T>& a, const FaceBucket& b, int fpb, hipStream
                      s, a, b.faces, b.count, fpb);
   return hipGetLastError();
 }
+template <int NL, int NH, class T>
+hipError_t run_face_visc(const ResArgs<T>& a, const FaceBucket& b, int fpb, hipStream_t s) {
+  const int grid = (b.count + fpb - 1) / fpb;
+  if (!block_ok(round64(fpb * NH * NH))) return hipErrorInvalidConfiguration;
+  const size_t lds = NL < NH ? (size_t)fpb * (20 * NL * NL + 4 * NH * NH) * sizeof(T) : 0;
+  hipLaunchKernelGGL((k_face_visc<NL, NH, T>), dim3(grid), dim3(round64(fpb * NH * NH)), lds, s, a, b.faces, b.count,
+                     fpb);
+  return hipGetLastError();
+}
 template <int N, class T, bool NS>
 hipError_t run_bface(const ResArgs<T>& a, const BFaceBucket& b, hipStream_t s) {
   const int tot = b.count * N * N;
@@ -114,6 +123,30 @@ hipError_t face_n(const ResArgs<T>& a, const FaceBucket& b, int fpb, hipStream_t
   }
 }
 
+template <class T, int NL>
+hipError_t face_visc_nh(const ResArgs<T>& a, const FaceBucket& b, int fpb, hipStream_t s) {
+  switch (b.nh) {
+    case 2: if constexpr (NL <= 2) return run_face_visc<NL, 2, T>(a, b, fpb, s); break;
+    case 3: if constexpr (NL <= 3) return run_face_visc<NL, 3, T>(a, b, fpb, s); break;
+    case 4: if constexpr (NL <= 4) return run_face_visc<NL, 4, T>(a, b, fpb, s); break;
+    case 5: if constexpr (NL <= 5) return run_face_visc<NL, 5, T>(a, b, fpb, s); break;
+    case 6: return run_face_visc<NL, 6, T>(a, b, fpb, s);
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+template <class T>
+hipError_t face_visc_n(const ResArgs<T>& a, const FaceBucket& b, int fpb, hipStream_t s) {
+  switch (b.nl) {
+    case 2: return face_visc_nh<T, 2>(a, b, fpb, s);
+    case 3: return face_visc_nh<T, 3>(a, b, fpb, s);
+    case 4: return face_visc_nh<T, 4>(a, b, fpb, s);
+    case 5: return face_visc_nh<T, 5>(a, b, fpb, s);
+    case 6: return face_visc_nh<T, 6>(a, b, fpb, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <class T, bool NS>
 hipError_t residual_stages(const ResArgs<T>& a, const MeshDev& M, int sk, hipStream_t s) {
   hipError_t e;
@@ -124,10 +157,16 @@ hipError_t residual_stages(const ResArgs<T>& a, const MeshDev& M, int sk, hipStr
     if ((e = trace_n<T, NS>(a, b, b.epb_trace[sk], s)) != hipSuccess) return e;
     if (P) P->end(s);
   }
+  const bool split = NS && M.split_faces[0][sk];
   for (const FaceBucket& b : M.fb) {
     if (!b.count) continue;
     if (P) P->begin("k_face", b.nl, b.nh, b.count, s);
-    if ((e = face_n<T, NS>(a, b, b.fpb[sk], s)) != hipSuccess) return e;
+    if (split) {
+      if ((e = face_n<T, false>(a, b, b.fpb[sk], s)) != hipSuccess) return e;
+      if ((e = face_visc_n<T>(a, b, b.fpb[sk], s)) != hipSuccess) return e;
+    } else if ((e = face_n<T, NS>(a, b, b.fpb[sk], s)) != hipSuccess) {
+      return e;
+    }
     if (P) P->end(s);
   }
   for (const BFaceBucket& b : M.bb) {
@@ -150,16 +189,30 @@ hipError_t residual_fused(const ResArgs<T>& a, const MeshDev& M, int sk, hipStre
   const FusedPlan& P = M.plan[sk];
   ProfHook* H = M.prof;
   const char* names[3] = {"k_trace_fused", "k_face_fused", "k_div_fused"};
+  hipError_t e;
   for (int st = 0; st < 3; ++st) {
     if (!P.count[st]) continue;
     if (H) H->begin(names[st], 0, 0, P.count[st], s);
     if (st == 0)
       hipLaunchKernelGGL((k_trace_fused<T, NS>), dim3(P.count[0]), dim3(256), P.lds[0], s, a, M.all_elems, P.tiles[0]);
-    else if (st == 1)
+    else if (st == 1 && NS && M.split_faces[1][sk]) {
+      // two-pass face stage: interior tiles (first n_interior), then boundary tiles
+      if (P.n_interior > 0) {
+        hipLaunchKernelGGL((k_face_split_fused<T, 0>), dim3(P.n_interior), dim3(256), P.lds[1], s, a, M.all_faces,
+                           P.tiles[1]);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_face_split_fused<T, 1>), dim3(P.n_interior), dim3(256), P.lds[1], s, a, M.all_faces,
+                           P.tiles[1]);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+      if (P.count[1] > P.n_interior)
+        hipLaunchKernelGGL((k_bface_fused<T, NS>), dim3(P.count[1] - P.n_interior), dim3(256), 0, s, a, M.all_faces,
+                           P.tiles[1] + P.n_interior);
+    } else if (st == 1)
       hipLaunchKernelGGL((k_face_fused<T, NS>), dim3(P.count[1]), dim3(256), P.lds[1], s, a, M.all_faces, P.tiles[1]);
     else
       hipLaunchKernelGGL((k_div_fused<T, NS>), dim3(P.count[2]), dim3(256), P.lds[2], s, a, M.all_elems, P.tiles[2]);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (H) H->end(s);
   }

@@ -436,6 +436,140 @@ __device__ __forceinline__ void bface_body(const ResArgs<T>& a, const int4* __re
   }
 }
 
+// ------------------------------------------------- viscous face correction
+// Navier-Stokes interior faces in two passes: the inviscid pass is face_body
+// with the Euler flag (common solution, jumps, f_inv . S), this pass
+// subtracts the viscous common flux (eq. com_grad_q and the viscous part of
+// f_com . S) from the face slots it wrote.  Each pass needs about half the
+// registers of the one-pass face function, so both run two waves per SIMD.
+// The low side of a mixed face receives the L2 projection of the viscous flux
+// (the projection is linear, so the two passes together give the projection
+// of the full flux).  LDS: [fpb][20][NL2] low-side q and gradient traces,
+// [fpb][4][NH2] viscous flux at the high side's points.
+template <int NL, int NH, class T>
+__device__ __forceinline__ void face_visc_body(const ResArgs<T>& a, const int4* __restrict__ faces, int nf, int fpb,
+                                               int blk, unsigned char* smem) {
+  using B = base_t<T>;
+  constexpr int NH2 = NH * NH, NL2 = NL * NL;
+  constexpr bool MIX = NL < NH;
+  T* slow = reinterpret_cast<T*>(smem);           // [fpb][20][NL2]
+  T* sout = slow + (MIX ? fpb * 20 * NL2 : 0);     // [fpb][4][NH2]
+  const OpsTab<B>& O = ops<B>();
+  const int tid = threadIdx.x;
+  const int lf = tid / NH2, pt = tid - lf * NH2;
+  const int fi = blk * fpb + lf;
+  const bool act = lf < fpb && fi < nf;
+  const FaceRec F = face_rec(act ? faces[fi] : make_int4(0, 0, 0, 0));
+  const bool lowR = MIX && F.low_is_R;
+  const bool lowL = MIX && !F.low_is_R;
+  if (MIX) {
+    for (int it = tid; it < fpb * 20 * NL2; it += blockDim.x) {
+      const int l2 = it / (20 * NL2), rem = it - l2 * 20 * NL2;
+      const int vv = rem / NL2, p2 = rem - vv * NL2;
+      const int f2 = blk * fpb + l2;
+      if (f2 >= nf) continue;
+      const FaceRec G2 = face_rec(faces[f2]);
+      const long o = (G2.low_is_R ? G2.oR : G2.oL) + p2;
+      slow[it] = vv < 5 ? a.QF[(long)vv * a.nfp + o] : a.GF[(long)(vv - 5) * a.nfp + o];
+    }
+    __syncthreads();
+  }
+  const int A = pt % NH, Bq = pt / NH;
+  T fv[4];
+  if (act) {
+    T q[2][5], g[5][3];
+#pragma unroll
+    for (int vc = 0; vc < 15; ++vc) g[vc / 3][vc % 3] = T(B(0));
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const bool low = s ? lowR : lowL;
+      if (low) {
+        const T* src = slow + lf * 20 * NL2;
+#pragma unroll
+        for (int vv = 0; vv < 20; ++vv) {
+          T acc = T(B(0));
+#pragma unroll
+          for (int b = 0; b < NL; ++b) {
+            T row = T(B(0));
+#pragma unroll
+            for (int aa = 0; aa < NL; ++aa) row = fmab(O.I[NL - 2][NH - 2][A][aa], src[vv * NL2 + aa + NL * b], row);
+            acc = fmab(O.I[NL - 2][NH - 2][Bq][b], row, acc);
+          }
+          if (vv < 5) q[s][vv] = acc;
+          else g[(vv - 5) / 3][(vv - 5) % 3] += acc;
+        }
+      } else {
+        const long o = (s ? F.oR : F.oL) + pt;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q[s][v] = a.QF[(long)v * a.nfp + o];
+#pragma unroll
+        for (int vc = 0; vc < 15; ++vc) g[vc / 3][vc % 3] += a.GF[(long)vc * a.nfp + o];
+      }
+    }
+    const B ta = O.x[NH][A], tb = O.x[NH][Bq];
+    B S[3], JL, SR[3], JR;
+    face_geom<B>(a.geo + 24L * F.L, F.d, B(1), ta, tb, S, JL);
+    face_geom<B>(a.geo + 24L * F.R, F.d, B(-1), ta, tb, SR, JR);
+    const int nL = lowL ? NL : NH, nR = lowR ? NL : NH;
+    const B cL = B(0.5) * B(nL * nL) / JL;
+    const B cR = -B(0.5) * B(nR * nR) / JR;
+    // common solution and the BR2 common gradient from the jumps
+    // q_com - q^- = (q^+ - q^-)/2, q_com - q^+ = -(q^+ - q^-)/2
+    T qc[5], Gc[5][3];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      qc[v] = B(0.5) * (q[0][v] + q[1][v]);
+      const T jl = qc[v] - q[0][v], jr = qc[v] - q[1][v];
+      const T lift = cL * jl + cR * jr;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Gc[v][c] = B(0.5) * (g[v][c] + S[c] * lift);
+    }
+    T tau[3][3], e[3];
+    viscous_terms<T, B>(qc, Gc, a.gas, tau, e);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fv[c] = tau[c][0] * S[0] + tau[c][1] * S[1] + tau[c][2] * S[2];
+    fv[3] = e[0] * S[0] + e[1] * S[1] + e[2] * S[2];
+    if (!lowL) {
+      const long o = F.oL + pt;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a.FS[(long)(1 + c) * a.nfp + o] = a.FS[(long)(1 + c) * a.nfp + o] - fv[c];
+    }
+    if (!lowR) {
+      const long o = F.oR + pt;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a.FS[(long)(1 + c) * a.nfp + o] = a.FS[(long)(1 + c) * a.nfp + o] - fv[c];
+    }
+    if (MIX) {
+      T* dst = sout + lf * 4 * NH2;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) dst[c * NH2 + pt] = fv[c];
+    }
+  }
+  if (MIX) {
+    __syncthreads();
+    for (int it = tid; it < fpb * NL2; it += blockDim.x) {
+      const int l2 = it / NL2, p2 = it - l2 * NL2;
+      const int f2 = blk * fpb + l2;
+      if (f2 >= nf) continue;
+      const FaceRec G2 = face_rec(faces[f2]);
+      const long o = (G2.low_is_R ? G2.oR : G2.oL) + p2;
+      const int aa = p2 % NL, bb = p2 / NL;
+      const T* src = sout + l2 * 4 * NH2;
+      for (int c = 0; c < 4; ++c) {
+        T acc = T(B(0));
+#pragma unroll
+        for (int Bq2 = 0; Bq2 < NH; ++Bq2) {
+          T row = T(B(0));
+#pragma unroll
+          for (int A2 = 0; A2 < NH; ++A2) row = fmab(O.P[NL - 2][NH - 2][aa][A2], src[c * NH2 + A2 + NH * Bq2], row);
+          acc = fmab(O.P[NL - 2][NH - 2][bb][Bq2], row, acc);
+        }
+        a.FS[(long)(1 + c) * a.nfp + o] = a.FS[(long)(1 + c) * a.nfp + o] - acc;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ div stage
 // Block: epb elements x N^3 threads.  LDS per element: a region X of 5 N^3
 // (q, then one direction of the contravariant flux at a time) and a region Y
@@ -621,6 +755,13 @@ __global__ void __launch_bounds__(FRX_MAX_THREADS) k_face(ResArgs<T> a, const in
   extern __shared__ __align__(16) unsigned char smem[];
   face_body<NL, NH, T, NS>(a, faces, nf, fpb, blockIdx.x, smem);
 }
+template <int NL, int NH, class T>
+__global__ void __launch_bounds__(FRX_MAX_THREADS) k_face_visc(ResArgs<T> a, const int4* __restrict__ faces, int nf,
+                                                               int fpb) {
+  if (a.skip && *a.skip) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  face_visc_body<NL, NH, T>(a, faces, nf, fpb, blockIdx.x, smem);
+}
 template <int N, class T, bool NS>
 __global__ void __launch_bounds__(FRX_MAX_THREADS) k_bface(ResArgs<T> a, const int4* __restrict__ faces, int nf) {
   if (a.skip && *a.skip) return;
@@ -699,6 +840,46 @@ __global__ void __launch_bounds__(FRX_MAX_THREADS) k_face_fused(ResArgs<T> a, co
   }
 }
 #undef FRX_FCASE
+#undef FRX_BCASE
+
+// Two-pass face stage of Navier-Stokes (interior-face tiles only, which the
+// plan puts first): PASS 0 the inviscid pass, PASS 1 the viscous correction.
+#define FRX_SCASE(NL, NH)                                                        \
+  case 8 * NL + NH:                                                             \
+    if constexpr (PASS == 0) face_body<NL, NH, T, false>(a, faces + t.y, t.z, t.w, 0, smem); \
+    else face_visc_body<NL, NH, T>(a, faces + t.y, t.z, t.w, 0, smem);           \
+    break;
+
+template <class T, int PASS>
+__global__ void __launch_bounds__(FRX_MAX_THREADS) k_face_split_fused(ResArgs<T> a, const int4* __restrict__ faces,
+                                                                      const int4* __restrict__ tiles) {
+  if (a.skip && *a.skip) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int4 t = tiles[blockIdx.x];
+  switch (t.x) {
+    FRX_SCASE(2, 2) FRX_SCASE(2, 3) FRX_SCASE(2, 4) FRX_SCASE(2, 5) FRX_SCASE(2, 6)
+    FRX_SCASE(3, 3) FRX_SCASE(3, 4) FRX_SCASE(3, 5) FRX_SCASE(3, 6)
+    FRX_SCASE(4, 4) FRX_SCASE(4, 5) FRX_SCASE(4, 6)
+    FRX_SCASE(5, 5) FRX_SCASE(5, 6)
+    FRX_SCASE(6, 6)
+    default: break;
+  }
+}
+#undef FRX_SCASE
+
+// Boundary-face tiles of the two-pass face stage (the plan puts them last).
+#define FRX_BCASE(N) \
+  case 64 + N: bface_body<N, T, NS>(a, faces + t.y, t.z, 0); break;
+template <class T, bool NS>
+__global__ void __launch_bounds__(FRX_MAX_THREADS) k_bface_fused(ResArgs<T> a, const int4* __restrict__ faces,
+                                                                 const int4* __restrict__ tiles) {
+  if (a.skip && *a.skip) return;
+  const int4 t = tiles[blockIdx.x];
+  switch (t.x) {
+    FRX_BCASE(2) FRX_BCASE(3) FRX_BCASE(4) FRX_BCASE(5) FRX_BCASE(6)
+    default: break;
+  }
+}
 #undef FRX_BCASE
 
 }  // namespace frx

@@ -763,8 +763,17 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
           }
         }
       }
-      std::stable_sort(tiles.begin(), tiles.end(),
-                       [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) { return x.first > y.first; });
+      // by decreasing work; in the face stage interior-face tiles (code < 64)
+      // before boundary-face tiles, so that the two-pass face stage can launch
+      // each group on its own
+      std::stable_sort(tiles.begin(), tiles.end(), [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) {
+        const bool bx = x.second.x >= 64, by = y.second.x >= 64;
+        if (bx != by) return !bx;
+        return x.first > y.first;
+      });
+      int nint = 0;
+      for (auto& x : tiles) nint += x.second.x < 64 ? 1 : 0;
+      if (st == 1) P.n_interior = nint;
       std::vector<int4> t;
       for (auto& x : tiles) t.push_back(x.second);
       P.count[st] = (int)t.size();
@@ -1205,9 +1214,22 @@ fr_status fr_project(fr_ctx src, const double* U_src, fr_ctx dst, double* U_dst,
 }
 
 fr_status fr_set_launch(fr_ctx c, int32_t mode) {
-  if (!c || (mode != FR_LAUNCH_PER_BUCKET && mode != FR_LAUNCH_FUSED)) return c ? fail(c, FR_E_INVALID, "fr_set_launch: mode") : FR_E_INVALID;
-  if (c->M.fused != (mode == FR_LAUNCH_FUSED)) {
-    c->M.fused = mode == FR_LAUNCH_FUSED;
+  if (!c) return FR_E_INVALID;
+  const int base = mode & ~(FR_LAUNCH_FACES_TWO_PASS | FR_LAUNCH_FACES_ONE_PASS);
+  if ((base != FR_LAUNCH_PER_BUCKET && base != FR_LAUNCH_FUSED) ||
+      ((mode & FR_LAUNCH_FACES_TWO_PASS) && (mode & FR_LAUNCH_FACES_ONE_PASS)))
+    return fail(c, FR_E_INVALID, "fr_set_launch: mode");
+  const bool fused = base == FR_LAUNCH_FUSED;
+  bool changed = c->M.fused != fused;
+  c->M.fused = fused;
+  if (mode & (FR_LAUNCH_FACES_TWO_PASS | FR_LAUNCH_FACES_ONE_PASS)) {
+    const bool two = (mode & FR_LAUNCH_FACES_TWO_PASS) != 0;
+    for (int sk = 0; sk < SK_COUNT; ++sk) {
+      changed = changed || c->M.split_faces[fused][sk] != two;
+      c->M.split_faces[fused][sk] = two;
+    }
+  }
+  if (changed) {
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
   }
@@ -1310,6 +1332,22 @@ fr_status fr_autotune(fr_ctx c, const double* U, void* stream) {
         }
         f.fpb[sk] = best;
       }
+    }
+    // Navier-Stokes face stage in one or two passes, per launch mode and
+    // scalar kind: the faster of the two
+    if (c->M.physics == 1) {
+      const bool fused0 = c->M.fused;
+      for (int fm = 0; fm < 2; ++fm) {
+        c->M.fused = fm == 1;
+        for (int sk = 0; sk < SK_COUNT; ++sk) {
+          c->M.split_faces[fm][sk] = false;
+          const float t1 = timed(sk);
+          c->M.split_faces[fm][sk] = true;
+          const float t2 = timed(sk);
+          c->M.split_faces[fm][sk] = t2 < t1;
+        }
+      }
+      c->M.fused = fused0;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

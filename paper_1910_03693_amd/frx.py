@@ -22,6 +22,7 @@ FR_ROE, FR_RUSANOV = 0, 1
 FR_F64, FR_F32 = 0, 1
 FR_JV_EXACT, FR_JV_FD = 0, 1
 FR_LAUNCH_PER_BUCKET, FR_LAUNCH_FUSED = 0, 1
+FR_LAUNCH_FACES_TWO_PASS, FR_LAUNCH_FACES_ONE_PASS = 4, 8
 STATUS_NAMES = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_NOMEM", -3: "FR_E_HIP", -4: "FR_E_NOTCONVERGED",
                 -5: "FR_E_NONPHYSICAL", -6: "FR_E_UNSUPPORTED"}
 EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_residual", "fr_residual_jvp", "fr_jvp", "fr_vjp", "gmres_stage_solve",
@@ -335,8 +336,14 @@ class Context:
     def autotune(self, U):
         fr_autotune(self.h, U)
 
-    def set_launch(self, fused):
-        fr_set_launch(self.h, FR_LAUNCH_FUSED if fused else FR_LAUNCH_PER_BUCKET)
+    def set_launch(self, fused, two_pass_faces=None):
+        """fused: one launch per stage over all degrees (else one per bucket);
+        two_pass_faces: True / False force the Navier-Stokes face stage into
+        two kernels / one kernel, None keeps the current (autotuned) choice."""
+        mode = FR_LAUNCH_FUSED if fused else FR_LAUNCH_PER_BUCKET
+        if two_pass_faces is not None:
+            mode |= FR_LAUNCH_FACES_TWO_PASS if two_pass_faces else FR_LAUNCH_FACES_ONE_PASS
+        fr_set_launch(self.h, mode)
 
     def profile(self, U, op=0, reps=10):
         return fr_profile(self.h, U, op, reps)

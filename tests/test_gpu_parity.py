@@ -80,26 +80,31 @@ def _pair(frx, oracle_mod, case):
     return orc, ctx, U
 
 
-@pytest.mark.parametrize("fused", [False, True], ids=["per_bucket", "fused"])
+# launch variants: (fused, two-pass Navier-Stokes face stage)
+LAUNCH = {"per_bucket": (False, False), "fused": (True, False), "per_bucket_2pass": (False, True),
+          "fused_2pass": (True, True)}
+
+
+@pytest.mark.parametrize("launch", list(LAUNCH))
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_residual_parity_small(frx, oracle_mod, name, fused):
-    print("case", name, "fused", fused, flush=True)
+def test_residual_parity_small(frx, oracle_mod, name, launch):
+    print("case", name, "launch", launch, flush=True)
     case = CASES[name]
     orc, ctx, U = _pair(frx, oracle_mod, case)
-    ctx.set_launch(fused)
+    ctx.set_launch(*LAUNCH[launch])
     R = ctx.residual(U)
     torch.cuda.synchronize()
     _full_size_residual_check(R.cpu().numpy(), orc, case, name)
     assert ctx.nonphysical() == 0
 
 
-@pytest.mark.parametrize("fused", [False, True], ids=["per_bucket", "fused"])
+@pytest.mark.parametrize("launch", list(LAUNCH))
 @pytest.mark.parametrize("name", sorted(set(CASES) - {"vortex_p2_rusanov"}))
-def test_exact_jvp_parity_small(frx, oracle_mod, name, fused):
-    print("case", name, "fused", fused, flush=True)
+def test_exact_jvp_parity_small(frx, oracle_mod, name, launch):
+    print("case", name, "launch", launch, flush=True)
     case = CASES[name]
     orc, ctx, U = _pair(frx, oracle_mod, case)
-    ctx.set_launch(fused)
+    ctx.set_launch(*LAUNCH[launch])
     v = I.random_direction(case.U.size, 4000 + len(name)).reshape(case.U.shape)
     Jv = ctx.jvp(U, torch.tensor(v, device="cuda"))
     torch.cuda.synchronize()
@@ -160,10 +165,10 @@ def _full_size_residual_check(R, orc, case, label):
     assert err_ld <= tol
 
 
-@pytest.mark.parametrize("fused", [False, True], ids=["per_bucket", "fused"])
-def test_residual_parity_ns_mixed_32x32x4(frx, c2, fused):
+@pytest.mark.parametrize("launch", list(LAUNCH))
+def test_residual_parity_ns_mixed_32x32x4(frx, c2, launch):
     case, orc, ctx, U = c2
-    ctx.set_launch(fused)
+    ctx.set_launch(*LAUNCH[launch])
     R = ctx.residual(U)
     torch.cuda.synchronize()
     _full_size_residual_check(R.cpu().numpy(), orc, case, "c2 residual")
@@ -181,10 +186,10 @@ def test_residual_and_tangent_in_one_pass_32x32x4(frx, c2):
     assert err <= 1e-12
 
 
-@pytest.mark.parametrize("fused", [False, True], ids=["per_bucket", "fused"])
-def test_jvp_parity_ns_mixed_32x32x4(frx, c2, fused):
+@pytest.mark.parametrize("launch", list(LAUNCH))
+def test_jvp_parity_ns_mixed_32x32x4(frx, c2, launch):
     case, orc, ctx, U = c2
-    ctx.set_launch(fused)
+    ctx.set_launch(*LAUNCH[launch])
     v = I.random_direction(case.U.size, 4002).reshape(case.U.shape)
     vt = torch.tensor(v, device="cuda")
     ref = orc.jvp(case.U, v)
@@ -203,9 +208,11 @@ def test_jvp_parity_ns_mixed_32x32x4(frx, c2, fused):
     assert efd <= 1e-5 and abs(efd - rel_err(ofd, ref)) <= 1e-5
 
 
-def test_residual_parity_wall_32x32x8(frx, oracle_mod):
+@pytest.mark.parametrize("launch", ["per_bucket", "fused_2pass"])
+def test_residual_parity_wall_32x32x8(frx, oracle_mod, launch):
     case = I.config(4)
     orc, ctx, U = _pair(frx, oracle_mod, case)
+    ctx.set_launch(*LAUNCH[launch])
     R = ctx.residual(U)
     torch.cuda.synchronize()
     _full_size_residual_check(R.cpu().numpy(), orc, case, "c4 residual")
