@@ -47,7 +47,7 @@ typedef enum {
   FR_E_NOMEM = -2,         /* device allocation failed */
   FR_E_HIP = -3,           /* a HIP runtime call failed */
   FR_E_NOTCONVERGED = -4,  /* solver stopped by its iteration budget */
-  FR_E_NONPHYSICAL = -5,   /* rho <= 0 or p <= 0 was met */
+  FR_E_NONPHYSICAL = -5,   /* rho <= 0, p <= 0 or a NaN of either was met */
   FR_E_UNSUPPORTED = -6
 } fr_status;
 

@@ -616,7 +616,8 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int4* __rest
     T q[5], Gq[5][3];
 #pragma unroll
     for (int v = 0; v < 5; ++v) q[v] = qs[v * N3 + k];
-    if (val(q[0]) <= B(0) || val(pressure<T, B>(q, a.gas)) <= B(0)) *a.flag = 1;
+    // (written so that a NaN density or pressure is flagged as well)
+    if (!(val(q[0]) > B(0)) || !(val(pressure<T, B>(q, a.gas)) > B(0))) *a.flag = 1;
     if (NS) {
       const T* jm = sY + le * 30 * N2;
       const B iJ = B(1) / J;

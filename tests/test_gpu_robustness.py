@@ -1,0 +1,104 @@
+"""Determinism and failure handling on the GPU.
+
+* Every reduction is a fixed-order two-level sum and no kernel uses atomics on
+  floating-point data, so repeated calls give bitwise identical results:
+  residual, tangents, one-pass residual and tangent, adjoint, GMRES with and
+  without graphs, an ESDIRK2 step.
+* Failure paths, forced from the host (no kernel is made to fault): a GMRES
+  budget too small for its tolerance returns FR_E_NOTCONVERGED with the best
+  iterate; an ESDIRK step whose GMRES budget is too small halves the pseudo
+  time step; NaN and negative densities raise the non-physical flag.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1910_03693_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def frx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_03693_amd import frx as F
+    F.lib()
+    return F
+
+
+def _case():
+    return I.case_ns_mixed(4, 4, 2, k=95, lengths=(1.0, 1.0, 0.5), wall=True, pvals=(1, 2, 3, 4), pw=(1, 1, 1, 1),
+                           re=200.0, ma=0.3)
+
+
+@pytest.mark.parametrize("fused", [False, True], ids=["per_bucket", "fused"])
+def test_repeated_calls_are_bitwise_identical(frx, fused):
+    case = _case()
+    ctx = frx.Context.from_case(case)
+    ctx.set_launch(fused)
+    U = torch.tensor(case.U, device="cuda")
+    v = torch.tensor(I.random_direction(case.U.size, 96).reshape(case.U.shape), device="cuda")
+
+    def everything():
+        out = [ctx.residual(U).clone(), ctx.jvp(U, v).clone(),
+               ctx.jvp(U, v.float(), precision=frx.FR_F32).clone(),
+               ctx.jvp(U, v, jv_mode=frx.FR_JV_FD).clone(), ctx.vjp(U, v).clone()]
+        out += [t.clone() for t in ctx.residual_jvp(U, v)]
+        for g in (False, True):
+            x, _ = ctx.gmres(U, 30.0, v, restart=10, max_iter=25, tol=0.0, use_graph=g)
+            out.append(x.clone())
+        Uw = U.clone()
+        ctx.esdirk_step(Uw, 0.01, gmres=dict(restart=20, tol=1e-3, use_graph=True), dtau_init=1e-3, dtau_max=1e-2,
+                        tol_pseudo=1e-4, max_ptc_iter=20)
+        out.append(Uw)
+        return out
+
+    a = everything()
+    b = everything()
+    for i, (x, y) in enumerate(zip(a, b)):
+        assert torch.equal(x, y), i
+
+
+def test_gmres_budget_too_small_reports_not_converged(frx):
+    case = _case()
+    ctx = frx.Context.from_case(case)
+    U = torch.tensor(case.U, device="cuda")
+    F = torch.tensor(I.random_direction(case.U.size, 97).reshape(case.U.shape), device="cuda")
+    x, st = ctx.gmres(U, 5.0, F, restart=5, max_iter=5, tol=1e-30)
+    assert st["status"] == frx.FR_E_NOTCONVERGED and not st["converged"]
+    assert st["iterations"] == 5 and 0.0 < st["rel_res"] < 1.0
+    assert torch.isfinite(x).all().item()
+
+
+def test_esdirk_small_gmres_budget_halves_pseudo_time_step(frx):
+    case = _case()
+    ctx = frx.Context.from_case(case)
+    U = torch.tensor(case.U, device="cuda")
+    st = ctx.esdirk_step(U, 0.05, gmres=dict(restart=2, max_iter=2, tol=1e-6), dtau_init=0.05, dtau_max=0.05,
+                         dtau_min=0.05 / 64, tol_pseudo=1e-4, max_ptc_iter=3)
+    print(st)
+    assert st["halvings"] > 0
+    assert st["status"] in (frx.FR_OK, frx.FR_E_NOTCONVERGED)
+
+
+@pytest.mark.parametrize("bad", ["nan_density", "negative_density", "nan_energy"])
+def test_nonphysical_states_are_flagged(frx, bad):
+    case = _case()
+    ctx = frx.Context.from_case(case)
+    U = torch.tensor(case.U, device="cuda")
+    if bad == "nan_density":
+        U[0, 7] = math.nan
+    elif bad == "negative_density":
+        U[0, 7] = -0.5
+    else:
+        U[4, 11] = math.nan
+    ctx.residual(U)
+    assert ctx.nonphysical() == 1
+    assert ctx.nonphysical() == 0
+    # the implicit step refuses such a state with FR_E_NONPHYSICAL
+    with pytest.raises(frx.FrError) as ei:
+        ctx.esdirk_step(U, 0.01, gmres=dict(restart=5, tol=1e-2), dtau_init=1e-3, dtau_max=1e-2, max_ptc_iter=2)
+    assert ei.value.status == frx.FR_E_NONPHYSICAL
