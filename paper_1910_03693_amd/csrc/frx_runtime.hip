@@ -587,7 +587,8 @@ void note_cycle(fr_ctx c, int mode, int prec_bytes, int m, int iters) {
 
 // Restarted GMRES on the device.  x (float64, device) receives the solution.
 template <class TV>
-fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats* st, hipStream_t s) {
+fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats* st, hipStream_t s,
+                    double nF_known) {
   const long n = c->ndof;
   const int m = o.restart;
   GmresDev G = gdev(c, m);
@@ -595,8 +596,8 @@ fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats*
   TV* w = (TV*)c->wv;
   TV* xv = (TV*)c->xv;
   const double eps = o.fd_eps > 0 ? o.fd_eps : 1e-6;
-  // ||F||, tolerance, budget
-  const double nF = norm2(c, c->Fb, s);
+  // ||F|| (unless the caller has it), tolerance, budget
+  const double nF = nF_known >= 0.0 ? nF_known : norm2(c, c->Fb, s);
   hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(KR_THREADS), 0, s, x, n, 0.0);
   FRX_TRY(hipGetLastError());
   fr_gmres_stats stats{0, 0, 0.0, 1};
@@ -659,7 +660,7 @@ fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats*
 
 // Prepare linearisation state and right-hand side, then run GMRES.
 fr_status gmres_solve(fr_ctx c, const double* U, double shift, const double* F, double* dU, const fr_gmres_opts& o,
-                      fr_gmres_stats* st, hipStream_t s, const double* R0_known) {
+                      fr_gmres_stats* st, hipStream_t s, const double* R0_known, double nF_known = -1.0) {
   if (o.restart < 1 || o.restart > 200 || o.max_iter < 1 || !(o.tol >= 0.0))
     throw StatusErr{FR_E_INVALID, "gmres options out of range"};
   if (o.precision == FR_F32 && o.jv_mode != FR_JV_EXACT)
@@ -685,9 +686,9 @@ fr_status gmres_solve(fr_ctx c, const double* U, double shift, const double* F, 
     hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const double*)c->Ulin,
                        c->uf, n);
     FRX_TRY(hipGetLastError());
-    return gmres_run<float>(c, o, dU, st, s);
+    return gmres_run<float>(c, o, dU, st, s, nF_known);
   }
-  return gmres_run<double>(c, o, dU, st, s);
+  return gmres_run<double>(c, o, dU, st, s, nF_known);
 }
 
 // Tile tables of the fused launches: every degree bucket cut into blocks of
@@ -1137,8 +1138,16 @@ fr_status esdirk_step(fr_ctx c, double* U, double dt, const fr_step_opts* o, fr_
         hipLaunchKernelGGL(k_stage_F, dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const double*)q, (const double*)Rq,
                            (const double*)rhs, 1.0 / (w * dt), F, n);
         FRX_TRY(hipGetLastError());
-        const double nF = norm2(c, F, s);
-        check_flag(c, s);
+        // ||F|| and the non-physical flag in one round trip
+        dot_to<double>(c, F, nullptr, c->sc + 15, nullptr, s);
+        FRX_TRY(hipMemcpyAsync(c->hpin, c->sc + 15, sizeof(double), hipMemcpyDeviceToHost, s));
+        FRX_TRY(hipMemcpyAsync(c->ipin, c->M.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        FRX_TRY(hipStreamSynchronize(s));
+        const double nF = std::sqrt(c->hpin[0]);
+        if (c->ipin[0]) {
+          hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->M.flag, 0);
+          throw StatusErr{FR_E_NONPHYSICAL, "non-physical state (rho <= 0 or p <= 0) met in the residual"};
+        }
         if (m == 0) nF0 = nF;
         else dtau = std::min(dtau * nFprev / nF, o->dtau_max);  // SER
         stats.final_rel_F = nF0 > 0 ? nF / nF0 : 0.0;
@@ -1149,7 +1158,7 @@ fr_status esdirk_step(fr_ctx c, double* U, double dt, const fr_step_opts* o, fr_
         }
         while (true) {
           fr_gmres_stats gs;
-          fr_status gr = gmres_solve(c, q, 1.0 / (w * dt) + 1.0 / dtau, F, dq, o->gmres, &gs, s, Rq);
+          fr_status gr = gmres_solve(c, q, 1.0 / (w * dt) + 1.0 / dtau, F, dq, o->gmres, &gs, s, Rq, nF);
           stats.gmres_iterations += gs.iterations;
           if (gr == FR_OK) break;
           if (gr != FR_E_NOTCONVERGED) return gr;
