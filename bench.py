@@ -176,6 +176,8 @@ def main():
             "jvp_exact_f64": timed(lambda: ctx.jvp(U, v, out=Jv), reps),
             "jvp_exact_f32": timed(lambda: ctx.jvp(U, v32, precision=frx.FR_F32, out=J32), reps),
             "jvp_fd_f64": timed(lambda: ctx.jvp(U, v, jv_mode=frx.FR_JV_FD, out=Jv), reps),
+            "residual_and_jvp_one_pass": timed(lambda: ctx.residual_jvp(U, v, R, Jv), reps),
+            "vjp_f64": timed(lambda: ctx.vjp(U, v, out=Jv), reps),
         }
         per_op[mode] = {k: {"ms": round(t, 5), "gdof_s": round(n_dof / (t * 1e-3) / 1e9, 3)} for k, t in ops.items()}
     ctx.set_launch(True)
@@ -410,6 +412,33 @@ def step_study(which):
     U = torch.tensor(case.U, device="cuda")
     out["n_dof"] = int(ctx.n_dof)
     out["dt"] = dt
+    # the operators alone on this workload (fused launches, HIP events)
+    ctx.set_launch(True)
+    vv = torch.tensor(I.random_direction(case.U.size, 4005).reshape(case.U.shape), device="cuda")
+    R, J = torch.empty_like(U), torch.empty_like(U)
+    J32 = torch.empty_like(vv, dtype=torch.float32)
+    v32 = vv.float()
+
+    def t_op(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ops = {"residual_f64": t_op(lambda: ctx.residual(U, out=R)),
+           "jvp_exact_f64": t_op(lambda: ctx.jvp(U, vv, out=J)),
+           "jvp_exact_f32": t_op(lambda: ctx.jvp(U, v32, precision=frx.FR_F32, out=J32)),
+           "residual_and_jvp_one_pass": t_op(lambda: ctx.residual_jvp(U, vv, R, J)),
+           "vjp_f64": t_op(lambda: ctx.vjp(U, vv, out=J))}
+    out["operators_fused"] = {k: {"ms": round(t, 4), "gdof_s": round(ctx.n_dof / (t * 1e-3) / 1e9, 3)}
+                              for k, t in ops.items()}
+    print(f"[bench] {which} operators: {out['operators_fused']}", file=sys.stderr, flush=True)
+    del R, J, J32, v32, vv
     out["settings"] = {**common, **g}
     variants = (("f64_exact_graph", dict(g, precision=frx.FR_F64, use_graph=True), True),
                 ("mixed_f32_exact_graph", dict(g, precision=frx.FR_F32, use_graph=True), True),

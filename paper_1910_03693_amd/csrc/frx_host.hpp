@@ -87,6 +87,10 @@ struct MeshDev {
   int4* all_elems = nullptr;      // concatenated bucket element records
   int4* all_faces = nullptr;      // concatenated interior + boundary face lists
   FusedPlan plan[SK_COUNT];
+  // adjoint: tiles of the reverse stages [trace_rev, face_rev, div_rev] over
+  // the element ids in all_ids (the order of all_elems)
+  FusedPlan vplan;
+  int* all_ids = nullptr;
   Gas<double> gas_d;
   Gas<float> gas_f;
 };

@@ -89,8 +89,44 @@ hipError_t face_rev_n(const VjpArgs& va, const FaceBucket& b, hipStream_t s) {
   }
 }
 
+// The fused path: forward traces and faces with the fused forward kernels of
+// the float64 plan, then one launch per reverse stage.
+template <bool NS>
+hipError_t vjp_fused(const ResArgs<double>& fa, const VjpArgs& va, const MeshDev& M, hipStream_t s) {
+  const FusedPlan& P = M.plan[SK_F64];
+  const FusedPlan& V = M.vplan;
+  hipError_t e;
+  if (P.count[0]) {
+    hipLaunchKernelGGL((k_trace_fused<double, NS>), dim3(P.count[0]), dim3(256), P.lds[0], s, fa, M.all_elems,
+                       P.tiles[0]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (P.count[1]) {
+    hipLaunchKernelGGL((k_face_fused<double, NS>), dim3(P.count[1]), dim3(256), P.lds[1], s, fa, M.all_faces,
+                       P.tiles[1]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (V.count[2]) {
+    hipLaunchKernelGGL((k_elem_rev_fused<NS, false>), dim3(V.count[2]), dim3(256), V.lds[2], s, va,
+                       (const int*)M.all_ids, V.tiles[2]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (V.count[1]) {
+    hipLaunchKernelGGL((k_face_rev_fused<NS>), dim3(V.count[1]), dim3(256), V.lds[1], s, va, M.all_faces,
+                       V.tiles[1]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (V.count[0]) {
+    hipLaunchKernelGGL((k_elem_rev_fused<NS, true>), dim3(V.count[0]), dim3(256), V.lds[0], s, va,
+                       (const int*)M.all_ids, V.tiles[0]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template <bool NS>
 hipError_t vjp_stages(const ResArgs<double>& fa, const VjpArgs& va, const MeshDev& M, hipStream_t s) {
+  if (M.fused) return vjp_fused<NS>(fa, va, M, s);
   hipError_t e;
   // forward face intermediates
   for (const ElemBucket& b : M.eb)

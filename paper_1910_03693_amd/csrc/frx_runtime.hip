@@ -717,6 +717,8 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
     frange.emplace_back(64 + it->first, (int)faces.size(), (int)it->second.size(), it->first);
     faces.insert(faces.end(), it->second.begin(), it->second.end());
   }
+  M.all_ids = (int*)c->dalloc(sizeof(int) * std::max<size_t>(1, all.size()));
+  FRX_TRY(hipMemcpy(M.all_ids, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice));
   std::vector<int4> all_recs;
   for (int e : all) all_recs.push_back(make_int4(e, (int)c->sp_off_h[e], c->fp_off_h[e], 0));
   M.all_elems = (int4*)c->dalloc(sizeof(int4) * std::max<size_t>(1, all_recs.size()));
@@ -782,6 +784,54 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
       P.tiles[st] = (int4*)c->dalloc(sizeof(int4) * std::max<size_t>(1, t.size()));
       if (!t.empty()) FRX_TRY(hipMemcpy(P.tiles[st], t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice));
     }
+  }
+  // adjoint (float64): LDS per element 5 n^3 (trace_rev) and 5 n^3 + 30 n^2
+  // (div_rev); per mixed face (NV + 10) nl^2 + NV nh^2
+  FusedPlan& V = M.vplan;
+  for (int st = 0; st < 3; ++st) {
+    std::vector<std::pair<double, int4>> tiles;
+    size_t lds = 0;
+    if (st != 1) {
+      for (auto& kv : erange) {
+        const int n = kv.first, n3 = n * n * n;
+        const size_t per_el = (size_t)(5 * n3 + (st == 2 ? 30 * n * n : 0)) * 8;
+        int epb = std::max(1, 256 / n3);
+        while (epb > 1 && epb * per_el > cap) --epb;
+        lds = std::max(lds, epb * per_el);
+        for (int i = 0; i < kv.second.second; i += epb) {
+          const int cnt = std::min(epb, kv.second.second - i);
+          tiles.push_back({(double)cnt * n3 * n, make_int4(n, kv.second.first + i, cnt, epb)});
+        }
+      }
+    } else {
+      const int nv = ns ? 20 : 5;
+      for (auto& fr : frange) {
+        const int code = std::get<0>(fr), first = std::get<1>(fr), count = std::get<2>(fr);
+        if (code >= 64) {
+          const int n = code - 64, per = std::max(1, 256 / (n * n));
+          for (int i = 0; i < count; i += per)
+            tiles.push_back({(double)std::min(per, count - i) * n * n * 2.0,
+                             make_int4(code, first + i, std::min(per, count - i), per)});
+        } else {
+          const int nl = code / 8, nh = code % 8;
+          const size_t per_face = nl < nh ? (size_t)((nv + 10) * nl * nl + nv * nh * nh) * 8 : 0;
+          int fpb = std::max(1, 256 / (nh * nh));
+          while (fpb > 1 && fpb * per_face > cap) --fpb;
+          lds = std::max(lds, fpb * per_face);
+          for (int i = 0; i < count; i += fpb)
+            tiles.push_back({(double)std::min(fpb, count - i) * nh * nh * (nl < nh ? 1.5 : 1.0),
+                             make_int4(code, first + i, std::min(fpb, count - i), fpb)});
+        }
+      }
+    }
+    std::stable_sort(tiles.begin(), tiles.end(),
+                     [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) { return x.first > y.first; });
+    std::vector<int4> t;
+    for (auto& x : tiles) t.push_back(x.second);
+    V.count[st] = (int)t.size();
+    V.lds[st] = lds;
+    V.tiles[st] = (int4*)c->dalloc(sizeof(int4) * std::max<size_t>(1, t.size()));
+    if (!t.empty()) FRX_TRY(hipMemcpy(V.tiles[st], t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice));
   }
 }
 

@@ -163,15 +163,15 @@ __device__ void face_fn_vjp(const double qL[5], const double qR[5], const double
 
 // ---------------------------------------------------------------- div_rev
 template <int N, bool NS>
-__global__ void __launch_bounds__(256) k_div_rev(VjpArgs a, const int* __restrict__ elems, int nel, int epb) {
+__device__ __forceinline__ void div_rev_body(const VjpArgs& a, const int* __restrict__ elems, int nel, int epb,
+                                             int blk, unsigned char* smem) {
   constexpr int N2 = N * N, N3 = N2 * N;
-  extern __shared__ __align__(16) unsigned char smem[];
   double* sX = reinterpret_cast<double*>(smem);  // [epb][5][N3]
   double* sY = sX + epb * 5 * N3;                // [epb][6][5][N2]
   const OpsTab<double>& O = ops<double>();
   const int tid = threadIdx.x;
   const int le = tid / N3, k = tid - le * N3;
-  const int slot = blockIdx.x * epb + le;
+  const int slot = blk * epb + le;
   const bool act = le < epb && slot < nel;
   const int e = act ? elems[slot] : 0;
   const long off = act ? (long)a.sp_off[e] + k : 0;
@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(256) k_div_rev(VjpArgs a, const int* __restric
     for (int it = tid; it < epb * 30 * N2; it += blockDim.x) {
       const int l2 = it / (30 * N2), rem = it - l2 * 30 * N2;
       const int fv = rem / N2, p2 = rem - fv * N2;
-      const int s2 = blockIdx.x * epb + l2;
+      const int s2 = blk * epb + l2;
       if (s2 >= nel) continue;
       const int f = fv / 5, v = fv - f * 5;
       sY[it] = a.DQ[(long)v * a.nfp + a.fp_off[elems[s2]] + f * N2 + p2];
@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(256) k_div_rev(VjpArgs a, const int* __restric
   for (int it = tid; it < epb * 30 * N2; it += blockDim.x) {
     const int l2 = it / (30 * N2), rem = it - l2 * 30 * N2;
     const int fv = rem / N2, p2 = rem - fv * N2;
-    const int s2 = blockIdx.x * epb + l2;
+    const int s2 = blk * epb + l2;
     if (s2 >= nel) continue;
     const int f = fv / 5, v = fv - f * 5, d = f >> 1;
     const double* gf = (f & 1) ? O.gR[N] : O.gL[N];
@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(256) k_div_rev(VjpArgs a, const int* __restric
       for (int it = tid; it < epb * 10 * N2; it += blockDim.x) {
         const int l2 = it / (10 * N2), rem = it - l2 * 10 * N2;
         const int sv = rem / N2, p2 = rem - sv * N2;
-        const int s2 = blockIdx.x * epb + l2;
+        const int s2 = blk * epb + l2;
         if (s2 >= nel) continue;
         const int side = sv / 5, v = sv - side * 5, f = 2 * i + side;
         const double* gf = side ? O.gR[N] : O.gL[N];
@@ -317,21 +317,26 @@ __global__ void __launch_bounds__(256) k_div_rev(VjpArgs a, const int* __restric
     for (int v = 0; v < 5; ++v) a.out[(long)v * a.nsp + off] = Ub[v];
   }
 }
+template <int N, bool NS>
+__global__ void __launch_bounds__(256) k_div_rev(VjpArgs a, const int* __restrict__ elems, int nel, int epb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  div_rev_body<N, NS>(a, elems, nel, epb, blockIdx.x, smem);
+}
 
 // --------------------------------------------------------------- face_rev
 template <int NL, int NH, bool NS>
-__global__ void __launch_bounds__(256) k_face_rev(VjpArgs a, const int4* __restrict__ faces, int nf, int fpb) {
+__device__ __forceinline__ void face_rev_body(const VjpArgs& a, const int4* __restrict__ faces, int nf, int fpb,
+                                              int blk, unsigned char* smem) {
   constexpr int NH2 = NH * NH, NL2 = NL * NL;
   constexpr bool MIX = NL < NH;
   constexpr int NV = NS ? 20 : 5;
-  extern __shared__ __align__(16) unsigned char smem[];
   double* slow = reinterpret_cast<double*>(smem);           // [fpb][NV][NL2] forward low-side traces
   double* sadj = slow + (MIX ? fpb * NV * NL2 : 0);          // [fpb][10][NL2] low-side fS-bar, jump-bar
   double* sres = sadj + (MIX ? fpb * 10 * NL2 : 0);          // [fpb][NV][NH2] low-side results at high points
   const OpsTab<double>& O = ops<double>();
   const int tid = threadIdx.x;
   const int lf = tid / NH2, pt = tid - lf * NH2;
-  const int fi = blockIdx.x * fpb + lf;
+  const int fi = blk * fpb + lf;
   const bool act = lf < fpb && fi < nf;
   const FaceRec F = face_rec(act ? faces[fi] : make_int4(0, 0, 0, 0));
   const int L = F.L, R = F.R, d = F.d;
@@ -341,7 +346,7 @@ __global__ void __launch_bounds__(256) k_face_rev(VjpArgs a, const int4* __restr
     for (int it = tid; it < fpb * (NV + 10) * NL2; it += blockDim.x) {
       const int l2 = it / ((NV + 10) * NL2), rem = it - l2 * (NV + 10) * NL2;
       const int vv = rem / NL2, p2 = rem - vv * NL2;
-      const int f2 = blockIdx.x * fpb + l2;
+      const int f2 = blk * fpb + l2;
       if (f2 >= nf) continue;
       const FaceRec G2 = face_rec(faces[f2]);
       const long o = (G2.low_is_R ? G2.oR : G2.oL) + p2;
@@ -428,7 +433,7 @@ __global__ void __launch_bounds__(256) k_face_rev(VjpArgs a, const int4* __restr
     // transposed interpolation back to the low side's own points
     for (int it = tid; it < fpb * NL2; it += blockDim.x) {
       const int l2 = it / NL2, p2 = it - l2 * NL2;
-      const int f2 = blockIdx.x * fpb + l2;
+      const int f2 = blk * fpb + l2;
       if (f2 >= nf) continue;
       const FaceRec G2 = face_rec(faces[f2]);
       const long o = (G2.low_is_R ? G2.oR : G2.oL) + p2;
@@ -445,12 +450,17 @@ __global__ void __launch_bounds__(256) k_face_rev(VjpArgs a, const int4* __restr
     }
   }
 }
+template <int NL, int NH, bool NS>
+__global__ void __launch_bounds__(256) k_face_rev(VjpArgs a, const int4* __restrict__ faces, int nf, int fpb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  face_rev_body<NL, NH, NS>(a, faces, nf, fpb, blockIdx.x, smem);
+}
 
 // -------------------------------------------------------------- bface_rev
 template <int N, bool NS>
-__global__ void __launch_bounds__(256) k_bface_rev(VjpArgs a, const int4* __restrict__ faces, int nf) {
+__device__ __forceinline__ void bface_rev_body(const VjpArgs& a, const int4* __restrict__ faces, int nf, int blk) {
   constexpr int N2 = N * N;
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gid = blk * blockDim.x + threadIdx.x;
   if (gid >= nf * N2) return;
   const int fi = gid / N2, pt = gid - fi * N2;
   const int4 F = faces[fi];
@@ -486,19 +496,23 @@ __global__ void __launch_bounds__(256) k_bface_rev(VjpArgs a, const int4* __rest
   if (NS)
     for (int vc = 0; vc < 15; ++vc) a.GF[(long)vc * a.nfp + o] = gb[vc / 3][vc % 3];
 }
+template <int N, bool NS>
+__global__ void __launch_bounds__(256) k_bface_rev(VjpArgs a, const int4* __restrict__ faces, int nf) {
+  bface_rev_body<N, NS>(a, faces, nf, blockIdx.x);
+}
 
 // -------------------------------------------------------------- trace_rev
 // out += transposed extrapolation of the q-trace adjoints + transposed
 // uncorrected gradient of the gradient-trace adjoints.
 template <int N, bool NS>
-__global__ void __launch_bounds__(256) k_trace_rev(VjpArgs a, const int* __restrict__ elems, int nel, int epb) {
+__device__ __forceinline__ void trace_rev_body(const VjpArgs& a, const int* __restrict__ elems, int nel, int epb,
+                                               int blk, unsigned char* smem) {
   constexpr int N2 = N * N, N3 = N2 * N;
-  extern __shared__ __align__(16) unsigned char smem[];
   double* sX = reinterpret_cast<double*>(smem);  // [epb][5][N3]
   const OpsTab<double>& O = ops<double>();
   const int tid = threadIdx.x;
   const int le = tid / N3, k = tid - le * N3;
-  const int slot = blockIdx.x * epb + le;
+  const int slot = blk * epb + le;
   const bool act = le < epb && slot < nel;
   const int e = act ? elems[slot] : 0;
   const long off = act ? (long)a.sp_off[e] + k : 0;
@@ -566,5 +580,53 @@ __global__ void __launch_bounds__(256) k_trace_rev(VjpArgs a, const int* __restr
     for (int v = 0; v < 5; ++v) a.out[(long)v * a.nsp + off] = Ub[v];
   }
 }
+template <int N, bool NS>
+__global__ void __launch_bounds__(256) k_trace_rev(VjpArgs a, const int* __restrict__ elems, int nel, int epb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  trace_rev_body<N, NS>(a, elems, nel, epb, blockIdx.x, smem);
+}
+
+// ------------------------------------------------------- fused launches
+// One launch per reverse stage over every degree bucket, as in the forward
+// pass: tiles[blockIdx.x] = (code, first, count, per) with code n for element
+// tiles, 8 nl + nh for interior faces, 64 + n for boundary faces.
+#define FRX_VCASE(N) \
+  case N:            \
+    if constexpr (TRACE) trace_rev_body<N, NS>(a, elems + t.y, t.z, t.w, 0, smem); \
+    else div_rev_body<N, NS>(a, elems + t.y, t.z, t.w, 0, smem);                   \
+    break;
+template <bool NS, bool TRACE>
+__global__ void __launch_bounds__(256) k_elem_rev_fused(VjpArgs a, const int* __restrict__ elems,
+                                                        const int4* __restrict__ tiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int4 t = tiles[blockIdx.x];
+  switch (t.x) {
+    FRX_VCASE(2) FRX_VCASE(3) FRX_VCASE(4) FRX_VCASE(5) FRX_VCASE(6)
+    default: break;
+  }
+}
+#undef FRX_VCASE
+
+#define FRX_VFCASE(NL, NH) \
+  case 8 * NL + NH: face_rev_body<NL, NH, NS>(a, faces + t.y, t.z, t.w, 0, smem); break;
+#define FRX_VBCASE(N) \
+  case 64 + N: bface_rev_body<N, NS>(a, faces + t.y, t.z, 0); break;
+template <bool NS>
+__global__ void __launch_bounds__(256) k_face_rev_fused(VjpArgs a, const int4* __restrict__ faces,
+                                                        const int4* __restrict__ tiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int4 t = tiles[blockIdx.x];
+  switch (t.x) {
+    FRX_VFCASE(2, 2) FRX_VFCASE(2, 3) FRX_VFCASE(2, 4) FRX_VFCASE(2, 5) FRX_VFCASE(2, 6)
+    FRX_VFCASE(3, 3) FRX_VFCASE(3, 4) FRX_VFCASE(3, 5) FRX_VFCASE(3, 6)
+    FRX_VFCASE(4, 4) FRX_VFCASE(4, 5) FRX_VFCASE(4, 6)
+    FRX_VFCASE(5, 5) FRX_VFCASE(5, 6)
+    FRX_VFCASE(6, 6)
+    FRX_VBCASE(2) FRX_VBCASE(3) FRX_VBCASE(4) FRX_VBCASE(5) FRX_VBCASE(6)
+    default: break;
+  }
+}
+#undef FRX_VFCASE
+#undef FRX_VBCASE
 
 }  // namespace frx

@@ -55,12 +55,14 @@ def _tiny(kind):
     return c
 
 
+@pytest.mark.parametrize("fused", [False, True], ids=["per_bucket", "fused"])
 @pytest.mark.parametrize("kind", ["ns_wall_p1to3", "ns_periodic_p1to4_rusanov", "euler_periodic_p1to3_roe"])
-def test_vjp_matches_dense_jacobian(frx, oracle_mod, kind):
-    print("case", kind, flush=True)
+def test_vjp_matches_dense_jacobian(frx, oracle_mod, kind, fused):
+    print("case", kind, "fused", fused, flush=True)
     case = _tiny(kind)
     orc = oracle_mod.Oracle.from_case(case)
     ctx = frx.Context.from_case(case)
+    ctx.set_launch(fused)
     J = orc.jacobian(case.U)
     U = torch.tensor(case.U, device="cuda")
     for seed in (1, 2):
@@ -72,10 +74,12 @@ def test_vjp_matches_dense_jacobian(frx, oracle_mod, kind):
         assert err <= 1e-12
 
 
-def test_dot_product_identity_wall_32x32x8(frx, oracle_mod):
+@pytest.mark.parametrize("fused", [False, True], ids=["per_bucket", "fused"])
+def test_dot_product_identity_wall_32x32x8(frx, oracle_mod, fused):
     case = I.config(4)
     orc = oracle_mod.Oracle.from_case(case)
     ctx = frx.Context.from_case(case)
+    ctx.set_launch(fused)
     U = torch.tensor(case.U, device="cuda")
     for seed in range(3):
         rng = np.random.default_rng(4400 + seed)
