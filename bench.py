@@ -438,6 +438,30 @@ def step_study(which):
     out["operators_fused"] = {k: {"ms": round(t, 4), "gdof_s": round(ctx.n_dof / (t * 1e-3) / 1e9, 3)}
                               for k, t in ops.items()}
     print(f"[bench] {which} operators: {out['operators_fused']}", file=sys.stderr, flush=True)
+    # per-stage times of the float64 tangent and their algorithmic bandwidth
+    # (this working set does not fit the Infinity Cache)
+    kt = ctx.profile(U, op=1, reps=5)
+    counts_n = {int(p) + 1: int(c) for p, c in zip(*np.unique(case.elem_p, return_counts=True))}
+    pairs = {}
+    nbr = case.mesh["elem_nbr"]
+    for e in range(case.mesh["n_elem"]):
+        ne = int(case.elem_p[e]) + 1
+        for f in range(6):
+            nb = int(nbr[e, f])
+            if nb >= 0 and f % 2 == 1:
+                nn = int(case.elem_p[nb]) + 1
+                key = (min(ne, nn), max(ne, nn))
+                pairs[key] = pairs.get(key, 0) + 1
+            elif nb < 0:
+                pairs[(-ne, ne)] = pairs.get((-ne, ne), 0) + 1
+    stages = []
+    for k in kt:
+        by, fl = fused_counts(k["stage"], counts_n, pairs, 1)
+        stages.append({"stage": k["stage"], "ms": round(k["ms"], 4), "algorithmic_bytes": by,
+                       "gb_s": round(by / (k["ms"] * 1e-3) / 1e9, 1), "hbm_frac": round(by / (k["ms"] * 1e-3) / 1e9 /
+                                                                                      HBM_PEAK_GBS, 4)})
+    out["tangent_f64_stages"] = stages
+    print(f"[bench] {which} tangent stages: {stages}", file=sys.stderr, flush=True)
     del R, J, J32, v32, vv
     out["settings"] = {**common, **g}
     variants = (("f64_exact_graph", dict(g, precision=frx.FR_F64, use_graph=True), True),
