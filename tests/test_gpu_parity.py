@@ -63,6 +63,16 @@ def _tiny_cases():
     cs["mixed_p1to5_euler_roe"] = I.Case("t", m, p, U, 0, 0, 1.4, 0.0, 0.72, I._farfield(0.3), {})
     cw = I.case_ns_mixed(3, 4, 2, k=44, lengths=(1.0, 1.0, 0.5), wall=True, re=100.0, ma=0.3)
     cs["wall_farfield_ns_roe"] = cw
+    # uniform degree at both ends of the range: p = 1 only (largest tiles),
+    # p = 5 only with wall and far field (float64-dual traces one variable at
+    # a time)
+    mu1 = I.box_mesh(5, 4, 3, (1.0, 0.8, 0.6), noise=0.03, seed=46)
+    pu1 = np.ones(mu1["n_elem"], np.int8)
+    Uu1 = I.sample(mu1, pu1, lambda x, y, z: I.perturbed_uniform_flow(x, y, z, modes, 0.3))
+    cs["uniform_p1_ns_roe"] = I.Case("t", mu1, pu1, Uu1, 1, 0, 1.4, 1e-2, 0.72, I._farfield(0.3), {})
+    cu5 = I.case_ns_mixed(2, 2, 2, k=47, lengths=(1.0, 1.0, 0.5), wall=True, pvals=(5,), pw=(1,), re=100.0, ma=0.3)
+    cu5.flux = 1
+    cs["uniform_p5_ns_rusanov_wall"] = cu5
     m1 = I.box_mesh(1, 1, 1, (1.0, 1.0, 1.0), noise=0.0)
     p1 = np.array([3], np.int8)
     U1 = I.sample(m1, p1, lambda x, y, z: I.perturbed_uniform_flow(x, y, z, modes, 0.3))
