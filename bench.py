@@ -54,12 +54,16 @@ def nominal_counts(stage, nl, nh, units, op, ns=True):
     """Algorithmic bytes and nominal flops of one launch.
 
     Bytes: the launch's compulsory inputs and outputs (state, tangent
-    direction, face data, 24 geometry coefficients per element, result).
+    direction, face data, result; the element stages read 24 map
+    coefficients per element, the face stages the precomputed face-point
+    geometry: the area vector and, for Navier-Stokes, the lifting
+    coefficients).
     Flops: the arithmetic of the stage's formulation counted per solution or
     face point (multiply-add = 2), a dual number doubling the products."""
     sb_in = 8 if op < 2 else 4             # state / result precision
     n_in = 1 if op == 0 else 2             # U (and v for a tangent)
     sb_T = {0: 8, 1: 16, 2: 8}[op]         # face-buffer scalar
+    sb_g = 8 if op < 2 else 4              # geometry scalar
     dual = 1.0 if op == 0 else 2.5
     n = nh
     if stage == "k_trace":
@@ -71,10 +75,11 @@ def nominal_counts(stage, nl, nh, units, op, ns=True):
         by = units * (5 * n3 * sb_in * n_in + 24 * 8 + (60 if ns else 30) * n2 * sb_T + 5 * n3 * sb_in)
         fl = units * n3 * ((60 * n + 570) if ns else (30 * n + 160)) * dual + units * 60 * n3 * dual
     elif stage == "k_face":
-        by = units * ((20 if ns else 5) * (nl * nl + nh * nh) * sb_T + 48 * 8 + 10 * (nl * nl + nh * nh) * sb_T)
+        by = units * ((20 if ns else 5) * (nl * nl + nh * nh) * sb_T + (5 if ns else 3) * nh * nh * sb_g
+                      + 10 * (nl * nl + nh * nh) * sb_T)
         fl = units * nh * nh * (500 if ns else 200) * dual
     else:  # boundary faces
-        by = units * ((20 if ns else 5) * n * n * sb_T + 24 * 8 + 10 * n * n * sb_T)
+        by = units * ((20 if ns else 5) * n * n * sb_T + (4 if ns else 3) * n * n * sb_g + 10 * n * n * sb_T)
         fl = units * n * n * (400 if ns else 150) * dual
     return float(by), float(fl)
 

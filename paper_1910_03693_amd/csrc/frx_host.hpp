@@ -70,6 +70,8 @@ struct MeshDev {
   int* fp_off = nullptr;
   double* geo_d = nullptr;
   float* geo_f = nullptr;
+  double* fgeo_d = nullptr;  // [5][nfp] face-point geometry (see k_face_geo), float64
+  float* fgeo_f = nullptr;   // the same from the float32 map
   std::vector<ElemBucket> eb;
   std::vector<FaceBucket> fb;
   std::vector<BFaceBucket> bb;
@@ -131,4 +133,6 @@ hipError_t launch_indicator(const MeshDev& M, const double* U, int var, double* 
 hipError_t launch_select_degrees(const MeshDev& M, const double* U, int var, double nu_max, double nu_min, int p_min,
                                  int p_max, int8_t* p_new, hipStream_t s);
 hipError_t launch_project(const MeshDev& Ms, const double* Us, const MeshDev& Md, double* Ud, hipStream_t s);
+// fills M.fgeo_d and M.fgeo_f from the trilinear maps (once per mesh)
+hipError_t launch_face_geometry(const MeshDev& M, hipStream_t s);
 }  // namespace frx

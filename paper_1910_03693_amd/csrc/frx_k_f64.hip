@@ -14,6 +14,26 @@ hipError_t launch_residual_f64(const MeshDev& M, const ResCall<double>& c, hipSt
   return launch_residual_T<double>(M, c, SK_F64, s);
 }
 
+hipError_t launch_face_geometry(const MeshDev& M, hipStream_t s) {
+  for (const FaceBucket& b : M.fb) {
+    if (!b.count) continue;
+    const long tot = (long)b.count * b.nh * b.nh;
+    const dim3 grid((unsigned)((tot + 255) / 256));
+    hipLaunchKernelGGL(k_face_geo<double>, grid, dim3(256), 0, s, M.geo_d, b.faces, b.count, b.nl, b.nh, M.fgeo_d,
+                       M.nfp);
+    hipLaunchKernelGGL(k_face_geo<float>, grid, dim3(256), 0, s, M.geo_f, b.faces, b.count, b.nl, b.nh, M.fgeo_f,
+                       M.nfp);
+  }
+  for (const BFaceBucket& b : M.bb) {
+    if (!b.count) continue;
+    const long tot = (long)b.count * b.n * b.n;
+    const dim3 grid((unsigned)((tot + 255) / 256));
+    hipLaunchKernelGGL(k_bface_geo<double>, grid, dim3(256), 0, s, M.geo_d, b.faces, b.count, b.n, M.fgeo_d, M.nfp);
+    hipLaunchKernelGGL(k_bface_geo<float>, grid, dim3(256), 0, s, M.geo_f, b.faces, b.count, b.n, M.fgeo_f, M.nfp);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_indicator(const MeshDev& M, const double* U, int var, double* eta, double* eta_max,
                             hipStream_t s) {
   for (const ElemBucket& b : M.eb) {

@@ -165,6 +165,7 @@ hipError_t launch_vjp(const MeshDev& M, const double* U, const double* w, double
   fa.sp_off = M.sp_off;
   fa.fp_off = M.fp_off;
   fa.geo = M.geo_d;
+  fa.fgeo = M.fgeo_d;
   double* fb = reinterpret_cast<double*>(M.facebuf);
   fa.QF = fb;
   fa.GF = fb + 5L * M.nfp;

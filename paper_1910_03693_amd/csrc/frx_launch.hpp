@@ -9,6 +9,9 @@ namespace frx {
 template <class B> __host__ inline const B* geo_of(const MeshDev& M);
 template <> __host__ inline const double* geo_of<double>(const MeshDev& M) { return M.geo_d; }
 template <> __host__ inline const float* geo_of<float>(const MeshDev& M) { return M.geo_f; }
+template <class B> __host__ inline const B* fgeo_of(const MeshDev& M);
+template <> __host__ inline const double* fgeo_of<double>(const MeshDev& M) { return M.fgeo_d; }
+template <> __host__ inline const float* fgeo_of<float>(const MeshDev& M) { return M.fgeo_f; }
 template <class B> __host__ inline const Gas<B>& gas_of(const MeshDev& M);
 template <> __host__ inline const Gas<double>& gas_of<double>(const MeshDev& M) { return M.gas_d; }
 template <> __host__ inline const Gas<float>& gas_of<float>(const MeshDev& M) { return M.gas_f; }
@@ -237,6 +240,7 @@ hipError_t launch_residual_T(const MeshDev& M, const ResCall<base_t<T>>& c, int 
   a.sp_off = M.sp_off;
   a.fp_off = M.fp_off;
   a.geo = geo_of<B>(M);
+  a.fgeo = fgeo_of<B>(M);
   T* fb = reinterpret_cast<T*>(M.facebuf);
   a.QF = fb;
   a.GF = fb + 5L * M.nfp;

@@ -53,6 +53,7 @@ template <class T> struct ResArgs {
   const int* sp_off;   // [E] first solution point of each element
   const int* fp_off;   // [E] first face-slot point (6 n^2 per element)
   const B* geo;        // [E][24] trilinear monomial coefficients
+  const B* fgeo;       // [5][nfp] face-point geometry (k_face_geo)
   T* QF;               // [5][nfp]  q traces
   T* GF;               // [15][nfp] gradient traces (Navier-Stokes)
   T* DQ;               // [5][nfp]  q_com - q at own face points
@@ -282,7 +283,6 @@ __device__ __forceinline__ void face_body(const ResArgs<T>& a, const int4* __res
   const int fi = blk * fpb + lf;
   const bool act = lf < fpb && fi < nf;
   const FaceRec F = face_rec(act ? faces[fi] : make_int4(0, 0, 0, 0));
-  const int L = F.L, R = F.R, d = F.d;
   const bool lowR = MIX && F.low_is_R;
   const bool lowL = MIX && !F.low_is_R;
   if (MIX) {  // stage the low side's own-point traces
@@ -334,16 +334,13 @@ __device__ __forceinline__ void face_body(const ResArgs<T>& a, const int4* __res
         }
       }
     }
-    // geometry at the face point: S from L at r_d = +1, J of both sides
-    const B ta = O.x[NH][A], tb = O.x[NH][Bq];
-    B S[3], JL, SR[3], JR;
-    face_geom<B>(a.geo + 24L * L, d, B(1), ta, tb, S, JL);
+    // geometry at the face point, kept at the high side's slot
+    const long og = (lowL ? F.oR : F.oL) + pt;
+    const B S[3] = {a.fgeo[og], a.fgeo[a.nfp + og], a.fgeo[2L * a.nfp + og]};
     B cL = B(0), cR = B(0);
     if (NS) {
-      face_geom<B>(a.geo + 24L * R, d, B(-1), ta, tb, SR, JR);
-      const int nL = lowL ? NL : NH, nR = lowR ? NL : NH;
-      cL = B(0.5) * B(nL * nL) / JL;
-      cR = -B(0.5) * B(nR * nR) / JR;
+      cL = a.fgeo[3L * a.nfp + og];
+      cR = a.fgeo[4L * a.nfp + og];
     }
     T fS[5], jL[5], jR[5];
     face_fn<NS, T, B>(q[0], q[1], g[0], S, cL, cR, a.gas, a.flux, fS, jL, jR);
@@ -414,8 +411,7 @@ __device__ __forceinline__ void bface_body(const ResArgs<T>& a, const int4* __re
   if (gid >= nf * N2) return;
   const int fi = gid / N2, pt = gid - fi * N2;
   const int4 F = faces[fi];
-  const int e = F.x, f = F.y, bc = F.z, d = f >> 1, side = f & 1;
-  const OpsTab<B>& O = ops<B>();
+  const int bc = F.z, side = F.y & 1;
   const long o = F.w + pt;
   T q[5], g[5][3];
 #pragma unroll
@@ -424,9 +420,8 @@ __device__ __forceinline__ void bface_body(const ResArgs<T>& a, const int4* __re
 #pragma unroll
     for (int vc = 0; vc < 15; ++vc) g[vc / 3][vc % 3] = a.GF[(long)vc * a.nfp + o];
   }
-  B S[3], J;
-  face_geom<B>(a.geo + 24L * e, d, side ? B(1) : B(-1), O.x[N][pt % N], O.x[N][pt / N], S, J);
-  const B cf = (side ? B(0.5) : B(-0.5)) * B(N * N) / J;
+  const B S[3] = {a.fgeo[o], a.fgeo[a.nfp + o], a.fgeo[2L * a.nfp + o]};
+  const B cf = a.fgeo[3L * a.nfp + o];
   T fS[5], jmp[5];
   bface_fn<NS, T, B>(q, g, S, cf, bc, side, a.gas, a.flux, fS, jmp);
 #pragma unroll
@@ -434,6 +429,57 @@ __device__ __forceinline__ void bface_body(const ResArgs<T>& a, const int4* __re
     a.FS[(long)v * a.nfp + o] = fS[v];
     a.DQ[(long)v * a.nfp + o] = jmp[v];
   }
+}
+
+// ------------------------------------------------- face-point geometry
+// The face stages read their geometry per face point instead of evaluating
+// two trilinear maps there, which keeps 48 map coefficients out of the face
+// kernels' registers.  Computed once per mesh with the same formulas:
+// interior face point (grid of the high side, stored at that side's slot):
+// S from L's map at r_d = +1 and the BR2 lifting coefficients
+// cL = g_R'(+1)/J_L = n_L^2/(2 J_L) > 0, cR = g_L'(-1)/J_R = -n_R^2/(2 J_R);
+// boundary face point: S and c = +-n^2/(2 J) (+ on the +xi^d face).
+// Layout [5][nfp]: S_x, S_y, S_z, cL (or c), cR.
+template <class B>
+__global__ void k_face_geo(const B* __restrict__ geo, const int4* __restrict__ faces, int nf, int nl, int nh,
+                           B* __restrict__ fg, int nfp) {
+  const int nh2 = nh * nh;
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)nf * nh2) return;
+  const int fi = (int)(gid / nh2), pt = (int)(gid - (long)fi * nh2);
+  const FaceRec F = face_rec(faces[fi]);
+  const bool lowR = nl < nh && F.low_is_R, lowL = nl < nh && !F.low_is_R;
+  const OpsTab<B>& O = ops<B>();
+  const B ta = O.x[nh][pt % nh], tb = O.x[nh][pt / nh];
+  B S[3], JL, SR[3], JR;
+  face_geom<B>(geo + 24L * F.L, F.d, B(1), ta, tb, S, JL);
+  face_geom<B>(geo + 24L * F.R, F.d, B(-1), ta, tb, SR, JR);
+  const int nL = lowL ? nl : nh, nR = lowR ? nl : nh;
+  const long o = (lowL ? F.oR : F.oL) + pt;
+  fg[o] = S[0];
+  fg[nfp + o] = S[1];
+  fg[2L * nfp + o] = S[2];
+  fg[3L * nfp + o] = B(0.5) * B(nL * nL) / JL;
+  fg[4L * nfp + o] = -B(0.5) * B(nR * nR) / JR;
+}
+template <class B>
+__global__ void k_bface_geo(const B* __restrict__ geo, const int4* __restrict__ faces, int nf, int n,
+                            B* __restrict__ fg, int nfp) {
+  const int n2 = n * n;
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)nf * n2) return;
+  const int fi = (int)(gid / n2), pt = (int)(gid - (long)fi * n2);
+  const int4 F = faces[fi];
+  const int e = F.x, f = F.y, d = f >> 1, side = f & 1;
+  const OpsTab<B>& O = ops<B>();
+  B S[3], J;
+  face_geom<B>(geo + 24L * e, d, side ? B(1) : B(-1), O.x[n][pt % n], O.x[n][pt / n], S, J);
+  const long o = F.w + pt;
+  fg[o] = S[0];
+  fg[nfp + o] = S[1];
+  fg[2L * nfp + o] = S[2];
+  fg[3L * nfp + o] = (side ? B(0.5) : B(-0.5)) * B(n2) / J;
+  fg[4L * nfp + o] = B(0);
 }
 
 // ------------------------------------------------- viscous face correction
@@ -506,13 +552,10 @@ __device__ __forceinline__ void face_visc_body(const ResArgs<T>& a, const int4* 
         for (int vc = 0; vc < 15; ++vc) g[vc / 3][vc % 3] += a.GF[(long)vc * a.nfp + o];
       }
     }
-    const B ta = O.x[NH][A], tb = O.x[NH][Bq];
-    B S[3], JL, SR[3], JR;
-    face_geom<B>(a.geo + 24L * F.L, F.d, B(1), ta, tb, S, JL);
-    face_geom<B>(a.geo + 24L * F.R, F.d, B(-1), ta, tb, SR, JR);
-    const int nL = lowL ? NL : NH, nR = lowR ? NL : NH;
-    const B cL = B(0.5) * B(nL * nL) / JL;
-    const B cR = -B(0.5) * B(nR * nR) / JR;
+    const long og = (lowL ? F.oR : F.oL) + pt;
+    const B S[3] = {a.fgeo[og], a.fgeo[a.nfp + og], a.fgeo[2L * a.nfp + og]};
+    const B cL = a.fgeo[3L * a.nfp + og];
+    const B cR = a.fgeo[4L * a.nfp + og];
     // common solution and the BR2 common gradient from the jumps
     // q_com - q^- = (q^+ - q^-)/2, q_com - q^+ = -(q^+ - q^-)/2
     T qc[5], Gc[5][3];

@@ -1013,6 +1013,9 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
       M.gas_f.ff[v] = (float)d->farfield[v];
     }
     M.facebuf = C->dalloc(30L * nfp * 16);
+    M.fgeo_d = (double*)C->dalloc(sizeof(double) * 5L * nfp);
+    M.fgeo_f = (float*)C->dalloc(sizeof(float) * 5L * nfp);
+    FRX_TRY(launch_face_geometry(M, nullptr));
     M.p_dev = (int8_t*)C->dalloc(E);
     FRX_TRY(hipMemcpy(M.p_dev, d->elem_p, E, hipMemcpyHostToDevice));
     M.nbr = (int*)C->dalloc(sizeof(int) * 6L * E);
