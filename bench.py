@@ -219,9 +219,10 @@ def main():
         roof = {"bound": "hbm", "achieved": round(by / t_s / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
     roof["traffic"] = measured_traffic(dom["stage"])
-    roof["kernel"] = f"{dom['stage']}<{SK_NAME[1]},navier-stokes>" if dom["stage"].endswith("_fused") else \
+    flux = "rusanov" if case.flux == 1 else "roe"
+    roof["kernel"] = f"{dom['stage']}<{SK_NAME[1]},navier-stokes,{flux}>" if dom["stage"].endswith("_fused") else \
         f"{dom['stage']}<n={dom['n_hi']}{'' if dom['n_lo'] == dom['n_hi'] else ',' + str(dom['n_lo'])}," \
-        f"{SK_NAME[1]},navier-stokes>"
+        f"{SK_NAME[1]},navier-stokes,{flux}>"
     roof["launch_ms"] = round(dom["ms"], 5)
     roof["algorithmic_bytes"] = by
     roof["nominal_flops"] = fl

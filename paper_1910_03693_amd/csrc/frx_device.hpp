@@ -66,6 +66,13 @@ template <class B> __device__ __forceinline__ Dual<B> ssqrt(Dual<B> x) {
 // that is active (the convention of the complex step as well).
 template <class T> __device__ __forceinline__ T sabs(T x) { return val(x) < 0 ? T(-x) : x; }
 template <class T> __device__ __forceinline__ T smax(T a, T b) { return val(a) >= val(b) ? a : b; }
+// c ? a : b on values (a select between two arrays' addresses would put both
+// arrays in scratch)
+__device__ __forceinline__ double sel(bool c, double a, double b) { return c ? a : b; }
+__device__ __forceinline__ float sel(bool c, float a, float b) { return c ? a : b; }
+template <class B> __device__ __forceinline__ Dual<B> sel(bool c, Dual<B> a, Dual<B> b) {
+  return {c ? a.v : b.v, c ? a.d : b.d};
+}
 
 // Fused multiply-add on the base type, plain multiply-add on duals.
 template <class T, class B> __device__ __forceinline__ T fmab(B a, T x, T acc) { return acc + a * x; }
@@ -220,8 +227,11 @@ __device__ __forceinline__ void normal_flux(const T q[5], const B S[3], const Ga
 
 // Common inviscid flux dotted with the area vector S (eq. invis_com).
 // flux 0: Roe, with the wave decomposition written as a symmetric and an
-// antisymmetric acoustic part; no entropy fix.  flux 1: Rusanov.
-template <class T, class B>
+// antisymmetric acoustic part; no entropy fix.  flux 1: Rusanov.  FLUX >= 0
+// fixes the choice at compile time (the argument is then ignored): a kernel
+// that holds both solvers behind a branch on the argument keeps values of
+// both alive and needs far more registers.
+template <class T, class B, int FLUX = -1>
 __device__ __forceinline__ void riemann(const T qL[5], const T qR[5], const B S[3], const Gas<B>& G, int flux,
                                        T out[5]) {
   B area = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
@@ -229,7 +239,7 @@ __device__ __forceinline__ void riemann(const T qL[5], const T qR[5], const B S[
   T fL[5], fR[5], pL, pR, unL, unR;
   normal_flux<T, B>(qL, S, G, fL, pL, unL);  // un here carries the factor |S|
   normal_flux<T, B>(qR, S, G, fR, pR, unR);
-  if (flux == 1) {
+  if ((FLUX < 0 ? flux : FLUX) == 1) {
     T cL = ssqrt(G.gamma * pL / qL[0]), cR = ssqrt(G.gamma * pR / qR[0]);
     T lam = smax(T(sabs(unL) + area * cL), T(sabs(unR) + area * cR));
 #pragma unroll
@@ -271,24 +281,35 @@ __device__ __forceinline__ void riemann(const T qL[5], const T qR[5], const B S[
   for (int v = 0; v < 5; ++v) out[v] = B(0.5) * (fL[v] + fR[v]) - (B(0.5) * area) * diss[v];
 }
 
+// Solution jumps q_com - q of both sides of an interior face point, with the
+// common solution q_com = (q^- + q^+)/2 (eq. com_q).
+template <class T, class B>
+__device__ __forceinline__ void face_jumps(const T qL[5], const T qR[5], T jL[5], T jR[5]) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const T qc = B(0.5) * (qL[v] + qR[v]);
+    jL[v] = qc - qL[v];
+    jR[v] = qc - qR[v];
+  }
+}
+
 // Face function at one face point of an interior face (L on the minus side of
 // S, R on the plus side): common solution (eq. com_q), BR2 common gradient
 // (eq. com_grad_q) from gLR = grad q^- + grad q^+ and the liftings
-// r = S (q_com - q) g'(face) / J_f, common
-// normal flux f_com . S = Riemann(qL, qR) - f_vis(q_com, grad q_com) . S,
-// and the solution jumps q_com - q of both sides.  cL = g_R'(+1)/J_L > 0,
-// cR = g_L'(-1)/J_R < 0.
-template <bool NS, class T, class B>
+// r = S (q_com - q) g'(face) / J_f, and the common normal flux
+// f_com . S = Riemann(qL, qR) - f_vis(q_com, grad q_com) . S.  The jumps that
+// the face slots also receive come from face_jumps.  cL = g_R'(+1)/J_L > 0,
+// cR = g_L'(-1)/J_R < 0.  The viscous flux is evaluated before the Riemann
+// flux and the scheduler is kept from interleaving the two: each needs about
+// 200 registers per lane with float64 duals, the two interleaved over 320.
+template <bool NS, class T, class B, int FLUX = -1>
 __device__ __forceinline__ void face_fn(const T qL[5], const T qR[5], const T gLR[5][3], const B S[3], B cL, B cR,
-                                        const Gas<B>& G, int flux, T fS[5], T jL[5], T jR[5]) {
-  T qc[5];
+                                        const Gas<B>& G, int flux, T fS[5]) {
+  T qc[5], jL[5], jR[5];
+  face_jumps<T, B>(qL, qR, jL, jR);
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    qc[v] = B(0.5) * (qL[v] + qR[v]);
-    jL[v] = qc[v] - qL[v];
-    jR[v] = qc[v] - qR[v];
-  }
-  riemann<T, B>(qL, qR, S, G, flux, fS);
+  for (int v = 0; v < 5; ++v) qc[v] = B(0.5) * (qL[v] + qR[v]);
+  T fv[4];  // f_vis(q_com, grad q_com) . S, momentum and energy
   if (NS) {
     T Gc[5][3];
 #pragma unroll
@@ -300,8 +321,15 @@ __device__ __forceinline__ void face_fn(const T qL[5], const T qR[5], const T gL
     T tau[3][3], e[3];
     viscous_terms<T, B>(qc, Gc, G, tau, e);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) fS[1 + a] = fS[1 + a] - (tau[a][0] * S[0] + tau[a][1] * S[1] + tau[a][2] * S[2]);
-    fS[4] = fS[4] - (e[0] * S[0] + e[1] * S[1] + e[2] * S[2]);
+    for (int a = 0; a < 3; ++a) fv[a] = tau[a][0] * S[0] + tau[a][1] * S[1] + tau[a][2] * S[2];
+    fv[3] = e[0] * S[0] + e[1] * S[1] + e[2] * S[2];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  riemann<T, B, FLUX>(qL, qR, S, G, flux, fS);
+  if (NS) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) fS[1 + a] = fS[1 + a] - fv[a];
+    fS[4] = fS[4] - fv[3];
   }
 }
 
@@ -310,7 +338,7 @@ __device__ __forceinline__ void face_fn(const T qL[5], const T qR[5], const T gL
 // field (Riemann problem with the free stream, common solution halfway).
 // side = 1 if the element lies on the minus side of S (its +xi^d face).
 // cf = g'(face)/J_f of the element.
-template <bool NS, class T, class B>
+template <bool NS, class T, class B, int FLUX = -1>
 __device__ __forceinline__ void bface_fn(const T qi[5], const T gi[5][3], const B S[3], B cf, int bc, int side,
                                          const Gas<B>& G, int flux, T fS[5], T jump[5]) {
   T qb[5];
@@ -333,7 +361,7 @@ __device__ __forceinline__ void bface_fn(const T qi[5], const T gi[5][3], const 
       qm[v] = side ? qi[v] : qf;
       qp[v] = side ? qf : qi[v];
     }
-    riemann<T, B>(qm, qp, S, G, flux, fS);
+    riemann<T, B, FLUX>(qm, qp, S, G, flux, fS);
   }
 #pragma unroll
   for (int v = 0; v < 5; ++v) jump[v] = qb[v] - qi[v];

@@ -102,9 +102,9 @@ hipError_t vjp_fused(const ResArgs<double>& fa, const VjpArgs& va, const MeshDev
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (P.count[1]) {
-    hipLaunchKernelGGL((k_face_fused<double, NS>), dim3(P.count[1]), dim3(256), P.lds[1], s, fa, M.all_faces,
-                       P.tiles[1]);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = M.flux == 1 ? face_stage_fused<double, NS, 1>(fa, M, P, false, s)
+                    : face_stage_fused<double, NS, 0>(fa, M, P, false, s);
+    if (e != hipSuccess) return e;
   }
   if (V.count[2]) {
     hipLaunchKernelGGL((k_elem_rev_fused<NS, false>), dim3(V.count[2]), dim3(256), V.lds[2], s, va,

@@ -187,6 +187,32 @@ hipError_t residual_stages(const ResArgs<T>& a, const MeshDev& M, int sk, hipStr
   return hipSuccess;
 }
 
+// Face stage of the fused plan: interior-face tiles (one or two passes), then
+// the boundary-face tiles in a launch of their own.
+template <class T, bool NS, int FLUX>
+hipError_t face_stage_fused(const ResArgs<T>& a, const MeshDev& M, const FusedPlan& P, bool two_pass, hipStream_t s) {
+  hipError_t e;
+  if (P.n_interior > 0) {
+    if (two_pass) {
+      hipLaunchKernelGGL((k_face_split_fused<T, 0, FLUX>), dim3(P.n_interior), dim3(256), P.lds[1], s, a, M.all_faces,
+                         P.tiles[1]);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_face_split_fused<T, 1, FLUX>), dim3(P.n_interior), dim3(256), P.lds[1], s, a, M.all_faces,
+                         P.tiles[1]);
+    } else {
+      hipLaunchKernelGGL((k_face_fused<T, NS, FLUX>), dim3(P.n_interior), dim3(256), P.lds[1], s, a, M.all_faces,
+                         P.tiles[1]);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (P.count[1] > P.n_interior) {
+    hipLaunchKernelGGL((k_bface_fused<T, NS, FLUX>), dim3(P.count[1] - P.n_interior), dim3(256), 0, s, a, M.all_faces,
+                       P.tiles[1] + P.n_interior);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template <class T, bool NS>
 hipError_t residual_fused(const ResArgs<T>& a, const MeshDev& M, int sk, hipStream_t s) {
   const FusedPlan& P = M.plan[sk];
@@ -198,22 +224,11 @@ hipError_t residual_fused(const ResArgs<T>& a, const MeshDev& M, int sk, hipStre
     if (H) H->begin(names[st], 0, 0, P.count[st], s);
     if (st == 0)
       hipLaunchKernelGGL((k_trace_fused<T, NS>), dim3(P.count[0]), dim3(256), P.lds[0], s, a, M.all_elems, P.tiles[0]);
-    else if (st == 1 && NS && M.split_faces[1][sk]) {
-      // two-pass face stage: interior tiles (first n_interior), then boundary tiles
-      if (P.n_interior > 0) {
-        hipLaunchKernelGGL((k_face_split_fused<T, 0>), dim3(P.n_interior), dim3(256), P.lds[1], s, a, M.all_faces,
-                           P.tiles[1]);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_face_split_fused<T, 1>), dim3(P.n_interior), dim3(256), P.lds[1], s, a, M.all_faces,
-                           P.tiles[1]);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-      }
-      if (P.count[1] > P.n_interior)
-        hipLaunchKernelGGL((k_bface_fused<T, NS>), dim3(P.count[1] - P.n_interior), dim3(256), 0, s, a, M.all_faces,
-                           P.tiles[1] + P.n_interior);
-    } else if (st == 1)
-      hipLaunchKernelGGL((k_face_fused<T, NS>), dim3(P.count[1]), dim3(256), P.lds[1], s, a, M.all_faces, P.tiles[1]);
-    else
+    else if (st == 1) {
+      const bool two_pass = NS && M.split_faces[1][sk];
+      e = M.flux == 1 ? face_stage_fused<T, NS, 1>(a, M, P, two_pass, s) : face_stage_fused<T, NS, 0>(a, M, P, two_pass, s);
+      if (e != hipSuccess) return e;
+    } else
       hipLaunchKernelGGL((k_div_fused<T, NS>), dim3(P.count[2]), dim3(256), P.lds[2], s, a, M.all_elems, P.tiles[2]);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

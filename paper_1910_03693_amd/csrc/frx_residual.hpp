@@ -267,24 +267,43 @@ __device__ __forceinline__ void trace_body(const ResArgs<T>& a, const int4* __re
 // Interior faces whose sides have sizes {NL, NH}, NL <= NH.  Face record
 // (L, R, d, low_is_R): L's +d face is R's -d face; the area vector S points
 // from L to R and is evaluated once per face point from L's map.
-// Block: fpb faces x NH^2 threads (one face point each).
+// Block: fpb faces x NH^2 threads (one face point each).  The stage runs in
+// three phases: face_gather (the inputs of the face point, interpolated from
+// the low side of a mixed face), face_fn, face_scatter (the results to the
+// face slots of both sides, L2-projected to the low side of a mixed face).
+// The gather and scatter depend on (NL, NH), face_fn does not, so the fused
+// kernel holds one copy of face_fn after its switch over the tile kinds.
+
+// State of one interior face point between the phases.
+template <class T> struct FacePt {
+  using B = base_t<T>;
+  T q[2][5];   // q of both sides at the point
+  T g[5][3];   // sum of both sides' gradient traces (Navier-Stokes)
+  B S[3], cL, cR;
+  int oL, oR;  // first face slot of the face on L and on R
+  int lf, pt;  // face of the tile, point of the face
+  bool act, lowL, lowR;
+};
+
 template <int NL, int NH, class T, bool NS>
-__device__ __forceinline__ void face_body(const ResArgs<T>& a, const int4* __restrict__ faces, int nf, int fpb,
-                                          int blk, unsigned char* smem) {
+__device__ __forceinline__ void face_gather(const ResArgs<T>& a, const int4* __restrict__ faces, int nf, int fpb,
+                                            int blk, unsigned char* smem, FacePt<T>& P) {
   using B = base_t<T>;
   constexpr int NH2 = NH * NH, NL2 = NL * NL;
   constexpr bool MIX = NL < NH;
   constexpr int NV = NS ? 20 : 5;
-  T* slow = reinterpret_cast<T*>(smem);              // [fpb][NV][NL2] low-side traces
-  T* sout = slow + (MIX ? fpb * NV * NL2 : 0);       // [fpb][10][NH2] low-side results
+  T* slow = reinterpret_cast<T*>(smem);  // [fpb][NV][NL2] low-side traces
   const OpsTab<B>& O = ops<B>();
   const int tid = threadIdx.x;
-  const int lf = tid / NH2, pt = tid - lf * NH2;
-  const int fi = blk * fpb + lf;
-  const bool act = lf < fpb && fi < nf;
-  const FaceRec F = face_rec(act ? faces[fi] : make_int4(0, 0, 0, 0));
-  const bool lowR = MIX && F.low_is_R;
-  const bool lowL = MIX && !F.low_is_R;
+  P.lf = tid / NH2;
+  P.pt = tid - P.lf * NH2;
+  const int fi = blk * fpb + P.lf;
+  P.act = P.lf < fpb && fi < nf;
+  const FaceRec F = face_rec(P.act ? faces[fi] : make_int4(0, 0, 0, 0));
+  P.oL = F.oL;
+  P.oR = F.oR;
+  P.lowR = MIX && F.low_is_R;
+  P.lowL = MIX && !F.low_is_R;
   if (MIX) {  // stage the low side's own-point traces
     for (int it = tid; it < fpb * NV * NL2; it += blockDim.x) {
       const int l2 = it / (NV * NL2), rem = it - l2 * NV * NL2;
@@ -297,63 +316,76 @@ __device__ __forceinline__ void face_body(const ResArgs<T>& a, const int4* __res
     }
     __syncthreads();
   }
-  if (act) {
-    const int A = pt % NH, Bq = pt / NH;
-    // q of both sides and the SUM of their gradient traces (all that the
-    // BR2 common gradient needs), each side read at the face point
-    T q[2][5], g[1][5][3];
-    if (NS) {
+  if (!P.act) return;
+  const int pt = P.pt, A = pt % NH, Bq = pt / NH;
+  // q of both sides and the SUM of their gradient traces (all that the BR2
+  // common gradient needs), each side read at the face point
+  if (NS) {
 #pragma unroll
-      for (int vc = 0; vc < 15; ++vc) g[0][vc / 3][vc % 3] = T(B(0));
-    }
+    for (int vc = 0; vc < 15; ++vc) P.g[vc / 3][vc % 3] = T(B(0));
+  }
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const bool low = s ? lowR : lowL;
-      if (low) {
-        const T* src = slow + lf * NV * NL2;
+  for (int s = 0; s < 2; ++s) {
+    const bool low = s ? P.lowR : P.lowL;
+    if (low) {
+      const T* src = slow + P.lf * NV * NL2;
 #pragma unroll
-        for (int vv = 0; vv < NV; ++vv) {
-          T acc = T(B(0));
+      for (int vv = 0; vv < NV; ++vv) {
+        T acc = T(B(0));
 #pragma unroll
-          for (int b = 0; b < NL; ++b) {
-            T row = T(B(0));
+        for (int b = 0; b < NL; ++b) {
+          T row = T(B(0));
 #pragma unroll
-            for (int aa = 0; aa < NL; ++aa) row = fmab(O.I[NL - 2][NH - 2][A][aa], src[vv * NL2 + aa + NL * b], row);
-            acc = fmab(O.I[NL - 2][NH - 2][Bq][b], row, acc);
-          }
-          if (vv < 5) q[s][vv] = acc;
-          else g[0][(vv - 5) / 3][(vv - 5) % 3] += acc;
+          for (int aa = 0; aa < NL; ++aa) row = fmab(O.I[NL - 2][NH - 2][A][aa], src[vv * NL2 + aa + NL * b], row);
+          acc = fmab(O.I[NL - 2][NH - 2][Bq][b], row, acc);
         }
-      } else {
-        const long o = (s ? F.oR : F.oL) + pt;
+        if (vv < 5) P.q[s][vv] = acc;
+        else P.g[(vv - 5) / 3][(vv - 5) % 3] += acc;
+      }
+    } else {
+      const long o = (s ? F.oR : F.oL) + pt;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) q[s][v] = a.QF[(long)v * a.nfp + o];
-        if (NS) {
+      for (int v = 0; v < 5; ++v) P.q[s][v] = a.QF[(long)v * a.nfp + o];
+      if (NS) {
 #pragma unroll
-          for (int vc = 0; vc < 15; ++vc) g[0][vc / 3][vc % 3] += a.GF[(long)vc * a.nfp + o];
-        }
+        for (int vc = 0; vc < 15; ++vc) P.g[vc / 3][vc % 3] += a.GF[(long)vc * a.nfp + o];
       }
     }
-    // geometry at the face point, kept at the high side's slot
-    const long og = (lowL ? F.oR : F.oL) + pt;
-    const B S[3] = {a.fgeo[og], a.fgeo[a.nfp + og], a.fgeo[2L * a.nfp + og]};
-    B cL = B(0), cR = B(0);
-    if (NS) {
-      cL = a.fgeo[3L * a.nfp + og];
-      cR = a.fgeo[4L * a.nfp + og];
-    }
-    T fS[5], jL[5], jR[5];
-    face_fn<NS, T, B>(q[0], q[1], g[0], S, cL, cR, a.gas, a.flux, fS, jL, jR);
-    if (!lowL) {
-      const long o = F.oL + pt;
+  }
+  // geometry at the face point, kept at the high side's slot
+  const long og = (P.lowL ? F.oR : F.oL) + pt;
+  P.S[0] = a.fgeo[og];
+  P.S[1] = a.fgeo[a.nfp + og];
+  P.S[2] = a.fgeo[2L * a.nfp + og];
+  P.cL = P.cR = B(0);
+  if (NS) {
+    P.cL = a.fgeo[3L * a.nfp + og];
+    P.cR = a.fgeo[4L * a.nfp + og];
+  }
+}
+
+template <int NL, int NH, class T>
+__device__ __forceinline__ void face_scatter(const ResArgs<T>& a, const int4* __restrict__ faces, int nf, int fpb,
+                                             int blk, unsigned char* smem, const FacePt<T>& P, const T fS[5],
+                                             int nv_low) {
+  using B = base_t<T>;
+  constexpr int NH2 = NH * NH, NL2 = NL * NL;
+  constexpr bool MIX = NL < NH;
+  T* sout = reinterpret_cast<T*>(smem) + (MIX ? fpb * nv_low * NL2 : 0);  // [fpb][10][NH2] low-side results
+  const int pt = P.pt;
+  if (P.act) {
+    T jL[5], jR[5];
+    face_jumps<T, B>(P.q[0], P.q[1], jL, jR);
+    if (!P.lowL) {
+      const long o = P.oL + pt;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         a.FS[(long)v * a.nfp + o] = fS[v];
         a.DQ[(long)v * a.nfp + o] = jL[v];
       }
     }
-    if (!lowR) {
-      const long o = F.oR + pt;
+    if (!P.lowR) {
+      const long o = P.oR + pt;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         a.FS[(long)v * a.nfp + o] = fS[v];
@@ -361,23 +393,18 @@ __device__ __forceinline__ void face_body(const ResArgs<T>& a, const int4* __res
       }
     }
     if (MIX) {
-      // (two explicit branches: a select between the two jump arrays would
-      // be turned into a dynamically indexed private array in scratch)
-      T* dst = sout + lf * 10 * NH2;
+      T* dst = sout + P.lf * 10 * NH2;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) dst[v * NH2 + pt] = fS[v];
-      if (lowL) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) dst[(5 + v) * NH2 + pt] = jL[v];
-      } else {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) dst[(5 + v) * NH2 + pt] = jR[v];
+      for (int v = 0; v < 5; ++v) {
+        dst[v * NH2 + pt] = fS[v];
+        dst[(5 + v) * NH2 + pt] = sel(P.lowL, jL[v], jR[v]);
       }
     }
   }
   if (MIX) {
+    const OpsTab<B>& O = ops<B>();
     __syncthreads();
-    for (int it = tid; it < fpb * NL2; it += blockDim.x) {
+    for (int it = threadIdx.x; it < fpb * NL2; it += blockDim.x) {
       const int l2 = it / NL2, p2 = it - l2 * NL2;
       const int f2 = blk * fpb + l2;
       if (f2 >= nf) continue;
@@ -401,9 +428,20 @@ __device__ __forceinline__ void face_body(const ResArgs<T>& a, const int4* __res
   }
 }
 
+template <int NL, int NH, class T, bool NS, int FLUX = -1>
+__device__ __forceinline__ void face_body(const ResArgs<T>& a, const int4* __restrict__ faces, int nf, int fpb,
+                                          int blk, unsigned char* smem) {
+  using B = base_t<T>;
+  FacePt<T> P;
+  face_gather<NL, NH, T, NS>(a, faces, nf, fpb, blk, smem, P);
+  T fS[5];
+  if (P.act) face_fn<NS, T, B, FLUX>(P.q[0], P.q[1], P.g, P.S, P.cL, P.cR, a.gas, a.flux, fS);
+  face_scatter<NL, NH, T>(a, faces, nf, fpb, blk, smem, P, fS, NS ? 20 : 5);
+}
+
 // Boundary faces of elements of size N: record (e, f, bc, 0).  One thread per
 // face point.
-template <int N, class T, bool NS>
+template <int N, class T, bool NS, int FLUX = -1>
 __device__ __forceinline__ void bface_body(const ResArgs<T>& a, const int4* __restrict__ faces, int nf, int blk) {
   using B = base_t<T>;
   constexpr int N2 = N * N;
@@ -423,7 +461,7 @@ __device__ __forceinline__ void bface_body(const ResArgs<T>& a, const int4* __re
   const B S[3] = {a.fgeo[o], a.fgeo[a.nfp + o], a.fgeo[2L * a.nfp + o]};
   const B cf = a.fgeo[3L * a.nfp + o];
   T fS[5], jmp[5];
-  bface_fn<NS, T, B>(q, g, S, cf, bc, side, a.gas, a.flux, fS, jmp);
+  bface_fn<NS, T, B, FLUX>(q, g, S, cf, bc, side, a.gas, a.flux, fS, jmp);
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     a.FS[(long)v * a.nfp + o] = fS[v];
@@ -862,39 +900,53 @@ __global__ void __launch_bounds__(FRX_MAX_THREADS) k_div_fused(ResArgs<T> a, con
 }
 #undef FRX_ECASE
 
-#define FRX_FCASE(NL, NH) \
-  case 8 * NL + NH: face_body<NL, NH, T, NS>(a, faces + t.y, t.z, t.w, 0, smem); break;
-#define FRX_BCASE(N) \
-  case 64 + N: bface_body<N, T, NS>(a, faces + t.y, t.z, 0); break;
+// Interior-face tiles of the face stage (the plan puts them first), with the
+// Riemann solver fixed at compile time; boundary-face tiles go to
+// k_bface_fused, so that the wall and far-field code does not set the
+// register count of the interior faces.
+#define FRX_FLIST(X)                                            \
+  X(2, 2) X(2, 3) X(2, 4) X(2, 5) X(2, 6) X(3, 3) X(3, 4) X(3, 5) \
+  X(3, 6) X(4, 4) X(4, 5) X(4, 6) X(5, 5) X(5, 6) X(6, 6)
+#define FRX_GCASE(NL, NH) \
+  case 8 * NL + NH: face_gather<NL, NH, T, NS>(a, faces + t.y, t.z, t.w, 0, smem, P); break;
+#define FRX_SCASE(NL, NH) \
+  case 8 * NL + NH: face_scatter<NL, NH, T>(a, faces + t.y, t.z, t.w, 0, smem, P, fS, NS ? 20 : 5); break;
 
-template <class T, bool NS>
-__global__ void __launch_bounds__(FRX_MAX_THREADS) k_face_fused(ResArgs<T> a, const int4* __restrict__ faces,
+// At least two waves per SIMD: the float64-dual Navier-Stokes face needs
+// about 270 registers per lane, one wave per SIMD with nothing to overlap its
+// loads; held to 256 it spills about 26 registers to scratch and runs about
+// a fifth faster.  The other instantiations fit three waves as they are.
+template <class T, bool NS, int FLUX>
+__global__ void __launch_bounds__(FRX_MAX_THREADS) __attribute__((amdgpu_waves_per_eu(2))) k_face_fused(ResArgs<T> a, const int4* __restrict__ faces,
                                                     const int4* __restrict__ tiles) {
+  using B = base_t<T>;
   if (a.skip && *a.skip) return;
   extern __shared__ __align__(16) unsigned char smem[];
   const int4 t = tiles[blockIdx.x];
+  FacePt<T> P;
   switch (t.x) {
-    FRX_FCASE(2, 2) FRX_FCASE(2, 3) FRX_FCASE(2, 4) FRX_FCASE(2, 5) FRX_FCASE(2, 6)
-    FRX_FCASE(3, 3) FRX_FCASE(3, 4) FRX_FCASE(3, 5) FRX_FCASE(3, 6)
-    FRX_FCASE(4, 4) FRX_FCASE(4, 5) FRX_FCASE(4, 6)
-    FRX_FCASE(5, 5) FRX_FCASE(5, 6)
-    FRX_FCASE(6, 6)
-    FRX_BCASE(2) FRX_BCASE(3) FRX_BCASE(4) FRX_BCASE(5) FRX_BCASE(6)
+    FRX_FLIST(FRX_GCASE)
+    default: return;
+  }
+  T fS[5];
+  if (P.act) face_fn<NS, T, B, FLUX>(P.q[0], P.q[1], P.g, P.S, P.cL, P.cR, a.gas, a.flux, fS);
+  switch (t.x) {
+    FRX_FLIST(FRX_SCASE)
     default: break;
   }
 }
-#undef FRX_FCASE
-#undef FRX_BCASE
+#undef FRX_GCASE
+#undef FRX_SCASE
 
 // Two-pass face stage of Navier-Stokes (interior-face tiles only, which the
 // plan puts first): PASS 0 the inviscid pass, PASS 1 the viscous correction.
 #define FRX_SCASE(NL, NH)                                                        \
   case 8 * NL + NH:                                                             \
-    if constexpr (PASS == 0) face_body<NL, NH, T, false>(a, faces + t.y, t.z, t.w, 0, smem); \
+    if constexpr (PASS == 0) face_body<NL, NH, T, false, FLUX>(a, faces + t.y, t.z, t.w, 0, smem); \
     else face_visc_body<NL, NH, T>(a, faces + t.y, t.z, t.w, 0, smem);           \
     break;
 
-template <class T, int PASS>
+template <class T, int PASS, int FLUX>
 __global__ void __launch_bounds__(FRX_MAX_THREADS) k_face_split_fused(ResArgs<T> a, const int4* __restrict__ faces,
                                                                       const int4* __restrict__ tiles) {
   if (a.skip && *a.skip) return;
@@ -911,10 +963,10 @@ __global__ void __launch_bounds__(FRX_MAX_THREADS) k_face_split_fused(ResArgs<T>
 }
 #undef FRX_SCASE
 
-// Boundary-face tiles of the two-pass face stage (the plan puts them last).
+// Boundary-face tiles of the face stage (the plan puts them last).
 #define FRX_BCASE(N) \
-  case 64 + N: bface_body<N, T, NS>(a, faces + t.y, t.z, 0); break;
-template <class T, bool NS>
+  case 64 + N: bface_body<N, T, NS, FLUX>(a, faces + t.y, t.z, 0); break;
+template <class T, bool NS, int FLUX>
 __global__ void __launch_bounds__(FRX_MAX_THREADS) k_bface_fused(ResArgs<T> a, const int4* __restrict__ faces,
                                                                  const int4* __restrict__ tiles) {
   if (a.skip && *a.skip) return;
