@@ -59,8 +59,16 @@ __device__ void volume_flux_vjp(const double q[5], const double G[5][3], const d
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int v = 0; v < 5; ++v) s += Ft[i][v].d * Fb[i][v];
-    if (j < 5) qb[j] = s;
-    else Gb[(j - 5) / 3][(j - 5) % 3] = s;
+    // (stores by compare and select: an index by the loop counter would put
+    // the arrays in scratch)
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+      if (j == v) qb[v] = s;
+    if (NS) {
+#pragma unroll
+      for (int vc = 0; vc < 15; ++vc)
+        if (j == 5 + vc) Gb[vc / 3][vc % 3] = s;
+    }
   }
   if (!NS)
     for (int v = 0; v < 5; ++v)
@@ -283,7 +291,7 @@ __device__ __forceinline__ void div_rev_body(const VjpArgs& a, const int* __rest
       __syncthreads();
       if (act) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sX[(le * 5 + v) * N3 + k] = dqb[i][v];
+        for (int v = 0; v < 5; ++v) sX[(le * 5 + v) * N3 + k] = i == 0 ? dqb[0][v] : (i == 1 ? dqb[1][v] : dqb[2][v]);
       }
       __syncthreads();
       if (act) {
@@ -293,7 +301,7 @@ __device__ __forceinline__ void div_rev_body(const VjpArgs& a, const int* __rest
 #pragma unroll
           for (int m = 0; m < N; ++m) {
             const int kk = i == 0 ? m + N * (i1 + N * i2) : (i == 1 ? i0 + N * (m + N * i2) : i0 + N * (i1 + N * m));
-            Ub[v] = fma(O.D[N][m][id[i]], X[v * N3 + kk], Ub[v]);
+            Ub[v] = fma(O.D[N][m][i == 0 ? i0 : (i == 1 ? i1 : i2)], X[v * N3 + kk], Ub[v]);
           }
       }
       // adjoint of the solution jumps of the two faces of direction i
@@ -560,7 +568,7 @@ __device__ __forceinline__ void trace_rev_body(const VjpArgs& a, const int* __re
       __syncthreads();
       if (act) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sX[(le * 5 + v) * N3 + k] = dqb[i][v];
+        for (int v = 0; v < 5; ++v) sX[(le * 5 + v) * N3 + k] = i == 0 ? dqb[0][v] : (i == 1 ? dqb[1][v] : dqb[2][v]);
       }
       __syncthreads();
       if (act) {
@@ -570,7 +578,7 @@ __device__ __forceinline__ void trace_rev_body(const VjpArgs& a, const int* __re
 #pragma unroll
           for (int m = 0; m < N; ++m) {
             const int kk = i == 0 ? m + N * (i1 + N * i2) : (i == 1 ? i0 + N * (m + N * i2) : i0 + N * (i1 + N * m));
-            Ub[v] = fma(O.D[N][m][id[i]], X[v * N3 + kk], Ub[v]);
+            Ub[v] = fma(O.D[N][m][i == 0 ? i0 : (i == 1 ? i1 : i2)], X[v * N3 + kk], Ub[v]);
           }
       }
     }
