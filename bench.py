@@ -425,16 +425,20 @@ def step_study(which):
     J32 = torch.empty_like(vv, dtype=torch.float32)
     v32 = vv.float()
 
-    def t_op(fn, reps=10):
+    def t_op(fn, reps=10, batches=3):
+        # median over batches of reps calls: a single batch can catch a stall
         fn()
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(reps):
-            fn()
-        b.record()
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / reps
+        times = []
+        for _ in range(batches):
+            a.record()
+            for _ in range(reps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b) / reps)
+        return float(np.median(times))
 
     ops = {"residual_f64": t_op(lambda: ctx.residual(U, out=R)),
            "jvp_exact_f64": t_op(lambda: ctx.jvp(U, vv, out=J)),
