@@ -186,6 +186,12 @@ def main():
         }
         per_op[mode] = {k: {"ms": round(t, 5), "gdof_s": round(n_dof / (t * 1e-3) / 1e9, 3)} for k, t in ops.items()}
     ctx.set_launch(True)
+    # the nodal filter (p > 2, alpha = 0.2; one launch per filtered degree in either mode), in place
+    Uf = U.clone()
+    t_f = timed(lambda: ctx.nodal_filter(Uf, 0.2, 3, out=Uf), reps)
+    n_filt = int(5 * ((case.elem_p.astype(np.int64) + 1) ** 3)[case.elem_p >= 3].sum())
+    per_op["nodal_filter_p_gt_2"] = {"ms": round(t_f, 5), "filtered_dof": n_filt,
+                                     "gb_s": round(16 * n_filt / (t_f * 1e-3) / 1e9, 1)}
 
     # per-kernel timing of the float64 tangent in the batched launch (HIP events on this stream)
     kt = ctx.profile(U, op=1, reps=20)

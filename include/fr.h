@@ -192,6 +192,21 @@ fr_status fr_select_degrees(fr_ctx ctx, const double* U, int32_t var, double nu_
  * buffers).  FR_E_INVALID if the element counts or devices differ. */
 fr_status fr_project(fr_ctx src, const double* U_src, fr_ctx dst, double* U_dst, void* stream);
 
+/* Nodal polynomial filter (section 4.2, the SD7003 runs with p^3 elements;
+ * the method of Fischer and Mullen): in every element of degree p >= p_from
+ * (the paper filters p > 2, i.e. p_from = 3, with alpha = 0.2),
+ *   q <- (1 - alpha) q + alpha P q,
+ * P the projection onto the degree p - 1 space taken as in fr_project
+ * (reference-space L2 projection onto the tensor polynomials of degree
+ * p - 1, the highest Legendre mode of each direction removed) and evaluated
+ * at the element's solution points; all five variables.  Elements of lower
+ * degree keep their values.  U, U_out: device float64 [5][n_sp]; U_out may
+ * be U (in place), otherwise U is copied to U_out first on the stream.
+ * FR_E_INVALID for alpha outside [0, 1] or p_from outside 1..5.  The paper
+ * does not say when in the step the filter acts; the caller applies it (for
+ * example after each time step). */
+fr_status fr_filter(fr_ctx ctx, const double* U, double* U_out, double alpha, int32_t p_from, void* stream);
+
 /* Picks, per degree bucket and scalar kind, the launch shapes of the residual
  * kernels by timing the candidates on U (device float64). */
 fr_status fr_autotune(fr_ctx ctx, const double* U, void* stream);

@@ -133,6 +133,8 @@ hipError_t launch_indicator(const MeshDev& M, const double* U, int var, double* 
 hipError_t launch_select_degrees(const MeshDev& M, const double* U, int var, double nu_max, double nu_min, int p_min,
                                  int p_max, int8_t* p_new, hipStream_t s);
 hipError_t launch_project(const MeshDev& Ms, const double* Us, const MeshDev& Md, double* Ud, hipStream_t s);
+// nodal polynomial filter of the elements of degree >= p_from (Uout may be U)
+hipError_t launch_filter(const MeshDev& M, const double* U, double* Uout, double alpha, int p_from, hipStream_t s);
 // fills M.fgeo_d and M.fgeo_f from the trilinear maps (once per mesh)
 hipError_t launch_face_geometry(const MeshDev& M, hipStream_t s);
 }  // namespace frx

@@ -182,4 +182,68 @@ __global__ void __launch_bounds__(256) k_project(const double* __restrict__ Us, 
   for (int v = 0; v < 5; ++v) Ud[(long)v * nsp_d + off_d[e] + t] = acc[v];
 }
 
+// Nodal polynomial filter of the elements of size N (section 4.2, the
+// SD7003 case; the filter of Fischer and Mullen): q <- (1 - alpha) q +
+// alpha Pi q with Pi the reference-space L2 projection onto the tensor
+// polynomials of degree N - 2, i.e. the highest Legendre mode of each
+// direction removed, evaluated at the element's Gauss points.  One block per
+// element (N^3 threads used); Pi is applied direction by direction with the
+// N x N matrix M[i][a] = sum_{m < N-1} P_m(x_i) (2m+1)/2 w_a P_m(x_a).
+// Uout may be U: a block reads its element completely before writing it.
+template <int N>
+__global__ void __launch_bounds__(256) k_filter(const double* U, int nsp, const int4* __restrict__ recs,
+                                               double alpha, double* Uout) {
+  constexpr int N3 = N * N * N;
+  __shared__ double M[N][N];
+  __shared__ double X[5][N3], Y[5][N3];
+  const OpsTab<double>& O = ops<double>();
+  const int t = threadIdx.x;
+  const long off = recs[blockIdx.x].y;
+  if (t < N * N) {
+    const int i = t / N, a = t - i * N;
+    double s = 0.0;
+    for (int m = 0; m < N - 1; ++m) s += O.V[N][i][m] * O.Vinv[N][m][a];
+    M[i][a] = s;
+  }
+  double q[5];
+  if (t < N3) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      q[v] = U[(long)v * nsp + off + t];
+      X[v][t] = q[v];
+    }
+  }
+  const int i0 = t % N, i1 = (t / N) % N, i2 = t / (N * N);
+  __syncthreads();
+  if (t < N3) {  // along xi
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      double s = 0.0;
+#pragma unroll
+      for (int a = 0; a < N; ++a) s += M[i0][a] * X[v][a + N * (i1 + N * i2)];
+      Y[v][t] = s;
+    }
+  }
+  __syncthreads();
+  if (t < N3) {  // along eta
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      double s = 0.0;
+#pragma unroll
+      for (int b = 0; b < N; ++b) s += M[i1][b] * Y[v][i0 + N * (b + N * i2)];
+      X[v][t] = s;
+    }
+  }
+  __syncthreads();
+  if (t < N3) {  // along zeta, then the blend
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) s += M[i2][c] * X[v][i0 + N * (i1 + N * c)];
+      Uout[(long)v * nsp + off + t] = (1.0 - alpha) * q[v] + alpha * s;
+    }
+  }
+}
+
 }  // namespace frx

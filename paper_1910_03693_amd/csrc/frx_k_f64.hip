@@ -77,6 +77,24 @@ hipError_t launch_select_degrees(const MeshDev& M, const double* U, int var, dou
   return hipMemcpyAsync(p_new, a, M.E, hipMemcpyDeviceToDevice, s);
 }
 
+hipError_t launch_filter(const MeshDev& M, const double* U, double* Uout, double alpha, int p_from, hipStream_t s) {
+  for (const ElemBucket& b : M.eb) {
+    if (!b.count || b.n - 1 < p_from) continue;
+    const dim3 grid(b.count), blk(round64(b.n * b.n * b.n));
+    switch (b.n) {
+      case 2: hipLaunchKernelGGL(k_filter<2>, grid, blk, 0, s, U, M.nsp, (const int4*)b.recs, alpha, Uout); break;
+      case 3: hipLaunchKernelGGL(k_filter<3>, grid, blk, 0, s, U, M.nsp, (const int4*)b.recs, alpha, Uout); break;
+      case 4: hipLaunchKernelGGL(k_filter<4>, grid, blk, 0, s, U, M.nsp, (const int4*)b.recs, alpha, Uout); break;
+      case 5: hipLaunchKernelGGL(k_filter<5>, grid, blk, 0, s, U, M.nsp, (const int4*)b.recs, alpha, Uout); break;
+      case 6: hipLaunchKernelGGL(k_filter<6>, grid, blk, 0, s, U, M.nsp, (const int4*)b.recs, alpha, Uout); break;
+      default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_project(const MeshDev& Ms, const double* Us, const MeshDev& Md, double* Ud, hipStream_t s) {
   hipLaunchKernelGGL(k_project, dim3(Ms.E), dim3(256), 0, s, Us, Ms.nsp, (const int*)Ms.sp_off,
                      (const int8_t*)Ms.p_dev, Ud, Md.nsp, (const int*)Md.sp_off, (const int8_t*)Md.p_dev);

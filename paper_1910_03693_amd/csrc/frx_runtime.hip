@@ -1275,6 +1275,20 @@ fr_status fr_project(fr_ctx src, const double* U_src, fr_ctx dst, double* U_dst,
   });
 }
 
+fr_status fr_filter(fr_ctx c, const double* U, double* U_out, double alpha, int32_t p_from, void* stream) {
+  if (!c) return FR_E_INVALID;
+  if (!U || !U_out) return fail(c, FR_E_INVALID, "fr_filter: bad arguments");
+  if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(c, FR_E_INVALID, "fr_filter: alpha outside [0, 1]");
+  if (p_from < 1 || p_from > NMAX - 1) return fail(c, FR_E_INVALID, "fr_filter: p_from outside 1..5");
+  return guarded(c, [&]() -> fr_status {
+    hipStream_t s = S(stream);
+    if ((const double*)U_out != U)
+      FRX_TRY(hipMemcpyAsync(U_out, U, sizeof(double) * c->ndof, hipMemcpyDeviceToDevice, s));
+    FRX_TRY(launch_filter(c->M, U, U_out, alpha, p_from, s));
+    return FR_OK;
+  });
+}
+
 fr_status fr_set_launch(fr_ctx c, int32_t mode) {
   if (!c) return FR_E_INVALID;
   const int base = mode & ~(FR_LAUNCH_FACES_TWO_PASS | FR_LAUNCH_FACES_ONE_PASS);

@@ -26,7 +26,7 @@ FR_LAUNCH_FACES_TWO_PASS, FR_LAUNCH_FACES_ONE_PASS = 4, 8
 STATUS_NAMES = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_NOMEM", -3: "FR_E_HIP", -4: "FR_E_NOTCONVERGED",
                 -5: "FR_E_NONPHYSICAL", -6: "FR_E_UNSUPPORTED"}
 EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_residual", "fr_residual_jvp", "fr_jvp", "fr_vjp", "gmres_stage_solve",
-            "esdirk_step", "spectral_decay_indicator", "fr_select_degrees", "fr_project", "fr_autotune", "fr_profile",
+            "esdirk_step", "spectral_decay_indicator", "fr_select_degrees", "fr_project", "fr_filter", "fr_autotune", "fr_profile",
             "fr_set_launch", "fr_check", "fr_last_error")
 
 
@@ -93,6 +93,7 @@ def lib():
         L.spectral_decay_indicator.argtypes = [vp, vp, C.c_int32, vp, vp, vp]
         L.fr_select_degrees.argtypes = [vp, vp, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32, vp, vp]
         L.fr_project.argtypes = [vp, vp, vp, vp, vp]
+        L.fr_filter.argtypes = [vp, vp, vp, C.c_double, C.c_int32, vp]
         L.fr_autotune.argtypes = [vp, vp, vp]
         L.fr_check.argtypes = [vp, C.POINTER(C.c_int32), vp]
         L.fr_set_launch.argtypes = [vp, C.c_int32]
@@ -231,6 +232,12 @@ def fr_project(h_src, U_src, h_dst, U_dst, stream=None):
                                    _stream(stream)), h_dst)
 
 
+def fr_filter(h, U, U_out, alpha, p_from, stream=None):
+    n = U.numel()
+    return _check(lib().fr_filter(h, _dev(U, torch.float64), _dev(U_out, torch.float64, n), alpha, p_from,
+                                  _stream(stream)), h)
+
+
 def fr_autotune(h, U, stream=None):
     return _check(lib().fr_autotune(h, _dev(U, torch.float64), _stream(stream)), h)
 
@@ -331,6 +338,14 @@ class Context:
         """U (this context's layout) moved to the context `dst` (same mesh)."""
         out = torch.empty((5, dst.n_dof // 5), dtype=torch.float64, device=U.device)
         fr_project(self.h, U, dst.h, out)
+        return out
+
+    def nodal_filter(self, U, alpha=0.2, p_from=3, out=None):
+        """Nodal polynomial filter (section 4.2): in every element of degree
+        >= p_from, (1 - alpha) q + alpha (q projected onto degree p - 1).
+        out may be U (in place); by default a new tensor."""
+        out = torch.empty_like(U) if out is None else out
+        fr_filter(self.h, U, out, alpha, p_from)
         return out
 
     def autotune(self, U):
