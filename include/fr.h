@@ -100,13 +100,20 @@ typedef struct {
   int32_t converged;
 } fr_gmres_stats;
 
-/* Pseudo-transient continuation inside ESDIRK2 (section 2.3). */
+/* ESDIRK schemes of section 2.3: the three-stage, second-order ESDIRK2 and
+ * the six-stage, fourth-order ESDIRK4 (the implicit tableau of Kennedy and
+ * Carpenter's ARK4(3)6L[2]SA, which the paper takes from Bijl et al.). */
+enum { FR_ESDIRK2 = 0, FR_ESDIRK4 = 1 };
+
+/* Pseudo-transient continuation inside an ESDIRK step (section 2.3). */
 typedef struct {
   double dtau_init, dtau_max, dtau_min;  /* SER bounds (eq. ser); halving floor */
   double tol_pseudo;                     /* ||F|| / ||F^0|| stop (paper: 1e-4) */
   int32_t max_ptc_iter;
-  int32_t last_stage;                    /* 3: full step; 2: return stage 2's solution */
+  int32_t last_stage;                    /* 0 (or the stage count): full step; 2..s-1: return
+                                            that stage's solution */
   fr_gmres_opts gmres;
+  int32_t scheme;                        /* FR_ESDIRK2 (default, 0) or FR_ESDIRK4 */
 } fr_step_opts;
 
 typedef struct {
@@ -156,10 +163,12 @@ fr_status fr_vjp(fr_ctx ctx, const double* U, const double* w, double* JTw, void
 fr_status gmres_stage_solve(fr_ctx ctx, const double* U, double shift, const double* F, double* dU,
                             const fr_gmres_opts* opts, fr_gmres_stats* stats, void* stream);
 
-/* One step of the three-stage, second-order ESDIRK2 (eq. ESDIRK_ns):
- * stages 2 and 3 are solved by pseudo-transient continuation with SER
- * (eqs. pseudo_transient, ser) and GMRES; a GMRES failure halves dtau and
- * redoes the iterate.  U: device float64, in/out. */
+/* One step of ESDIRK2 or ESDIRK4 (eq. ESDIRK_ns, opts->scheme): stages
+ * 2..s are solved by pseudo-transient continuation with SER (eqs.
+ * pseudo_transient, ser) and GMRES; a GMRES failure halves dtau and redoes
+ * the iterate; each stage starts from the previous stage's solution.
+ * U: device float64, in/out.  FR_E_INVALID for an unknown scheme or a
+ * last_stage outside {0, 2..s}. */
 fr_status esdirk_step(fr_ctx ctx, double* U, double dt, const fr_step_opts* opts, fr_step_stats* stats,
                       void* stream);
 

@@ -64,6 +64,10 @@ def lib():
                                    C.c_int, C.c_double, ip, dp]
         L.oracle_esdirk2_step.restype = C.c_int
         L.oracle_esdirk2_step.argtypes = [C.c_void_p, dp, C.c_double, dp, dp]
+        L.oracle_esdirk_step.restype = C.c_int
+        L.oracle_esdirk_step.argtypes = [C.c_void_p, dp, C.c_double, dp, dp, C.c_int]
+        L.oracle_esdirk_tableau.restype = C.c_int
+        L.oracle_esdirk_tableau.argtypes = [C.c_int, dp, dp, dp]
         L.oracle_common_flux.argtypes = [C.c_int, C.c_double, dp, dp, dp, dp]
         L.oracle_physical_flux.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp, dp]
         L.oracle_esdirk2_tableau.argtypes = [dp, dp, dp]
@@ -116,6 +120,17 @@ def esdirk2_tableau():
     c = np.zeros(3)
     lib().oracle_esdirk2_tableau(_p(A), _p(b), _p(c))
     return A, b, c
+
+
+def esdirk_tableau(scheme):
+    """(A, b, c) of scheme 0 (ESDIRK2, 3 stages) or 1 (ESDIRK4, 6 stages)."""
+    A = np.zeros(36)
+    b = np.zeros(6)
+    c = np.zeros(6)
+    s = lib().oracle_esdirk_tableau(scheme, _p(A), _p(b), _p(c))
+    if s == 0:
+        raise ValueError(f"unknown ESDIRK scheme {scheme}")
+    return A[:s * s].reshape(s, s).copy(), b[:s].copy(), c[:s].copy()
 
 
 def radau_gL_d(p, x):
@@ -225,10 +240,17 @@ class Oracle:
 
     def esdirk2_step(self, U, dt, dtau_init, dtau_max, dtau_min=0.0, tol_pseudo=1e-4, tol_gmres=1e-1,
                      restart=60, max_gmres_it=100, max_ptc_it=200, jv_mode=1, fd_eps=1e-6, last_stage=3):
+        return self.esdirk_step(U, dt, dtau_init, dtau_max, dtau_min, tol_pseudo, tol_gmres, restart, max_gmres_it,
+                                max_ptc_it, jv_mode, fd_eps, last_stage, scheme=0)
+
+    def esdirk_step(self, U, dt, dtau_init, dtau_max, dtau_min=0.0, tol_pseudo=1e-4, tol_gmres=1e-1,
+                    restart=60, max_gmres_it=100, max_ptc_it=200, jv_mode=1, fd_eps=1e-6, last_stage=0, scheme=0):
+        """One step of scheme 0 (ESDIRK2) or 1 (ESDIRK4); last_stage 0 (or the
+        stage count) for the full step, 2..s-1 for a stage solution."""
         Uo = self._vec(U).copy()
         opts = _f64([dtau_init, dtau_max, dtau_min, tol_pseudo, tol_gmres, restart, max_gmres_it,
                      max_ptc_it, jv_mode, fd_eps, last_stage])
         stats = np.zeros(4)
-        st = lib().oracle_esdirk2_step(self.h, _p(Uo), dt, _p(opts), _p(stats))
+        st = lib().oracle_esdirk_step(self.h, _p(Uo), dt, _p(opts), _p(stats), scheme)
         return Uo, dict(status=st, ptc_iterations=int(stats[0]), gmres_iterations=int(stats[1]),
                         halvings=int(stats[2]), final_rel_F=float(stats[3]))

@@ -1029,33 +1029,63 @@ int oracle_gmres(void* h, const double* U, double shift, const double* F, double
   return gmres(c, shift, F, x, m, max_it, tol, iters, rel_res);
 }
 
-// One step of the three-stage, second-order, stiffly accurate ESDIRK2 (eq.
-// ESDIRK_ns): a_21 = a_22 = a_33 = gamma = 1 - sqrt(2)/2, a_31 = a_32 = (1-gamma)/2,
-// b = last row.  Stages 2..3 are solved by pseudo-transient continuation (eq.
-// pseudo_transient linearised as in eq. linearized_pseudo_transient_final) with
-// the SER update of eq. ser and restarted GMRES; a GMRES failure within
-// max_gmres_it halves dtau and redoes the iterate.  If last_stage < 3 the stage
-// solution q^{last_stage} is returned instead of q^{n+1}.
+// Butcher tableau of the ESDIRK schemes of section 2.3 (explicit first
+// stage, one diagonal coefficient, stiffly accurate: b = last row).  Scheme 0:
+// the three-stage, second-order ESDIRK2 (gamma = 1 - sqrt(2)/2); scheme 1: the
+// six-stage, fourth-order ESDIRK4 the paper takes from Bijl et al., the
+// implicit tableau of Kennedy and Carpenter's ARK4(3)6L[2]SA (gamma = 1/4).
+// Returns the number of stages, 0 for an unknown scheme.
+static int esdirk_tableau(int scheme, double A[6][6], double b[6]) {
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) A[i][j] = 0.0;
+  int s = 0;
+  if (scheme == 0) {
+    const double g = 1.0 - std::sqrt(2.0) / 2.0;
+    A[1][0] = g; A[1][1] = g;
+    A[2][0] = (1 - g) / 2; A[2][1] = (1 - g) / 2; A[2][2] = g;
+    s = 3;
+  } else if (scheme == 1) {
+    const double g = 0.25;
+    A[1][0] = g; A[1][1] = g;
+    A[2][0] = 8611.0 / 62500.0; A[2][1] = -1743.0 / 31250.0; A[2][2] = g;
+    A[3][0] = 5012029.0 / 34652500.0; A[3][1] = -654441.0 / 2922500.0; A[3][2] = 174375.0 / 388108.0; A[3][3] = g;
+    A[4][0] = 15267082809.0 / 155376265600.0; A[4][1] = -71443401.0 / 120774400.0;
+    A[4][2] = 730878875.0 / 902184768.0; A[4][3] = 2285395.0 / 8070912.0; A[4][4] = g;
+    A[5][0] = 82889.0 / 524892.0; A[5][1] = 0.0; A[5][2] = 15625.0 / 83664.0; A[5][3] = 69875.0 / 102672.0;
+    A[5][4] = -2260.0 / 8211.0; A[5][5] = g;
+    s = 6;
+  }
+  for (int j = 0; j < 6; ++j) b[j] = s ? A[s - 1][j] : 0.0;
+  return s;
+}
+
+// One step of an ESDIRK scheme (eq. ESDIRK_ns): stages 2..s each solved by
+// pseudo-transient continuation on eq. ESDIRK_conservative (Newton steps of
+// eq. pseudo_transient linearised as in eq. linearized_pseudo_transient_final)
+// with the SER update of eq. ser and restarted GMRES; a GMRES failure within
+// max_gmres_it halves dtau and redoes the iterate.  If 2 <= last_stage < s the
+// stage solution q^{last_stage} is returned instead of q^{n+1}.
 // opts: [dtau_init, dtau_max, dtau_min, tol_pseudo, tol_gmres, restart, max_gmres_it,
 //        max_ptc_it, jv_mode, fd_eps, last_stage]
 // stats: [ptc_iterations, gmres_iterations, halvings, final ||F||/||F0|| of the last stage]
-int oracle_esdirk2_step(void* h, double* U, double dt, const double* opts, double* stats) {
+int oracle_esdirk_step(void* h, double* U, double dt, const double* opts, double* stats, int scheme) {
   Mesh& M = *(Mesh*)h;
   long N = 5 * M.n_sp;
-  const double gam = 1.0 - std::sqrt(2.0) / 2.0;
-  const double A[3][3] = {{0, 0, 0}, {gam, gam, 0}, {(1 - gam) / 2, (1 - gam) / 2, gam}};
-  const double b[3] = {(1 - gam) / 2, (1 - gam) / 2, gam};
+  double A[6][6], b[6];
+  const int ns = esdirk_tableau(scheme, A, b);
+  if (!ns) return 3;
   double dtau_init = opts[0], dtau_max = opts[1], dtau_min = opts[2], tol_p = opts[3], tol_g = opts[4];
   int restart = (int)opts[5], max_git = (int)opts[6], max_ptc = (int)opts[7], mode = (int)opts[8];
   double fd_eps = opts[9];
   int last_stage = (int)opts[10];
+  if (last_stage < 2 || last_stage > ns) last_stage = ns;
   for (int i = 0; i < 4; ++i) stats[i] = 0;
   std::vector<double> qn(U, U + N), q(qn), rhs(N), F(N), dq(N), Rq(N);
-  std::vector<std::vector<double>> Rs(3, std::vector<double>(N));
+  std::vector<std::vector<double>> Rs(ns, std::vector<double>(N));
   residual<double>(M, qn.data(), Rs[0].data());
-  double w = gam;
+  const double w = A[1][1];
   int status = 0;
-  for (int i = 1; i < 3 && i < last_stage; ++i) {
+  for (int i = 1; i < last_stage; ++i) {
     for (long l = 0; l < N; ++l) {
       double s = qn[l];
       for (int j = 0; j < i; ++j) s += dt * A[i][j] * Rs[j][l];
@@ -1091,16 +1121,20 @@ int oracle_esdirk2_step(void* h, double* U, double dt, const double* opts, doubl
     if (status) break;
     residual<double>(M, q.data(), Rs[i].data());
   }
-  if (last_stage < 3) {
+  if (last_stage < ns) {
     for (long l = 0; l < N; ++l) U[l] = q[l];
   } else {
     for (long l = 0; l < N; ++l) {
       double s = qn[l];
-      for (int j = 0; j < 3; ++j) s += dt * b[j] * Rs[j][l];
+      for (int j = 0; j < ns; ++j) s += dt * b[j] * Rs[j][l];
       U[l] = s;
     }
   }
   return status;
+}
+
+int oracle_esdirk2_step(void* h, double* U, double dt, const double* opts, double* stats) {
+  return oracle_esdirk_step(h, U, dt, opts, stats, 0);
 }
 
 }  // extern "C"
@@ -1137,15 +1171,22 @@ void oracle_physical_flux_n(long npts, double gamma, double mu, double prandtl, 
   for (long i = 0; i < npts; ++i) oracle_physical_flux(gamma, mu, prandtl, q + 5 * i, G + 15 * i, f + 15 * i);
 }
 
-// The ESDIRK2 tableau used by oracle_esdirk2_step (A row-major 3x3, b, c).
-void oracle_esdirk2_tableau(double* A, double* b, double* c) {
-  const double gam = 1.0 - std::sqrt(2.0) / 2.0;
-  const double a[9] = {0, 0, 0, gam, gam, 0, (1 - gam) / 2, (1 - gam) / 2, gam};
-  for (int i = 0; i < 9; ++i) A[i] = a[i];
-  for (int i = 0; i < 3; ++i) {
-    b[i] = a[6 + i];
-    c[i] = a[3 * i] + a[3 * i + 1] + a[3 * i + 2];
+// The tableau used by oracle_esdirk_step (A row-major s x s, b, c); returns s.
+int oracle_esdirk_tableau(int scheme, double* A, double* b, double* c) {
+  double T[6][6], bb[6];
+  const int s = esdirk_tableau(scheme, T, bb);
+  for (int i = 0; i < s; ++i) {
+    b[i] = bb[i];
+    c[i] = 0.0;
+    for (int j = 0; j < s; ++j) {
+      A[i * s + j] = T[i][j];
+      c[i] += T[i][j];
+    }
   }
+  return s;
 }
+
+// The ESDIRK2 tableau (A row-major 3x3, b, c).
+void oracle_esdirk2_tableau(double* A, double* b, double* c) { oracle_esdirk_tableau(0, A, b, c); }
 
 }  // extern "C"

@@ -1154,24 +1154,84 @@ fr_status gmres_stage_solve(fr_ctx c, const double* U, double shift, const doubl
   });
 }
 
+// Butcher tableaux of the ESDIRK schemes (section 2.3): explicit first
+// stage, one diagonal coefficient w, stiffly accurate (b = last row).
+// ESDIRK2: three stages, second order, w = 1 - sqrt(2)/2.  ESDIRK4: six
+// stages, fourth order, w = 1/4, the scheme the paper cites from Bijl et al.
+// (the implicit tableau of Kennedy and Carpenter's ARK4(3)6L[2]SA).
+struct Esdirk {
+  int s = 0;
+  double A[6][6] = {};
+};
+Esdirk esdirk_scheme(int scheme) {
+  Esdirk T;
+  if (scheme == FR_ESDIRK2) {
+    const double w = 1.0 - std::sqrt(2.0) / 2.0;
+    T.s = 3;
+    T.A[1][0] = T.A[1][1] = w;
+    T.A[2][0] = T.A[2][1] = 0.5 * (1 - w);
+    T.A[2][2] = w;
+  } else if (scheme == FR_ESDIRK4) {
+    T.s = 6;
+    const double r[6][6] = {
+        {0, 0, 0, 0, 0, 0},
+        {0.25, 0.25, 0, 0, 0, 0},
+        {8611.0 / 62500.0, -1743.0 / 31250.0, 0.25, 0, 0, 0},
+        {5012029.0 / 34652500.0, -654441.0 / 2922500.0, 174375.0 / 388108.0, 0.25, 0, 0},
+        {15267082809.0 / 155376265600.0, -71443401.0 / 120774400.0, 730878875.0 / 902184768.0,
+         2285395.0 / 8070912.0, 0.25, 0},
+        {82889.0 / 524892.0, 0.0, 15625.0 / 83664.0, 69875.0 / 102672.0, -2260.0 / 8211.0, 0.25}};
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) T.A[i][j] = r[i][j];
+  }
+  return T;
+}
+
+// out = base + sum_k coef[k] x[k] (terms with a zero coefficient skipped),
+// three terms per pass
+void accumulate(fr_ctx c, double* out, const double* base, const double* coef, const double* const* x, int cnt,
+                hipStream_t s) {
+  const double* cf[6];
+  const double* xs[6];
+  int m = 0;
+  for (int k = 0; k < cnt; ++k)
+    if (coef[k] != 0.0) {
+      cf[m] = coef + k;
+      xs[m++] = x[k];
+    }
+  const double* src = base;
+  int k = 0;
+  do {
+    const double c1 = k < m ? *cf[k] : 0.0, c2 = k + 1 < m ? *cf[k + 1] : 0.0, c3 = k + 2 < m ? *cf[k + 2] : 0.0;
+    lincomb(c, out, 1.0, src, c1, k < m ? xs[k] : nullptr, c2, k + 1 < m ? xs[k + 1] : nullptr, c3,
+            k + 2 < m ? xs[k + 2] : nullptr, s);
+    src = out;
+    k += 3;
+  } while (k < m);
+}
+
 fr_status esdirk_step(fr_ctx c, double* U, double dt, const fr_step_opts* o, fr_step_stats* st, void* stream) {
   if (!c) return FR_E_INVALID;
   if (!U || !o || !(dt > 0.0)) return fail(c, FR_E_INVALID, "esdirk_step: bad arguments");
-  if (o->last_stage != 2 && o->last_stage != 3) return fail(c, FR_E_INVALID, "esdirk_step: last_stage must be 2 or 3");
+  const Esdirk T = esdirk_scheme(o->scheme);
+  if (!T.s) return fail(c, FR_E_INVALID, "esdirk_step: unknown scheme");
+  const int last_stage = o->last_stage == 0 ? T.s : o->last_stage;
+  if (last_stage < 2 || last_stage > T.s)
+    return fail(c, FR_E_INVALID, "esdirk_step: last_stage must be 0 (the full step) or 2..stages");
   return guarded(c, [&]() -> fr_status {
     hipStream_t s = S(stream);
     const long n = c->ndof;
-    if (!c->es) c->es = (double*)c->dalloc(sizeof(double) * 8 * n);
+    if (!c->es) c->es = (double*)c->dalloc(sizeof(double) * 11 * n);
     double* qn = c->es;
     double* q = qn + n;
     double* rhs = q + n;
     double* F = rhs + n;
     double* dq = F + n;
-    double* Rs = dq + n;  // 3 stage residuals
-    const double gam = 1.0 - std::sqrt(2.0) / 2.0;
-    const double A[3][3] = {{0, 0, 0}, {gam, gam, 0}, {0.5 * (1 - gam), 0.5 * (1 - gam), gam}};
-    const double b[3] = {0.5 * (1 - gam), 0.5 * (1 - gam), gam};
-    const double w = gam;
+    double* Rs = dq + n;  // up to 6 stage residuals
+    const double(&A)[6][6] = T.A;
+    const double w = A[1][1];
+    const double* Rj[6];
+    for (int j = 0; j < 6; ++j) Rj[j] = Rs + (size_t)j * n;
     fr_step_stats stats{0, 0, 0, 0, 0.0};
     FRX_TRY(hipMemcpyAsync(qn, U, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     FRX_TRY(hipMemcpyAsync(q, U, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
@@ -1180,8 +1240,10 @@ fr_status esdirk_step(fr_ctx c, double* U, double dt, const fr_step_opts* o, fr_
     rc.out = Rs;
     FRX_TRY(launch_residual_f64(c->M, rc, s));
     fr_status status = FR_OK;
-    for (int i = 1; i < 3 && i < o->last_stage; ++i) {
-      lincomb(c, rhs, 1.0, qn, dt * A[i][0], Rs, i > 1 ? dt * A[i][1] : 0.0, i > 1 ? Rs + n : nullptr, 0, nullptr, s);
+    for (int i = 1; i < last_stage; ++i) {
+      double cf[6];
+      for (int j = 0; j < i; ++j) cf[j] = dt * A[i][j];
+      accumulate(c, rhs, qn, cf, Rj, i, s);
       double dtau = o->dtau_init, nF0 = 0.0, nFprev = 0.0;
       double* Rq = Rs + (size_t)i * n;
       for (int m = 0;; ++m) {
@@ -1230,10 +1292,12 @@ fr_status esdirk_step(fr_ctx c, double* U, double dt, const fr_step_opts* o, fr_
       stats.stages += 1;
       if (status != FR_OK) break;
     }
-    if (o->last_stage < 3 || status != FR_OK) {
+    if (last_stage < T.s || status != FR_OK) {
       FRX_TRY(hipMemcpyAsync(U, q, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    } else {
-      lincomb(c, U, 1.0, qn, dt * b[0], Rs, dt * b[1], Rs + n, dt * b[2], Rs + 2 * n, s);
+    } else {  // q^{n+1} = q^n + dt sum_j b_j R(q^j), b the last row
+      double cf[6];
+      for (int j = 0; j < T.s; ++j) cf[j] = dt * A[T.s - 1][j];
+      accumulate(c, U, qn, cf, Rj, T.s, s);
     }
     FRX_TRY(hipStreamSynchronize(s));
     if (st) *st = stats;

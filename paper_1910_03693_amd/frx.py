@@ -23,6 +23,7 @@ FR_F64, FR_F32 = 0, 1
 FR_JV_EXACT, FR_JV_FD = 0, 1
 FR_LAUNCH_PER_BUCKET, FR_LAUNCH_FUSED = 0, 1
 FR_LAUNCH_FACES_TWO_PASS, FR_LAUNCH_FACES_ONE_PASS = 4, 8
+FR_ESDIRK2, FR_ESDIRK4 = 0, 1
 STATUS_NAMES = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_NOMEM", -3: "FR_E_HIP", -4: "FR_E_NOTCONVERGED",
                 -5: "FR_E_NONPHYSICAL", -6: "FR_E_UNSUPPORTED"}
 EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_residual", "fr_residual_jvp", "fr_jvp", "fr_vjp", "gmres_stage_solve",
@@ -55,7 +56,7 @@ class fr_gmres_stats(C.Structure):
 class fr_step_opts(C.Structure):
     _fields_ = [("dtau_init", C.c_double), ("dtau_max", C.c_double), ("dtau_min", C.c_double),
                 ("tol_pseudo", C.c_double), ("max_ptc_iter", C.c_int32), ("last_stage", C.c_int32),
-                ("gmres", fr_gmres_opts)]
+                ("gmres", fr_gmres_opts), ("scheme", C.c_int32)]
 
 
 class fr_step_stats(C.Structure):
@@ -194,10 +195,12 @@ def gmres_stage_solve(h, U, shift, F, dU, opts, stream=None, check=True):
     return r, dict(iterations=st.iterations, cycles=st.cycles, rel_res=st.rel_res, converged=bool(st.converged))
 
 
-def step_opts(dtau_init, dtau_max, dtau_min=0.0, tol_pseudo=1e-4, max_ptc_iter=200, last_stage=3, gmres=None):
+def step_opts(dtau_init, dtau_max, dtau_min=0.0, tol_pseudo=1e-4, max_ptc_iter=200, last_stage=0, gmres=None,
+              scheme=FR_ESDIRK2):
+    """last_stage 0: the full step; 2..s-1: that stage's solution."""
     o = fr_step_opts()
     o.dtau_init, o.dtau_max, o.dtau_min, o.tol_pseudo = dtau_init, dtau_max, dtau_min, tol_pseudo
-    o.max_ptc_iter, o.last_stage = max_ptc_iter, last_stage
+    o.max_ptc_iter, o.last_stage, o.scheme = max_ptc_iter, last_stage, scheme
     o.gmres = gmres if gmres is not None else gmres_opts()
     return o
 

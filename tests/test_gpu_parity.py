@@ -355,6 +355,55 @@ def test_esdirk_full_step_mixed_vs_plain(frx, oracle_mod):
         assert err <= 1e-6
 
 
+@pytest.mark.parametrize("last_stage", [3, 5, 0], ids=["stage3", "stage5", "full"])
+def test_esdirk4_vortex_to_1e8(frx, oracle_mod, last_stage):
+    """ESDIRK4 (six stages): stage solutions and the full step on the vortex
+    against the oracle's ESDIRK4, both solved to 1e-8."""
+    case = CASES["vortex_p2_rusanov"]
+    orc, ctx, U = _pair(frx, oracle_mod, case)
+    kw = dict(dtau_init=0.05, dtau_max=10.0, tol_pseudo=1e-8, last_stage=last_stage)
+    Uo, so = orc.esdirk_step(case.U, 0.1, restart=20, tol_gmres=1e-8, jv_mode=1, scheme=1, **kw)
+    Ug = U.clone()
+    sg = ctx.esdirk_step(Ug, 0.1, gmres=dict(restart=20, tol=1e-8, jv_mode=frx.FR_JV_FD), scheme=frx.FR_ESDIRK4,
+                         **kw)
+    print("ESDIRK4 last stage", last_stage, sg, so)
+    assert sg["status"] == 0 and so["status"] == 0
+    assert sg["stages"] == (5 if last_stage == 0 else last_stage - 1)
+    err = np.linalg.norm(Ug.cpu().numpy() - Uo) / np.linalg.norm(Uo)
+    print("rel diff", err)
+    assert err <= 1e-7
+
+
+def test_esdirk4_full_step_mixed_ns(frx, oracle_mod):
+    """ESDIRK4 full step on mixed p = 1..5 Navier-Stokes: FP64 exact tangent
+    with graphs and the mixed FP32 form against the oracle's ESDIRK4."""
+    case = CASES["mixed_p1to5_ns_roe"]
+    orc, ctx, U = _pair(frx, oracle_mod, case)
+    kw = dict(dtau_init=0.005, dtau_max=0.05, tol_pseudo=1e-6)
+    Uo, so = orc.esdirk_step(case.U, 0.05, restart=30, tol_gmres=1e-3, jv_mode=0, scheme=1, **kw)
+    assert so["status"] == 0
+    ref = np.linalg.norm(Uo)
+    ctx.set_launch(True)
+    for g in (dict(restart=30, tol=1e-3, jv_mode=frx.FR_JV_EXACT, precision=frx.FR_F64, use_graph=True),
+              dict(restart=30, tol=1e-3, jv_mode=frx.FR_JV_EXACT, precision=frx.FR_F32, use_graph=True)):
+        Ug = U.clone()
+        sg = ctx.esdirk_step(Ug, 0.05, gmres=g, scheme=frx.FR_ESDIRK4, **kw)
+        err = np.linalg.norm(Ug.cpu().numpy() - Uo) / ref
+        print("ESDIRK4 full step", g, sg, "rel diff to oracle", err)
+        assert sg["status"] == 0 and sg["stages"] == 5
+        assert err <= 1e-6
+
+
+def test_esdirk_invalid_scheme_and_stage(frx, oracle_mod):
+    case = CASES["vortex_p2_rusanov"]
+    orc, ctx, U = _pair(frx, oracle_mod, case)
+    for kw in (dict(scheme=2), dict(scheme=frx.FR_ESDIRK2, last_stage=4), dict(scheme=frx.FR_ESDIRK4, last_stage=7),
+               dict(scheme=frx.FR_ESDIRK4, last_stage=1)):
+        with pytest.raises(frx.FrError) as ei:
+            ctx.esdirk_step(U.clone(), 0.05, dtau_init=0.05, dtau_max=1.0, **kw)
+        assert ei.value.status == frx.FR_E_INVALID
+
+
 def test_indicator_degree_field_matches_oracle(frx, oracle_mod):
     """The degree field of the vortex-street workload (at 16x16x2) chosen from
     the GPU indicator equals the one chosen from the oracle's indicator with

@@ -423,6 +423,79 @@ def test_esdirk2_stage_converges(oracle_mod):
     assert np.linalg.norm(res) <= 1e-7 * np.linalg.norm(F0) / (w) + 1e-12
 
 
+# ------------------------------------------------------------------- ESDIRK4
+def test_esdirk4_tableau_order_and_stability(oracle_mod):
+    """The six-stage ESDIRK4 (section 2.3, from Bijl et al.): explicit first
+    stage, one diagonal coefficient, stiffly accurate, and the eight
+    conditions of order 4; L-stable, A-stable on samples, R(z) = e^z + O(z^5)."""
+    A, b, c = oracle_mod.esdirk_tableau(1)
+    one = np.ones(6)
+    assert A.shape == (6, 6)
+    assert np.allclose(A @ one, c, atol=1e-15)
+    assert np.all(A[0] == 0) and np.all(np.diag(A)[1:] == A[1, 1]) and np.all(np.triu(A, 1) == 0)
+    assert np.array_equal(A[5], b)
+    Ac = A @ c
+    conds = [b.sum() - 1, b @ c - 1 / 2, b @ c ** 2 - 1 / 3, b @ Ac - 1 / 6,
+             b @ c ** 3 - 1 / 4, b @ (c * Ac) - 1 / 8, b @ (A @ c ** 2) - 1 / 12, b @ (A @ Ac) - 1 / 24]
+    assert max(abs(x) for x in conds) < 1e-14, conds
+    # not fifth order (a plausible slip, e.g. a wrong b, would also break these)
+    assert abs(b @ c ** 4 - 1 / 5) > 1e-4
+
+    def R(z):
+        return 1 + z * b @ np.linalg.solve(np.eye(6) - z * A, one)
+
+    def R_det(z):
+        return np.linalg.det(np.eye(6) - z * A + z * np.outer(one, b)) / np.linalg.det(np.eye(6) - z * A)
+
+    assert abs(R_det(-1e8)) < 1e-6                        # L-stable
+    for z in (-0.1, -1.0, -10.0, -100.0, 1j, 5j, 30j, -1 + 3j):
+        assert abs(R(z)) <= 1 + 1e-12                    # A-stable samples
+    for z in (3e-2, 1e-2):                               # fourth order
+        assert abs(R(z) - np.exp(z)) < 0.05 * abs(z) ** 5
+
+
+@pytest.mark.slow
+def test_esdirk4_temporal_order_on_vortex(oracle_mod):
+    c = I.case_vortex(4, 4, 1, lengths=(10.0, 10.0, 2.5), p=2)
+    orc = oracle_mod.Oracle.from_case(c)
+    T = 0.8
+
+    def run(nsteps):
+        U = c.U.copy()
+        for _ in range(nsteps):
+            U, st = orc.esdirk_step(U, T / nsteps, 10.0, 10.0, tol_pseudo=1e-12, tol_gmres=1e-13,
+                                    restart=40, max_gmres_it=400, jv_mode=0, scheme=1)
+            assert st["status"] == 0
+        return U
+
+    ref = run(16)
+    e1 = np.linalg.norm(run(2) - ref)
+    e2 = np.linalg.norm(run(4) - ref)
+    rate = math.log(e1 / e2) / math.log(2)
+    print("ESDIRK4 errors", e1, e2, "rate", rate)
+    assert rate > 3.5, rate
+
+
+def test_esdirk4_stage_converges(oracle_mod):
+    """Stage 4 of ESDIRK4 satisfies its equation
+    q_4 - dt g R(q_4) = q^n + dt sum_{j<4} a_4j R(q_j), with the stage
+    solutions q_2, q_3 returned by the same routine."""
+    c = I.case_vortex(4, 4, 1, lengths=(10.0, 10.0, 2.5), p=2)
+    orc = oracle_mod.Oracle.from_case(c)
+    A, b, cc = oracle_mod.esdirk_tableau(1)
+    dt = 0.05
+    kw = dict(tol_pseudo=1e-10, tol_gmres=1e-11, restart=30, jv_mode=0, scheme=1)
+    q = [c.U]
+    for st_ in (2, 3, 4):
+        Ui, st = orc.esdirk_step(c.U, dt, 0.05, 10.0, last_stage=st_, **kw)
+        assert st["status"] == 0
+        q.append(Ui)
+    R = [orc.residual(x) for x in q]
+    rhs = c.U + dt * sum(A[3, j] * R[j] for j in range(3))
+    res = q[3] - dt * A[3, 3] * R[3] - rhs
+    assert np.linalg.norm(res) <= 1e-8 * np.linalg.norm(dt * R[0])
+
+
 # ----------------------------------------------------------------- indicator
 def test_indicator_pins(oracle_mod):
     mesh = I.box_mesh(2, 2, 2, (2.0, 2.0, 2.0), origin=(-1.0, -1.0, -1.0))
