@@ -327,7 +327,8 @@ def copy_calibration(torch, mib):
 
 def implicit_steps(ctx, case, U, frx, torch):
     """One ESDIRK2 step, plain float64 / finite-difference Jv / uniform launches
-    versus mixed float32 exact Jv + float32 basis + graph, same tolerances."""
+    versus mixed float32 exact Jv + float32 basis + graph, same tolerances;
+    and one six-stage ESDIRK4 step in the mixed form."""
     dt = 0.005
     common = dict(dtau_init=dt / 10, dtau_max=dt, tol_pseudo=1e-4, max_ptc_iter=50)
     plain_g = dict(restart=30, max_iter=100, tol=1e-1, jv_mode=frx.FR_JV_FD, precision=frx.FR_F64,
@@ -337,15 +338,17 @@ def implicit_steps(ctx, case, U, frx, torch):
     exact64_g = dict(mixed_g, precision=frx.FR_F64)
     res = {"dt": dt, "settings": {**common, "restart": 30, "tol_gmres": 1e-1}}
     outs = {}
-    for name, g, fused in (("plain_f64_fd", plain_g, False), ("mixed_f32_exact_graph", mixed_g, True),
-                           ("f64_exact_graph", exact64_g, True)):
+    for name, g, fused, scheme in (("plain_f64_fd", plain_g, False, frx.FR_ESDIRK2),
+                                   ("mixed_f32_exact_graph", mixed_g, True, frx.FR_ESDIRK2),
+                                   ("f64_exact_graph", exact64_g, True, frx.FR_ESDIRK2),
+                                   ("esdirk4_mixed_f32_exact_graph", mixed_g, True, frx.FR_ESDIRK4)):
         ctx.set_launch(fused)
         Uw = U.clone()
-        ctx.esdirk_step(Uw, dt, gmres=g, **common)  # warm-up (allocation, capture)
+        ctx.esdirk_step(Uw, dt, gmres=g, scheme=scheme, **common)  # warm-up (allocation, capture)
         Uw = U.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = ctx.esdirk_step(Uw, dt, gmres=g, **common)
+        st = ctx.esdirk_step(Uw, dt, gmres=g, scheme=scheme, **common)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
         outs[name] = Uw
