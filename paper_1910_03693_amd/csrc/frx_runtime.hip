@@ -740,7 +740,11 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
           const int tv = (ns && 20 * n3 * sb > 65536) ? 5 : (ns ? 20 : 5);
           const size_t per_el = st == 0 ? (size_t)tv * n3 * sb : (size_t)(5 * n3 + 30 * n * n) * sb;
           int epb = std::max(1, 256 / n3);
-          while (epb > 1 && epb * per_el > cap) --epb;
+          // trace tiles at most 53 KB: three blocks per CU (160 KB of LDS),
+          // which the trace kernels' registers allow; the divergence kernels'
+          // registers allow two, so they keep 64 KB
+          const size_t cap_st = st == 0 ? 53 * 1024 : cap;
+          while (epb > 1 && epb * per_el > cap_st) --epb;
           lds = std::max(lds, epb * per_el);
           for (int i = 0; i < kv.second.second; i += epb) {
             const int cnt = std::min(epb, kv.second.second - i);
