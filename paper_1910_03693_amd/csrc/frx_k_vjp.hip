@@ -111,9 +111,18 @@ hipError_t vjp_fused(const ResArgs<double>& fa, const VjpArgs& va, const MeshDev
                        (const int*)M.all_ids, V.tiles[2]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if (V.count[1]) {
-    hipLaunchKernelGGL((k_face_rev_fused<NS>), dim3(V.count[1]), dim3(256), V.lds[1], s, va, M.all_faces,
-                       V.tiles[1]);
+  if (V.n_interior > 0) {
+    if (M.flux == 1)
+      hipLaunchKernelGGL((k_face_rev_fused<NS, 1>), dim3(V.n_interior), dim3(256), V.lds[1], s, va, M.all_faces,
+                         V.tiles[1]);
+    else
+      hipLaunchKernelGGL((k_face_rev_fused<NS, 0>), dim3(V.n_interior), dim3(256), V.lds[1], s, va, M.all_faces,
+                         V.tiles[1]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (V.count[1] > V.n_interior) {
+    hipLaunchKernelGGL((k_bface_rev_fused<NS>), dim3(V.count[1] - V.n_interior), dim3(256), 0, s, va, M.all_faces,
+                       V.tiles[1] + V.n_interior);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (V.count[0]) {
@@ -184,6 +193,7 @@ hipError_t launch_vjp(const MeshDev& M, const double* U, const double* w, double
   va.sp_off = M.sp_off;
   va.fp_off = M.fp_off;
   va.geo = M.geo_d;
+  va.fgeo = M.fgeo_d;
   va.QF = fa.QF;
   va.GF = fa.GF;
   va.DQ = fa.DQ;

@@ -828,10 +828,18 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
         }
       }
     }
-    std::stable_sort(tiles.begin(), tiles.end(),
-                     [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) { return x.first > y.first; });
+    // by decreasing work, interior-face tiles before boundary-face tiles
+    std::stable_sort(tiles.begin(), tiles.end(), [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) {
+      const bool bx = x.second.x >= 64, by = y.second.x >= 64;
+      if (bx != by) return !bx;
+      return x.first > y.first;
+    });
     std::vector<int4> t;
     for (auto& x : tiles) t.push_back(x.second);
+    if (st == 1) {
+      V.n_interior = 0;
+      for (auto& x : t) V.n_interior += x.x < 64 ? 1 : 0;
+    }
     V.count[st] = (int)t.size();
     V.lds[st] = lds;
     V.tiles[st] = (int4*)c->dalloc(sizeof(int4) * std::max<size_t>(1, t.size()));

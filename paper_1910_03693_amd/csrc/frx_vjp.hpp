@@ -27,6 +27,7 @@ struct VjpArgs {
   const int* sp_off;
   const int* fp_off;
   const double* geo;
+  const double* fgeo;  // [5][nfp] face-point geometry (k_face_geo)
   double* QF;  // forward q traces, then their adjoints
   double* GF;  // forward gradient traces, then their adjoints
   double* DQ;  // forward solution jumps, then their adjoints
@@ -87,7 +88,8 @@ __device__ __forceinline__ void visc_dot_S(const D64 q[5], const D64 G[5][3], co
 }
 
 // Adjoint of face_fn at one point: given fSb, jLb, jRb return qLb, qRb, gLb, gRb.
-template <bool NS>
+// FLUX >= 0 fixes the Riemann solver at compile time (as in riemann).
+template <bool NS, int FLUX = -1>
 __device__ void face_fn_vjp(const double qL[5], const double qR[5], const double gL[5][3], const double gR[5][3],
                             const double S[3], double cL, double cR, const Gas<double>& gas, int flux,
                             const double fSb[5], const double jLb[5], const double jRb[5], double qLb[5],
@@ -101,7 +103,7 @@ __device__ void face_fn_vjp(const double qL[5], const double qR[5], const double
       a[v] = D64(qL[v], j == v ? 1.0 : 0.0);
       b[v] = D64(qR[v], j == 5 + v ? 1.0 : 0.0);
     }
-    riemann<D64, double>(a, b, S, gas, flux, o);
+    riemann<D64, double, FLUX>(a, b, S, gas, flux, o);
     double s = 0.0;
 #pragma unroll
     for (int v = 0; v < 5; ++v) s += o[v].d * fSb[v];
@@ -332,24 +334,38 @@ __global__ void __launch_bounds__(256) k_div_rev(VjpArgs a, const int* __restric
 }
 
 // --------------------------------------------------------------- face_rev
+// Like the forward face stage, in three phases: face_rev_gather (forward
+// inputs and output adjoints of the face point, interpolated from the low
+// side of a mixed face), face_fn_vjp (once per point; the fused kernel holds
+// a single copy after its switch over the tile kinds), face_rev_scatter (the
+// adjoints to the face slots, transposed interpolation to the low side).
+struct FaceRevPt {
+  double q[2][5], g[2][5][3];  // forward q and gradient traces of both sides
+  double fSb[5], jb[2][5];     // adjoints of f_com . S and of both jumps
+  double S[3], cL, cR;
+  int oL, oR, lf, pt;
+  bool act, lowL, lowR;
+};
+
 template <int NL, int NH, bool NS>
-__device__ __forceinline__ void face_rev_body(const VjpArgs& a, const int4* __restrict__ faces, int nf, int fpb,
-                                              int blk, unsigned char* smem) {
+__device__ __forceinline__ void face_rev_gather(const VjpArgs& a, const int4* __restrict__ faces, int nf, int fpb,
+                                                int blk, unsigned char* smem, FaceRevPt& P) {
   constexpr int NH2 = NH * NH, NL2 = NL * NL;
   constexpr bool MIX = NL < NH;
   constexpr int NV = NS ? 20 : 5;
   double* slow = reinterpret_cast<double*>(smem);           // [fpb][NV][NL2] forward low-side traces
   double* sadj = slow + (MIX ? fpb * NV * NL2 : 0);          // [fpb][10][NL2] low-side fS-bar, jump-bar
-  double* sres = sadj + (MIX ? fpb * 10 * NL2 : 0);          // [fpb][NV][NH2] low-side results at high points
   const OpsTab<double>& O = ops<double>();
   const int tid = threadIdx.x;
-  const int lf = tid / NH2, pt = tid - lf * NH2;
-  const int fi = blk * fpb + lf;
-  const bool act = lf < fpb && fi < nf;
-  const FaceRec F = face_rec(act ? faces[fi] : make_int4(0, 0, 0, 0));
-  const int L = F.L, R = F.R, d = F.d;
-  const bool lowR = MIX && F.low_is_R;
-  const bool lowL = MIX && !F.low_is_R;
+  P.lf = tid / NH2;
+  P.pt = tid - P.lf * NH2;
+  const int fi = blk * fpb + P.lf;
+  P.act = P.lf < fpb && fi < nf;
+  const FaceRec F = face_rec(P.act ? faces[fi] : make_int4(0, 0, 0, 0));
+  P.oL = F.oL;
+  P.oR = F.oR;
+  P.lowR = MIX && F.low_is_R;
+  P.lowL = MIX && !F.low_is_R;
   if (MIX) {
     for (int it = tid; it < fpb * (NV + 10) * NL2; it += blockDim.x) {
       const int l2 = it / ((NV + 10) * NL2), rem = it - l2 * (NV + 10) * NL2;
@@ -368,68 +384,76 @@ __device__ __forceinline__ void face_rev_body(const VjpArgs& a, const int4* __re
     }
     __syncthreads();
   }
-  double qb[2][5], gb[2][5][3];
-  if (act) {
-    const int A = pt % NH, Bq = pt / NH;
-    double q[2][5], g[2][5][3], fSb[5], jb[2][5];
-    for (int v = 0; v < 5; ++v) fSb[v] = 0.0;
-    for (int s = 0; s < 2; ++s) {
-      const bool low = s ? lowR : lowL;
-      if (low) {
-        const double* src = slow + lf * NV * NL2;
-        for (int vv = 0; vv < NV; ++vv) {
-          double acc = 0.0;
-          for (int b = 0; b < NL; ++b) {
-            double row = 0.0;
-            for (int aa = 0; aa < NL; ++aa) row = fma(O.I[NL - 2][NH - 2][A][aa], src[vv * NL2 + aa + NL * b], row);
-            acc = fma(O.I[NL - 2][NH - 2][Bq][b], row, acc);
-          }
-          if (vv < 5) q[s][vv] = acc;
-          else g[s][(vv - 5) / 3][(vv - 5) % 3] = acc;
+  if (!P.act) return;
+  const int pt = P.pt, A = pt % NH, Bq = pt / NH;
+  for (int v = 0; v < 5; ++v) P.fSb[v] = 0.0;
+  for (int s = 0; s < 2; ++s) {
+    const bool low = s ? P.lowR : P.lowL;
+    if (low) {
+      const double* src = slow + P.lf * NV * NL2;
+      for (int vv = 0; vv < NV; ++vv) {
+        double acc = 0.0;
+        for (int b = 0; b < NL; ++b) {
+          double row = 0.0;
+          for (int aa = 0; aa < NL; ++aa) row = fma(O.I[NL - 2][NH - 2][A][aa], src[vv * NL2 + aa + NL * b], row);
+          acc = fma(O.I[NL - 2][NH - 2][Bq][b], row, acc);
         }
-        // transposed projection of the low side's adjoints
-        const double* adj = sadj + lf * 10 * NL2;
-        for (int w = 0; w < 10; ++w) {
-          double acc = 0.0;
-          for (int b = 0; b < NL; ++b)
-            for (int aa = 0; aa < NL; ++aa)
-              acc += O.P[NL - 2][NH - 2][aa][A] * O.P[NL - 2][NH - 2][b][Bq] * adj[w * NL2 + aa + NL * b];
-          if (w < 5) fSb[w] += acc;
-          else jb[s][w - 5] = NS ? acc : 0.0;
-        }
+        if (vv < 5) P.q[s][vv] = acc;
+        else P.g[s][(vv - 5) / 3][(vv - 5) % 3] = acc;
+      }
+      // transposed projection of the low side's adjoints
+      const double* adj = sadj + P.lf * 10 * NL2;
+      for (int w = 0; w < 10; ++w) {
+        double acc = 0.0;
+        for (int b = 0; b < NL; ++b)
+          for (int aa = 0; aa < NL; ++aa)
+            acc += O.P[NL - 2][NH - 2][aa][A] * O.P[NL - 2][NH - 2][b][Bq] * adj[w * NL2 + aa + NL * b];
+        if (w < 5) P.fSb[w] += acc;
+        else P.jb[s][w - 5] = NS ? acc : 0.0;
+      }
+    } else {
+      const long o = (s ? F.oR : F.oL) + pt;
+      for (int v = 0; v < 5; ++v) {
+        P.q[s][v] = a.QF[(long)v * a.nfp + o];
+        P.fSb[v] += a.FS[(long)v * a.nfp + o];
+        P.jb[s][v] = NS ? a.DQ[(long)v * a.nfp + o] : 0.0;  // Euler: jumps do not enter R
+      }
+      if (NS) {
+        for (int vc = 0; vc < 15; ++vc) P.g[s][vc / 3][vc % 3] = a.GF[(long)vc * a.nfp + o];
       } else {
-        const long o = (s ? F.oR : F.oL) + pt;
-        for (int v = 0; v < 5; ++v) {
-          q[s][v] = a.QF[(long)v * a.nfp + o];
-          fSb[v] += a.FS[(long)v * a.nfp + o];
-          jb[s][v] = NS ? a.DQ[(long)v * a.nfp + o] : 0.0;  // Euler: jumps do not enter R
-        }
-        if (NS) {
-          for (int vc = 0; vc < 15; ++vc) g[s][vc / 3][vc % 3] = a.GF[(long)vc * a.nfp + o];
-        } else {
-          for (int vc = 0; vc < 15; ++vc) g[s][vc / 3][vc % 3] = 0.0;
-        }
+        for (int vc = 0; vc < 15; ++vc) P.g[s][vc / 3][vc % 3] = 0.0;
       }
     }
-    double S[3], JL, SR[3], JR;
-    face_geom<double>(a.geo + 24L * L, d, 1.0, O.x[NH][A], O.x[NH][Bq], S, JL);
-    double cL = 0.0, cR = 0.0;
-    if (NS) {
-      face_geom<double>(a.geo + 24L * R, d, -1.0, O.x[NH][A], O.x[NH][Bq], SR, JR);
-      const int nL = lowL ? NL : NH, nR = lowR ? NL : NH;
-      cL = 0.5 * (double)(nL * nL) / JL;
-      cR = -0.5 * (double)(nR * nR) / JR;
-    }
-    face_fn_vjp<NS>(q[0], q[1], g[0], g[1], S, cL, cR, a.gas, a.flux, fSb, jb[0], jb[1], qb[0], qb[1], gb[0], gb[1]);
+  }
+  // geometry of the face point, kept at the high side's slot
+  const long og = (P.lowL ? F.oR : F.oL) + pt;
+  P.S[0] = a.fgeo[og];
+  P.S[1] = a.fgeo[a.nfp + og];
+  P.S[2] = a.fgeo[2L * a.nfp + og];
+  P.cL = NS ? a.fgeo[3L * a.nfp + og] : 0.0;
+  P.cR = NS ? a.fgeo[4L * a.nfp + og] : 0.0;
+}
+
+template <int NL, int NH, bool NS>
+__device__ __forceinline__ void face_rev_scatter(const VjpArgs& a, const int4* __restrict__ faces, int nf, int fpb,
+                                                 int blk, unsigned char* smem, const FaceRevPt& P,
+                                                 const double qb[2][5], const double gb[2][5][3]) {
+  constexpr int NH2 = NH * NH, NL2 = NL * NL;
+  constexpr bool MIX = NL < NH;
+  constexpr int NV = NS ? 20 : 5;
+  double* sres = reinterpret_cast<double*>(smem) + (MIX ? fpb * (NV + 10) * NL2 : 0);  // [fpb][NV][NH2]
+  const OpsTab<double>& O = ops<double>();
+  const int tid = threadIdx.x, pt = P.pt;
+  if (P.act) {
     for (int s = 0; s < 2; ++s) {
-      const bool low = s ? lowR : lowL;
+      const bool low = s ? P.lowR : P.lowL;
       if (!low) {
-        const long o = (s ? F.oR : F.oL) + pt;
+        const long o = (s ? P.oR : P.oL) + pt;
         for (int v = 0; v < 5; ++v) a.QF[(long)v * a.nfp + o] = qb[s][v];
         if (NS)
           for (int vc = 0; vc < 15; ++vc) a.GF[(long)vc * a.nfp + o] = gb[s][vc / 3][vc % 3];
       } else {
-        double* dst = sres + lf * NV * NH2;
+        double* dst = sres + P.lf * NV * NH2;
         for (int v = 0; v < 5; ++v) dst[v * NH2 + pt] = qb[s][v];
         if (NS)
           for (int vc = 0; vc < 15; ++vc) dst[(5 + vc) * NH2 + pt] = gb[s][vc / 3][vc % 3];
@@ -457,6 +481,18 @@ __device__ __forceinline__ void face_rev_body(const VjpArgs& a, const int4* __re
       }
     }
   }
+}
+
+template <int NL, int NH, bool NS>
+__device__ __forceinline__ void face_rev_body(const VjpArgs& a, const int4* __restrict__ faces, int nf, int fpb,
+                                              int blk, unsigned char* smem) {
+  FaceRevPt P;
+  face_rev_gather<NL, NH, NS>(a, faces, nf, fpb, blk, smem, P);
+  double qb[2][5], gb[2][5][3];
+  if (P.act)
+    face_fn_vjp<NS>(P.q[0], P.q[1], P.g[0], P.g[1], P.S, P.cL, P.cR, a.gas, a.flux, P.fSb, P.jb[0], P.jb[1], qb[0],
+                    qb[1], gb[0], gb[1]);
+  face_rev_scatter<NL, NH, NS>(a, faces, nf, fpb, blk, smem, P, qb, gb);
 }
 template <int NL, int NH, bool NS>
 __global__ void __launch_bounds__(256) k_face_rev(VjpArgs a, const int4* __restrict__ faces, int nf, int fpb) {
@@ -615,26 +651,49 @@ __global__ void __launch_bounds__(256) k_elem_rev_fused(VjpArgs a, const int* __
 }
 #undef FRX_VCASE
 
-#define FRX_VFCASE(NL, NH) \
-  case 8 * NL + NH: face_rev_body<NL, NH, NS>(a, faces + t.y, t.z, t.w, 0, smem); break;
-#define FRX_VBCASE(N) \
-  case 64 + N: bface_rev_body<N, NS>(a, faces + t.y, t.z, 0); break;
-template <bool NS>
+#define FRX_VFLIST(X)                                           \
+  X(2, 2) X(2, 3) X(2, 4) X(2, 5) X(2, 6) X(3, 3) X(3, 4) X(3, 5) \
+  X(3, 6) X(4, 4) X(4, 5) X(4, 6) X(5, 5) X(5, 6) X(6, 6)
+#define FRX_VGCASE(NL, NH) \
+  case 8 * NL + NH: face_rev_gather<NL, NH, NS>(a, faces + t.y, t.z, t.w, 0, smem, P); break;
+#define FRX_VSCASE(NL, NH) \
+  case 8 * NL + NH: face_rev_scatter<NL, NH, NS>(a, faces + t.y, t.z, t.w, 0, smem, P, qb, gb); break;
+// Interior-face tiles (the plan puts them first); boundary-face tiles go to
+// k_bface_rev_fused.
+template <bool NS, int FLUX>
 __global__ void __launch_bounds__(256) k_face_rev_fused(VjpArgs a, const int4* __restrict__ faces,
                                                         const int4* __restrict__ tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int4 t = tiles[blockIdx.x];
+  FaceRevPt P;
   switch (t.x) {
-    FRX_VFCASE(2, 2) FRX_VFCASE(2, 3) FRX_VFCASE(2, 4) FRX_VFCASE(2, 5) FRX_VFCASE(2, 6)
-    FRX_VFCASE(3, 3) FRX_VFCASE(3, 4) FRX_VFCASE(3, 5) FRX_VFCASE(3, 6)
-    FRX_VFCASE(4, 4) FRX_VFCASE(4, 5) FRX_VFCASE(4, 6)
-    FRX_VFCASE(5, 5) FRX_VFCASE(5, 6)
-    FRX_VFCASE(6, 6)
+    FRX_VFLIST(FRX_VGCASE)
+    default: return;
+  }
+  double qb[2][5], gb[2][5][3];
+  if (P.act)
+    face_fn_vjp<NS, FLUX>(P.q[0], P.q[1], P.g[0], P.g[1], P.S, P.cL, P.cR, a.gas, a.flux, P.fSb, P.jb[0], P.jb[1],
+                          qb[0], qb[1], gb[0], gb[1]);
+  switch (t.x) {
+    FRX_VFLIST(FRX_VSCASE)
+    default: break;
+  }
+}
+#undef FRX_VGCASE
+#undef FRX_VSCASE
+#undef FRX_VFLIST
+
+#define FRX_VBCASE(N) \
+  case 64 + N: bface_rev_body<N, NS>(a, faces + t.y, t.z, 0); break;
+template <bool NS>
+__global__ void __launch_bounds__(256) k_bface_rev_fused(VjpArgs a, const int4* __restrict__ faces,
+                                                         const int4* __restrict__ tiles) {
+  const int4 t = tiles[blockIdx.x];
+  switch (t.x) {
     FRX_VBCASE(2) FRX_VBCASE(3) FRX_VBCASE(4) FRX_VBCASE(5) FRX_VBCASE(6)
     default: break;
   }
 }
-#undef FRX_VFCASE
 #undef FRX_VBCASE
 
 }  // namespace frx
