@@ -953,15 +953,12 @@ __global__ void __launch_bounds__(FRX_MAX_THREADS) k_face_split_fused(ResArgs<T>
   extern __shared__ __align__(16) unsigned char smem[];
   const int4 t = tiles[blockIdx.x];
   switch (t.x) {
-    FRX_SCASE(2, 2) FRX_SCASE(2, 3) FRX_SCASE(2, 4) FRX_SCASE(2, 5) FRX_SCASE(2, 6)
-    FRX_SCASE(3, 3) FRX_SCASE(3, 4) FRX_SCASE(3, 5) FRX_SCASE(3, 6)
-    FRX_SCASE(4, 4) FRX_SCASE(4, 5) FRX_SCASE(4, 6)
-    FRX_SCASE(5, 5) FRX_SCASE(5, 6)
-    FRX_SCASE(6, 6)
+    FRX_FLIST(FRX_SCASE)
     default: break;
   }
 }
 #undef FRX_SCASE
+#undef FRX_FLIST
 
 // Boundary-face tiles of the face stage (the plan puts them last).
 #define FRX_BCASE(N) \
