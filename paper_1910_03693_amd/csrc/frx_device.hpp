@@ -13,6 +13,14 @@ namespace frx {
 constexpr int NMAX = 6;  // n = p + 1 <= 6 (p <= 5)
 #define FRX_MAX_THREADS 256  // launch bound of every residual-stage kernel
 
+// Waves per SIMD that each fused residual stage is built for, per scalar
+// kind (double, Dual<double>, Dual<float>) and stage (trace, face,
+// divergence).  A 256-thread block is one wave on each of the CU's four
+// SIMDs, so the target is also the number of blocks per CU: the kernel gets
+// the register budget of that many waves (amdgpu_waves_per_eu) and the fused
+// plan keeps every tile's LDS within 160 KB / waves (64 KB at most).
+constexpr int FRX_STAGE_WAVES[3][3] = {{4, 3, 3}, {4, 2, 3}, {4, 4, 3}};
+
 // ------------------------------------------------------------------ scalars
 // Forward-mode dual number: value and directional derivative.  The residual
 // kernels instantiated with Dual<B> compute R(U) and J(U) v in one sweep.
@@ -26,6 +34,11 @@ template <class B> struct Dual {
 template <class T> struct base_of { using type = T; };
 template <class B> struct base_of<Dual<B>> { using type = B; };
 template <class T> using base_t = typename base_of<T>::type;
+template <class T> struct scalar_kind;
+template <> struct scalar_kind<double> { static constexpr int value = 0; };
+template <> struct scalar_kind<Dual<double>> { static constexpr int value = 1; };
+template <> struct scalar_kind<Dual<float>> { static constexpr int value = 2; };
+template <class T, int ST> struct StageWaves { static constexpr int value = FRX_STAGE_WAVES[scalar_kind<T>::value][ST]; };
 template <class T> struct is_dual { static constexpr bool value = false; };
 template <class B> struct is_dual<Dual<B>> { static constexpr bool value = true; };
 

@@ -868,7 +868,7 @@ __global__ void __launch_bounds__(FRX_MAX_THREADS) k_div(ResArgs<T> a, const int
   case N: BODY<N, T, NS>(a, elems + t.y, t.z, t.w, 0, smem); break;
 
 template <class T, bool NS>
-__global__ void __launch_bounds__(FRX_MAX_THREADS) k_trace_fused(ResArgs<T> a, const int4* __restrict__ elems,
+__global__ void __launch_bounds__(FRX_MAX_THREADS) __attribute__((amdgpu_waves_per_eu(StageWaves<T, 0>::value))) k_trace_fused(ResArgs<T> a, const int4* __restrict__ elems,
                                                      const int4* __restrict__ tiles) {
   if (a.skip && *a.skip) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -884,7 +884,7 @@ __global__ void __launch_bounds__(FRX_MAX_THREADS) k_trace_fused(ResArgs<T> a, c
 }
 
 template <class T, bool NS>
-__global__ void __launch_bounds__(FRX_MAX_THREADS) k_div_fused(ResArgs<T> a, const int4* __restrict__ elems,
+__global__ void __launch_bounds__(FRX_MAX_THREADS) __attribute__((amdgpu_waves_per_eu(StageWaves<T, 2>::value))) k_div_fused(ResArgs<T> a, const int4* __restrict__ elems,
                                                    const int4* __restrict__ tiles) {
   if (a.skip && *a.skip) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -912,12 +912,12 @@ __global__ void __launch_bounds__(FRX_MAX_THREADS) k_div_fused(ResArgs<T> a, con
 #define FRX_SCASE(NL, NH) \
   case 8 * NL + NH: face_scatter<NL, NH, T>(a, faces + t.y, t.z, t.w, 0, smem, P, fS, NS ? 20 : 5); break;
 
-// At least two waves per SIMD: the float64-dual Navier-Stokes face needs
-// about 270 registers per lane, one wave per SIMD with nothing to overlap its
-// loads; held to 256 it spills about 26 registers to scratch and runs about
-// a fifth faster.  The other instantiations fit three waves as they are.
+// Register budget from FRX_STAGE_WAVES: the float64-dual Navier-Stokes face
+// needs about 270 registers per lane, one wave per SIMD with nothing to
+// overlap its loads; held to two waves (256) it spills about 26 registers to
+// scratch and runs about a fifth faster.
 template <class T, bool NS, int FLUX>
-__global__ void __launch_bounds__(FRX_MAX_THREADS) __attribute__((amdgpu_waves_per_eu(2))) k_face_fused(ResArgs<T> a, const int4* __restrict__ faces,
+__global__ void __launch_bounds__(FRX_MAX_THREADS) __attribute__((amdgpu_waves_per_eu(StageWaves<T, 1>::value))) k_face_fused(ResArgs<T> a, const int4* __restrict__ faces,
                                                     const int4* __restrict__ tiles) {
   using B = base_t<T>;
   if (a.skip && *a.skip) return;

@@ -734,16 +734,14 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
     for (int st = 0; st < 3; ++st) {
       std::vector<std::pair<double, int4>> tiles;
       size_t lds = 0;
+      // LDS per tile within the share of the blocks per CU the stage is built for
+      const size_t cap_st = std::min<size_t>(cap, 160 * 1024 / FRX_STAGE_WAVES[sk][st]);
       if (st != 1) {
         for (auto& kv : erange) {
           const int n = kv.first, n3 = n * n * n;
           const int tv = (ns && 20 * n3 * sb > 65536) ? 5 : (ns ? 20 : 5);
           const size_t per_el = st == 0 ? (size_t)tv * n3 * sb : (size_t)(5 * n3 + 30 * n * n) * sb;
           int epb = std::max(1, 256 / n3);
-          // trace tiles at most 53 KB: three blocks per CU (160 KB of LDS),
-          // which the trace kernels' registers allow; the divergence kernels'
-          // registers allow two, so they keep 64 KB
-          const size_t cap_st = st == 0 ? 53 * 1024 : cap;
           while (epb > 1 && epb * per_el > cap_st) --epb;
           lds = std::max(lds, epb * per_el);
           for (int i = 0; i < kv.second.second; i += epb) {
@@ -762,7 +760,7 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
             const int nl = code / 8, nh = code % 8;
             const size_t per_face = nl < nh ? (size_t)((ns ? 20 : 5) * nl * nl + 10 * nh * nh) * sb : 0;
             int fpb = std::max(1, 256 / (nh * nh));
-            while (fpb > 1 && fpb * per_face > cap) --fpb;
+            while (fpb > 1 && fpb * per_face > cap_st) --fpb;
             lds = std::max(lds, fpb * per_face);
             for (int i = 0; i < count; i += fpb)
               tiles.push_back({(double)std::min(fpb, count - i) * nh * nh * (nl < nh ? 1.5 : 1.0),
