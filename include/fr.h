@@ -211,7 +211,8 @@ fr_status fr_project(fr_ctx src, const double* U_src, fr_ctx dst, double* U_dst,
  * at the element's solution points; all five variables.  Elements of lower
  * degree keep their values.  U, U_out: device float64 [5][n_sp]; U_out may
  * be U (in place), otherwise U is copied to U_out first on the stream.
- * FR_E_INVALID for alpha outside [0, 1] or p_from outside 1..5.  The paper
+ * FR_E_INVALID for alpha outside [0, 1], p_from outside 1..5 or a U_out
+ * that overlaps U without being U.  The paper
  * does not say when in the step the filter acts; the caller applies it (for
  * example after each time step). */
 fr_status fr_filter(fr_ctx ctx, const double* U, double* U_out, double alpha, int32_t p_from, void* stream);

@@ -1352,6 +1352,8 @@ fr_status fr_project(fr_ctx src, const double* U_src, fr_ctx dst, double* U_dst,
 fr_status fr_filter(fr_ctx c, const double* U, double* U_out, double alpha, int32_t p_from, void* stream) {
   if (!c) return FR_E_INVALID;
   if (!U || !U_out) return fail(c, FR_E_INVALID, "fr_filter: bad arguments");
+  if ((const double*)U_out != U && U_out < U + c->ndof && U < (const double*)U_out + c->ndof)
+    return fail(c, FR_E_INVALID, "fr_filter: U_out overlaps U without being U");
   if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(c, FR_E_INVALID, "fr_filter: alpha outside [0, 1]");
   if (p_from < 1 || p_from > NMAX - 1) return fail(c, FR_E_INVALID, "fr_filter: p_from outside 1..5");
   return guarded(c, [&]() -> fr_status {

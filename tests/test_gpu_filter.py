@@ -73,6 +73,14 @@ def test_invalid_arguments(frx, case):
         with pytest.raises(frx.FrError) as ei:
             ctx.nodal_filter(U, alpha, p_from)
         assert ei.value.status == -1
+    # an output that overlaps the input without being it is refused
+    big = torch.zeros(2 * U.numel(), dtype=torch.float64, device="cuda")
+    big[:U.numel()] = U.reshape(-1)
+    src = big[:U.numel()].view_as(U)
+    dst = big[7:7 + U.numel()].view_as(U)
+    with pytest.raises(frx.FrError) as ei:
+        ctx.nodal_filter(src, 0.2, 3, out=dst)
+    assert ei.value.status == -1
 
 
 def test_full_size_workload(frx):
