@@ -29,6 +29,9 @@
  *    fr_last_error() describes the last error of a context.  No call aborts
  *    the process or lets a C++ exception escape.
  *  - A context may be used by one host thread and one stream at a time.
+ *  - Output arrays must not overlap the call's inputs or each other ("must not
+ *    alias" below means any overlap, not only the same start address); the
+ *    calls that can check it return FR_E_INVALID.
  */
 #ifndef FR_H
 #define FR_H

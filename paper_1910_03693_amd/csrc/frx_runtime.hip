@@ -1063,8 +1063,17 @@ fr_status fr_layout(fr_ctx c, int64_t* n_dof, int64_t* sp_offset) {
   return FR_OK;
 }
 
+// true if the byte ranges [a, a + na) and [b, b + nb) share memory
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + nb && y < x + na;
+}
+
 fr_status fr_residual(fr_ctx c, const double* U, double* R, void* stream) {
-  if (!c || !U || !R || (const void*)U == (void*)R) return c ? fail(c, FR_E_INVALID, "fr_residual: bad arguments") : FR_E_INVALID;
+  if (!c) return FR_E_INVALID;
+  const size_t nb = sizeof(double) * c->ndof;
+  if (!U || !R || overlap(U, nb, R, nb)) return fail(c, FR_E_INVALID, "fr_residual: bad arguments");
   return guarded(c, [&]() -> fr_status {
     ResCall<double> rc;
     rc.U = U;
@@ -1076,8 +1085,9 @@ fr_status fr_residual(fr_ctx c, const double* U, double* R, void* stream) {
 
 fr_status fr_residual_jvp(fr_ctx c, const double* U, const double* v, double* R, double* Jv, void* stream) {
   if (!c) return FR_E_INVALID;
-  if (!U || !v || !R || !Jv || (const double*)R == U || (const double*)Jv == v || R == Jv ||
-      (const double*)R == v || (const double*)Jv == U)
+  const size_t nb = sizeof(double) * c->ndof;
+  if (!U || !v || !R || !Jv || overlap(R, nb, U, nb) || overlap(Jv, nb, v, nb) || overlap(R, nb, Jv, nb) ||
+      overlap(R, nb, v, nb) || overlap(Jv, nb, U, nb))
     return fail(c, FR_E_INVALID, "fr_residual_jvp: bad arguments");
   return guarded(c, [&]() -> fr_status {
     ResCall<double> rc;
@@ -1093,7 +1103,9 @@ fr_status fr_residual_jvp(fr_ctx c, const double* U, const double* v, double* R,
 fr_status fr_jvp(fr_ctx c, const double* U, const void* v, void* Jv, int32_t prec, int32_t mode, double eps,
                  void* stream) {
   if (!c) return FR_E_INVALID;
-  if (!U || !v || !Jv || v == Jv) return fail(c, FR_E_INVALID, "fr_jvp: bad arguments");
+  const size_t nb = sizeof(double) * c->ndof, nv = (prec == FR_F32 ? sizeof(float) : sizeof(double)) * c->ndof;
+  if (!U || !v || !Jv || overlap(v, nv, Jv, nv) || overlap(U, nb, Jv, nv))
+    return fail(c, FR_E_INVALID, "fr_jvp: bad arguments");
   if (prec != FR_F64 && prec != FR_F32) return fail(c, FR_E_INVALID, "fr_jvp: precision");
   if (mode != FR_JV_EXACT && mode != FR_JV_FD) return fail(c, FR_E_INVALID, "fr_jvp: mode");
   if (mode == FR_JV_FD && prec != FR_F64) return fail(c, FR_E_UNSUPPORTED, "fr_jvp: finite differences need float64");
@@ -1144,7 +1156,9 @@ fr_status fr_jvp(fr_ctx c, const double* U, const void* v, void* Jv, int32_t pre
 
 fr_status fr_vjp(fr_ctx c, const double* U, const double* w, double* JTw, void* stream) {
   if (!c) return FR_E_INVALID;
-  if (!U || !w || !JTw || w == JTw) return fail(c, FR_E_INVALID, "fr_vjp: bad arguments");
+  const size_t nb = sizeof(double) * c->ndof;
+  if (!U || !w || !JTw || overlap(w, nb, JTw, nb) || overlap(U, nb, JTw, nb))
+    return fail(c, FR_E_INVALID, "fr_vjp: bad arguments");
   return guarded(c, [&]() -> fr_status {
     FRX_TRY(launch_vjp(c->M, U, w, JTw, S(stream)));
     return FR_OK;
@@ -1154,7 +1168,9 @@ fr_status fr_vjp(fr_ctx c, const double* U, const double* w, double* JTw, void* 
 fr_status gmres_stage_solve(fr_ctx c, const double* U, double shift, const double* F, double* dU,
                             const fr_gmres_opts* o, fr_gmres_stats* st, void* stream) {
   if (!c) return FR_E_INVALID;
-  if (!U || !F || !dU || !o || dU == F || dU == U) return fail(c, FR_E_INVALID, "gmres_stage_solve: bad arguments");
+  const size_t nb = sizeof(double) * c->ndof;
+  if (!U || !F || !dU || !o || overlap(dU, nb, F, nb) || overlap(dU, nb, U, nb))
+    return fail(c, FR_E_INVALID, "gmres_stage_solve: bad arguments");
   return guarded(c, [&]() -> fr_status {
     hipStream_t s = S(stream);
     fr_status r = gmres_solve(c, U, shift, F, dU, *o, st, s, nullptr);
@@ -1340,7 +1356,8 @@ fr_status fr_select_degrees(fr_ctx c, const double* U, int32_t var, double nu_ma
 
 fr_status fr_project(fr_ctx src, const double* U_src, fr_ctx dst, double* U_dst, void* stream) {
   if (!src || !dst) return FR_E_INVALID;
-  if (!U_src || !U_dst || (const double*)U_dst == U_src) return fail(dst, FR_E_INVALID, "fr_project: bad arguments");
+  if (!U_src || !U_dst || overlap(U_dst, sizeof(double) * dst->ndof, U_src, sizeof(double) * src->ndof))
+    return fail(dst, FR_E_INVALID, "fr_project: bad arguments");
   if (src->M.E != dst->M.E || src->dev != dst->dev)
     return fail(dst, FR_E_INVALID, "fr_project: the two contexts must hold the same mesh on the same device");
   return guarded(dst, [&]() -> fr_status {
@@ -1352,7 +1369,8 @@ fr_status fr_project(fr_ctx src, const double* U_src, fr_ctx dst, double* U_dst,
 fr_status fr_filter(fr_ctx c, const double* U, double* U_out, double alpha, int32_t p_from, void* stream) {
   if (!c) return FR_E_INVALID;
   if (!U || !U_out) return fail(c, FR_E_INVALID, "fr_filter: bad arguments");
-  if ((const double*)U_out != U && U_out < U + c->ndof && U < (const double*)U_out + c->ndof)
+  const size_t nb = sizeof(double) * c->ndof;
+  if ((const double*)U_out != U && overlap(U_out, nb, U, nb))
     return fail(c, FR_E_INVALID, "fr_filter: U_out overlaps U without being U");
   if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(c, FR_E_INVALID, "fr_filter: alpha outside [0, 1]");
   if (p_from < 1 || p_from > NMAX - 1) return fail(c, FR_E_INVALID, "fr_filter: p_from outside 1..5");

@@ -102,3 +102,39 @@ def test_nonphysical_states_are_flagged(frx, bad):
     with pytest.raises(frx.FrError) as ei:
         ctx.esdirk_step(U, 0.01, gmres=dict(restart=5, tol=1e-2), dtau_init=1e-3, dtau_max=1e-2, max_ptc_iter=2)
     assert ei.value.status == frx.FR_E_NONPHYSICAL
+
+
+def test_overlapping_outputs_are_refused(frx):
+    """Every compute call refuses an output that overlaps one of its inputs
+    (here shifted by a few elements inside one allocation) before launching
+    anything; the same buffers apart are accepted."""
+    case = _case()
+    ctx = frx.Context.from_case(case)
+    n = case.U.size
+    pool = torch.zeros(3 * n + 16, dtype=torch.float64, device="cuda")
+    U = pool[:n].view(case.U.shape)
+    U.copy_(torch.tensor(case.U, device="cuda"))
+    v = torch.tensor(I.random_direction(n, 97).reshape(case.U.shape), device="cuda")
+    near_U = pool[5:5 + n].view(case.U.shape)       # overlaps U
+    far = pool[2 * n + 16:3 * n + 16].view(case.U.shape)  # apart from U
+    h = ctx.h
+    refused = [
+        lambda: frx.fr_residual(h, U, near_U),
+        lambda: frx.fr_jvp(h, U, v, near_U),
+        lambda: frx.fr_vjp(h, U, v, near_U),
+        lambda: frx.fr_residual_jvp(h, U, v, near_U, far),
+        lambda: frx.fr_residual_jvp(h, U, v, far, near_U),
+        lambda: frx.fr_filter(h, U, near_U, 0.2, 3),
+    ]
+    for k, call in enumerate(refused):
+        with pytest.raises(frx.FrError) as ei:
+            call()
+        assert ei.value.status == frx.FR_E_INVALID, k
+    r, _ = frx.gmres_stage_solve(h, U, 10.0, v, near_U, frx.gmres_opts(), check=False)
+    assert r == frx.FR_E_INVALID
+    # the same calls with separate outputs go through
+    frx.fr_residual(h, U, far)
+    frx.fr_jvp(h, U, v, far)
+    frx.fr_filter(h, U, far, 0.2, 3)
+    torch.cuda.synchronize()
+    assert torch.isfinite(far).all()
