@@ -3,7 +3,8 @@
 * Every reduction is a fixed-order two-level sum and no kernel uses atomics on
   floating-point data, so repeated calls give bitwise identical results:
   residual, tangents, one-pass residual and tangent, adjoint, GMRES with and
-  without graphs, an ESDIRK2 step.
+  without graphs, an ESDIRK2 step, an ESDIRK4 step (mixed form), the nodal
+  filter.
 * Failure paths, forced from the host (no kernel is made to fault): a GMRES
   budget too small for its tolerance returns FR_E_NOTCONVERGED with the best
   iterate; an ESDIRK step whose GMRES budget is too small halves the pseudo
@@ -54,6 +55,11 @@ def test_repeated_calls_are_bitwise_identical(frx, fused):
         ctx.esdirk_step(Uw, 0.01, gmres=dict(restart=20, tol=1e-3, use_graph=True), dtau_init=1e-3, dtau_max=1e-2,
                         tol_pseudo=1e-4, max_ptc_iter=20)
         out.append(Uw)
+        U4 = U.clone()
+        ctx.esdirk_step(U4, 0.01, gmres=dict(restart=20, tol=1e-3, use_graph=True, precision=frx.FR_F32),
+                        dtau_init=1e-3, dtau_max=1e-2, tol_pseudo=1e-4, max_ptc_iter=20, scheme=frx.FR_ESDIRK4)
+        out.append(U4)
+        out.append(ctx.nodal_filter(U, 0.2, 1).clone())
         return out
 
     a = everything()
