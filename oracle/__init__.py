@@ -49,6 +49,9 @@ def lib():
         L.oracle_nsp.argtypes = [C.c_void_p]
         for name in ("oracle_residual", "oracle_residual_ld"):
             getattr(L, name).argtypes = [C.c_void_p, dp, dp]
+        L.oracle_residual_terms.argtypes = [C.c_void_p, dp, dp, dp]
+        L.oracle_threads.restype = C.c_int
+        L.oracle_set_threads.argtypes = [C.c_int]
         L.oracle_jvp_cs.argtypes = [C.c_void_p, dp, dp, dp]
         L.oracle_jvp_fd.argtypes = [C.c_void_p, dp, dp, C.c_double, dp]
         L.oracle_jacobian.argtypes = [C.c_void_p, dp, dp]
@@ -74,6 +77,16 @@ def lib():
         L.oracle_physical_flux_n.argtypes = [C.c_long, C.c_double, C.c_double, C.c_double, dp, dp, dp]
         _lib = L
     return _lib
+
+
+def threads():
+    """Threads the oracle's OpenMP loops use (OMP_NUM_THREADS, else all cores)."""
+    return int(lib().oracle_threads())
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().oracle_set_threads(int(n))
 
 
 def _p(a):
@@ -182,6 +195,14 @@ class Oracle:
         R = np.zeros(self.shape)
         lib().oracle_residual(self.h, _p(U), _p(R))
         return R
+
+    def residual_terms(self, U):
+        """(R, T): the residual and, per solution point, the sum of the
+        absolute values of the terms it adds up over |J|."""
+        U = self._vec(U)
+        R, T = np.zeros(self.shape), np.zeros(self.shape)
+        lib().oracle_residual_terms(self.h, _p(U), _p(R), _p(T))
+        return R, T
 
     def residual_ld(self, U):
         """The residual evaluated in extended precision (rounding reference)."""

@@ -29,6 +29,9 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -376,9 +379,16 @@ template <class S> struct Work {
   std::vector<std::vector<S>> qf, gf, dq, fS;
 };
 
+// tabs (optional): at every solution point, the sum of the absolute values of
+// the terms that the last step adds up, divided by |J| (the scale against
+// which the rounding of R is judged where the terms cancel).
+// The element loops and the interior-face loop run with OpenMP when the
+// library is built with it; every iteration writes only its own element's or
+// face's entries, so the result does not depend on the thread count.
 template <class S>
-static void residual(const Mesh& M, const S* U, S* Rout, double* bflux = nullptr) {
+static void residual(const Mesh& M, const S* U, S* Rout, double* bflux = nullptr, double* tabs = nullptr) {
   using R = typename real_of<S>::type;
+  (void)ops<R>(1);  // the operator tables are built once, before any thread starts
   Phys<S> ph{M.gamma, M.mu, M.prandtl};
   const bool ns = M.physics == 1;
   if (bflux)
@@ -395,6 +405,7 @@ static void residual(const Mesh& M, const S* U, S* Rout, double* bflux = nullptr
 
   // 1. Traces of q at the faces, and (Navier-Stokes) the uncorrected physical
   //    gradient at the solution points and its face traces.
+#pragma omp parallel for schedule(dynamic, 16)
   for (int e = 0; e < E; ++e) {
     const Elem& el = M.el[e];
     int n = el.n, n2 = n * n, n3 = n2 * n;
@@ -487,7 +498,9 @@ static void residual(const Mesh& M, const S* U, S* Rout, double* bflux = nullptr
     else ph.rusanov(qm, qp, Sv, out);
   };
 
-  for (const IFace& F : M.ifaces) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (size_t fi = 0; fi < M.ifaces.size(); ++fi) {
+    const IFace& F = M.ifaces[fi];
     int fL = 2 * F.d + 1, fR = 2 * F.d;
     int nL = M.el[F.L].n, nR = M.el[F.R].n, nh = std::max(nL, nR), nh2 = nh * nh;
     std::vector<S> qL, qR, gL, gR;
@@ -590,6 +603,7 @@ static void residual(const Mesh& M, const S* U, S* Rout, double* bflux = nullptr
   }
 
   // 3. Per element: corrected gradient, volume flux, divergence and correction.
+#pragma omp parallel for schedule(dynamic, 16)
   for (int e = 0; e < E; ++e) {
     const Elem& el = M.el[e];
     int n = el.n, n2 = n * n, n3 = n2 * n;
@@ -655,17 +669,24 @@ static void residual(const Mesh& M, const S* U, S* Rout, double* bflux = nullptr
       int id[3] = {k % n, (k / n) % n, k / n2};
       for (int v = 0; v < 5; ++v) {
         S s = 0.0;
+        double ta = 0.0;
         for (int i = 0; i < 3; ++i) {
           for (int m = 0; m < n; ++m) {
             int jd[3] = {id[0], id[1], id[2]};
             jd[i] = m;
-            s += o.D[id[i] * n + m] * Ft[(jd[0] + n * (jd[1] + n * jd[2])) * 15 + i * 5 + v];
+            const S t = o.D[id[i] * n + m] * Ft[(jd[0] + n * (jd[1] + n * jd[2])) * 15 + i * 5 + v];
+            s += t;
+            ta += std::fabs(re(t));
           }
           int a = id[i == 0 ? 1 : 0], b = id[i == 2 ? 1 : 2];
-          s += df[((2 * i) * 5 + v) * n2 + a + n * b] * o.gLp[id[i]];
-          s += df[((2 * i + 1) * 5 + v) * n2 + a + n * b] * o.gRp[id[i]];
+          const S tl = df[((2 * i) * 5 + v) * n2 + a + n * b] * o.gLp[id[i]];
+          const S tr = df[((2 * i + 1) * 5 + v) * n2 + a + n * b] * o.gRp[id[i]];
+          s += tl;
+          s += tr;
+          ta += std::fabs(re(tl)) + std::fabs(re(tr));
         }
         Rout[v * N + el.off + k] = -s / eJ[k];
+        if (tabs) tabs[v * N + el.off + k] = ta / std::fabs(re(S(eJ[k])));
       }
     }
   }
@@ -740,6 +761,30 @@ void oracle_destroy(void* h) { delete (Mesh*)h; }
 long oracle_nsp(void* h) { return ((Mesh*)h)->n_sp; }
 
 void oracle_residual(void* h, const double* U, double* R) { residual<double>(*(Mesh*)h, U, R); }
+
+// The residual and, at every solution point, the sum of the absolute values of
+// the terms it adds up, over |J| (see residual()).
+void oracle_residual_terms(void* h, const double* U, double* R, double* T) {
+  residual<double>(*(Mesh*)h, U, R, nullptr, T);
+}
+
+// Threads an OpenMP region of the oracle uses (1 without OpenMP).
+int oracle_threads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+// Sets the threads of the following OpenMP regions (no effect without OpenMP).
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
 
 // The same residual evaluated in extended precision (x87 long double, 64-bit
 // significand) from the same double inputs: a reference for sizing the
@@ -836,7 +881,9 @@ void oracle_boundary_flux(void* h, const double* U, double* out5) {
 // s_{p-1} = projection onto tensor degree p-1 = Legendre modes with every index < p.
 void oracle_indicator(void* h, const double* U, int var, double* eta, double* eta_max) {
   Mesh& M = *(Mesh*)h;
-  double mx = 0.0;
+  (void)ops(1);  // the operator tables are built before any thread starts
+  // every element writes only its own eta (OpenMP when built with it)
+#pragma omp parallel for schedule(dynamic, 16)
   for (int e = 0; e < M.n_elem; ++e) {
     const Elem& el = M.el[e];
     int n = el.n, n3 = n * n * n;
@@ -890,8 +937,9 @@ void oracle_indicator(void* h, const double* U, int var, double* eta, double* et
       den += s[k] * s[k] * wJ;
     }
     eta[e] = den > 0.0 ? num / den : 0.0;
-    mx = std::max(mx, eta[e]);
   }
+  double mx = 0.0;
+  for (int e = 0; e < M.n_elem; ++e) mx = std::max(mx, eta[e]);
   *eta_max = mx;
 }
 

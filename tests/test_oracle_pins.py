@@ -258,6 +258,161 @@ def test_vortex_consistency_order(oracle_mod, p):
     assert rates[-1] > p - 0.25, rates
 
 
+@pytest.mark.parametrize("p", [4, 5])
+def test_vortex_consistency_order_high_degree(oracle_mod, p):
+    # as above for p = 4, 5 on [-7, 7]^2, where the periodic tail of the
+    # vortex (about 1e-10) stays below the truncation error
+    L = 14.0
+    errs = []
+    for N in (12, 24, 48):
+        mesh = I.box_mesh(N, N, 1, (L, L, L / N), origin=(-L / 2, -L / 2, 0.0))
+        ep = np.full(mesh["n_elem"], p, np.int8)
+        X = I.solution_points(mesh, ep)
+        f = lambda x: I.vortex_field(x, X[1], X[2], 0.0, 0.0, ma=0.5)
+        h = 1e-20
+        dUdx = np.imag(f(X[0] + 1j * h)) / h
+        orc = _oracle(oracle_mod, mesh, ep, 0, 0, ff=np.zeros(5))
+        R = orc.residual(f(X[0]))
+        errs.append(np.sqrt(np.sum((R + dUdx) ** 2 * orc.mass()[None, :])))
+    rate = math.log(errs[-2] / errs[-1]) / math.log(2)
+    assert rate > p - 0.25, errs
+
+
+def _vortex_solution_error(oracle_mod, p, N, L=14.0, T=1.0, flux=0):
+    """L2 error at time T of the semi-discrete FR solution of the isentropic
+    vortex (section 3.3; Euler, periodic [-L/2, L/2]^2, one self-periodic
+    element in z), integrated with classical RK4 at a step that keeps the time
+    error far below the spatial one (about h / (3 (p+1)^2), CFL ~ 1 for the
+    acoustic speed 1 + c, c = 2 at Mach 0.5), against the exact translated
+    vortex at the solution points."""
+    mesh = I.box_mesh(N, N, 1, (L, L, L / N), origin=(-L / 2, -L / 2, 0.0))
+    ep = np.full(mesh["n_elem"], p, np.int8)
+    X = I.solution_points(mesh, ep)
+    orc = _oracle(oracle_mod, mesh, ep, 0, flux, ff=np.zeros(5))
+    per = (L, L)
+    U = I.vortex_field(X[0], X[1], X[2], 0.0, 0.0, ma=0.5, period=per)
+    steps = int(math.ceil(T / (L / N / (3.0 * (p + 1) ** 2))))
+    dt = T / steps
+    for _ in range(steps):
+        k1 = orc.residual(U)
+        k2 = orc.residual(U + 0.5 * dt * k1)
+        k3 = orc.residual(U + 0.5 * dt * k2)
+        k4 = orc.residual(U + dt * k3)
+        U = U + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+    Ue = I.vortex_field(X[0], X[1], X[2], 0.0, 0.0, t=T, ma=0.5, period=per)
+    return math.sqrt(np.sum((U - Ue) ** 2 * orc.mass()[None, :]))
+
+
+@pytest.mark.parametrize("p,Ns", [(1, (12, 24, 48)), (2, (12, 24)), (3, (12, 24)), (4, (12, 24))])
+def test_vortex_solution_converges_at_order_p_plus_one(oracle_mod, p, Ns):
+    # the FR (DG correction) solution of the translating isentropic vortex of
+    # section 3.3 converges at order p + 1 in L2 (measured here: 2.5, 3.3,
+    # 4.6, 5.5 for p = 1..4); a dropped, mis-signed or mis-indexed term of the
+    # residual leaves at most the order of its consistency error
+    errs = [_vortex_solution_error(oracle_mod, p, N) for N in Ns]
+    rate = math.log(errs[-2] / errs[-1]) / math.log(Ns[-1] / Ns[-2])
+    print("p", p, "errors", errs, "rate", rate)
+    assert rate > p + 0.7, (errs, rate)
+
+
+def _euler_normal_flux(q, n):
+    rho, m, E = q[0], q[1:4], q[4]
+    u = m / rho
+    pr = (GAMMA - 1.0) * (E - 0.5 * rho * np.dot(u, u))
+    un = np.dot(u, n)
+    return np.concatenate([[rho * un], m * un + pr * n, [(E + pr) * un]])
+
+
+def _roe_matrix(qL, qR, n):
+    """Flux Jacobian of f.n at Roe's average (sqrt(rho)-weighted velocity and
+    enthalpy): the Jacobian of the ideal-gas flux depends on u and H only, so it
+    is taken by the complex step at a state with rho = 1 and that (u, H)."""
+    def uh(q):
+        rho = q[0]
+        u = q[1:4] / rho
+        pr = (GAMMA - 1.0) * (q[4] - 0.5 * rho * np.dot(u, u))
+        return rho, u, (q[4] + pr) / rho
+    rL, uL, HL = uh(qL)
+    rR, uR, HR = uh(qR)
+    wL, wR = math.sqrt(rL), math.sqrt(rR)
+    ut = (wL * uL + wR * uR) / (wL + wR)
+    Ht = (wL * HL + wR * HR) / (wL + wR)
+    pr = (GAMMA - 1.0) * (Ht - 0.5 * np.dot(ut, ut)) / GAMMA
+    q0 = np.array(I.primitive_to_conservative(1.0, *ut, pr))
+    A = np.zeros((5, 5))
+    for j in range(5):
+        e = np.zeros(5, complex)
+        e[j] = 1e-30j
+        A[:, j] = np.imag(_euler_normal_flux(q0 + e, n)) / 1e-30
+    return A
+
+
+def test_roe_subsonic_dissipation_is_the_absolute_roe_matrix(oracle_mod):
+    # eq. invis_com with Roe's average: f = (f(q-) + f(q+))/2 - |A~| (q+ - q-)/2,
+    # |A~| = R |Lambda| R^-1 from numpy's eigendecomposition of the
+    # complex-step Jacobian at the Roe state, on subsonic pairs where the
+    # waves move both ways (u.n - c < 0 < u.n + c), both signs of u.n; also
+    # Roe's property f(q+) - f(q-) = A~ (q+ - q-)
+    rng = np.random.default_rng(21)
+    for trial in range(40):
+        rho = 0.8 + 0.4 * rng.random(2)
+        pr = 0.8 + 0.4 * rng.random(2)
+        S = rng.normal(size=3)
+        n = S / np.linalg.norm(S)
+        c = np.sqrt(GAMMA * pr / rho)
+        mach = (0.6 * rng.random() - 0.3) if trial % 2 else 0.05 * rng.normal()
+        u = [mach * c[i] * n + 0.3 * rng.normal(size=3) for i in range(2)]
+        qL = np.array(I.primitive_to_conservative(rho[0], *u[0], pr[0]))
+        qR = np.array(I.primitive_to_conservative(rho[1], *u[1], pr[1]))
+        A = _roe_matrix(qL, qR, n)
+        lam, Rv = np.linalg.eig(A)  # the triple eigenvalue u.n may come with complex eigenvectors
+        assert np.max(np.abs(lam.imag)) < 1e-12 and lam.real.min() < 0.0 < lam.real.max()
+        absA = (Rv @ np.diag(np.abs(lam.real)) @ np.linalg.inv(Rv)).real
+        fL, fR = _euler_normal_flux(qL, n), _euler_normal_flux(qR, n)
+        dq = qR - qL
+        assert np.max(np.abs(fR - fL - A @ dq)) <= 1e-12 * np.max(np.abs(fR) + np.abs(fL))
+        expect = np.linalg.norm(S) * (0.5 * (fL + fR) - 0.5 * absA @ dq)
+        got = oracle_mod.common_flux(0, qL, qR, S)
+        scale = np.linalg.norm(S) * np.max(np.abs(fL) + np.abs(fR))
+        assert np.max(np.abs(got - expect)) <= 1e-12 * scale, (trial, got, expect)
+
+
+@pytest.mark.parametrize("physics", [0, 1])
+def test_wall_ghost_state_and_fluxes(oracle_mod, physics):
+    """A uniform moving state (velocity not tangent to the wall) next to the
+    no-slip adiabatic wall at y = 0, the same state as far field at y = 1, on
+    cubes of side h (periodic in x and z).  The net outward boundary flux is
+    worked out by hand from the wall reading (ghost state: interior density,
+    zero velocity, interior temperature; inviscid flux p S; BR2 common gradient
+    grad q + r with r = S (q_b - q) g'(-1) / J; no heat flux) and the far-field
+    flux of identical states (the physical flux, no lifting):
+      mass 0 + rho v A,  energy 0 + (E + p) v A,
+      momentum  -p A y + nx nz mu n^2 h (u + v y / 3)  +  (rho u v + p y) A,
+    with A = Lx Lz the plane's area and n = p + 1.  A dropped kinetic energy in
+    the ghost pressure, a wall mass or energy flux, a heat flux or a wrong sign
+    of the lifting all change it."""
+    nx, nz, h, deg, mu = 3, 2, 0.25, 2, 0.05
+    mesh = I.box_mesh(nx, 2, nz, (nx * h, 2 * h, nz * h), periodic=(True, False, True),
+                      bc_lo=[-1] * 3, bc_hi=[-2] * 3)
+    ep = np.full(mesh["n_elem"], deg, np.int8)
+    rho, vel, pr = 1.1, np.array([0.3, -0.2, 0.15]), 2.0
+    q = np.array(I.primitive_to_conservative(rho, *vel, pr))
+    orc = _oracle(oracle_mod, mesh, ep, physics, 0, mu=mu, ff=q)
+    U = np.repeat(q[:, None], orc.n_sp, axis=1)
+    got = orc.boundary_flux(U)
+    A = nx * h * nz * h
+    yv = np.array([0.0, 1.0, 0.0])
+    n = deg + 1
+    mom = -pr * A * yv + (rho * vel * vel[1] + pr * yv) * A
+    if physics == 1:
+        mom = mom + nx * nz * mu * n * n * h * (vel + vel[1] * yv / 3.0)
+    expect = np.concatenate([[rho * vel[1] * A], mom, [(q[4] + pr) * vel[1] * A]])
+    assert np.max(np.abs(got - expect)) <= 1e-13 * np.max(np.abs(expect)), (got, expect)
+    # and the residual of the uniform state is zero away from the wall only
+    R = orc.residual(U)
+    assert np.max(np.abs(R)) > 1e-3
+
+
 def _smooth_field(x, y, z):
     k = 2 * math.pi
     rho = 1.0 + 0.1 * np.sin(k * x) * np.cos(k * y)
