@@ -1,23 +1,40 @@
 """Benchmark of the FR hot path on one MI355X.
 
-Workload: Navier-Stokes, mixed degree, 32x32x4 periodic hexahedra with
-perturbed vertices, Re 3900, Pr 0.72, Mach 0.2 base flow plus seeded
-divergence-free Fourier modes, p in {1,2,3,4} with weights .4/.3/.2/.1
-(synthetic, seeded).  A step computes the FR residual R(U) and the exact
-tangent J(U) v in float64, both from one forward-mode (dual-number) pass;
-`value` is GDOF/s for that pair (n_dof / step time); the same pair from two
-separate calls is reported beside it.  The same run also reports each operator alone, the
-float32 and finite-difference tangents, the implicit ESDIRK2 step in its
-plain (float64, finite-difference Jv, per-bucket launches, no graph) and
-mixed (float32 exact Jv and Krylov basis, graph-captured Arnoldi) forms, the
-roofline of the dominant kernel and the CPU oracle on a bounded sample.
+Headline workload: the 128x128x8 periodic box (131,072 hexahedra, 29.6 M
+DOF) at Re 60000, Pr 0.72, Mach 0.1 base flow plus seeded divergence-free
+Fourier modes, vertices perturbed by 5 % of the element width, p in
+{1,2,3,4} with weights .3/.3/.25/.15 (synthetic, seeded).  A step computes
+the FR residual R(U) and the exact tangent J(U) v in float64 from one
+forward-mode (dual-number) pass; `value` is n_dof / (median step time) in
+GDOF/s, with every input resident in HBM.
+
+The same run reports, on that workload:
+  * every operator alone (residual, float64 / float32 / finite-difference
+    tangents, adjoint), in the degree-bucketed (fused) and per-bucket launch
+    modes, median of >= 20 calls;
+  * per-stage times of the step (HIP events on the launching stream, median);
+  * the roofline of the step: the algorithmic bytes and flops of the
+    residual + tangent per DOF (compulsory traffic: U and v read, R and Jv
+    written, 217 B of mesh data per element; sum-factorised flops) against
+    the FP64 vector peak and the HBM peak;
+  * the implicit ESDIRK2 stage solve at these settings (GMRES(30) to 1e-6,
+    PTC to 1e-4, dt 0.002) in the mixed form (float32 exact tangent and
+    Krylov basis, captured Arnoldi graphs), in float64 with the exact
+    tangent, and in the plain form (float64, finite-difference tangent,
+    per-bucket launches, no graph) with the state-scaled step;
+  * the same quantities on the 32x32x4 Re 3900 workload (cache-resident:
+    absolute numbers only), including the full ESDIRK2 and ESDIRK4 steps;
+  * the CPU oracle on a bounded sample of the headline workload at one
+    thread and at every host thread.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --study {c3,c5,c3adapt}
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -30,73 +47,149 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6
 FP32_VECTOR_TFLOPS = 157.3
-SK_NAME = {0: "float64", 1: "dual float64", 2: "dual float32"}
+MESH_BYTES_PER_ELEMENT = 217  # 8 vertices (192 B), 6 neighbour ids (24 B), the degree (1 B)
+TANGENT_FLOP_FACTOR = 2.25    # dual-number pass / residual (value and derivative parts)
 
 
-def fused_counts(stage, elem_p, faces_by_pair, op, ns=True):
-    """Bytes and nominal flops of one fused launch: the sum over its buckets."""
-    by = fl = 0.0
-    if stage in ("k_trace_fused", "k_div_fused"):
-        base = stage.replace("_fused", "")
-        for n, cnt in elem_p.items():
-            b, f = nominal_counts(base, n, n, cnt, op, ns)
-            by += b
-            fl += f
-    else:
-        for (nl, nh), cnt in faces_by_pair.items():
-            b, f = nominal_counts("k_face" if nl > 0 else "k_bface", abs(nl), nh, cnt, op, ns)
-            by += b
-            fl += f
-    return by, fl
+def residual_flops_per_dof(n, ns=True):
+    """Sum-factorised flops per DOF of the float64 residual at n = p + 1:
+    about 60 n^4 per element for the gradient and divergence contractions,
+    plus pointwise flux, metric and correction work per solution point and
+    Riemann / viscous work per face point (planning model, per DOF)."""
+    return (12.0 * n + 165.0 + 200.0 / n) if ns else (6.0 * n + 60.0 + 100.0 / n)
 
 
-def nominal_counts(stage, nl, nh, units, op, ns=True):
-    """Algorithmic bytes and nominal flops of one launch.
+def work_model(elem_p, ns=True):
+    """Per-DOF algorithmic work of the hot path on a degree field:
+    bytes (compulsory HBM traffic) and flops of each operator."""
+    n = elem_p.astype(np.int64) + 1
+    dof = 5 * n ** 3
+    n_dof, E = float(dof.sum()), float(len(n))
+    fres = float((dof * np.array([residual_flops_per_dof(k, ns) for k in n])).sum())
+    mesh = MESH_BYTES_PER_ELEMENT * E
+    return {
+        "n_dof": n_dof,
+        "residual": {"bytes": 16 * n_dof + mesh, "flops": fres},
+        "jvp_f64": {"bytes": 24 * n_dof + mesh, "flops": TANGENT_FLOP_FACTOR * fres},
+        "jvp_f32": {"bytes": 12 * n_dof + mesh, "flops": TANGENT_FLOP_FACTOR * fres},
+        "residual_and_jvp": {"bytes": 32 * n_dof + mesh, "flops": TANGENT_FLOP_FACTOR * fres},
+    }
 
-    Bytes: the launch's compulsory inputs and outputs (state, tangent
-    direction, face data, result; the element stages read 24 map
-    coefficients per element, the face stages the precomputed face-point
-    geometry: the area vector and, for Navier-Stokes, the lifting
-    coefficients).
-    Flops: the arithmetic of the stage's formulation counted per solution or
-    face point (multiply-add = 2), a dual number doubling the products."""
-    sb_in = 8 if op < 2 else 4             # state / result precision
-    n_in = 1 if op == 0 else 2             # U (and v for a tangent)
-    sb_T = {0: 8, 1: 16, 2: 8}[op]         # face-buffer scalar
-    sb_g = 8 if op < 2 else 4              # geometry scalar
-    dual = 1.0 if op == 0 else 2.5
-    n = nh
-    if stage == "k_trace":
-        n3, n2 = n ** 3, n * n
-        by = units * (5 * n3 * sb_in * n_in + (24 * 8 if ns else 0) + (30 + (90 if ns else 0)) * n2 * sb_T)
-        fl = units * (60 * n3 + (n3 * (30 * n + 185) + 180 * n3 if ns else 0)) * dual
-    elif stage == "k_div":
-        n3, n2 = n ** 3, n * n
-        by = units * (5 * n3 * sb_in * n_in + 24 * 8 + (60 if ns else 30) * n2 * sb_T + 5 * n3 * sb_in)
-        fl = units * n3 * ((60 * n + 570) if ns else (30 * n + 160)) * dual + units * 60 * n3 * dual
-    elif stage == "k_face":
-        by = units * ((20 if ns else 5) * (nl * nl + nh * nh) * sb_T + (5 if ns else 3) * nh * nh * sb_g
-                      + 10 * (nl * nl + nh * nh) * sb_T)
-        fl = units * nh * nh * (500 if ns else 200) * dual
-    else:  # boundary faces
-        by = units * ((20 if ns else 5) * n * n * sb_T + (4 if ns else 3) * n * n * sb_g + 10 * n * n * sb_T)
-        fl = units * n * n * (400 if ns else 150) * dual
-    return float(by), float(fl)
+
+def roofline(work, t_s, peak_tflops=FP64_VECTOR_TFLOPS):
+    """Fractions of the FP64 vector peak and of the HBM peak; the bound is the
+    roof that takes longer for this work."""
+    flops, by = work["flops"], work["bytes"]
+    t_alu = flops / (peak_tflops * 1e12)
+    t_hbm = by / (HBM_PEAK_GBS * 1e9)
+    alu = {"bound": "alu", "achieved": round(flops / t_s / 1e12, 3), "peak": peak_tflops, "unit": "TFLOP/s",
+           "frac": round(flops / t_s / 1e12 / peak_tflops, 4)}
+    hbm = {"achieved_gbs": round(by / t_s / 1e9, 1), "frac": round(by / t_s / 1e9 / HBM_PEAK_GBS, 4)}
+    out = dict(alu) if t_alu >= t_hbm else {"bound": "hbm", "achieved": hbm["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                                            "unit": "GB/s", "frac": hbm["frac"]}
+    out["alu_frac"] = alu["frac"]
+    out["hbm_frac"] = hbm["frac"]
+    out["hbm_achieved_gbs"] = hbm["achieved_gbs"]
+    out["algorithmic_bytes"] = by
+    out["algorithmic_flops"] = flops
+    out["attainable_gdof_s"] = round(work_n_dof(work) / max(t_alu, t_hbm) / 1e9, 2)
+    return out
+
+
+def work_n_dof(work):
+    return work.get("n_dof", 0.0)
+
+
+def median_ms(fn, reps, warmup, stream, torch):
+    """Median over `reps` calls of fn, each bracketed by HIP events on the
+    launching stream."""
+    for _ in range(max(1, warmup)):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    t = [a.elapsed_time(b) for a, b in evs]
+    return float(np.median(t)), float(np.mean(t))
+
+
+def stage_medians(ctx, U, op, reps=20):
+    """Per-launch times of one operator's kernels (fr_profile, HIP events on
+    the stream): medians over `reps` single runs."""
+    runs = [ctx.profile(U, op=op, reps=1) for _ in range(reps)]
+    out = []
+    for i, k in enumerate(runs[0]):
+        ms = float(np.median([r[i]["ms"] for r in runs]))
+        out.append({"stage": k["stage"], "units": int(k["units"]), "ms": round(ms, 5)})
+    return out
+
+
+def measured_traffic(name):
+    """HBM bytes per call of an operator from a committed rocprofv3 counter
+    summary under profiles/ (lines 'source_sha256: ...', 'traffic_bytes:
+    ...'), or None if there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", name)
+    try:
+        with open(path) as f:
+            kv = dict(line.split(":", 1) for line in f if line.count(":") >= 1 and not line.startswith(("#", "|")))
+    except OSError:
+        return None
+    kv = {k.strip().strip("-* `"): v.strip().strip("`") for k, v in kv.items()}
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes"])
+    except (KeyError, ValueError):
+        return None
+
+
+# sources that define the residual and tangent kernels: a counter summary is
+# used only while they hash to the value recorded in it
+KERNEL_SOURCES = ("frx_device.hpp", "frx_residual.hpp", "frx_launch.hpp", "frx_host.hpp", "frx_k_dual64.hip")
+TRAFFIC_PROFILE = "residual_jvp_dual64_ns_128x128x8_hbm_traffic.md"
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1910_03693_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def host_cpu():
+    """lscpu's model name and the number of host cores."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--no-implicit", action="store_true", help="skip the ESDIRK2 step comparison")
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-implicit", action="store_true", help="skip the implicit-step comparisons")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-small", action="store_true", help="skip the 32x32x4 workload")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB five times (reference for the HBM byte counters)")
     ap.add_argument("--study", choices=("c3", "c5", "c3adapt"), default=None,
-                    help="instead of the headline: the implicit-step comparison on the 64x64x8 vortex street "
-                         "(c3, degrees from the indicator) or the 128x128x8 Re 60000 box (c5)")
+                    help="instead of the headline: implicit steps on the 64x64x8 vortex street (c3) or the "
+                         "128x128x8 box (c5), or the adaptive vortex-street loop (c3adapt)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the hot path is built and "
@@ -114,125 +207,71 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    case = I.config(2)
-    ctx = frx.Context.from_case(case)
-    U = torch.tensor(case.U, device=dev)
-    v = torch.tensor(I.random_direction(case.U.size, 4002).reshape(case.U.shape), device=dev)
-    v32 = v.float()
-    R = torch.empty_like(U)
-    Jv = torch.empty_like(U)
-    J32 = torch.empty_like(v32)
-    n_dof = ctx.n_dof
-    print(f"[bench] workload ns_mixed 32x32x4, {case.mesh['n_elem']} elements, {n_dof} DOF", file=sys.stderr,
-          flush=True)
-    ctx.autotune(U)
     stream = torch.cuda.current_stream()
-
-    def timed(fn, reps):
-        for _ in range(max(1, args.warmup)):
-            fn()
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(reps):
-            fn()
-        b.record(stream)
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / reps  # ms
+    case = I.config(5)
+    ctx = frx.Context.from_case(case, max_restart=30, graphs=frx.FR_GRAPHS_F64_EXACT | frx.FR_GRAPHS_F32_EXACT)
+    U = torch.tensor(case.U, device=dev)
+    v = torch.tensor(I.random_direction(case.U.size, 4005).reshape(case.U.shape), device=dev)
+    n_dof = ctx.n_dof
+    E = int(case.mesh["n_elem"])
+    print(f"[bench] workload 128x128x8 Re 60000, {E} elements, {n_dof} DOF", file=sys.stderr, flush=True)
+    ctx.autotune(U)
+    ctx.set_launch(True)  # the batched design: one degree-bucketed launch per stage
+    R, Jv = torch.empty_like(U), torch.empty_like(U)
 
     def step():
-        # R(U) and J(U) v in float64 from one forward-mode pass: the dual-number
-        # kernels carry the residual in their value part
+        # R(U) and J(U) v in float64 from one forward-mode pass
         ctx.residual_jvp(U, v, R, Jv)
 
-    def step_separate():
-        ctx.residual(U, out=R)
-        ctx.jvp(U, v, out=Jv)
-
-    # the batched design: one degree-bucketed launch per stage
-    ctx.set_launch(True)
-
-    # headline: K timed steps of (residual + exact float64 tangent)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms_step = ev0.elapsed_time(ev1) / args.steps
+    ms_step, ms_mean = median_ms(step, args.steps, args.warmup, stream, torch)
     value = n_dof / (ms_step * 1e-3) / 1e9
-    print(f"[bench] residual + exact Jv (one pass): {ms_step:.4f} ms/step, {value:.2f} GDOF/s", file=sys.stderr,
-          flush=True)
+    print(f"[bench] residual + exact Jv (one pass): median {ms_step:.4f} ms/step (mean {ms_mean:.4f}), "
+          f"{value:.3f} GDOF/s", file=sys.stderr, flush=True)
+
+    W = work_model(case.elem_p)
+    W["residual_and_jvp"]["n_dof"] = n_dof
+    roof = roofline(W["residual_and_jvp"], ms_step * 1e-3)
+    stages = stage_medians(ctx, U, op=3)
+    roof["kernel"] = ("fr_residual_jvp: " + " + ".join(s["stage"] for s in stages) +
+                      " (Dual<double>, navier-stokes, roe)")
+    roof["launch_ms"] = round(ms_step, 5)
+    roof["stages"] = [dict(s, share=round(s["ms"] / sum(x["ms"] for x in stages), 3)) for s in stages]
+    roof["work_model"] = (f"{W['residual_and_jvp']['flops'] / n_dof:.1f} flop/DOF "
+                          f"({TANGENT_FLOP_FACTOR} x the residual's 12n + 165 + 200/n), "
+                          f"{W['residual_and_jvp']['bytes'] / n_dof:.2f} B/DOF (U, v, R, Jv + "
+                          f"{MESH_BYTES_PER_ELEMENT} B/element)")
+    roof["traffic"] = measured_traffic(TRAFFIC_PROFILE)
+    if roof["traffic"] is not None:
+        roof["traffic_over_algorithmic"] = round(roof["traffic"] / roof["algorithmic_bytes"], 2)
+    print(f"[bench] roofline {roof}", file=sys.stderr, flush=True)
 
     reps = max(20, args.steps // 2)
-    ms_sep = timed(step_separate, args.steps)
-    print(f"[bench] separate residual and exact Jv calls: {ms_sep:.4f} ms, {n_dof / (ms_sep * 1e-3) / 1e9:.2f} GDOF/s",
-          file=sys.stderr, flush=True)
+    v32 = v.float()
+    J32 = torch.empty_like(v32)
     per_op = {}
     for mode in ("fused", "per_bucket"):
         ctx.set_launch(mode == "fused")
         ops = {
-            "residual_f64": timed(lambda: ctx.residual(U, out=R), reps),
-            "jvp_exact_f64": timed(lambda: ctx.jvp(U, v, out=Jv), reps),
-            "jvp_exact_f32": timed(lambda: ctx.jvp(U, v32, precision=frx.FR_F32, out=J32), reps),
-            "jvp_fd_f64": timed(lambda: ctx.jvp(U, v, jv_mode=frx.FR_JV_FD, out=Jv), reps),
-            "residual_and_jvp_one_pass": timed(lambda: ctx.residual_jvp(U, v, R, Jv), reps),
-            "vjp_f64": timed(lambda: ctx.vjp(U, v, out=Jv), reps),
+            "residual_f64": (lambda: ctx.residual(U, out=R), W["residual"]),
+            "jvp_exact_f64": (lambda: ctx.jvp(U, v, out=Jv), W["jvp_f64"]),
+            "jvp_exact_f32": (lambda: ctx.jvp(U, v32, precision=frx.FR_F32, out=J32), W["jvp_f32"]),
+            "jvp_fd_f64": (lambda: ctx.jvp(U, v, jv_mode=frx.FR_JV_FD, out=Jv), None),
+            "residual_and_jvp_one_pass": (lambda: ctx.residual_jvp(U, v, R, Jv), W["residual_and_jvp"]),
+            "vjp_f64": (lambda: ctx.vjp(U, v, out=Jv), None),
         }
-        per_op[mode] = {k: {"ms": round(t, 5), "gdof_s": round(n_dof / (t * 1e-3) / 1e9, 3)} for k, t in ops.items()}
+        res = {}
+        for k, (fn, w) in ops.items():
+            t, _ = median_ms(fn, reps, 2, stream, torch)
+            r = {"ms": round(t, 4), "gdof_s": round(n_dof / (t * 1e-3) / 1e9, 3)}
+            if w is not None:
+                w = dict(w, n_dof=n_dof)
+                rf = roofline(w, t * 1e-3, FP32_VECTOR_TFLOPS if k == "jvp_exact_f32" else FP64_VECTOR_TFLOPS)
+                r.update(alu_frac=rf["alu_frac"], hbm_frac=rf["hbm_frac"])
+            res[k] = r
+        per_op[mode] = res
+        print(f"[bench] operators ({mode}): {res}", file=sys.stderr, flush=True)
     ctx.set_launch(True)
-    # the nodal filter (p > 2, alpha = 0.2; one launch per filtered degree in either mode), in place
-    Uf = U.clone()
-    t_f = timed(lambda: ctx.nodal_filter(Uf, 0.2, 3, out=Uf), reps)
-    n_filt = int(5 * ((case.elem_p.astype(np.int64) + 1) ** 3)[case.elem_p >= 3].sum())
-    per_op["nodal_filter_p_gt_2"] = {"ms": round(t_f, 5), "filtered_dof": n_filt,
-                                     "gb_s": round(16 * n_filt / (t_f * 1e-3) / 1e9, 1)}
-
-    # per-kernel timing of the float64 tangent in the batched launch (HIP events on this stream)
-    kt = ctx.profile(U, op=1, reps=20)
-    for k in kt:
-        k["total_ms"] = k["ms"]
-    dom = max(kt, key=lambda k: k["ms"])
-    counts_n = {int(p) + 1: int(c) for p, c in zip(*np.unique(case.elem_p, return_counts=True))}
-    pairs = {}
-    nbr = case.mesh["elem_nbr"]
-    for e in range(case.mesh["n_elem"]):
-        ne = int(case.elem_p[e]) + 1
-        for f in range(6):
-            nb = int(nbr[e, f])
-            if nb >= 0 and f % 2 == 1:
-                nn = int(case.elem_p[nb]) + 1
-                key = (min(ne, nn), max(ne, nn))
-                pairs[key] = pairs.get(key, 0) + 1
-            elif nb < 0:
-                pairs[(-ne, ne)] = pairs.get((-ne, ne), 0) + 1
-    if dom["stage"].endswith("_fused"):
-        by, fl = fused_counts(dom["stage"], counts_n, pairs, 1)
-    else:
-        by, fl = nominal_counts(dom["stage"], dom["n_lo"], dom["n_hi"], dom["units"], 1)
-    intensity = fl / by
-    ridge = FP64_VECTOR_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
-    t_s = dom["ms"] * 1e-3
-    if intensity >= ridge:
-        roof = {"bound": "alu", "achieved": round(fl / t_s / 1e12, 3), "peak": FP64_VECTOR_TFLOPS,
-                "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "hbm", "achieved": round(by / t_s / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    roof["traffic"] = measured_traffic(dom["stage"])
-    flux = "rusanov" if case.flux == 1 else "roe"
-    roof["kernel"] = f"{dom['stage']}<{SK_NAME[1]},navier-stokes,{flux}>" if dom["stage"].endswith("_fused") else \
-        f"{dom['stage']}<n={dom['n_hi']}{'' if dom['n_lo'] == dom['n_hi'] else ',' + str(dom['n_lo'])}," \
-        f"{SK_NAME[1]},navier-stokes,{flux}>"
-    roof["launch_ms"] = round(dom["ms"], 5)
-    roof["algorithmic_bytes"] = by
-    roof["nominal_flops"] = fl
-    print(f"[bench] dominant kernel {roof['kernel']}: {dom['ms']:.4f} ms, {roof}", file=sys.stderr, flush=True)
+    del J32, v32
 
     out = {
         "metric": "GDOF/s for FR residual + exact Jv; implicit step time, mixed vs plain FP64",
@@ -242,68 +281,35 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 5),
+        "ms_per_step_mean": round(ms_mean, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded mesh, degrees and Fourier-mode flow field)",
-        "config": {"workload": "navier-stokes mixed-degree 32x32x4 periodic hex, Re 3900, Mach 0.2, "
-                               "p in {1,2,3,4} w .4/.3/.2/.1, perturbed vertices",
-                   "n_elem": int(case.mesh["n_elem"]), "n_dof": int(n_dof),
-                   "step": "R(U) and exact J(U)v, float64, from one forward-mode pass (fr_residual_jvp)",
+        "config": {"workload": "navier-stokes mixed-degree 128x128x8 periodic hex (131072 elements), Re 60000, "
+                               "Mach 0.1, p in {1,2,3,4} w .3/.3/.25/.15, perturbed vertices",
+                   "n_elem": E, "n_dof": int(n_dof),
+                   "step": "R(U) and exact J(U)v, float64, from one forward-mode pass (fr_residual_jvp), "
+                           "median of the timed steps",
                    "parallelism": "single GPU"},
-        "separate_calls": {"ms": round(ms_sep, 5), "gdof_s": round(n_dof / (ms_sep * 1e-3) / 1e9, 3),
-                           "calls": "fr_residual + fr_jvp(exact, float64)"},
-        "operators": per_op,
-        "kernels_jvp_f64": [{k2: (round(v2, 5) if isinstance(v2, float) else v2) for k2, v2 in k.items()
-                             if k2 != "total_ms"} for k in kt],
         "roofline": roof,
+        "operators": per_op,
+        "launch_shapes": "autotuned (fr_autotune) on this workload",
     }
-
     if args.copy_calibration > 0:
         out["copy_calibration"] = copy_calibration(torch, args.copy_calibration)
     if not args.no_implicit:
-        out["implicit_step"] = implicit_steps(ctx, case, U, frx, torch)
+        out["implicit_stage_128x128x8"] = implicit_stage_c5(ctx, case, U, frx, torch)
+    del R, Jv, v
+    ctx.close()
+    del U
+    torch.cuda.empty_cache()
+    if not args.no_small:
+        out["small_32x32x4"] = small_workload(frx, I, torch, args, stream, not args.no_implicit)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds, value)
     print(json.dumps(out), flush=True)
-
-
-# Sources that define the dominant kernel (the fused face stage of the float64
-# tangent).  Its HBM traffic is taken from the rocprofv3 FETCH_SIZE / WRITE_SIZE
-# summary under profiles/ only while these files hash to the value recorded
-# there; after any change to them `traffic` is null until the counters are
-# taken again.
-TRAFFIC_SOURCES = ("frx_device.hpp", "frx_residual.hpp", "frx_launch.hpp", "frx_host.hpp", "frx_k_dual64.hip")
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "face_fused_dual64_ns_32x32x4_hbm_traffic.md")
-
-
-def kernel_source_hash():
-    import hashlib
-
-    h = hashlib.sha256()
-    for name in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, "paper_1910_03693_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
-
-
-def measured_traffic(stage):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (lines 'kernel: ...', 'source_sha256: ...', 'traffic_bytes: ...'),
-    or None if there is none or the kernel's sources have changed since."""
-    try:
-        with open(TRAFFIC_PROFILE) as f:
-            kv = dict(line.split(":", 1) for line in f if line.count(":") >= 1 and not line.startswith(("#", "|")))
-    except OSError:
-        return None
-    kv = {k.strip().strip("-* `"): v.strip().strip("`") for k, v in kv.items()}
-    if kv.get("kernel") != stage or kv.get("source_sha256") != kernel_source_hash():
-        return None
-    try:
-        return float(kv["traffic_bytes"])
-    except (KeyError, ValueError):
-        return None
 
 
 def copy_calibration(torch, mib):
@@ -325,42 +331,155 @@ def copy_calibration(torch, mib):
             "gb_s": round(2 * n * 8 / (ms * 1e-3) / 1e9, 1)}
 
 
-def implicit_steps(ctx, case, U, frx, torch):
-    """One ESDIRK2 step, plain float64 / finite-difference Jv / uniform launches
-    versus mixed float32 exact Jv + float32 basis + graph, same tolerances;
-    and one six-stage ESDIRK4 step in the mixed form."""
+def _timed_step(ctx, U, dt, torch, **kw):
+    Uw = U.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = ctx.esdirk_step(Uw, dt, **kw)
+    torch.cuda.synchronize()
+    return Uw, (time.perf_counter() - t0) * 1e3, st
+
+
+def implicit_stage_c5(ctx, case, U, frx, torch):
+    """The first implicit stage of an ESDIRK2 step (dt 0.002; PTC from
+    dtau 2e-4 up to 4e-3, to 1e-4; GMRES(30) to 1e-6 relative, at most 300
+    products) in three forms: mixed (float32 exact tangent and basis, graph),
+    float64 exact (graph) and plain (float64 finite differences with the step
+    scaled to the state, per-bucket launches, no graph).  The plain form with
+    the paper's absolute step (1e-6 along the unit direction, 29.6 M
+    components) stagnates here: see the c5 study."""
+    dt = 0.002
+    common = dict(dtau_init=2e-4, dtau_max=4e-3, tol_pseudo=1e-4, max_ptc_iter=50, last_stage=2)
+    g = dict(restart=30, max_iter=300, tol=1e-6)
+    res = {"dt": dt, "settings": {**common, **g}}
+    outs = {}
+    for name, gv, fused in (("mixed_f32_exact_graph", dict(g, precision=frx.FR_F32, use_graph=True), True),
+                            ("f64_exact_graph", dict(g, precision=frx.FR_F64, use_graph=True), True),
+                            ("plain_f64_fd_scaled", dict(g, jv_mode=frx.FR_JV_FD_SCALED, precision=frx.FR_F64),
+                             False)):
+        ctx.set_launch(fused)
+        Uw, ms, st = _timed_step(ctx, U, dt, torch, gmres=gv, **common)
+        outs[name] = Uw
+        res[name] = {"ms": round(ms, 1), **st, "launch": "fused" if fused else "per-bucket"}
+        print(f"[bench] 128x128x8 stage {name}: {ms:.1f} ms {st}", file=sys.stderr, flush=True)
+    ctx.set_launch(True)
+    ref = outs["f64_exact_graph"]
+    for name in ("mixed_f32_exact_graph", "plain_f64_fd_scaled"):
+        res[f"rel_diff_{name}_vs_f64_exact"] = (outs[name] - ref).norm().item() / ref.norm().item()
+    res["rel_change_of_stage"] = (ref - U).norm().item() / U.norm().item()
+    res["speedup_mixed_vs_plain"] = round(res["plain_f64_fd_scaled"]["ms"] / res["mixed_f32_exact_graph"]["ms"], 3)
+    return res
+
+
+def small_workload(frx, I, torch, args, stream, implicit):
+    """The 32x32x4 Re 3900 workload: cache-resident (U is 6 MB), so its numbers
+    are absolute, not HBM evidence."""
+    case = I.config(2)
+    ctx = frx.Context.from_case(case, max_restart=30, graphs=frx.FR_GRAPHS_F64_EXACT | frx.FR_GRAPHS_F32_EXACT)
+    U = torch.tensor(case.U, device="cuda")
+    v = torch.tensor(I.random_direction(case.U.size, 4002).reshape(case.U.shape), device="cuda")
+    R, Jv = torch.empty_like(U), torch.empty_like(U)
+    ctx.autotune(U)
+    ctx.set_launch(True)
+    t, tm = median_ms(lambda: ctx.residual_jvp(U, v, R, Jv), max(20, args.steps), args.warmup, stream, torch)
+    res = {"n_dof": int(ctx.n_dof), "residual_and_jvp_one_pass": {"ms": round(t, 5), "ms_mean": round(tm, 5),
+                                                                   "gdof_s": round(ctx.n_dof / (t * 1e-3) / 1e9, 3)}}
+    ops = {"residual_f64": lambda: ctx.residual(U, out=R), "jvp_exact_f64": lambda: ctx.jvp(U, v, out=Jv),
+           "jvp_fd_f64": lambda: ctx.jvp(U, v, jv_mode=frx.FR_JV_FD, out=Jv), "vjp_f64": lambda: ctx.vjp(U, v, out=Jv)}
+    for k, fn in ops.items():
+        tk, _ = median_ms(fn, 20, 2, stream, torch)
+        res[k] = {"ms": round(tk, 5), "gdof_s": round(ctx.n_dof / (tk * 1e-3) / 1e9, 3)}
+    print(f"[bench] 32x32x4: {res}", file=sys.stderr, flush=True)
+    if implicit:
+        res["implicit_step"] = implicit_steps_small(ctx, U, frx, torch)
+    ctx.close()
+    return res
+
+
+def implicit_steps_small(ctx, U, frx, torch):
+    """One ESDIRK2 step (dt 0.005, dtau from dt/10 to dt, PTC to 1e-4,
+    GMRES(30) to 1e-1): plain (float64, finite-difference Jv with the paper's
+    step, per-bucket launches, no graph) versus mixed (float32 exact Jv and
+    basis, graph) and float64 exact (graph); and one ESDIRK4 step, mixed."""
     dt = 0.005
     common = dict(dtau_init=dt / 10, dtau_max=dt, tol_pseudo=1e-4, max_ptc_iter=50)
-    plain_g = dict(restart=30, max_iter=100, tol=1e-1, jv_mode=frx.FR_JV_FD, precision=frx.FR_F64,
-                   use_graph=False)
-    mixed_g = dict(restart=30, max_iter=100, tol=1e-1, jv_mode=frx.FR_JV_EXACT, precision=frx.FR_F32,
-                   use_graph=True)
-    exact64_g = dict(mixed_g, precision=frx.FR_F64)
-    res = {"dt": dt, "settings": {**common, "restart": 30, "tol_gmres": 1e-1}}
+    base = dict(restart=30, max_iter=100, tol=1e-1)
+    res = {"dt": dt, "settings": {**common, **base}}
     outs = {}
-    for name, g, fused, scheme in (("plain_f64_fd", plain_g, False, frx.FR_ESDIRK2),
-                                   ("mixed_f32_exact_graph", mixed_g, True, frx.FR_ESDIRK2),
-                                   ("f64_exact_graph", exact64_g, True, frx.FR_ESDIRK2),
-                                   ("esdirk4_mixed_f32_exact_graph", mixed_g, True, frx.FR_ESDIRK4)):
+    for name, g, fused, scheme in (
+            ("plain_f64_fd", dict(base, jv_mode=frx.FR_JV_FD), False, frx.FR_ESDIRK2),
+            ("mixed_f32_exact_graph", dict(base, precision=frx.FR_F32, use_graph=True), True, frx.FR_ESDIRK2),
+            ("f64_exact_graph", dict(base, precision=frx.FR_F64, use_graph=True), True, frx.FR_ESDIRK2),
+            ("esdirk4_mixed_f32_exact_graph", dict(base, precision=frx.FR_F32, use_graph=True), True,
+             frx.FR_ESDIRK4)):
         ctx.set_launch(fused)
-        Uw = U.clone()
-        ctx.esdirk_step(Uw, dt, gmres=g, scheme=scheme, **common)  # warm-up (allocation, capture)
-        Uw = U.clone()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st = ctx.esdirk_step(Uw, dt, gmres=g, scheme=scheme, **common)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3
+        _timed_step(ctx, U, dt, torch, gmres=g, scheme=scheme, **common)  # warm-up
+        Uw, ms, st = _timed_step(ctx, U, dt, torch, gmres=g, scheme=scheme, **common)
         outs[name] = Uw
-        res[name] = {"ms": round(ms, 3), **st}
-        res[name]["launch"] = "fused" if fused else "per-bucket"
-        print(f"[bench] implicit step {name}: {ms:.2f} ms {st}", file=sys.stderr, flush=True)
+        res[name] = {"ms": round(ms, 3), **st, "launch": "fused" if fused else "per-bucket"}
+        print(f"[bench] 32x32x4 step {name}: {ms:.2f} ms {st}", file=sys.stderr, flush=True)
     ctx.set_launch(True)
-    d = (outs["plain_f64_fd"] - outs["mixed_f32_exact_graph"]).norm().item()
-    res["rel_diff_mixed_vs_plain"] = d / outs["plain_f64_fd"].norm().item()
+    res["rel_diff_mixed_vs_plain"] = ((outs["plain_f64_fd"] - outs["mixed_f32_exact_graph"]).norm().item() /
+                                      outs["plain_f64_fd"].norm().item())
     res["rel_change_of_step"] = (outs["plain_f64_fd"] - U).norm().item() / U.norm().item()
     res["speedup_mixed_vs_plain"] = round(res["plain_f64_fd"]["ms"] / res["mixed_f32_exact_graph"]["ms"], 3)
     return res
+
+
+def slab_of(case, nx_slab):
+    """The first nx_slab columns (in x) of a structured box workload: its
+    elements, degrees and state, closed periodically in x (the sample the
+    CPU oracle is timed on)."""
+    from paper_1910_03693_amd import inputs as I
+
+    nx, ny, nz = case.mesh["shape"]
+    ix = np.arange(case.mesh["n_elem"]) % nx
+    sel = np.nonzero(ix < nx_slab)[0]  # mesh order (x fastest) is kept
+    L = case.mesh["lengths"]
+    m = I.box_mesh(nx_slab, ny, nz, (L[0] * nx_slab / nx, L[1], L[2]))
+    m["elem_xyz"] = case.mesh["elem_xyz"][sel]
+    off = I.sp_offsets(case.elem_p)
+    cols = np.concatenate([np.arange(off[e], off[e + 1]) for e in sel])
+    sub = I.Case("slab", m, case.elem_p[sel].copy(), np.ascontiguousarray(case.U[:, cols]), case.physics,
+                 case.flux, case.gamma, case.mu, case.prandtl, case.farfield, {})
+    return sub
+
+
+def cpu_baseline(case, seconds, gpu_value):
+    """The CPU oracle as it stands (plain loops; OpenMP over elements and
+    faces), timed on the host: residual + complex-step exact tangent (the
+    headline step's two results) on a 16x128x8 slab of the headline workload
+    (an eighth of its elements, same degrees and field), once at one thread and
+    once at every host thread, each repeated until `seconds` have passed."""
+    import oracle
+
+    sub = slab_of(case, 16)
+    orc = oracle.Oracle.from_case(sub)
+    v = np.random.default_rng(4005).normal(size=sub.U.shape)
+    model, _ = host_cpu()
+    ncpu = oracle.threads()  # OpenMP's default: OMP_NUM_THREADS if set, else the cores it may use
+    runs = {}
+    for th in (1, ncpu):
+        oracle.set_threads(th)
+        t0 = time.perf_counter()
+        ts = []
+        while True:
+            t1 = time.perf_counter()
+            orc.residual(sub.U)
+            orc.jvp(sub.U, v)
+            ts.append(time.perf_counter() - t1)
+            if time.perf_counter() - t0 >= seconds:
+                break
+        med = float(np.median(ts))
+        runs[th] = {"gdof_s": round(sub.U.size / med / 1e9, 6), "seconds_per_step": round(med, 3), "reps": len(ts)}
+        print(f"[bench] cpu oracle, {th} thread(s): {runs[th]}", file=sys.stderr, flush=True)
+    oracle.set_threads(ncpu)
+    best = runs[ncpu]
+    return {"value": best["gdof_s"], "unit": "GDOF/s", "cores": ncpu, "kind": "oracle",
+            "sample": f"residual + complex-step exact Jv on a 16x128x8 slab of the 128x128x8 workload "
+                      f"({sub.U.size} DOF), median of {best['reps']} at {ncpu} threads",
+            "single_thread": runs[1], "all_threads": best, "host_cpu": model,
+            "gpu_over_cpu": round(gpu_value / best["gdof_s"], 1)}
 
 
 def adaptive_study(steps=4):
@@ -375,7 +494,7 @@ def adaptive_study(steps=4):
 
     p, _ = adapt.indicator_degree_field(lambda ep: I.case_street(elem_p=ep))
     case = I.case_street(elem_p=p)
-    ctx = frx.Context.from_case(case)
+    ctx = frx.Context.from_case(case, max_restart=30, graphs=frx.FR_GRAPHS_F32_EXACT)
     ctx.set_launch(True)
     U = torch.tensor(case.U, device="cuda")
     dt = 0.05
@@ -388,7 +507,7 @@ def adaptive_study(steps=4):
         st = ctx.esdirk_step(U, dt, gmres=g, **common)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        case, ctx2, U = adapt.adapt_step(case, ctx, U)
+        case, ctx2, U = adapt.adapt_step(case, ctx, U, reserve=dict(max_restart=30, graphs=frx.FR_GRAPHS_F32_EXACT))
         ctx2.set_launch(True)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
@@ -403,10 +522,12 @@ def adaptive_study(steps=4):
 
 
 def step_study(which):
-    """One ESDIRK2 step in the plain, FP64-exact and mixed forms on a larger
-    workload (not the headline): c3 = 64x64x8 vortex street with the degree
-    field chosen by the spectral-decay indicator; c5 = 128x128x8 box at
-    Re 60000, Mach 0.1 with the settings of the paper's SD7003 runs."""
+    """Implicit steps on a larger workload (not the headline): c3 = 64x64x8
+    vortex street with the degree field chosen by the spectral-decay indicator
+    (one full ESDIRK2 step, GMRES(30) to 1e-1); c5 = the 128x128x8 box at
+    Re 60000, Mach 0.1 with the settings of the paper's SD7003 runs (one full
+    ESDIRK2 step, GMRES(30) to 1e-6), including the plain form with the
+    paper's absolute finite-difference step."""
     import torch
 
     from paper_1910_03693_amd import adapt, frx
@@ -423,107 +544,29 @@ def step_study(which):
         case = I.config(5)
         dt, common = 0.002, dict(dtau_init=2e-4, dtau_max=4e-3, tol_pseudo=1e-4, max_ptc_iter=50)
         g = dict(restart=30, max_iter=300, tol=1e-6)
-    ctx = frx.Context.from_case(case)
+    ctx = frx.Context.from_case(case, max_restart=30, graphs=frx.FR_GRAPHS_F64_EXACT | frx.FR_GRAPHS_F32_EXACT)
     U = torch.tensor(case.U, device="cuda")
+    ctx.autotune(U)
     out["n_dof"] = int(ctx.n_dof)
     out["dt"] = dt
-    # the operators alone on this workload (fused launches, HIP events)
-    ctx.set_launch(True)
-    vv = torch.tensor(I.random_direction(case.U.size, 4005).reshape(case.U.shape), device="cuda")
-    R, J = torch.empty_like(U), torch.empty_like(U)
-    J32 = torch.empty_like(vv, dtype=torch.float32)
-    v32 = vv.float()
-
-    def t_op(fn, reps=10, batches=3):
-        # median over batches of reps calls: a single batch can catch a stall
-        fn()
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        times = []
-        for _ in range(batches):
-            a.record()
-            for _ in range(reps):
-                fn()
-            b.record()
-            torch.cuda.synchronize()
-            times.append(a.elapsed_time(b) / reps)
-        return float(np.median(times))
-
-    ops = {"residual_f64": t_op(lambda: ctx.residual(U, out=R)),
-           "jvp_exact_f64": t_op(lambda: ctx.jvp(U, vv, out=J)),
-           "jvp_exact_f32": t_op(lambda: ctx.jvp(U, v32, precision=frx.FR_F32, out=J32)),
-           "residual_and_jvp_one_pass": t_op(lambda: ctx.residual_jvp(U, vv, R, J)),
-           "vjp_f64": t_op(lambda: ctx.vjp(U, vv, out=J))}
-    out["operators_fused"] = {k: {"ms": round(t, 4), "gdof_s": round(ctx.n_dof / (t * 1e-3) / 1e9, 3)}
-                              for k, t in ops.items()}
-    print(f"[bench] {which} operators: {out['operators_fused']}", file=sys.stderr, flush=True)
-    # per-stage times of the float64 tangent and their algorithmic bandwidth
-    # (this working set does not fit the Infinity Cache)
-    kt = ctx.profile(U, op=1, reps=5)
-    counts_n = {int(p) + 1: int(c) for p, c in zip(*np.unique(case.elem_p, return_counts=True))}
-    pairs = {}
-    nbr = case.mesh["elem_nbr"]
-    for e in range(case.mesh["n_elem"]):
-        ne = int(case.elem_p[e]) + 1
-        for f in range(6):
-            nb = int(nbr[e, f])
-            if nb >= 0 and f % 2 == 1:
-                nn = int(case.elem_p[nb]) + 1
-                key = (min(ne, nn), max(ne, nn))
-                pairs[key] = pairs.get(key, 0) + 1
-            elif nb < 0:
-                pairs[(-ne, ne)] = pairs.get((-ne, ne), 0) + 1
-    stages = []
-    for k in kt:
-        by, fl = fused_counts(k["stage"], counts_n, pairs, 1)
-        stages.append({"stage": k["stage"], "ms": round(k["ms"], 4), "algorithmic_bytes": by,
-                       "gb_s": round(by / (k["ms"] * 1e-3) / 1e9, 1), "hbm_frac": round(by / (k["ms"] * 1e-3) / 1e9 /
-                                                                                      HBM_PEAK_GBS, 4)})
-    out["tangent_f64_stages"] = stages
-    print(f"[bench] {which} tangent stages: {stages}", file=sys.stderr, flush=True)
-    del R, J, J32, v32, vv
     out["settings"] = {**common, **g}
     variants = (("f64_exact_graph", dict(g, precision=frx.FR_F64, use_graph=True), True),
                 ("mixed_f32_exact_graph", dict(g, precision=frx.FR_F32, use_graph=True), True),
-                ("plain_f64_fd", dict(g, jv_mode=frx.FR_JV_FD, precision=frx.FR_F64, use_graph=False), False))
+                ("plain_f64_fd_scaled", dict(g, jv_mode=frx.FR_JV_FD_SCALED, precision=frx.FR_F64), False),
+                ("plain_f64_fd", dict(g, jv_mode=frx.FR_JV_FD, precision=frx.FR_F64), False))
     outs = {}
     for name, gv, fused in variants:
         ctx.set_launch(fused)
-        Uw = U.clone()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st = ctx.esdirk_step(Uw, dt, gmres=gv, **common)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3
+        Uw, ms, st = _timed_step(ctx, U, dt, torch, gmres=gv, **common)
         outs[name] = Uw
         out[name] = {"ms": round(ms, 1), **st, "launch": "fused" if fused else "per-bucket"}
         print(f"[bench] {which} {name}: {ms:.1f} ms {st}", file=sys.stderr, flush=True)
     ref = outs["f64_exact_graph"]
-    for name in ("mixed_f32_exact_graph", "plain_f64_fd"):
+    for name in ("mixed_f32_exact_graph", "plain_f64_fd_scaled", "plain_f64_fd"):
         out[f"rel_diff_{name}_vs_f64_exact"] = (outs[name] - ref).norm().item() / ref.norm().item()
-    out["speedup_mixed_vs_plain"] = round(out["plain_f64_fd"]["ms"] / out["mixed_f32_exact_graph"]["ms"], 3)
+    out["speedup_mixed_vs_plain_scaled"] = round(out["plain_f64_fd_scaled"]["ms"] /
+                                                 out["mixed_f32_exact_graph"]["ms"], 3)
     return out
-
-
-def cpu_baseline(case, seconds):
-    """The CPU oracle as it stands (single thread) on a bounded sample: repeated
-    residual + complex-step exact tangent on the same workload."""
-    import oracle
-
-    orc = oracle.Oracle.from_case(case)
-    v = np.random.default_rng(4002).normal(size=case.U.shape)
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        orc.residual(case.U)
-        orc.jvp(case.U, v)
-        n += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = (time.perf_counter() - t0) / n
-    return {"value": round(case.U.size / dt / 1e9, 6), "unit": "GDOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} x (residual + complex-step exact Jv) on the full 32x32x4 workload, "
-                      f"{dt:.3f} s each, single-threaded"}
 
 
 if __name__ == "__main__":

@@ -20,9 +20,10 @@
  *    gmres_stage_solve and esdirk_step synchronise the stream to read their
  *    convergence scalars.
  *  - The library owns its workspace.  fr_create allocates the mesh data and
- *    the residual's face buffers; the first Krylov or time-step call on a
- *    context allocates that solver's workspace (for the largest restart seen),
- *    later calls reuse it.
+ *    the residual's face buffers; fr_reserve allocates the Krylov and
+ *    time-step workspace and instantiates the captured Arnoldi graphs.  No
+ *    compute call allocates device memory: a solver call that needs more than
+ *    was reserved returns FR_E_INVALID.
  *  - Errors: argument errors return at once; a failed HIP call returns
  *    FR_E_HIP; a density or pressure <= 0 met by a residual kernel raises a
  *    device flag that the next synchronising call reports as FR_E_NONPHYSICAL.
@@ -58,7 +59,12 @@ enum { FR_EULER = 0, FR_NAVIER_STOKES = 1 };
 enum { FR_ROE = 0, FR_RUSANOV = 1 };
 enum { FR_BC_WALL = -1, FR_BC_FARFIELD = -2 };
 typedef enum { FR_F64 = 0, FR_F32 = 1 } fr_prec;
-typedef enum { FR_JV_EXACT = 0, FR_JV_FD = 1 } fr_jv_mode;
+/* Jacobian-vector product: exact tangent, or the finite difference of
+ * section 2.3 with the step eps taken along the unit direction (FR_JV_FD, the
+ * paper's fixed eps = 1e-6), or with the step scaled to the state as
+ * eps sqrt(1 + ||U||_2) (FR_JV_FD_SCALED, Walker and Pernice's choice for
+ * matrix-free Newton-Krylov; a reading, the paper fixes no scaling). */
+typedef enum { FR_JV_EXACT = 0, FR_JV_FD = 1, FR_JV_FD_SCALED = 2 } fr_jv_mode;
 
 /*
  * Mesh and physics (section 2.1 and 2.2 of the paper).  Conforming hexahedra:
@@ -88,12 +94,13 @@ typedef struct {
   int32_t restart;    /* Krylov basis size m per cycle (paper: 60) */
   int32_t max_iter;   /* operator products per solve (paper: 100) */
   double tol;         /* stop when ||r|| <= tol ||F|| (paper: 1e-1) */
-  int32_t jv_mode;    /* FR_JV_EXACT (dual-number tangent) or FR_JV_FD */
+  int32_t jv_mode;    /* FR_JV_EXACT (dual-number tangent), FR_JV_FD or FR_JV_FD_SCALED */
   int32_t precision;  /* FR_F64, or FR_F32 (exact Jv and Krylov basis in
                          float32; Hessenberg, rotations, dots and the update
                          stay float64) */
   double fd_eps;      /* finite-difference step along the unit direction (1e-6) */
-  int32_t use_graph;  /* replay each Arnoldi cycle as a captured HIP graph */
+  int32_t use_graph;  /* replay each Arnoldi cycle from the graphs that fr_reserve
+                         captured for this (jv_mode, precision) */
 } fr_gmres_opts;
 
 typedef struct {
@@ -110,7 +117,8 @@ enum { FR_ESDIRK2 = 0, FR_ESDIRK4 = 1 };
 
 /* Pseudo-transient continuation inside an ESDIRK step (section 2.3). */
 typedef struct {
-  double dtau_init, dtau_max, dtau_min;  /* SER bounds (eq. ser); halving floor */
+  double dtau_init, dtau_max, dtau_min;  /* SER bounds (eq. ser); halving floor: need
+                                            0 < dtau_min <= dtau_init <= dtau_max */
   double tol_pseudo;                     /* ||F|| / ||F^0|| stop (paper: 1e-4) */
   int32_t max_ptc_iter;
   int32_t last_stage;                    /* 0 (or the stage count): full step; 2..s-1: return
@@ -137,6 +145,29 @@ fr_status fr_destroy(fr_ctx ctx);
  * NULL, the first solution point of every element (host [n_elem + 1]). */
 fr_status fr_layout(fr_ctx ctx, int64_t* n_dof, int64_t* sp_offset);
 
+/* Graph sets of fr_reserve: the Arnoldi iteration (section 2.3, the GMRES
+ * inner loop) captured per (jv_mode, precision). */
+enum {
+  FR_GRAPHS_F64_EXACT = 1,
+  FR_GRAPHS_F32_EXACT = 2,
+  FR_GRAPHS_F64_FD = 4,
+  FR_GRAPHS_F64_FD_SCALED = 8,
+  FR_GRAPHS_ALL = 15
+};
+
+/* Allocates the workspace of gmres_stage_solve and esdirk_step (section
+ * 2.3): a Krylov basis of max_restart + 1 vectors of n_dof float64 entries
+ * (float32 bases use half of it), the Hessenberg system and 11 n_dof float64
+ * vectors of ESDIRK stages, and captures the Arnoldi graphs of every set in
+ * graph_sets (or-ed FR_GRAPHS_* bits; sets reserved earlier are kept).  It
+ * synchronises the device.  Later solver calls with restart <= max_restart
+ * and use_graph on a reserved set allocate nothing; a larger restart, an
+ * unreserved graph set or an esdirk_step before any fr_reserve returns
+ * FR_E_INVALID.  Calling it again with a larger max_restart reallocates;
+ * fr_set_launch and fr_autotune capture the reserved graphs again.
+ * FR_E_INVALID for max_restart outside 1..200 or unknown bits. */
+fr_status fr_reserve(fr_ctx ctx, int32_t max_restart, int32_t graph_sets);
+
 /* R = -(P(div f) + delta) of eq. FR_diff (with R = -div f of eq. ESDIRK_ns).
  * U, R: device [5][n_sp] float64.  R must not alias U. */
 fr_status fr_residual(fr_ctx ctx, const double* U, double* R, void* stream);
@@ -151,7 +182,9 @@ fr_status fr_residual_jvp(fr_ctx ctx, const double* U, const double* v, double* 
 /* Jv = dR/dU(U) v.  FR_JV_EXACT: forward-mode (dual-number) residual kernels;
  * precision FR_F64: v, Jv float64; FR_F32: v, Jv float32, computed from a
  * float32 copy of U.  FR_JV_FD: the finite difference of section 2.3,
- * (R(U + eps v/|v|) - R(U)) |v| / eps, float64 only.  Jv must not alias v. */
+ * (R(U + h v/|v|) - R(U)) |v| / h with h = fd_eps (0 selects 1e-6);
+ * FR_JV_FD_SCALED: the same with h = fd_eps sqrt(1 + ||U||_2); float64 only.
+ * Jv must not alias v; fd_eps < 0 is FR_E_INVALID. */
 fr_status fr_jvp(fr_ctx ctx, const double* U, const void* v, void* Jv, int32_t precision, int32_t jv_mode,
                  double fd_eps, void* stream);
 
@@ -169,9 +202,11 @@ fr_status gmres_stage_solve(fr_ctx ctx, const double* U, double shift, const dou
 /* One step of ESDIRK2 or ESDIRK4 (eq. ESDIRK_ns, opts->scheme): stages
  * 2..s are solved by pseudo-transient continuation with SER (eqs.
  * pseudo_transient, ser) and GMRES; a GMRES failure halves dtau and redoes
- * the iterate; each stage starts from the previous stage's solution.
- * U: device float64, in/out.  FR_E_INVALID for an unknown scheme or a
- * last_stage outside {0, 2..s}. */
+ * the iterate, until dtau would fall below dtau_min (then FR_E_NOTCONVERGED);
+ * each stage starts from the previous stage's solution.  U: device float64,
+ * in/out.  FR_E_INVALID for an unknown scheme, a last_stage outside
+ * {0, 2..s}, dtau bounds that are not 0 < dtau_min <= dtau_init <= dtau_max,
+ * or a context without fr_reserve. */
 fr_status esdirk_step(fr_ctx ctx, double* U, double dt, const fr_step_opts* opts, fr_step_stats* stats,
                       void* stream);
 
@@ -225,7 +260,8 @@ fr_status fr_filter(fr_ctx ctx, const double* U, double* U_out, double alpha, in
 fr_status fr_autotune(fr_ctx ctx, const double* U, void* stream);
 
 /* Per-launch timing of one operator's kernels (op 0: residual float64,
- * 1: exact tangent float64, 2: exact tangent float32; U doubles as the
+ * 1: exact tangent float64, 2: exact tangent float32, 3: residual and
+ * float64 tangent from one pass as fr_residual_jvp; U doubles as the
  * direction).  Each launch is bracketed by HIP events on `stream`; out[i]
  * receives the stage ("k_trace", "k_face", "k_bface", "k_div"), the degree
  * sizes n = p + 1 of its bucket, the elements or faces it processes and the

@@ -24,8 +24,9 @@ struct GmresDev {
   double* part;   // [(m+1) x nblk] multi-dot partials
   double* hbuf;   // [m+1] current multi-dot result
   double* sc;     // scalars: 0 beta, 1 ||F||, 2 tol, 3 residual estimate, 4 1/h_{j+1,j}, 5 sigma
-  int* ist;       // ints: 0 done flag, 1 iterations of this cycle, 2 total iterations
-  int m;
+  int* ist;       // ints: 0 done flag, 1 iterations of this cycle, 2 total iterations, 3 iteration budget,
+                  // 4 length of this cycle (<= m)
+  int m;          // leading dimension of H: the largest cycle the workspace holds
   int nblk;
 };
 
@@ -181,7 +182,7 @@ __device__ __forceinline__ void givens_step(const GmresDev& G, int j, const doub
   G.sc[4] = hn > 0.0 ? 1.0 / hn : 0.0;
   G.ist[1] = j + 1;
   G.ist[2] += 1;
-  if (res <= G.sc[2] * G.sc[1] || hn == 0.0 || G.ist[2] >= G.ist[3] || j + 1 == m) G.ist[0] = 1;
+  if (res <= G.sc[2] * G.sc[1] || hn == 0.0 || G.ist[2] >= G.ist[3] || j + 1 >= G.ist[4]) G.ist[0] = 1;
 }
 
 __global__ void k_givens(GmresDev G, int j, const double* __restrict__ h1, const double* __restrict__ h2,
@@ -330,14 +331,16 @@ __global__ void __launch_bounds__(KR_THREADS) k_lincomb(double* __restrict__ out
   }
 }
 
-// finite-difference perturbation Up = U + eps * v / ||v||  (||v||^2 on device)
+// finite-difference perturbation Up = U + eps * v / ||v||  (||v||^2 and eps
+// on the device, so that a captured graph reads the current step)
 template <class TV>
 __global__ void __launch_bounds__(KR_THREADS) k_fd_perturb(const double* __restrict__ U, const TV* __restrict__ v,
-                                                          const double* __restrict__ nrm2, double eps,
-                                                          double* __restrict__ Up, long n, const int* __restrict__ done) {
+                                                          const double* __restrict__ nrm2,
+                                                          const double* __restrict__ epsp, double* __restrict__ Up,
+                                                          long n, const int* __restrict__ done) {
   if (done && *done) return;
   const double nv = sqrt(*nrm2);
-  const double s = nv > 0.0 ? eps / nv : 0.0;
+  const double s = nv > 0.0 ? *epsp / nv : 0.0;
   for (long t = (long)blockIdx.x * KR_THREADS + threadIdx.x; t < n; t += (long)gridDim.x * KR_THREADS)
     Up[t] = U[t] + s * (double)v[t];
 }
@@ -346,12 +349,13 @@ __global__ void __launch_bounds__(KR_THREADS) k_fd_perturb(const double* __restr
 template <class TV, class TO>
 __global__ void __launch_bounds__(KR_THREADS) k_fd_combine(const TV* __restrict__ v, const double* __restrict__ R1,
                                                           const double* __restrict__ R0,
-                                                          const double* __restrict__ nrm2, double eps,
+                                                          const double* __restrict__ nrm2,
+                                                          const double* __restrict__ epsp,
                                                           const double* __restrict__ sigma, TO* __restrict__ out,
                                                           long n, const int* __restrict__ done) {
   if (done && *done) return;
   const double nv = sqrt(*nrm2);
-  const double sg = *sigma;
+  const double sg = *sigma, eps = *epsp;
   for (long t = (long)blockIdx.x * KR_THREADS + threadIdx.x; t < n; t += (long)gridDim.x * KR_THREADS)
     out[t] = (TO)(sg * (double)v[t] - nv * (R1[t] - R0[t]) / eps);
 }
@@ -359,6 +363,12 @@ __global__ void __launch_bounds__(KR_THREADS) k_fd_combine(const TV* __restrict_
 template <class TS, class TD>
 __global__ void __launch_bounds__(KR_THREADS) k_cast(const TS* __restrict__ s, TD* __restrict__ d, long n) {
   for (long t = (long)blockIdx.x * KR_THREADS + threadIdx.x; t < n; t += (long)gridDim.x * KR_THREADS) d[t] = (TD)s[t];
+}
+
+// *out = eps sqrt(1 + sqrt(*nrm2)): the finite-difference step scaled to the
+// state (Walker and Pernice's choice), *nrm2 = ||U||^2
+__global__ void k_fd_scaled_eps(const double* __restrict__ nrm2, double eps, double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = eps * sqrt(1.0 + sqrt(*nrm2));
 }
 
 __global__ void k_set_scalar(double* p, double v) {

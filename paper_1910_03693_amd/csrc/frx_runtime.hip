@@ -209,17 +209,32 @@ void default_shapes(MeshDev& M, int sk) {
 
 // ===================================================================== context
 struct GraphKey {
-  int mode, prec, m, j0, j1;  // Arnoldi iterations j0 .. j1 - 1 of a GMRES(m) cycle
+  int mode, prec, j0, j1;  // Arnoldi iterations j0 .. j1 - 1 of a cycle (any length <= the reserved restart)
   bool operator<(const GraphKey& o) const {
-    return std::tie(mode, prec, m, j0, j1) < std::tie(o.mode, o.prec, o.m, o.j0, o.j1);
+    return std::tie(mode, prec, j0, j1) < std::tie(o.mode, o.prec, o.j0, o.j1);
   }
 };
-// Captured Arnoldi graphs cover the first `k` iterations of a cycle, k = the
-// iterations the previous cycle of the same (mode, precision, m) needed, then
-// ARNOLDI_CHUNK iterations at a time.  Between two graphs the host reads the
+// Captured Arnoldi graphs, all instantiated by fr_reserve for the reserved
+// restart M: "heads" cover iterations [0, h) for h in {3, 6, 12, ...} below M
+// and h = M; "chunks" cover [3i, min(3i + 3, M)).  A cycle replays the largest
+// head not above the iterations that the previous cycle of the same (mode,
+// precision) needed, then chunks.  Between two graphs the host reads the
 // device's converged flag, so a converged cycle stops early instead of
-// replaying skipped kernels up to m.
+// replaying skipped kernels up to its end.  The cycle length, the shift and
+// the finite-difference step are read from device memory, so one graph set
+// serves every restart <= M and every step size.
 constexpr int ARNOLDI_CHUNK = 3;
+std::vector<int> arnoldi_heads(int M) {
+  std::vector<int> h;
+  for (int k = ARNOLDI_CHUNK; k < M; k *= 2) h.push_back(k);
+  h.push_back(M);
+  return h;
+}
+// graph-set bits of fr_reserve for (jv mode, precision)
+inline int graph_bit(int mode, int prec) {
+  return mode == FR_JV_EXACT ? (prec == FR_F32 ? FR_GRAPHS_F32_EXACT : FR_GRAPHS_F64_EXACT)
+                             : (mode == FR_JV_FD ? FR_GRAPHS_F64_FD : FR_GRAPHS_F64_FD_SCALED);
+}
 
 struct fr_ctx_s {
   MeshDev M;
@@ -242,7 +257,7 @@ struct fr_ctx_s {
   double* hpin = nullptr; // pinned host scalars
   int* ipin = nullptr;
   // Krylov workspace
-  int m_alloc = -1, prec_alloc = -1;
+  int m_alloc = -1;      // largest cycle the Krylov workspace holds
   void* Vb = nullptr;     // (m+1) x ndof basis
   void* wv = nullptr;     // ndof work vector (basis type)
   void* xv = nullptr;     // ndof basis-type copy of x
@@ -255,7 +270,8 @@ struct fr_ctx_s {
   double* H = nullptr;    // Hessenberg etc. (one block)
   float* sigf = nullptr;  // float copy of the shift
   std::map<GraphKey, hipGraphExec_t> graphs;
-  std::map<std::tuple<int, int, int>, int> cycle_iters;  // (mode, precision, m) -> iterations of the last cycle
+  int graph_sets = 0;  // FR_GRAPHS_* bits instantiated by fr_reserve
+  std::map<std::pair<int, int>, int> cycle_iters;  // (mode, precision) -> iterations of the last cycle
   // ESDIRK workspace
   double* es = nullptr;   // 8 x ndof
   // VJP workspace
@@ -351,16 +367,20 @@ void check_flag(fr_ctx c, hipStream_t s) {
 // --------------------------------------------------------- Krylov workspace
 // Device scalars: sc[0..5] GMRES (see GmresDev), sc[6] sigma, sc[8..] misc,
 // sc[15] norm scratch; h1 = sc + 32, h2 = h1 + (mmax+1), nrm = h2 + (mmax+1).
-void ensure_krylov(fr_ctx c, int m, int prec) {
-  if (c->m_alloc >= m && c->prec_alloc >= prec) return;
-  const int mm = std::max(m, c->m_alloc);
-  const int pp = std::max(prec, c->prec_alloc);
-  // graphs reference the old buffers
+void drop_graphs(fr_ctx c) {
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
+}
+
+// Sized for cycles of up to m iterations; called by fr_create (m = 1) and
+// fr_reserve only, never by a solver call.
+void ensure_krylov(fr_ctx c, int m) {
+  if (c->m_alloc >= m) return;
+  const int mm = std::max(m, c->m_alloc);
+  // graphs reference the old buffers
+  drop_graphs(c);
   for (void* p : {c->Vb, c->wv, c->xv, (void*)c->H, (void*)c->part, (void*)c->sc, (void*)c->ist}) c->dfree(p);
   const size_t vb = 8;  // basis storage sized for float64 (float32 uses half)
-  (void)pp;
   c->Vb = c->dalloc((size_t)(mm + 1) * c->ndof * vb);
   c->wv = c->dalloc((size_t)c->ndof * vb);
   c->xv = c->dalloc((size_t)c->ndof * vb);
@@ -379,11 +399,11 @@ void ensure_krylov(fr_ctx c, int m, int prec) {
     c->sigf = (float*)c->dalloc(sizeof(float) * 4);
   }
   c->m_alloc = mm;
-  c->prec_alloc = pp;
 }
 
-GmresDev gdev(fr_ctx c, int m) {
+GmresDev gdev(fr_ctx c) {
   GmresDev G;
+  const int m = c->m_alloc;
   G.m = m;
   G.H = c->H;
   G.cs = c->H + (size_t)(m + 1) * m;
@@ -401,7 +421,7 @@ GmresDev gdev(fr_ctx c, int m) {
 // The GMRES operator A x = sigma x - J(Ulin) x (sigma in sc[6], float copy in
 // sigf) applied to `in` (basis type) into `out` (basis type).
 template <class TV>
-void apply_A(fr_ctx c, int mode, const TV* in, TV* out, double eps, const int* done, hipStream_t s) {
+void apply_A(fr_ctx c, int mode, const TV* in, TV* out, const int* done, hipStream_t s) {
   const MeshDev& M = c->M;
   if (mode == FR_JV_EXACT) {
     if constexpr (sizeof(TV) == 8) {
@@ -432,8 +452,8 @@ void apply_A(fr_ctx c, int mode, const TV* in, TV* out, double eps, const int* d
     FRX_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(KR_THREADS), 0, s, c->part, NBLK, nrm, done);
     FRX_TRY(hipGetLastError());
-    hipLaunchKernelGGL((k_fd_perturb<TV>), dim3(grid_for(c->ndof)), dim3(KR_THREADS), 0, s, c->Ulin, in, nrm, eps,
-                       c->Up, (long)c->ndof, done);
+    hipLaunchKernelGGL((k_fd_perturb<TV>), dim3(grid_for(c->ndof)), dim3(KR_THREADS), 0, s, c->Ulin, in, nrm,
+                       (const double*)(c->sc + 7), c->Up, (long)c->ndof, done);
     FRX_TRY(hipGetLastError());
     ResCall<double> rc;
     rc.U = c->Up;
@@ -441,7 +461,7 @@ void apply_A(fr_ctx c, int mode, const TV* in, TV* out, double eps, const int* d
     rc.skip = done;
     FRX_TRY(launch_residual_f64(M, rc, s));
     hipLaunchKernelGGL((k_fd_combine<TV, TV>), dim3(grid_for(c->ndof)), dim3(KR_THREADS), 0, s, in, c->R1, c->R0,
-                       nrm, eps, c->sc + 6, out, (long)c->ndof, done);
+                       nrm, (const double*)(c->sc + 7), c->sc + 6, out, (long)c->ndof, done);
     FRX_TRY(hipGetLastError());
   }
 }
@@ -493,8 +513,9 @@ void gs_fused(fr_ctx c, const GmresDev& G, int j, double* h1, double* h2, double
 
 // One Arnoldi iteration j with CGS2 (all kernels skip once *done is set).
 template <class TV>
-void arnoldi_step(fr_ctx c, int mode, int m, int j, double eps, hipStream_t s) {
-  GmresDev G = gdev(c, m);
+void arnoldi_step(fr_ctx c, int mode, int j, hipStream_t s) {
+  GmresDev G = gdev(c);
+  const int m = G.m;
   const long n = c->ndof;
   TV* V = (TV*)c->Vb;
   TV* w = (TV*)c->wv;
@@ -502,7 +523,7 @@ void arnoldi_step(fr_ctx c, int mode, int m, int j, double eps, hipStream_t s) {
   double* h1 = c->sc + 32;
   double* h2 = h1 + (m + 1);
   double* nr = h2 + (m + 1);
-  apply_A<TV>(c, mode, V + (size_t)j * n, w, eps, done, s);
+  apply_A<TV>(c, mode, V + (size_t)j * n, w, done, s);
   const int nv = j + 1;
   if (nv <= 32) {
     gs_fused<TV>(c, G, j, h1, h2, nr, V + (size_t)(j + 1) * n, done, s);
@@ -536,39 +557,62 @@ void arnoldi_step(fr_ctx c, int mode, int m, int j, double eps, hipStream_t s) {
   FRX_TRY(hipGetLastError());
 }
 
+// Captures Arnoldi iterations [j0, j1) of (mode, TV) as a graph (fr_reserve).
 template <class TV>
-void arnoldi_cycle(fr_ctx c, int mode, int m, double eps, bool use_graph, hipStream_t s) {
+void capture_range(fr_ctx c, int mode, int j0, int j1) {
+  if (!c->cap) FRX_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  hipGraph_t g;
+  FRX_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  try {
+    for (int j = j0; j < j1; ++j) arnoldi_step<TV>(c, mode, j, c->cap);
+  } catch (...) {
+    hipGraph_t tmp = nullptr;
+    (void)hipStreamEndCapture(c->cap, &tmp);
+    if (tmp) (void)hipGraphDestroy(tmp);
+    throw;
+  }
+  FRX_TRY(hipStreamEndCapture(c->cap, &g));
+  hipGraphExec_t ex;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  FRX_TRY(e);
+  c->graphs[GraphKey{mode, (int)sizeof(TV), j0, j1}] = ex;
+}
+
+// Instantiates the heads and chunks of every graph set in c->graph_sets.
+void instantiate_graphs(fr_ctx c) {
+  drop_graphs(c);
+  const int M = c->m_alloc;
+  for (int bit : {FR_GRAPHS_F64_EXACT, FR_GRAPHS_F32_EXACT, FR_GRAPHS_F64_FD, FR_GRAPHS_F64_FD_SCALED}) {
+    if (!(c->graph_sets & bit)) continue;
+    const int mode = bit == FR_GRAPHS_F64_FD ? FR_JV_FD : (bit == FR_GRAPHS_F64_FD_SCALED ? FR_JV_FD_SCALED : FR_JV_EXACT);
+    const bool f32 = bit == FR_GRAPHS_F32_EXACT;
+    auto cap = [&](int j0, int j1) {
+      if (f32) capture_range<float>(c, mode, j0, j1);
+      else capture_range<double>(c, mode, j0, j1);
+    };
+    for (int h : arnoldi_heads(M)) cap(0, h);
+    for (int j0 = 0; j0 < M; j0 += ARNOLDI_CHUNK) cap(j0, std::min(M, j0 + ARNOLDI_CHUNK));
+  }
+}
+
+// One cycle of m <= M iterations (the length is in ist[4] on the device).
+template <class TV>
+void arnoldi_cycle(fr_ctx c, int mode, int m, bool use_graph, hipStream_t s) {
   if (!use_graph) {
-    for (int j = 0; j < m; ++j) arnoldi_step<TV>(c, mode, m, j, eps, s);
+    for (int j = 0; j < m; ++j) arnoldi_step<TV>(c, mode, j, s);
     return;
   }
-  const auto ck = std::make_tuple(mode, (int)sizeof(TV), m);
-  auto pit = c->cycle_iters.find(ck);
-  const int first = std::max(1, std::min(m, pit == c->cycle_iters.end() ? ARNOLDI_CHUNK : pit->second));
+  auto pit = c->cycle_iters.find({mode, (int)sizeof(TV)});
+  const int prev = pit == c->cycle_iters.end() ? ARNOLDI_CHUNK : pit->second;
+  int first = 0;
+  for (int h : arnoldi_heads(c->m_alloc))
+    if (first == 0 || h <= prev) first = h;  // the largest head <= prev, at least the smallest
   for (int j0 = 0; j0 < m;) {
-    const int j1 = std::min(m, j0 == 0 ? first : j0 + ARNOLDI_CHUNK);
-    GraphKey key{mode, (int)sizeof(TV), m, j0, j1};
-    auto it = c->graphs.find(key);
-    if (it == c->graphs.end()) {
-      if (!c->cap) FRX_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
-      FRX_TRY(hipStreamSynchronize(s));
-      hipGraph_t g;
-      FRX_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-      try {
-        for (int j = j0; j < j1; ++j) arnoldi_step<TV>(c, mode, m, j, eps, c->cap);
-      } catch (...) {
-        hipGraph_t tmp;
-        (void)hipStreamEndCapture(c->cap, &tmp);
-        if (tmp) (void)hipGraphDestroy(tmp);
-        throw;
-      }
-      FRX_TRY(hipStreamEndCapture(c->cap, &g));
-      hipGraphExec_t ex;
-      hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      FRX_TRY(e);
-      it = c->graphs.emplace(key, ex).first;
-    }
+    const int j1 = j0 == 0 ? first : std::min(c->m_alloc, j0 + ARNOLDI_CHUNK);
+    auto it = c->graphs.find(GraphKey{mode, (int)sizeof(TV), j0, j1});
+    if (it == c->graphs.end())
+      throw StatusErr{FR_E_INVALID, "no reserved Arnoldi graph for this mode and precision (fr_reserve)"};
     FRX_TRY(hipGraphLaunch(it->second, s));
     if (j1 < m) {
       FRX_TRY(hipMemcpyAsync(c->ipin + 8, c->ist, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -581,9 +625,7 @@ void arnoldi_cycle(fr_ctx c, int mode, int m, double eps, bool use_graph, hipStr
 
 // Iterations of the cycle just finished (read by gmres_run after its
 // synchronisation) sizes the first graph of the next cycle.
-void note_cycle(fr_ctx c, int mode, int prec_bytes, int m, int iters) {
-  c->cycle_iters[std::make_tuple(mode, prec_bytes, m)] = iters;
-}
+void note_cycle(fr_ctx c, int mode, int prec_bytes, int iters) { c->cycle_iters[{mode, prec_bytes}] = iters; }
 
 // Restarted GMRES on the device.  x (float64, device) receives the solution.
 template <class TV>
@@ -591,11 +633,10 @@ fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats*
                     double nF_known) {
   const long n = c->ndof;
   const int m = o.restart;
-  GmresDev G = gdev(c, m);
+  GmresDev G = gdev(c);
   TV* V = (TV*)c->Vb;
   TV* w = (TV*)c->wv;
   TV* xv = (TV*)c->xv;
-  const double eps = o.fd_eps > 0 ? o.fd_eps : 1e-6;
   // ||F|| (unless the caller has it), tolerance, budget
   const double nF = nF_known >= 0.0 ? nF_known : norm2(c, c->Fb, s);
   hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(KR_THREADS), 0, s, x, n, 0.0);
@@ -609,6 +650,7 @@ fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats*
   hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, c->sc + 2, o.tol);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->ist + 2, 0);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->ist + 3, o.max_iter);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->ist + 4, m);
   FRX_TRY(hipGetLastError());
   double res = nF;
   int total = 0, cycles = 0;
@@ -620,7 +662,7 @@ fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats*
     } else {
       hipLaunchKernelGGL((k_cast<double, TV>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const double*)x, xv, n);
       FRX_TRY(hipGetLastError());
-      apply_A<TV>(c, o.jv_mode, xv, w, eps, nullptr, s);
+      apply_A<TV>(c, o.jv_mode, xv, w, nullptr, s);
       hipLaunchKernelGGL((k_cast<TV, double>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const TV*)w, c->R1, n);
       FRX_TRY(hipGetLastError());
       lincomb(c, c->rb, 1.0, c->Fb, -1.0, c->R1, 0, nullptr, 0, nullptr, s);
@@ -631,7 +673,7 @@ fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats*
     hipLaunchKernelGGL((k_scale<double, TV>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const double*)c->rb, V, n,
                        (const double*)(c->sc + 4), 0, (const int*)nullptr);
     FRX_TRY(hipGetLastError());
-    arnoldi_cycle<TV>(c, o.jv_mode, m, eps, o.use_graph != 0, s);
+    arnoldi_cycle<TV>(c, o.jv_mode, m, o.use_graph != 0, s);
     hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, s, G);
     FRX_TRY(hipGetLastError());
     hipLaunchKernelGGL((k_update_x<TV>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const TV*)V, n,
@@ -643,7 +685,7 @@ fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats*
     ++cycles;
     total = c->ipin[2];
     res = c->hpin[3];
-    if (o.use_graph) note_cycle(c, o.jv_mode, (int)sizeof(TV), m, c->ipin[1]);
+    if (o.use_graph) note_cycle(c, o.jv_mode, (int)sizeof(TV), c->ipin[1]);
     if (res <= o.tol * nF) {
       conv = true;
       break;
@@ -661,18 +703,33 @@ fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats*
 // Prepare linearisation state and right-hand side, then run GMRES.
 fr_status gmres_solve(fr_ctx c, const double* U, double shift, const double* F, double* dU, const fr_gmres_opts& o,
                       fr_gmres_stats* st, hipStream_t s, const double* R0_known, double nF_known = -1.0) {
-  if (o.restart < 1 || o.restart > 200 || o.max_iter < 1 || !(o.tol >= 0.0))
+  if (o.restart < 1 || o.max_iter < 1 || !(o.tol >= 0.0) || !(o.fd_eps >= 0.0) ||
+      (o.jv_mode != FR_JV_EXACT && o.jv_mode != FR_JV_FD && o.jv_mode != FR_JV_FD_SCALED) ||
+      (o.precision != FR_F64 && o.precision != FR_F32))
     throw StatusErr{FR_E_INVALID, "gmres options out of range"};
   if (o.precision == FR_F32 && o.jv_mode != FR_JV_EXACT)
     throw StatusErr{FR_E_UNSUPPORTED, "float32 GMRES needs the exact tangent"};
-  ensure_krylov(c, o.restart, o.precision);
+  if (o.restart > c->m_alloc)
+    throw StatusErr{FR_E_INVALID, "restart " + std::to_string(o.restart) + " exceeds the reserved workspace (" +
+                                      std::to_string(c->m_alloc) + "); call fr_reserve"};
+  if (o.use_graph && !(c->graph_sets & graph_bit(o.jv_mode, o.precision)))
+    throw StatusErr{FR_E_INVALID, "Arnoldi graphs of this mode and precision were not reserved (fr_reserve)"};
   const long n = c->ndof;
   if (U != c->Ulin) FRX_TRY(hipMemcpyAsync(c->Ulin, U, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   if (F != c->Fb) FRX_TRY(hipMemcpyAsync(c->Fb, F, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, c->sc + 6, shift);
   hipLaunchKernelGGL((k_cast<double, float>), dim3(1), dim3(1), 0, s, (const double*)(c->sc + 6), c->sigf, 1L);
   FRX_TRY(hipGetLastError());
-  if (o.jv_mode == FR_JV_FD) {
+  if (o.jv_mode != FR_JV_EXACT) {
+    // finite-difference step on the device: eps, or eps sqrt(1 + ||U||) (scaled)
+    const double eps = o.fd_eps > 0 ? o.fd_eps : 1e-6;
+    if (o.jv_mode == FR_JV_FD_SCALED) {
+      dot_to<double>(c, c->Ulin, nullptr, c->sc + 12, nullptr, s);
+      hipLaunchKernelGGL(k_fd_scaled_eps, dim3(1), dim3(1), 0, s, (const double*)(c->sc + 12), eps, c->sc + 7);
+    } else {
+      hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, c->sc + 7, eps);
+    }
+    FRX_TRY(hipGetLastError());
     if (R0_known) {
       FRX_TRY(hipMemcpyAsync(c->R0, R0_known, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     } else {
@@ -1040,7 +1097,7 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
     C->uf = (float*)C->dalloc(sizeof(float) * C->ndof);
     FRX_TRY(hipHostMalloc((void**)&C->hpin, 64 * sizeof(double), 0));
     FRX_TRY(hipHostMalloc((void**)&C->ipin, 64 * sizeof(int), 0));
-    ensure_krylov(C.get(), 1, 0);
+    ensure_krylov(C.get(), 1);
     FRX_TRY(hipDeviceSynchronize());
     c = C.release();
     return FR_OK;
@@ -1061,6 +1118,22 @@ fr_status fr_layout(fr_ctx c, int64_t* n_dof, int64_t* sp_offset) {
   if (n_dof) *n_dof = c->ndof;
   if (sp_offset) std::copy(c->sp_off_h.begin(), c->sp_off_h.end(), sp_offset);
   return FR_OK;
+}
+
+fr_status fr_reserve(fr_ctx c, int32_t max_restart, int32_t graph_sets) {
+  if (!c) return FR_E_INVALID;
+  if (max_restart < 1 || max_restart > 200 ||
+      (graph_sets & ~(FR_GRAPHS_F64_EXACT | FR_GRAPHS_F32_EXACT | FR_GRAPHS_F64_FD | FR_GRAPHS_F64_FD_SCALED)))
+    return fail(c, FR_E_INVALID, "fr_reserve: max_restart outside 1..200 or unknown graph-set bits");
+  return guarded(c, [&]() -> fr_status {
+    FRX_TRY(hipDeviceSynchronize());
+    ensure_krylov(c, max_restart);
+    if (!c->es) c->es = (double*)c->dalloc(sizeof(double) * 11 * c->ndof);
+    c->graph_sets |= graph_sets;
+    instantiate_graphs(c);
+    FRX_TRY(hipDeviceSynchronize());
+    return FR_OK;
+  });
 }
 
 // true if the byte ranges [a, a + na) and [b, b + nb) share memory
@@ -1107,8 +1180,9 @@ fr_status fr_jvp(fr_ctx c, const double* U, const void* v, void* Jv, int32_t pre
   if (!U || !v || !Jv || overlap(v, nv, Jv, nv) || overlap(U, nb, Jv, nv))
     return fail(c, FR_E_INVALID, "fr_jvp: bad arguments");
   if (prec != FR_F64 && prec != FR_F32) return fail(c, FR_E_INVALID, "fr_jvp: precision");
-  if (mode != FR_JV_EXACT && mode != FR_JV_FD) return fail(c, FR_E_INVALID, "fr_jvp: mode");
-  if (mode == FR_JV_FD && prec != FR_F64) return fail(c, FR_E_UNSUPPORTED, "fr_jvp: finite differences need float64");
+  if (mode != FR_JV_EXACT && mode != FR_JV_FD && mode != FR_JV_FD_SCALED) return fail(c, FR_E_INVALID, "fr_jvp: mode");
+  if (mode != FR_JV_EXACT && prec != FR_F64) return fail(c, FR_E_UNSUPPORTED, "fr_jvp: finite differences need float64");
+  if (!(eps >= 0.0)) return fail(c, FR_E_INVALID, "fr_jvp: fd_eps must be >= 0 (0: the default 1e-6)");
   return guarded(c, [&]() -> fr_status {
     hipStream_t s = S(stream);
     const long n = c->ndof;
@@ -1129,9 +1203,16 @@ fr_status fr_jvp(fr_ctx c, const double* U, const void* v, void* Jv, int32_t pre
     } else {
       const double e = eps > 0 ? eps : 1e-6;
       double* nrm = c->sc + 10;
+      double* epsd = c->sc + 13;
       dot_to<double>(c, (const double*)v, nullptr, nrm, nullptr, s);
+      if (mode == FR_JV_FD_SCALED) {
+        dot_to<double>(c, U, nullptr, c->sc + 14, nullptr, s);
+        hipLaunchKernelGGL(k_fd_scaled_eps, dim3(1), dim3(1), 0, s, (const double*)(c->sc + 14), e, epsd);
+      } else {
+        hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, epsd, e);
+      }
       hipLaunchKernelGGL((k_fd_perturb<double>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, U, (const double*)v, nrm,
-                         e, c->t0, n, (const int*)nullptr);
+                         (const double*)epsd, c->t0, n, (const int*)nullptr);
       FRX_TRY(hipGetLastError());
       ResCall<double> rc;
       rc.U = c->t0;
@@ -1142,7 +1223,8 @@ fr_status fr_jvp(fr_ctx c, const double* U, const void* v, void* Jv, int32_t pre
       FRX_TRY(launch_residual_f64(c->M, rc, s));
       hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, c->sc + 11, 0.0);
       hipLaunchKernelGGL((k_fd_combine<double, double>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const double*)v,
-                         c->t1, c->t2, nrm, e, (const double*)(c->sc + 11), (double*)Jv, n, (const int*)nullptr);
+                         c->t1, c->t2, nrm, (const double*)epsd, (const double*)(c->sc + 11), (double*)Jv, n,
+                         (const int*)nullptr);
       FRX_TRY(hipGetLastError());
       // k_fd_combine computes sigma v - |v|(R1 - R0)/eps; with sigma = 0 negate
       hipLaunchKernelGGL(k_lincomb, dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (double*)Jv, n, -1.0,
@@ -1244,10 +1326,14 @@ fr_status esdirk_step(fr_ctx c, double* U, double dt, const fr_step_opts* o, fr_
   const int last_stage = o->last_stage == 0 ? T.s : o->last_stage;
   if (last_stage < 2 || last_stage > T.s)
     return fail(c, FR_E_INVALID, "esdirk_step: last_stage must be 0 (the full step) or 2..stages");
+  if (!(o->dtau_init > 0.0) || !(o->dtau_min > 0.0) || !(o->dtau_max >= o->dtau_init) ||
+      !(o->dtau_min <= o->dtau_init) || !(o->tol_pseudo >= 0.0) || o->max_ptc_iter < 0)
+    return fail(c, FR_E_INVALID,
+                "esdirk_step: need 0 < dtau_min <= dtau_init <= dtau_max, tol_pseudo >= 0, max_ptc_iter >= 0");
+  if (!c->es) return fail(c, FR_E_INVALID, "esdirk_step: the step workspace was not reserved (fr_reserve)");
   return guarded(c, [&]() -> fr_status {
     hipStream_t s = S(stream);
     const long n = c->ndof;
-    if (!c->es) c->es = (double*)c->dalloc(sizeof(double) * 11 * n);
     double* qn = c->es;
     double* q = qn + n;
     double* rhs = q + n;
@@ -1305,6 +1391,7 @@ fr_status esdirk_step(fr_ctx c, double* U, double dt, const fr_step_opts* o, fr_
           if (gr != FR_E_NOTCONVERGED) return gr;
           dtau *= 0.5;
           stats.halvings += 1;
+          // dtau_min > 0 bounds the halvings of one iterate (by log2(dtau_max / dtau_min))
           if (dtau < o->dtau_min) {
             status = FR_E_NOTCONVERGED;
             break;
@@ -1399,11 +1486,12 @@ fr_status fr_set_launch(fr_ctx c, int32_t mode) {
       c->M.split_faces[fused][sk] = two;
     }
   }
-  if (changed) {
-    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-    c->graphs.clear();
-  }
-  return FR_OK;
+  if (!changed) return FR_OK;
+  // the reserved graphs hold the old kernels: capture them again
+  return guarded(c, [&]() -> fr_status {
+    instantiate_graphs(c);
+    return FR_OK;
+  });
 }
 
 fr_status fr_check(fr_ctx c, int32_t* nonphysical, void* stream) {
@@ -1521,16 +1609,15 @@ fr_status fr_autotune(fr_ctx c, const double* U, void* stream) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    // captured graphs hold the old shapes
-    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-    c->graphs.clear();
+    // the reserved graphs hold the old shapes: capture them again
+    instantiate_graphs(c);
     return FR_OK;
   });
 }
 
 fr_status fr_profile(fr_ctx c, const double* U, int32_t op, int32_t reps, fr_kernel_time* out, int32_t max_out,
                      int32_t* n_out, void* stream) {
-  if (!c || !U || !out || !n_out || reps < 1 || op < 0 || op > 2) return c ? fail(c, FR_E_INVALID, "fr_profile: bad arguments") : FR_E_INVALID;
+  if (!c || !U || !out || !n_out || reps < 1 || op < 0 || op > 3) return c ? fail(c, FR_E_INVALID, "fr_profile: bad arguments") : FR_E_INVALID;
   return guarded(c, [&]() -> fr_status {
     hipStream_t s = S(stream);
     const long n = c->ndof;
@@ -1543,11 +1630,12 @@ fr_status fr_profile(fr_ctx c, const double* U, int32_t op, int32_t reps, fr_ker
         rc.U = U;
         rc.out = c->t0;
         FRX_TRY(launch_residual_f64(c->M, rc, s));
-      } else if (op == 1) {
+      } else if (op == 1 || op == 3) {
         ResCall<double> rc;
         rc.U = U;
         rc.V = U;
         rc.out = c->t0;
+        if (op == 3) rc.out_val = c->t2;  // the one-pass residual and tangent
         FRX_TRY(launch_residual_dual64(c->M, rc, s));
       } else {
         ResCall<float> rc;

@@ -20,13 +20,14 @@ FR_OK, FR_E_INVALID, FR_E_NOMEM, FR_E_HIP, FR_E_NOTCONVERGED, FR_E_NONPHYSICAL, 
 FR_EULER, FR_NAVIER_STOKES = 0, 1
 FR_ROE, FR_RUSANOV = 0, 1
 FR_F64, FR_F32 = 0, 1
-FR_JV_EXACT, FR_JV_FD = 0, 1
+FR_JV_EXACT, FR_JV_FD, FR_JV_FD_SCALED = 0, 1, 2
+FR_GRAPHS_F64_EXACT, FR_GRAPHS_F32_EXACT, FR_GRAPHS_F64_FD, FR_GRAPHS_F64_FD_SCALED, FR_GRAPHS_ALL = 1, 2, 4, 8, 15
 FR_LAUNCH_PER_BUCKET, FR_LAUNCH_FUSED = 0, 1
 FR_LAUNCH_FACES_TWO_PASS, FR_LAUNCH_FACES_ONE_PASS = 4, 8
 FR_ESDIRK2, FR_ESDIRK4 = 0, 1
 STATUS_NAMES = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_NOMEM", -3: "FR_E_HIP", -4: "FR_E_NOTCONVERGED",
                 -5: "FR_E_NONPHYSICAL", -6: "FR_E_UNSUPPORTED"}
-EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_residual", "fr_residual_jvp", "fr_jvp", "fr_vjp", "gmres_stage_solve",
+EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_reserve", "fr_residual", "fr_residual_jvp", "fr_jvp", "fr_vjp", "gmres_stage_solve",
             "esdirk_step", "spectral_decay_indicator", "fr_select_degrees", "fr_project", "fr_filter", "fr_autotune", "fr_profile",
             "fr_set_launch", "fr_check", "fr_last_error")
 
@@ -84,6 +85,7 @@ def lib():
         L.fr_create.argtypes = [C.POINTER(fr_mesh_desc), C.POINTER(vp)]
         L.fr_destroy.argtypes = [vp]
         L.fr_layout.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.fr_reserve.argtypes = [vp, C.c_int32, C.c_int32]
         L.fr_residual.argtypes = [vp, vp, vp, vp]
         L.fr_jvp.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_double, vp]
         L.fr_vjp.argtypes = [vp, vp, vp, vp, vp]
@@ -121,6 +123,22 @@ def _check(st, ctx=None):
     return st
 
 
+# (n_dof, n_elem) of every live handle, recorded by fr_create: the wrappers
+# refuse tensors of another context's size before anything is launched
+_SIZES = {}
+
+
+def _sizes(h):
+    try:
+        return _SIZES[h.value if isinstance(h, C.c_void_p) else h]
+    except KeyError:
+        raise ValueError("unknown or destroyed context handle") from None
+
+
+def _ndof(h):
+    return _sizes(h)[0]
+
+
 def _dev(t, dtype, n=None):
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError("expected a CUDA (HIP) tensor")
@@ -149,11 +167,19 @@ def fr_create(elem_xyz, elem_nbr, elem_p, physics=FR_EULER, flux=FR_RUSANOV, gam
         d.farfield[i] = float(ff[i])
     h = C.c_void_p()
     _check(lib().fr_create(C.byref(d), C.byref(h)))
+    n = C.c_int64()
+    _check(lib().fr_layout(h, C.byref(n), None), h)
+    _SIZES[h.value] = (n.value, len(p))
     return h
 
 
 def fr_destroy(h):
+    _SIZES.pop(h.value if isinstance(h, C.c_void_p) else h, None)
     return lib().fr_destroy(h)
+
+
+def fr_reserve(h, max_restart=40, graph_sets=FR_GRAPHS_ALL):
+    return _check(lib().fr_reserve(h, int(max_restart), int(graph_sets)), h)
 
 
 def fr_layout(h, n_elem):
@@ -164,18 +190,21 @@ def fr_layout(h, n_elem):
 
 
 def fr_residual(h, U, R, stream=None):
-    return _check(lib().fr_residual(h, _dev(U, torch.float64), _dev(R, torch.float64, U.numel()), _stream(stream)), h)
+    n = _ndof(h)
+    return _check(lib().fr_residual(h, _dev(U, torch.float64, n), _dev(R, torch.float64, n), _stream(stream)), h)
 
 
 def fr_jvp(h, U, v, Jv, precision=FR_F64, jv_mode=FR_JV_EXACT, fd_eps=1e-6, stream=None):
     dt = torch.float64 if precision == FR_F64 else torch.float32
-    return _check(lib().fr_jvp(h, _dev(U, torch.float64), _dev(v, dt, U.numel()), _dev(Jv, dt, U.numel()),
+    n = _ndof(h)
+    return _check(lib().fr_jvp(h, _dev(U, torch.float64, n), _dev(v, dt, n), _dev(Jv, dt, n),
                                precision, jv_mode, fd_eps, _stream(stream)), h)
 
 
 def fr_vjp(h, U, w, JTw, stream=None):
-    return _check(lib().fr_vjp(h, _dev(U, torch.float64), _dev(w, torch.float64, U.numel()),
-                               _dev(JTw, torch.float64, U.numel()), _stream(stream)), h)
+    n = _ndof(h)
+    return _check(lib().fr_vjp(h, _dev(U, torch.float64, n), _dev(w, torch.float64, n),
+                               _dev(JTw, torch.float64, n), _stream(stream)), h)
 
 
 def gmres_opts(restart=30, max_iter=100, tol=1e-1, jv_mode=FR_JV_EXACT, precision=FR_F64, fd_eps=1e-6,
@@ -188,16 +217,20 @@ def gmres_opts(restart=30, max_iter=100, tol=1e-1, jv_mode=FR_JV_EXACT, precisio
 
 def gmres_stage_solve(h, U, shift, F, dU, opts, stream=None, check=True):
     st = fr_gmres_stats()
-    r = lib().gmres_stage_solve(h, _dev(U, torch.float64), float(shift), _dev(F, torch.float64, U.numel()),
-                                _dev(dU, torch.float64, U.numel()), C.byref(opts), C.byref(st), _stream(stream))
+    n = _ndof(h)
+    r = lib().gmres_stage_solve(h, _dev(U, torch.float64, n), float(shift), _dev(F, torch.float64, n),
+                                _dev(dU, torch.float64, n), C.byref(opts), C.byref(st), _stream(stream))
     if check and r not in (FR_OK, FR_E_NOTCONVERGED):
         _check(r, h)
     return r, dict(iterations=st.iterations, cycles=st.cycles, rel_res=st.rel_res, converged=bool(st.converged))
 
 
-def step_opts(dtau_init, dtau_max, dtau_min=0.0, tol_pseudo=1e-4, max_ptc_iter=200, last_stage=0, gmres=None,
+def step_opts(dtau_init, dtau_max, dtau_min=None, tol_pseudo=1e-4, max_ptc_iter=200, last_stage=0, gmres=None,
               scheme=FR_ESDIRK2):
-    """last_stage 0: the full step; 2..s-1: that stage's solution."""
+    """last_stage 0: the full step; 2..s-1: that stage's solution.  dtau_min
+    defaults to dtau_init / 2^20 (at most 20 halvings below the start)."""
+    if dtau_min is None:
+        dtau_min = dtau_init / 2.0 ** 20
     o = fr_step_opts()
     o.dtau_init, o.dtau_max, o.dtau_min, o.tol_pseudo = dtau_init, dtau_max, dtau_min, tol_pseudo
     o.max_ptc_iter, o.last_stage, o.scheme = max_ptc_iter, last_stage, scheme
@@ -207,7 +240,8 @@ def step_opts(dtau_init, dtau_max, dtau_min=0.0, tol_pseudo=1e-4, max_ptc_iter=2
 
 def esdirk_step(h, U, dt, opts, stream=None, check=True):
     st = fr_step_stats()
-    r = lib().esdirk_step(h, _dev(U, torch.float64), float(dt), C.byref(opts), C.byref(st), _stream(stream))
+    r = lib().esdirk_step(h, _dev(U, torch.float64, _ndof(h)), float(dt), C.byref(opts), C.byref(st),
+                          _stream(stream))
     if check and r not in (FR_OK, FR_E_NOTCONVERGED):
         _check(r, h)
     return r, dict(ptc_iterations=st.ptc_iterations, gmres_iterations=st.gmres_iterations, halvings=st.halvings,
@@ -215,42 +249,45 @@ def esdirk_step(h, U, dt, opts, stream=None, check=True):
 
 
 def spectral_decay_indicator(h, U, var, eta, eta_max, stream=None):
-    return _check(lib().spectral_decay_indicator(h, _dev(U, torch.float64), var, _dev(eta, torch.float64),
+    n, ne = _sizes(h)
+    return _check(lib().spectral_decay_indicator(h, _dev(U, torch.float64, n), var, _dev(eta, torch.float64, ne),
                                                  _dev(eta_max, torch.float64, 1), _stream(stream)), h)
 
 
 def fr_residual_jvp(h, U, v, R, Jv, stream=None):
-    n = U.numel()
-    return _check(lib().fr_residual_jvp(h, _dev(U, torch.float64), _dev(v, torch.float64, n), _dev(R, torch.float64, n),
+    n = _ndof(h)
+    return _check(lib().fr_residual_jvp(h, _dev(U, torch.float64, n), _dev(v, torch.float64, n), _dev(R, torch.float64, n),
                                         _dev(Jv, torch.float64, n), _stream(stream)), h)
 
 
 def fr_select_degrees(h, U, var, nu_max, nu_min, p_min, p_max, p_new, stream=None):
-    return _check(lib().fr_select_degrees(h, _dev(U, torch.float64), var, nu_max, nu_min, p_min, p_max,
-                                          _dev(p_new, torch.int8), _stream(stream)), h)
+    n, ne = _sizes(h)
+    return _check(lib().fr_select_degrees(h, _dev(U, torch.float64, n), var, nu_max, nu_min, p_min, p_max,
+                                          _dev(p_new, torch.int8, ne), _stream(stream)), h)
 
 
 def fr_project(h_src, U_src, h_dst, U_dst, stream=None):
-    return _check(lib().fr_project(h_src, _dev(U_src, torch.float64), h_dst, _dev(U_dst, torch.float64),
-                                   _stream(stream)), h_dst)
+    return _check(lib().fr_project(h_src, _dev(U_src, torch.float64, _ndof(h_src)), h_dst,
+                                   _dev(U_dst, torch.float64, _ndof(h_dst)), _stream(stream)), h_dst)
 
 
 def fr_filter(h, U, U_out, alpha, p_from, stream=None):
-    n = U.numel()
-    return _check(lib().fr_filter(h, _dev(U, torch.float64), _dev(U_out, torch.float64, n), alpha, p_from,
+    n = _ndof(h)
+    return _check(lib().fr_filter(h, _dev(U, torch.float64, n), _dev(U_out, torch.float64, n), alpha, p_from,
                                   _stream(stream)), h)
 
 
 def fr_autotune(h, U, stream=None):
-    return _check(lib().fr_autotune(h, _dev(U, torch.float64), _stream(stream)), h)
+    return _check(lib().fr_autotune(h, _dev(U, torch.float64, _ndof(h)), _stream(stream)), h)
 
 
 def fr_profile(h, U, op=0, reps=10, stream=None):
     """Average duration of every kernel launch of one operator (0 residual,
-    1 float64 tangent, 2 float32 tangent), timed with HIP events."""
+    1 float64 tangent, 2 float32 tangent, 3 residual and float64 tangent in
+    one pass), timed with HIP events."""
     buf = (fr_kernel_time * 128)()
     n = C.c_int32(0)
-    _check(lib().fr_profile(h, _dev(U, torch.float64), op, reps, buf, 128, C.byref(n), _stream(stream)), h)
+    _check(lib().fr_profile(h, _dev(U, torch.float64, _ndof(h)), op, reps, buf, 128, C.byref(n), _stream(stream)), h)
     return [dict(stage=buf[i].stage.decode(), n_lo=buf[i].n_lo, n_hi=buf[i].n_hi, units=buf[i].units,
                  ms=buf[i].ms) for i in range(n.value)]
 
@@ -267,18 +304,27 @@ def fr_check(h, stream=None):
 
 # ------------------------------------------------------------------- context
 class Context:
-    """A mesh on the GPU; methods take and return torch tensors shaped [5, n_sp]."""
+    """A mesh on the GPU; methods take and return torch tensors shaped [5, n_sp].
+
+    max_restart / graphs: the solver workspace and Arnoldi graph sets that
+    fr_reserve makes at construction (max_restart=0 reserves nothing; the
+    solver calls then refuse to run until reserve() is called)."""
 
     def __init__(self, elem_xyz, elem_nbr, elem_p, physics=FR_EULER, flux=FR_RUSANOV, gamma=1.4, mu=0.0,
-                 prandtl=0.72, farfield=None):
+                 prandtl=0.72, farfield=None, max_restart=40, graphs=0):
         self.n_elem = len(elem_p)
         self.h = fr_create(elem_xyz, elem_nbr, elem_p, physics, flux, gamma, mu, prandtl, farfield)
         self.n_dof, self.sp_offset = fr_layout(self.h, self.n_elem)
         self.n_sp = self.n_dof // 5
+        if max_restart:
+            fr_reserve(self.h, max_restart, graphs)
 
     @classmethod
-    def from_case(cls, case):
-        return cls(**case.desc())
+    def from_case(cls, case, **kw):
+        return cls(**case.desc(), **kw)
+
+    def reserve(self, max_restart=40, graphs=FR_GRAPHS_ALL):
+        fr_reserve(self.h, max_restart, graphs)
 
     def close(self):
         if getattr(self, "h", None):

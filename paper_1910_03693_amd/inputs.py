@@ -58,39 +58,31 @@ def box_mesh(nx, ny, nz, lengths, periodic=(True, True, True), noise=0.0,
                 sl[d] = nu[d] - 1
                 disp[tuple(sl)] = 0.0
 
-    def vertex(ix, iy, iz):
-        # a periodic image (index n) takes the displacement of plane 0
-        idx = (ix, iy, iz)
-        u = [idx[d] % nn[d] if periodic[d] else idx[d] for d in range(3)]
-        base = np.asarray(origin) + np.asarray(idx, dtype=np.float64) * h
-        return base + disp[u[0], u[1], u[2]]
-
     E = nx * ny * nz
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ijk = [ix.ravel(), iy.ravel(), iz.ravel()]  # element e = ix + nx (iy + ny iz)
     elem_xyz = np.zeros((E, 8, 3))
+    for c in range(2):
+        for b in range(2):
+            for a in range(2):
+                idx = [ijk[0] + a, ijk[1] + b, ijk[2] + c]
+                # a periodic image (index n) takes the displacement of plane 0
+                u = [idx[d] % nn[d] if periodic[d] else idx[d] for d in range(3)]
+                base = np.asarray(origin)[None, :] + np.stack(idx, axis=1).astype(np.float64) * h[None, :]
+                elem_xyz[:, a + 2 * b + 4 * c] = base + disp[u[0], u[1], u[2]]
     elem_nbr = np.zeros((E, 6), dtype=np.int32)
     bc_lo = bc_lo or [BC_WALL] * 3
     bc_hi = bc_hi or [BC_WALL] * 3
-    for iz in range(nz):
-        for iy in range(ny):
-            for ix in range(nx):
-                e = ix + nx * (iy + ny * iz)
-                for c in range(2):
-                    for b in range(2):
-                        for a in range(2):
-                            elem_xyz[e, a + 2 * b + 4 * c] = vertex(ix + a, iy + b, iz + c)
-                ijk = [ix, iy, iz]
-                for d in range(3):
-                    for s in range(2):
-                        j = list(ijk)
-                        j[d] += 1 if s else -1
-                        if 0 <= j[d] < nn[d]:
-                            nb = j[0] + nx * (j[1] + ny * j[2])
-                        elif periodic[d]:
-                            j[d] %= nn[d]
-                            nb = j[0] + nx * (j[1] + ny * j[2])
-                        else:
-                            nb = bc_hi[d] if s else bc_lo[d]
-                        elem_nbr[e, 2 * d + s] = nb
+    for d in range(3):
+        for s in range(2):
+            j = [q.copy() for q in ijk]
+            j[d] = j[d] + (1 if s else -1)
+            inside = (j[d] >= 0) & (j[d] < nn[d])
+            j[d] = j[d] % nn[d]
+            nb = j[0] + nx * (j[1] + ny * j[2])
+            if not periodic[d]:
+                nb = np.where(inside, nb, bc_hi[d] if s else bc_lo[d])
+            elem_nbr[:, 2 * d + s] = nb
     return {"elem_xyz": elem_xyz, "elem_nbr": elem_nbr, "n_elem": E,
             "shape": nn, "lengths": tuple(L), "periodic": tuple(periodic)}
 
@@ -206,21 +198,31 @@ class FourierModes:
         L = np.asarray(self.lengths)
         return 2 * math.pi * self.m / L[None, :]
 
-    def raw(self, x, y, z, chunk=40000):
+    def raw(self, x, y, z, chunk=65536):
         # exp(i k.x) = ex[mx] ey[my] ez[mz]: one complex exponential per axis and
-        # integer wavenumber, then gathered products per mode
+        # integer wavenumber; the amplitudes on the dense (mx, my, mz) lattice
+        # (zero off the ball) are contracted one axis at a time
         L = np.asarray(self.lengths)
         mi = self.m.astype(np.int64)
         lo = mi.min(axis=0)
         span = mi.max(axis=0) - lo + 1
+        A = np.zeros((span[0], span[1], span[2], 3), complex)
+        A[mi[:, 0] - lo[0], mi[:, 1] - lo[1], mi[:, 2] - lo[2]] = self.a
+        A = A.reshape(span[0], -1)
         out = np.zeros((3, x.size))
         for s in range(0, x.size, chunk):
             cols = []
             for d, c in enumerate((x[s:s + chunk], y[s:s + chunk], z[s:s + chunk])):
-                ms = lo[d] + np.arange(span[d])
-                cols.append(np.exp(1j * np.outer(c, 2 * math.pi * ms / L[d])))
-            ph = cols[0][:, mi[:, 0] - lo[0]] * cols[1][:, mi[:, 1] - lo[1]] * cols[2][:, mi[:, 2] - lo[2]]
-            out[:, s:s + chunk] = np.real(ph @ self.a).T
+                # powers of exp(i 2 pi c / L) from exp(i 2 pi lo c / L) on
+                th = 2 * math.pi * c / L[d]
+                pw = np.empty((c.size, span[d]), complex)
+                pw[:, 0] = np.exp(1j * lo[d] * th)
+                if span[d] > 1:
+                    pw[:, 1:] = np.exp(1j * th)[:, None]
+                cols.append(np.cumprod(pw, axis=1))
+            t = (cols[0] @ A).reshape(-1, span[1], span[2], 3)
+            t = np.einsum("pyzc,py->pzc", t, cols[1])
+            out[:, s:s + chunk] = np.real(np.einsum("pzc,pz->cp", t, cols[2]))
         return out
 
     def __call__(self, x, y, z):
@@ -250,7 +252,11 @@ def lamb_oseen_street(x, y, z, ma=0.2, gamma=GAMMA, a=1.0, b_over_a=0.281, yc=4.
             dx = x - cx
             dy = y - yy
             r2 = dx * dx + dy * dy + 1e-300
-            ut = G / (2 * math.pi * r2) * (1.0 - np.exp(-r2 / core2))  # u_theta / r
+            # 1 - exp(-r^2/rc^2) is 1.0 in float64 beyond r^2 = 40 rc^2
+            core = np.ones_like(r2)
+            near = r2 < 40.0 * core2
+            core[near] = 1.0 - np.exp(-r2[near] / core2)
+            ut = (G / (2 * math.pi)) * core / r2  # u_theta / r
             u += -ut * dy
             v += ut * dx
     w = np.zeros_like(x)

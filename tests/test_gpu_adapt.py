@@ -1,7 +1,8 @@
 """p-adaptation on the GPU (section 3.1): degree selection (indicator,
-criteria, face limiter) against the oracle's indicator with the criteria and
-limiter written out here (integer result: bit-exact), and the projection of
-the state between degree fields against the oracle's projection."""
+criteria, face limiter) against the oracle's indicator and the oracle's
+criteria and limiter (oracle/degrees.py; integer result: bit-exact), and the
+projection of the state between degree fields against the oracle's
+projection."""
 import numpy as np
 import pytest
 
@@ -21,14 +22,9 @@ def frx():
 
 
 def oracle_degrees(oracle_mod, case, nu_max=0.1, nu_min=0.001, p_min=1, p_max=5):
+    from oracle import degrees
     eta, mx = oracle_mod.Oracle.from_case(case).indicator(case.U, var=1)
-    p = np.clip(case.elem_p.astype(np.int64) + (eta > nu_max * mx) - (eta < nu_min * mx), p_min, p_max)
-    nbr = case.mesh["elem_nbr"]
-    while True:
-        need = np.maximum(p, np.where(nbr >= 0, p[np.clip(nbr, 0, None)], 0).max(axis=1) - 1)
-        if np.array_equal(need, p):
-            return p
-        p = need
+    return degrees.select_degrees(case.elem_p, eta, mx, case.mesh["elem_nbr"], nu_max, nu_min, p_min, p_max)
 
 
 def _mixed_case():

@@ -83,9 +83,9 @@ def _tiny_cases():
 CASES = _tiny_cases()
 
 
-def _pair(frx, oracle_mod, case):
+def _pair(frx, oracle_mod, case, **reserve):
     orc = oracle_mod.Oracle.from_case(case)
-    ctx = frx.Context.from_case(case)
+    ctx = frx.Context.from_case(case, **reserve)
     U = torch.tensor(case.U, device="cuda")
     return orc, ctx, U
 
@@ -218,6 +218,59 @@ def test_jvp_parity_ns_mixed_32x32x4(frx, c2, launch):
     assert efd <= 1e-5 and abs(efd - rel_err(ofd, ref)) <= 1e-5
 
 
+def _fd_floor(orc, U, vu, eps):
+    """Rounding noise of a float64 finite difference on these inputs: the
+    oracle's float64 difference against the same difference of its
+    extended-precision residuals (same perturbed state)."""
+    Up = U + eps * vu
+    fd_ld = (orc.residual_ld(Up) - orc.residual_ld(U)) / eps
+    return rel_err(orc.jvp_fd(U, vu, eps), fd_ld)
+
+
+@pytest.mark.parametrize("mode", ["fd", "fd_scaled"])
+@pytest.mark.parametrize("name", ["vortex_1", "ns_mixed_32x32x4"])
+def test_fd_jvp_matches_oracle_fd_elementwise(frx, oracle_mod, name, mode):
+    """fr_jvp(FR_JV_FD / FR_JV_FD_SCALED) against the oracle's finite
+    difference at the same step along the unit direction (eps = 1e-6, or
+    1e-6 sqrt(1 + ||U||) scaled), element by element.  Both sides round R to
+    float64 and the difference divides that rounding by the step, so the bound
+    is max(1e-7, 4x the oracle's own rounding noise of the difference)."""
+    case = CASES["vortex_p2_rusanov_3d"] if name == "vortex_1" else I.config(2)
+    print("case", name, mode, flush=True)
+    orc, ctx, U = _pair(frx, oracle_mod, case, max_restart=0)
+    ctx.set_launch(True)
+    v = I.random_direction(case.U.size, 4010).reshape(case.U.shape)
+    nv = np.linalg.norm(v)
+    eps = 1e-6 if mode == "fd" else 1e-6 * math.sqrt(1.0 + np.linalg.norm(case.U))
+    jv = frx.FR_JV_FD if mode == "fd" else frx.FR_JV_FD_SCALED
+    got = ctx.jvp(U, torch.tensor(v, device="cuda"), jv_mode=jv, fd_eps=1e-6).cpu().numpy()
+    ref = orc.jvp_fd(case.U, v / nv, eps) * nv
+    floor = _fd_floor(orc, case.U, v / nv, eps)
+    err = rel_err(got, ref)
+    exact = rel_err(got, orc.jvp(case.U, v))
+    print(f"{name} {mode}: rel err vs oracle fd {err:.3e} (rounding floor {floor:.3e}); vs exact {exact:.3e}")
+    assert err <= max(1e-7, 4 * floor)
+
+
+def test_esdirk_forced_halving_matches_oracle(frx, oracle_mod):
+    """A GMRES budget too small for the first pseudo time step: both sides
+    halve dtau the same number of times in each iterate and reach the same
+    stage solution."""
+    case = CASES["vortex_p2_rusanov"]
+    orc, ctx, U = _pair(frx, oracle_mod, case)
+    kw = dict(dtau_init=2.0, dtau_max=2.0, dtau_min=2.0 / 2 ** 12, tol_pseudo=1e-8, last_stage=2)
+    Uo, so = orc.esdirk2_step(case.U, 0.05, restart=4, max_gmres_it=4, tol_gmres=1e-3, jv_mode=1, **kw)
+    Ug = U.clone()
+    sg = ctx.esdirk_step(Ug, 0.05, gmres=dict(restart=4, max_iter=4, tol=1e-3, jv_mode=frx.FR_JV_FD), **kw)
+    print("forced halving", sg, so)
+    assert so["halvings"] > 0
+    assert sg["halvings"] == so["halvings"] and sg["ptc_iterations"] == so["ptc_iterations"]
+    assert sg["status"] == so["status"] == 0
+    err = np.linalg.norm(Ug.cpu().numpy() - Uo) / np.linalg.norm(Uo)
+    print("rel diff", err)
+    assert err <= 1e-7
+
+
 @pytest.mark.parametrize("launch", ["per_bucket", "fused_2pass"])
 def test_residual_parity_wall_32x32x8(frx, oracle_mod, launch):
     case = I.config(4)
@@ -269,7 +322,7 @@ def test_indicator_parity(frx, oracle_mod):
 
 def test_gmres_fixed_iterations_parity(frx, oracle_mod):
     case = CASES["mixed_p1to5_ns_roe"]
-    orc, ctx, U = _pair(frx, oracle_mod, case)
+    orc, ctx, U = _pair(frx, oracle_mod, case, graphs=frx.FR_GRAPHS_ALL)
     F = I.random_direction(case.U.size, 77).reshape(case.U.shape)
     shift = 20.0
     xo, so = orc.gmres(case.U, shift, F, m=12, max_it=10, tol=0.0, jv_mode=0)
@@ -288,7 +341,7 @@ def test_gmres_long_cycle_parity(frx, oracle_mod):
     (up to 32 basis vectors) and the split multi-dot / multi-axpy path beyond
     them, against the oracle's modified Gram-Schmidt."""
     case = CASES["mixed_p1to5_ns_roe"]
-    orc, ctx, U = _pair(frx, oracle_mod, case)
+    orc, ctx, U = _pair(frx, oracle_mod, case, graphs=frx.FR_GRAPHS_ALL)
     F = I.random_direction(case.U.size, 80).reshape(case.U.shape)
     shift = 8.0
     xo, so = orc.gmres(case.U, shift, F, m=40, max_it=36, tol=0.0, jv_mode=0)
@@ -305,7 +358,7 @@ def test_gmres_long_cycle_parity(frx, oracle_mod):
 @pytest.mark.parametrize("mode", ["exact64", "fd64", "exact32", "exact64_graph", "exact32_graph"])
 def test_gmres_converged(frx, oracle_mod, mode):
     case = CASES["wall_farfield_ns_roe"]
-    orc, ctx, U = _pair(frx, oracle_mod, case)
+    orc, ctx, U = _pair(frx, oracle_mod, case, graphs=frx.FR_GRAPHS_ALL)
     F = I.random_direction(case.U.size, 78).reshape(case.U.shape)
     shift = 50.0  # (a shift of 5 makes GMRES(8) stagnate at 0.192 here, oracle and GPU alike)
     kw = dict(restart=8, max_iter=400, tol=1e-6, use_graph="graph" in mode,
@@ -339,7 +392,7 @@ def test_esdirk_stage_vortex_to_1e8(frx, oracle_mod):
 
 def test_esdirk_full_step_mixed_vs_plain(frx, oracle_mod):
     case = CASES["mixed_p1to5_ns_roe"]
-    orc, ctx, U = _pair(frx, oracle_mod, case)
+    orc, ctx, U = _pair(frx, oracle_mod, case, graphs=frx.FR_GRAPHS_ALL)
     kw = dict(dtau_init=0.005, dtau_max=0.05, tol_pseudo=1e-6)
     Uo, so = orc.esdirk2_step(case.U, 0.05, restart=30, tol_gmres=1e-3, jv_mode=0, **kw)
     ref = np.linalg.norm(Uo)
@@ -378,7 +431,7 @@ def test_esdirk4_full_step_mixed_ns(frx, oracle_mod):
     """ESDIRK4 full step on mixed p = 1..5 Navier-Stokes: FP64 exact tangent
     with graphs and the mixed FP32 form against the oracle's ESDIRK4."""
     case = CASES["mixed_p1to5_ns_roe"]
-    orc, ctx, U = _pair(frx, oracle_mod, case)
+    orc, ctx, U = _pair(frx, oracle_mod, case, graphs=frx.FR_GRAPHS_ALL)
     kw = dict(dtau_init=0.005, dtau_max=0.05, tol_pseudo=1e-6)
     Uo, so = orc.esdirk_step(case.U, 0.05, restart=30, tol_gmres=1e-3, jv_mode=0, scheme=1, **kw)
     assert so["status"] == 0
@@ -405,29 +458,18 @@ def test_esdirk_invalid_scheme_and_stage(frx, oracle_mod):
 
 
 def test_indicator_degree_field_matches_oracle(frx, oracle_mod):
-    """The degree field of the vortex-street workload (at 16x16x2) chosen from
-    the GPU indicator equals the one chosen from the oracle's indicator with
-    the criteria written out again here (integer result: bit-exact)."""
+    """The degree field of the vortex-street workload (at 16x16x2) chosen by
+    the device (fr_select_degrees each sweep) equals the one the oracle's
+    indicator, criteria and limiter choose (integer result: bit-exact)."""
+    from oracle import degrees
     from paper_1910_03693_amd import adapt
 
     def make(ep):
         return I.case_street(16, 16, 2, elem_p=ep)
 
     p_gpu, hist = adapt.indicator_degree_field(make)
-    # the oracle side, with its own statement of the criteria and limiter
-    p = np.full(make(None).mesh["n_elem"], 5, np.int64)
-    for _ in range(4):
-        case = make(p.astype(np.int8))
-        eta, mx = oracle_mod.Oracle.from_case(case).indicator(case.U, var=1)
-        pn = np.clip(p + (eta > 0.1 * mx) - (eta < 0.001 * mx), 1, 5)
-        if np.array_equal(pn, p):
-            break
-        p = pn
-    nbr = case.mesh["elem_nbr"]
-    while True:
-        need = np.maximum(p, np.where(nbr >= 0, p[np.clip(nbr, 0, None)], 0).max(axis=1) - 1)
-        if np.array_equal(need, p):
-            break
-        p = need
-    print("degree histogram", np.bincount(p_gpu, minlength=6)[1:], hist)
+    p, hist_o = degrees.indicator_degree_field(
+        make, lambda case: oracle_mod.Oracle.from_case(case).indicator(case.U, var=1))
+    print("degree histogram", np.bincount(p_gpu, minlength=6)[1:], hist, hist_o)
     assert np.array_equal(p_gpu.astype(np.int64), p)
+    assert hist == hist_o

@@ -38,7 +38,7 @@ def _case():
 @pytest.mark.parametrize("fused", [False, True], ids=["per_bucket", "fused"])
 def test_repeated_calls_are_bitwise_identical(frx, fused):
     case = _case()
-    ctx = frx.Context.from_case(case)
+    ctx = frx.Context.from_case(case, graphs=frx.FR_GRAPHS_ALL)
     ctx.set_launch(fused)
     U = torch.tensor(case.U, device="cuda")
     v = torch.tensor(I.random_direction(case.U.size, 96).reshape(case.U.shape), device="cuda")
