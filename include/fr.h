@@ -172,6 +172,21 @@ fr_status fr_reserve(fr_ctx ctx, int32_t max_restart, int32_t graph_sets);
  * U, R: device [5][n_sp] float64.  R must not alias U. */
 fr_status fr_residual(fr_ctx ctx, const double* U, double* R, void* stream);
 
+/* fr_residual for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same kernels and result, with the face-slot buffers of the residual stages
+ * in a static device array of 64 MiB that the library holds on every GPU it
+ * runs on until the process ends, instead of the context's workspace.  The
+ * call allocates nothing.  Limit: 30 x 8 bytes per own face point, i.e.
+ * 240 * 6 * sum_e (p_e + 1)^2 <= 64 MiB (a 32x32x4 mesh of degrees 1..4 fits,
+ * 128x128x8 does not); a larger mesh returns FR_E_INVALID with the size it
+ * needs.  Every call on one GPU shares that GPU's array and overwrites what
+ * the last call left there (each call writes every entry it reads, so nothing
+ * needs clearing); calls that overlap in time on one GPU, from any context or
+ * stream, race.  The context's device must be current (else FR_E_INVALID).
+ * U, R: device [5][n_sp] float64, R must not alias U. */
+fr_status fr_residual_noalloc(fr_ctx ctx, const double* U, double* R, void* stream);
+
 /* R(U) and the exact tangent J(U) v in float64 from one forward-mode pass:
  * the dual-number residual kernels carry the residual in their value part and
  * the tangent in their derivative part (as a forward-mode derivative returns

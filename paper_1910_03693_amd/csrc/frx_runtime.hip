@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -207,6 +208,32 @@ void default_shapes(MeshDev& M, int sk) {
 }
 }  // namespace frx
 
+// =============================================== scratch of fr_residual_noalloc
+// Face-slot buffers of the float64 residual for callers that cannot allocate:
+// a file-scope device array (every GPU the library runs on holds its own copy
+// until the process ends).  Host code never uses the array's name as an
+// address: fr_create looks up each device's copy with hipGetSymbolAddress,
+// with that device current, and keeps the pointer.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device -> address of its copy of `scratch`
+
+// The address of `scratch` on device `dev`, which must be current.
+void* scratch_on_device(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* p = nullptr;
+  FRX_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw StatusErr{FR_E_HIP, "hipGetSymbolAddress returned no address for the static scratch"};
+  g_scratch_ptr[dev] = p;
+  return p;
+}
+}  // namespace
+
 // ===================================================================== context
 struct GraphKey {
   int mode, prec, j0, j1;  // Arnoldi iterations j0 .. j1 - 1 of a cycle (any length <= the reserved restart)
@@ -276,6 +303,8 @@ struct fr_ctx_s {
   double* es = nullptr;   // 8 x ndof
   // VJP workspace
   void* vjpw = nullptr;
+  // this device's copy of the static scratch of fr_residual_noalloc
+  void* scratch_dev = nullptr;
 
   void* dalloc(size_t bytes) {
     void* p = nullptr;
@@ -956,6 +985,7 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
     validate_desc(d);
     std::unique_ptr<fr_ctx_s> C(new fr_ctx_s);
     FRX_TRY(hipGetDevice(&C->dev));
+    C->scratch_dev = scratch_on_device(C->dev);
     ensure_tables(C->dev);
     MeshDev& M = C->M;
     const int E = d->n_elem;
@@ -1148,6 +1178,36 @@ fr_status fr_residual(fr_ctx c, const double* U, double* R, void* stream) {
   const size_t nb = sizeof(double) * c->ndof;
   if (!U || !R || overlap(U, nb, R, nb)) return fail(c, FR_E_INVALID, "fr_residual: bad arguments");
   return guarded(c, [&]() -> fr_status {
+    ResCall<double> rc;
+    rc.U = U;
+    rc.out = R;
+    FRX_TRY(launch_residual_f64(c->M, rc, S(stream)));
+    return FR_OK;
+  });
+}
+
+fr_status fr_residual_noalloc(fr_ctx c, const double* U, double* R, void* stream) {
+  if (!c) return FR_E_INVALID;
+  const size_t nb = sizeof(double) * c->ndof;
+  if (!U || !R || overlap(U, nb, R, nb)) return fail(c, FR_E_INVALID, "fr_residual_noalloc: bad arguments");
+  // the float64 stages keep 30 face-slot values per own face point (q, grad q,
+  // q_com - q, f_com . S)
+  const size_t need = 30 * sizeof(double) * (size_t)c->M.nfp;
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(c, FR_E_INVALID, "fr_residual_noalloc: the mesh needs " + std::to_string(need) +
+                                     " bytes of face-slot scratch, more than the " +
+                                     std::to_string(NOALLOC_SCRATCH_BYTES) + " it holds (use fr_residual)");
+  return guarded(c, [&]() -> fr_status {
+    int dev = -1;
+    FRX_TRY(hipGetDevice(&dev));
+    if (dev != c->dev) throw StatusErr{FR_E_INVALID, "fr_residual_noalloc: the context's device is not current"};
+    // the same kernels as fr_residual, with the face slots in the static scratch
+    struct Swap {
+      MeshDev& M;
+      void* saved;
+      ~Swap() { M.facebuf = saved; }
+    } swap{c->M, c->M.facebuf};
+    c->M.facebuf = c->scratch_dev;
     ResCall<double> rc;
     rc.U = U;
     rc.out = R;

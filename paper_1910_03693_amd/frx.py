@@ -27,7 +27,7 @@ FR_LAUNCH_FACES_TWO_PASS, FR_LAUNCH_FACES_ONE_PASS = 4, 8
 FR_ESDIRK2, FR_ESDIRK4 = 0, 1
 STATUS_NAMES = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_NOMEM", -3: "FR_E_HIP", -4: "FR_E_NOTCONVERGED",
                 -5: "FR_E_NONPHYSICAL", -6: "FR_E_UNSUPPORTED"}
-EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_reserve", "fr_residual", "fr_residual_jvp", "fr_jvp", "fr_vjp", "gmres_stage_solve",
+EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_reserve", "fr_residual", "fr_residual_noalloc", "fr_residual_jvp", "fr_jvp", "fr_vjp", "gmres_stage_solve",
             "esdirk_step", "spectral_decay_indicator", "fr_select_degrees", "fr_project", "fr_filter", "fr_autotune", "fr_profile",
             "fr_set_launch", "fr_check", "fr_last_error")
 
@@ -87,6 +87,7 @@ def lib():
         L.fr_layout.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.fr_reserve.argtypes = [vp, C.c_int32, C.c_int32]
         L.fr_residual.argtypes = [vp, vp, vp, vp]
+        L.fr_residual_noalloc.argtypes = [vp, vp, vp, vp]
         L.fr_jvp.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_double, vp]
         L.fr_vjp.argtypes = [vp, vp, vp, vp, vp]
         L.fr_residual_jvp.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -192,6 +193,12 @@ def fr_layout(h, n_elem):
 def fr_residual(h, U, R, stream=None):
     n = _ndof(h)
     return _check(lib().fr_residual(h, _dev(U, torch.float64, n), _dev(R, torch.float64, n), _stream(stream)), h)
+
+
+def fr_residual_noalloc(h, U, R, stream=None):
+    n = _ndof(h)
+    return _check(lib().fr_residual_noalloc(h, _dev(U, torch.float64, n), _dev(R, torch.float64, n),
+                                            _stream(stream)), h)
 
 
 def fr_jvp(h, U, v, Jv, precision=FR_F64, jv_mode=FR_JV_EXACT, fd_eps=1e-6, stream=None):
