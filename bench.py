@@ -28,7 +28,7 @@ The same run reports, on that workload:
     thread and at every host thread.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-       python bench.py --study {c3,c5,c3adapt}
+       python bench.py --study {c3,c5,c3adapt,g2}
 """
 from __future__ import annotations
 
@@ -184,19 +184,26 @@ def main():
     ap.add_argument("--no-implicit", action="store_true", help="skip the implicit-step comparisons")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-small", action="store_true", help="skip the 32x32x4 workload")
+    ap.add_argument("--no-ops", action="store_true", help="skip the table of single operators")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB five times (reference for the HBM byte counters)")
-    ap.add_argument("--study", choices=("c3", "c5", "c3adapt"), default=None,
+    ap.add_argument("--study", choices=("c3", "c5", "c3adapt", "g2"), default=None,
                     help="instead of the headline: implicit steps on the 64x64x8 vortex street (c3) or the "
-                         "128x128x8 box (c5), or the adaptive vortex-street loop (c3adapt)")
+                         "128x128x8 box (c5), the adaptive vortex-street loop (c3adapt), or the p / p_max "
+                         "refinement study of the isentropic vortex, uniform against adaptive degrees (g2)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the hot path is built and "
               "measured on a single MI355X, with no collectives).", file=sys.stderr)
         sys.exit(2)
     if args.study:
-        res = adaptive_study() if args.study == "c3adapt" else step_study(args.study)
+        if args.study == "c3adapt":
+            res = adaptive_study()
+        elif args.study == "g2":
+            res = g2_study()
+        else:
+            res = step_study(args.study)
         print(json.dumps(res), flush=True)
         return
 
@@ -215,7 +222,12 @@ def main():
     n_dof = ctx.n_dof
     E = int(case.mesh["n_elem"])
     print(f"[bench] workload 128x128x8 Re 60000, {E} elements, {n_dof} DOF", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
     ctx.autotune(U)
+    t_tune = time.perf_counter() - t0
+    shapes = {name: ctx.launch_shapes(k) for k, name in enumerate(("float64", "dual_float64", "dual_float32"))}
+    print(f"[bench] autotuned in {t_tune:.1f} s; fused shapes (stage, code, items per tile) of the float64 dual "
+          f"kernels: {shapes['dual_float64']}", file=sys.stderr, flush=True)
     ctx.set_launch(True)  # the batched design: one degree-bucketed launch per stage
     R, Jv = torch.empty_like(U), torch.empty_like(U)
 
@@ -249,7 +261,7 @@ def main():
     v32 = v.float()
     J32 = torch.empty_like(v32)
     per_op = {}
-    for mode in ("fused", "per_bucket"):
+    for mode in () if args.no_ops else ("fused", "per_bucket"):
         ctx.set_launch(mode == "fused")
         ops = {
             "residual_f64": (lambda: ctx.residual(U, out=R), W["residual"]),
@@ -295,7 +307,10 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roof,
         "operators": per_op,
-        "launch_shapes": "autotuned (fr_autotune) on this workload",
+        "launch_shapes": {"source": "fr_autotune on this workload", "seconds": round(t_tune, 2),
+                          "fused_items_per_tile": {k: [list(x) for x in v2] for k, v2 in shapes.items()},
+                          "legend": "(stage 0 trace / 1 interior faces / 2 divergence, code n or 8 n_low + n_high, "
+                                    "items per 256-thread tile)"},
     }
     if args.copy_calibration > 0:
         out["copy_calibration"] = copy_calibration(torch, args.copy_calibration)
@@ -566,6 +581,101 @@ def step_study(which):
         out[f"rel_diff_{name}_vs_f64_exact"] = (outs[name] - ref).norm().item() / ref.norm().item()
     out["speedup_mixed_vs_plain_scaled"] = round(out["plain_f64_fd_scaled"]["ms"] /
                                                  out["mixed_f32_exact_graph"]["ms"], 3)
+    return out
+
+
+def _vortex_l2_error(case, U, t, uinf, period):
+    """L2 errors (over the domain, Gauss weights times |J| of the cube
+    elements) of the solution against the exact translated vortex sampled at
+    the same solution points: all conserved variables, and density alone."""
+    from paper_1910_03693_amd import inputs as I
+
+    X = I.solution_points(case.mesh, case.elem_p)
+    Ue = I.vortex_field(X[0], X[1], X[2], 0.0, 0.0, t=t, ma=0.5, uinf=uinf, period=period)
+    h = np.asarray(case.mesh["lengths"]) / np.asarray(case.mesh["shape"])
+    jac = float(np.prod(h / 2.0))
+    w = np.empty(X.shape[1])
+    off = I.sp_offsets(case.elem_p)
+    for n in range(2, 7):
+        els = np.nonzero(case.elem_p.astype(np.int64) + 1 == n)[0]
+        if not len(els):
+            continue
+        g = np.polynomial.legendre.leggauss(n)[1]
+        wk = (g[None, None, :] * g[None, :, None] * g[:, None, None]).ravel()  # xi fastest
+        for e in els:
+            w[off[e]:off[e + 1]] = wk * jac
+    d = U - Ue
+    return float(np.sqrt(np.sum(d * d * w[None, :]))), float(np.sqrt(np.sum(d[0] * d[0] * w)))
+
+
+def g2_study(p_values=(1, 2, 3, 4, 5), steps=60):
+    """The p / p_max refinement study of the isentropic vortex (section 3.3):
+    2-D vortex (alpha 5, phi 1/2) in the free stream (rho, u, v, w) =
+    (1, 1, 1, 0), Mach 0.5, on a periodic [-10, 10]^2 x [0, 0.8] box of
+    50 x 50 x 2 cubes, 60 ESDIRK2 steps of dt = 0.05 (PTC from dtau 0.05 up to
+    10, to 1e-4; GMRES(30) to 1e-1), in the mixed form on one GPU.  For each
+    k: uniform p = k against the adaptive solver with p_min = 1, p_max = k
+    (started from uniform p_max, adapted after every step on the device:
+    indicator of rho u, nu_max 0.1, nu_min 0.001, one-degree face limiter, new
+    context, projected state).  Reports the L2 error against the exact
+    translated vortex at t = 3, the run time (every step and adaptation), and
+    the run-time reduction of the adaptive solver."""
+    import torch
+
+    from paper_1910_03693_amd import adapt, frx
+    from paper_1910_03693_amd import inputs as I
+
+    L, Lz, uinf, dt = 20.0, 0.8, (1.0, 1.0, 0.0), 0.05
+    mesh = I.box_mesh(50, 50, 2, (L, L, Lz), origin=(-L / 2, -L / 2, 0.0))
+    period = (L, L)
+    common = dict(dtau_init=0.05, dtau_max=10.0, tol_pseudo=1e-4, max_ptc_iter=100)
+    g = dict(restart=30, max_iter=100, tol=1e-1, precision=frx.FR_F32, use_graph=True)
+    reserve = dict(max_restart=30, graphs=frx.FR_GRAPHS_F32_EXACT)
+
+    def make(ep):
+        U = I.sample(mesh, ep, lambda x, y, z: I.vortex_field(x, y, z, 0.0, 0.0, ma=0.5, uinf=uinf, period=period))
+        return I.Case("vortex", mesh, np.asarray(ep, np.int8), U, 0, 0, I.GAMMA, 0.0, 0.72, np.zeros(5), {})
+
+    def run(k, adaptive):
+        case = make(np.full(mesh["n_elem"], k, np.int8))
+        ctx = frx.Context.from_case(case, **reserve)
+        ctx.set_launch(True)
+        U = torch.tensor(case.U, device="cuda")
+        gm = ptc = 0
+        dof_steps = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st = ctx.esdirk_step(U, dt, gmres=g, **common)
+            if st["status"] != frx.FR_OK:
+                raise RuntimeError(f"step failed: {st}")
+            gm += st["gmres_iterations"]
+            ptc += st["ptc_iterations"]
+            dof_steps.append(ctx.n_dof)
+            if adaptive:
+                case, ctx2, U = adapt.adapt_step(case, ctx, U, p_min=1, p_max=k, reserve=reserve)
+                ctx2.set_launch(True)
+                ctx.close()
+                ctx = ctx2
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        err, err_rho = _vortex_l2_error(case, U.cpu().numpy(), steps * dt, uinf, period)
+        ctx.close()
+        rec = {"run_ms": round(ms, 1), "l2_error": err, "l2_error_rho": err_rho, "gmres_iterations": gm,
+               "ptc_iterations": ptc, "mean_dof": int(np.mean(dof_steps)),
+               "final_degree_histogram_p1_to_p5": np.bincount(case.elem_p, minlength=6)[1:].tolist()}
+        print(f"[bench] g2 {'adaptive p_max' if adaptive else 'uniform p'} = {k}: {rec}", file=sys.stderr,
+              flush=True)
+        return rec
+
+    out = {"study": "g2", "mesh": "50x50x2 periodic cubes on [-10,10]^2 x [0,0.8]", "dt": dt, "steps": steps,
+           "settings": {**common, **g}, "uniform": {}, "adaptive": {}}
+    run(2, False)  # warm-up: kernels and graph paths loaded once
+    for k in p_values:
+        out["uniform"][k] = run(k, False)
+        out["adaptive"][k] = run(k, True) if k > 1 else dict(out["uniform"][k])
+        out["adaptive"][k]["run_time_reduction"] = round(1.0 - out["adaptive"][k]["run_ms"] /
+                                                         out["uniform"][k]["run_ms"], 4)
     return out
 
 

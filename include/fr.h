@@ -270,9 +270,21 @@ fr_status fr_project(fr_ctx src, const double* U_src, fr_ctx dst, double* U_dst,
  * example after each time step). */
 fr_status fr_filter(fr_ctx ctx, const double* U, double* U_out, double alpha, int32_t p_from, void* stream);
 
-/* Picks, per degree bucket and scalar kind, the launch shapes of the residual
- * kernels by timing the candidates on U (device float64). */
+/* Picks, per scalar kind, the launch shapes of the residual kernels by timing
+ * the candidates on U (device float64): elements (faces) per block of every
+ * degree bucket in the per-bucket mode; items per tile of every stage and
+ * degree (degree pair) in the fused plans; the one- or two-pass face stage.
+ * It synchronises the stream and captures the reserved Arnoldi graphs again
+ * with the chosen shapes. */
 fr_status fr_autotune(fr_ctx ctx, const double* U, void* stream);
+
+/* Items per tile of the fused (degree-bucketed) plans of one scalar kind
+ * (0: float64, 1: float64 dual numbers, 2: float32 dual numbers), as chosen by
+ * fr_autotune or the default: out[3 i .. 3 i + 2] = (stage: 0 traces, 1
+ * interior faces, 2 divergence; code: n = p + 1 of an element bucket, or
+ * 8 n_low + n_high of a face bucket; items per 256-thread tile), host memory,
+ * for up to max_out entries; *n_out = entries written. */
+fr_status fr_launch_shapes(fr_ctx ctx, int32_t kind, int32_t* out, int32_t max_out, int32_t* n_out);
 
 /* Per-launch timing of one operator's kernels (op 0: residual float64,
  * 1: exact tangent float64, 2: exact tangent float32, 3: residual and

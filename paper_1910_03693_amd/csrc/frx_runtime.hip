@@ -299,6 +299,12 @@ struct fr_ctx_s {
   std::map<GraphKey, hipGraphExec_t> graphs;
   int graph_sets = 0;  // FR_GRAPHS_* bits instantiated by fr_reserve
   std::map<std::pair<int, int>, int> cycle_iters;  // (mode, precision) -> iterations of the last cycle
+  // fused plans: element ranges per degree, face ranges per code, chosen items
+  // per tile per (scalar kind, stage, code) (absent: the default), table sizes
+  std::map<int, std::pair<int, int>> erange;
+  std::vector<std::tuple<int, int, int, int>> frange;
+  std::map<int, int> shape[SK_COUNT][3];
+  int plan_cap[3] = {0, 0, 0};
   // ESDIRK workspace
   double* es = nullptr;   // 8 x ndof
   // VJP workspace
@@ -778,15 +784,99 @@ fr_status gmres_solve(fr_ctx c, const double* U, double shift, const double* F, 
 }
 
 // Tile tables of the fused launches: every degree bucket cut into blocks of
-// 256 threads (elements or faces per block limited by the thread count and an
-// LDS cap), all tiles of a stage sorted by decreasing work.
+// 256 threads, all tiles of a stage sorted by decreasing work.  The items per
+// tile (elements of one degree, or faces of one degree pair) are a shape of
+// (scalar kind, stage, bucket code) that fr_autotune may change; the default
+// fills the 256 threads within the stage's LDS cap.
+
+// LDS bytes per item of a stage for the bucket code (n for elements, 8 nl + nh
+// for interior faces)
+size_t item_lds(bool ns, size_t sb, int st, int code) {
+  if (st != 1) {
+    const int n = code, n3 = n * n * n;
+    const int tv = (ns && 20 * n3 * sb > 65536) ? 5 : (ns ? 20 : 5);
+    return st == 0 ? (size_t)tv * n3 * sb : (size_t)(5 * n3 + 30 * n * n) * sb;
+  }
+  const int nl = code / 8, nh = code % 8;
+  return nl < nh ? (size_t)((ns ? 20 : 5) * nl * nl + 10 * nh * nh) * sb : 0;
+}
+// threads of one item: n^3 (elements) or nh^2 (faces)
+int item_threads(int st, int code) { return st != 1 ? code * code * code : (code % 8) * (code % 8); }
+// LDS cap per tile of a stage: the share of the blocks per CU it is built for
+size_t stage_lds_cap(int sk, int st) { return std::min<size_t>(64 * 1024, 160 * 1024 / FRX_STAGE_WAVES[sk][st]); }
+// the largest items per tile that fit 256 threads and the LDS cap
+int max_items(bool ns, int sk, int st, int code) {
+  const size_t per = item_lds(ns, scalar_bytes(sk), st, code);
+  int k = std::max(1, FRX_MAX_THREADS / item_threads(st, code));
+  while (k > 1 && per * k > stage_lds_cap(sk, st)) --k;
+  return k;
+}
+
+// (Re)builds the tile table of one stage of one scalar kind from the chosen
+// items per tile (c->shape), into the table allocated for the worst case.
+void plan_stage(fr_ctx c, int sk, int st) {
+  MeshDev& M = c->M;
+  const bool ns = M.physics == FR_NAVIER_STOKES;
+  FusedPlan& P = M.plan[sk];
+  std::vector<std::pair<double, int4>> tiles;
+  size_t lds = 0;
+  auto items = [&](int code) {
+    auto it = c->shape[sk][st].find(code);
+    return it != c->shape[sk][st].end() ? it->second : max_items(ns, sk, st, code);
+  };
+  if (st != 1) {
+    for (auto& kv : c->erange) {
+      const int n = kv.first, first = kv.second.first, count = kv.second.second;
+      const int epb = items(n);
+      lds = std::max(lds, epb * item_lds(ns, scalar_bytes(sk), st, n));
+      for (int i = 0; i < count; i += epb) {
+        const int cnt = std::min(epb, count - i);
+        tiles.push_back({(double)cnt * n * n * n * n, make_int4(n, first + i, cnt, epb)});
+      }
+    }
+  } else {
+    for (auto& fr : c->frange) {
+      const int code = std::get<0>(fr), first = std::get<1>(fr), count = std::get<2>(fr);
+      if (code >= 64) {
+        const int n = code - 64, per = std::max(1, 256 / (n * n));
+        for (int i = 0; i < count; i += per)
+          tiles.push_back({(double)std::min(per, count - i) * n * n * 2.0,
+                           make_int4(code, first + i, std::min(per, count - i), per)});
+      } else {
+        const int nl = code / 8, nh = code % 8;
+        const int fpb = items(code);
+        lds = std::max(lds, fpb * item_lds(ns, scalar_bytes(sk), st, code));
+        for (int i = 0; i < count; i += fpb)
+          tiles.push_back({(double)std::min(fpb, count - i) * nh * nh * (nl < nh ? 1.5 : 1.0),
+                           make_int4(code, first + i, std::min(fpb, count - i), fpb)});
+      }
+    }
+  }
+  // by decreasing work; in the face stage interior-face tiles (code < 64)
+  // before boundary-face tiles, so that the two-pass face stage can launch
+  // each group on its own
+  std::stable_sort(tiles.begin(), tiles.end(), [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) {
+    const bool bx = x.second.x >= 64, by = y.second.x >= 64;
+    if (bx != by) return !bx;
+    return x.first > y.first;
+  });
+  std::vector<int4> t;
+  for (auto& x : tiles) t.push_back(x.second);
+  if ((int)t.size() > c->plan_cap[st]) throw StatusErr{FR_E_INVALID, "tile table larger than its allocation"};
+  int nint = 0;
+  for (auto& x : t) nint += x.x < 64 ? 1 : 0;
+  if (st == 1) P.n_interior = nint;
+  P.count[st] = (int)t.size();
+  P.lds[st] = lds;
+  if (!t.empty()) FRX_TRY(hipMemcpy(P.tiles[st], t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice));
+}
+
 void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair<int, int>, std::vector<int4>>& fmap,
                        const std::map<int, std::vector<int4>>& bmap) {
   MeshDev& M = c->M;
   const int E = d->n_elem;
   std::vector<int> all;
-  std::vector<std::pair<int, int>> eb_range;  // n -> (first, count)
-  std::map<int, std::pair<int, int>> erange;
+  std::map<int, std::pair<int, int>>& erange = c->erange;  // n -> (first, count)
   for (int n = NMAX; n >= 2; --n) {
     const int first = (int)all.size();
     for (int e = 0; e < E; ++e)
@@ -794,7 +884,7 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
     if ((int)all.size() > first) erange[n] = {first, (int)all.size() - first};
   }
   std::vector<int4> faces;
-  std::vector<std::tuple<int, int, int, int>> frange;  // (code, first, count, nl)
+  std::vector<std::tuple<int, int, int, int>>& frange = c->frange;  // (code, first, count, nl)
   for (auto it = fmap.rbegin(); it != fmap.rend(); ++it) {
     frange.emplace_back(8 * it->first.first + it->first.second, (int)faces.size(), (int)it->second.size(), it->first.first);
     faces.insert(faces.end(), it->second.begin(), it->second.end());
@@ -813,66 +903,15 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
   if (!faces.empty())
     FRX_TRY(hipMemcpy(M.all_faces, faces.data(), sizeof(int4) * faces.size(), hipMemcpyHostToDevice));
   const bool ns = d->physics == FR_NAVIER_STOKES;
-  const size_t cap = 64 * 1024;
-  for (int sk = 0; sk < SK_COUNT; ++sk) {
-    const size_t sb = scalar_bytes(sk);
-    FusedPlan& P = M.plan[sk];
+  // tile tables sized for one item per tile, so that any shape fits
+  c->plan_cap[0] = c->plan_cap[2] = std::max(1, E);
+  c->plan_cap[1] = std::max<int>(1, (int)faces.size());
+  for (int sk = 0; sk < SK_COUNT; ++sk)
     for (int st = 0; st < 3; ++st) {
-      std::vector<std::pair<double, int4>> tiles;
-      size_t lds = 0;
-      // LDS per tile within the share of the blocks per CU the stage is built for
-      const size_t cap_st = std::min<size_t>(cap, 160 * 1024 / FRX_STAGE_WAVES[sk][st]);
-      if (st != 1) {
-        for (auto& kv : erange) {
-          const int n = kv.first, n3 = n * n * n;
-          const int tv = (ns && 20 * n3 * sb > 65536) ? 5 : (ns ? 20 : 5);
-          const size_t per_el = st == 0 ? (size_t)tv * n3 * sb : (size_t)(5 * n3 + 30 * n * n) * sb;
-          int epb = std::max(1, 256 / n3);
-          while (epb > 1 && epb * per_el > cap_st) --epb;
-          lds = std::max(lds, epb * per_el);
-          for (int i = 0; i < kv.second.second; i += epb) {
-            const int cnt = std::min(epb, kv.second.second - i);
-            tiles.push_back({(double)cnt * n3 * n, make_int4(n, kv.second.first + i, cnt, epb)});
-          }
-        }
-      } else {
-        for (auto& fr : frange) {
-          const int code = std::get<0>(fr), first = std::get<1>(fr), count = std::get<2>(fr);
-          if (code >= 64) {
-            const int n = code - 64, per = std::max(1, 256 / (n * n));
-            for (int i = 0; i < count; i += per)
-              tiles.push_back({(double)std::min(per, count - i) * n * n * 2.0, make_int4(code, first + i, std::min(per, count - i), per)});
-          } else {
-            const int nl = code / 8, nh = code % 8;
-            const size_t per_face = nl < nh ? (size_t)((ns ? 20 : 5) * nl * nl + 10 * nh * nh) * sb : 0;
-            int fpb = std::max(1, 256 / (nh * nh));
-            while (fpb > 1 && fpb * per_face > cap_st) --fpb;
-            lds = std::max(lds, fpb * per_face);
-            for (int i = 0; i < count; i += fpb)
-              tiles.push_back({(double)std::min(fpb, count - i) * nh * nh * (nl < nh ? 1.5 : 1.0),
-                               make_int4(code, first + i, std::min(fpb, count - i), fpb)});
-          }
-        }
-      }
-      // by decreasing work; in the face stage interior-face tiles (code < 64)
-      // before boundary-face tiles, so that the two-pass face stage can launch
-      // each group on its own
-      std::stable_sort(tiles.begin(), tiles.end(), [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) {
-        const bool bx = x.second.x >= 64, by = y.second.x >= 64;
-        if (bx != by) return !bx;
-        return x.first > y.first;
-      });
-      int nint = 0;
-      for (auto& x : tiles) nint += x.second.x < 64 ? 1 : 0;
-      if (st == 1) P.n_interior = nint;
-      std::vector<int4> t;
-      for (auto& x : tiles) t.push_back(x.second);
-      P.count[st] = (int)t.size();
-      P.lds[st] = lds;
-      P.tiles[st] = (int4*)c->dalloc(sizeof(int4) * std::max<size_t>(1, t.size()));
-      if (!t.empty()) FRX_TRY(hipMemcpy(P.tiles[st], t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice));
+      M.plan[sk].tiles[st] = (int4*)c->dalloc(sizeof(int4) * c->plan_cap[st]);
+      plan_stage(c, sk, st);
     }
-  }
+  const size_t cap = 64 * 1024;
   // adjoint (float64): LDS per element 5 n^3 (trace_rev) and 5 n^3 + 30 n^2
   // (div_rev); per mixed face (NV + 10) nl^2 + NV nh^2
   FusedPlan& V = M.vplan;
@@ -1651,6 +1690,44 @@ fr_status fr_autotune(fr_ctx c, const double* U, void* stream) {
         f.fpb[sk] = best;
       }
     }
+    // Fused plans: for every scalar kind, stage and bucket code (degree, or
+    // degree pair of interior faces), the items per tile among the largest
+    // that fits (256 threads, the stage's LDS cap), its half and its quarter
+    // that times fastest in the fused launch, one code at a time with the
+    // others at their current choice
+    {
+      const bool fused0 = c->M.fused;
+      c->M.fused = true;
+      const bool ns = c->M.physics == 1;
+      for (int sk = 0; sk < SK_COUNT; ++sk)
+        for (int st = 0; st < 3; ++st) {
+          std::vector<int> codes;
+          if (st != 1)
+            for (auto& kv : c->erange) codes.push_back(kv.first);
+          else
+            for (auto& fr : c->frange)
+              if (std::get<0>(fr) < 64) codes.push_back(std::get<0>(fr));
+          for (int code : codes) {
+            const int mx = max_items(ns, sk, st, code);
+            auto it = c->shape[sk][st].find(code);
+            int best = it != c->shape[sk][st].end() ? it->second : mx;
+            float tbest = timed(sk);
+            for (int k : {mx, mx / 2, mx / 4}) {
+              if (k < 1 || k == best) continue;
+              c->shape[sk][st][code] = k;
+              plan_stage(c, sk, st);
+              const float t = timed(sk);
+              if (t < tbest) {
+                tbest = t;
+                best = k;
+              }
+            }
+            c->shape[sk][st][code] = best;
+            plan_stage(c, sk, st);
+          }
+        }
+      c->M.fused = fused0;
+    }
     // Navier-Stokes face stage in one or two passes, per launch mode and
     // scalar kind: the faster of the two
     if (c->M.physics == 1) {
@@ -1738,6 +1815,32 @@ fr_status fr_profile(fr_ctx c, const double* U, int32_t op, int32_t reps, fr_ker
     *n_out = k;
     return FR_OK;
   });
+}
+
+fr_status fr_launch_shapes(fr_ctx c, int32_t kind, int32_t* out, int32_t max_out, int32_t* n_out) {
+  if (!c || !n_out || max_out < 0 || (max_out > 0 && !out) || kind < 0 || kind >= SK_COUNT)
+    return c ? fail(c, FR_E_INVALID, "fr_launch_shapes: bad arguments") : FR_E_INVALID;
+  const bool ns = c->M.physics == 1;
+  int k = 0;
+  for (int st = 0; st < 3; ++st) {
+    std::vector<int> codes;
+    if (st != 1)
+      for (auto& kv : c->erange) codes.push_back(kv.first);
+    else
+      for (auto& fr : c->frange)
+        if (std::get<0>(fr) < 64) codes.push_back(std::get<0>(fr));
+    for (int code : codes) {
+      if (k < max_out) {
+        auto it = c->shape[kind][st].find(code);
+        out[3 * k] = st;
+        out[3 * k + 1] = code;
+        out[3 * k + 2] = it != c->shape[kind][st].end() ? it->second : max_items(ns, kind, st, code);
+      }
+      ++k;
+    }
+  }
+  *n_out = std::min(k, max_out);
+  return FR_OK;
 }
 
 const char* fr_last_error(fr_ctx c) { return c ? c->err.c_str() : g_create_error.c_str(); }

@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_NOMEM", -3: "FR_E_HIP"
                 -5: "FR_E_NONPHYSICAL", -6: "FR_E_UNSUPPORTED"}
 EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_reserve", "fr_residual", "fr_residual_noalloc", "fr_residual_jvp", "fr_jvp", "fr_vjp", "gmres_stage_solve",
             "esdirk_step", "spectral_decay_indicator", "fr_select_degrees", "fr_project", "fr_filter", "fr_autotune", "fr_profile",
-            "fr_set_launch", "fr_check", "fr_last_error")
+            "fr_set_launch", "fr_check", "fr_launch_shapes", "fr_last_error")
 
 
 class FrError(RuntimeError):
@@ -103,6 +103,7 @@ def lib():
         L.fr_set_launch.argtypes = [vp, C.c_int32]
         L.fr_profile.argtypes = [vp, vp, C.c_int32, C.c_int32, C.POINTER(fr_kernel_time), C.c_int32,
                                  C.POINTER(C.c_int32), vp]
+        L.fr_launch_shapes.argtypes = [vp, C.c_int32, vp, C.c_int32, C.POINTER(C.c_int32)]
         L.fr_last_error.restype = C.c_char_p
         L.fr_last_error.argtypes = [vp]
         for name in EXPORTED:
@@ -299,6 +300,15 @@ def fr_profile(h, U, op=0, reps=10, stream=None):
                  ms=buf[i].ms) for i in range(n.value)]
 
 
+def fr_launch_shapes(h, kind):
+    """[(stage, code, items per tile)] of the fused plans of scalar kind
+    0 (float64), 1 (float64 dual) or 2 (float32 dual)."""
+    buf = np.zeros(3 * 256, dtype=np.int32)
+    n = C.c_int32(0)
+    _check(lib().fr_launch_shapes(h, int(kind), C.c_void_p(buf.ctypes.data), 256, C.byref(n)), h)
+    return [tuple(int(x) for x in buf[3 * i:3 * i + 3]) for i in range(n.value)]
+
+
 def fr_set_launch(h, mode):
     return _check(lib().fr_set_launch(h, mode), h)
 
@@ -415,6 +425,9 @@ class Context:
         if two_pass_faces is not None:
             mode |= FR_LAUNCH_FACES_TWO_PASS if two_pass_faces else FR_LAUNCH_FACES_ONE_PASS
         fr_set_launch(self.h, mode)
+
+    def launch_shapes(self, kind=1):
+        return fr_launch_shapes(self.h, kind)
 
     def profile(self, U, op=0, reps=10):
         return fr_profile(self.h, U, op, reps)
