@@ -148,7 +148,7 @@ def measured_traffic(name):
 
 # sources that define the residual and tangent kernels: a counter summary is
 # used only while they hash to the value recorded in it
-KERNEL_SOURCES = ("frx_device.hpp", "frx_residual.hpp", "frx_launch.hpp", "frx_host.hpp", "frx_k_dual64.hip")
+KERNEL_SOURCES = ("frx_device.hpp", "frx_residual.hpp", "frx_launch.hpp", "frx_k_dual64.hip")
 TRAFFIC_PROFILE = "residual_jvp_dual64_ns_128x128x8_hbm_traffic.md"
 
 
@@ -501,7 +501,8 @@ def adaptive_study(steps=4):
     """The paper's loop on the 64x64x8 vortex street: starting from the
     indicator's degree field, each time step is one implicit ESDIRK2 step
     (mixed form) followed by one p-adaptation on the device (indicator,
-    criteria, face limiter, new degree buckets, projected state)."""
+    criteria with the maximum indicator of the same degree, face limiter, new
+    degree buckets, projected state)."""
     import torch
 
     from paper_1910_03693_amd import adapt, frx
@@ -509,8 +510,7 @@ def adaptive_study(steps=4):
 
     p, _ = adapt.indicator_degree_field(lambda ep: I.case_street(elem_p=ep))
     case = I.case_street(elem_p=p)
-    ctx = frx.Context.from_case(case, max_restart=30, graphs=frx.FR_GRAPHS_F32_EXACT)
-    ctx.set_launch(True)
+    ctx = frx.Context.from_case(case, max_restart=30, graphs=frx.FR_GRAPHS_F32_EXACT, fused=True)
     U = torch.tensor(case.U, device="cuda")
     dt = 0.05
     common = dict(dtau_init=0.005, dtau_max=0.05, tol_pseudo=1e-4, max_ptc_iter=50)
@@ -522,8 +522,8 @@ def adaptive_study(steps=4):
         st = ctx.esdirk_step(U, dt, gmres=g, **common)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        case, ctx2, U = adapt.adapt_step(case, ctx, U, reserve=dict(max_restart=30, graphs=frx.FR_GRAPHS_F32_EXACT))
-        ctx2.set_launch(True)
+        case, ctx2, U = adapt.adapt_step(case, ctx, U, reserve=dict(max_restart=30, graphs=frx.FR_GRAPHS_F32_EXACT),
+                                         fused=True, eta_max_scope=frx.FR_ETA_MAX_SAME_DEGREE)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         ctx.close()
@@ -612,14 +612,16 @@ def g2_study(p_values=(1, 2, 3, 4, 5), steps=60):
     """The p / p_max refinement study of the isentropic vortex (section 3.3):
     2-D vortex (alpha 5, phi 1/2) in the free stream (rho, u, v, w) =
     (1, 1, 1, 0), Mach 0.5, on a periodic [-10, 10]^2 x [0, 0.8] box of
-    50 x 50 x 2 cubes, 60 ESDIRK2 steps of dt = 0.05 (PTC from dtau 0.05 up to
-    10, to 1e-4; GMRES(30) to 1e-1), in the mixed form on one GPU.  For each
-    k: uniform p = k against the adaptive solver with p_min = 1, p_max = k
-    (started from uniform p_max, adapted after every step on the device:
-    indicator of rho u, nu_max 0.1, nu_min 0.001, one-degree face limiter, new
-    context, projected state).  Reports the L2 error against the exact
-    translated vortex at t = 3, the run time (every step and adaptation), and
-    the run-time reduction of the adaptive solver."""
+    50 x 50 x 2 cubes, 60 steps of dt = 0.05 (PTC from dtau 0.05 up to 10, to
+    1e-4; GMRES(30) to 1e-1), in the mixed form on one GPU, with ESDIRK2 and
+    with ESDIRK4.  For each k: uniform p = k against the adaptive solver with
+    p_min = 1, p_max = k (started from uniform p_max, adapted after every step
+    on the device: indicator of rho u, nu_max 0.1, nu_min 0.001, one-degree
+    face limiter, new context, projected state), with the criteria's maximum
+    indicator read over all elements and over the elements of the same
+    degree.  Reports the L2 error against the exact translated vortex at
+    t = 3, the run time (every step and adaptation) and the run-time
+    reduction of the adaptive solver."""
     import torch
 
     from paper_1910_03693_amd import adapt, frx
@@ -636,46 +638,55 @@ def g2_study(p_values=(1, 2, 3, 4, 5), steps=60):
         U = I.sample(mesh, ep, lambda x, y, z: I.vortex_field(x, y, z, 0.0, 0.0, ma=0.5, uinf=uinf, period=period))
         return I.Case("vortex", mesh, np.asarray(ep, np.int8), U, 0, 0, I.GAMMA, 0.0, 0.72, np.zeros(5), {})
 
-    def run(k, adaptive):
+    def run(k, scheme, scope):
         case = make(np.full(mesh["n_elem"], k, np.int8))
-        ctx = frx.Context.from_case(case, **reserve)
-        ctx.set_launch(True)
+        ctx = frx.Context.from_case(case, fused=True, **reserve)
         U = torch.tensor(case.U, device="cuda")
         gm = ptc = 0
         dof_steps = []
+        t_adapt = 0.0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            st = ctx.esdirk_step(U, dt, gmres=g, **common)
+            st = ctx.esdirk_step(U, dt, gmres=g, scheme=scheme, **common)
             if st["status"] != frx.FR_OK:
                 raise RuntimeError(f"step failed: {st}")
             gm += st["gmres_iterations"]
             ptc += st["ptc_iterations"]
             dof_steps.append(ctx.n_dof)
-            if adaptive:
-                case, ctx2, U = adapt.adapt_step(case, ctx, U, p_min=1, p_max=k, reserve=reserve)
-                ctx2.set_launch(True)
+            if scope is not None:
+                ta = time.perf_counter()
+                case, ctx2, U = adapt.adapt_step(case, ctx, U, p_min=1, p_max=k, reserve=reserve, fused=True,
+                                                 eta_max_scope=scope)
                 ctx.close()
                 ctx = ctx2
+                t_adapt += time.perf_counter() - ta
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
         err, err_rho = _vortex_l2_error(case, U.cpu().numpy(), steps * dt, uinf, period)
         ctx.close()
-        rec = {"run_ms": round(ms, 1), "l2_error": err, "l2_error_rho": err_rho, "gmres_iterations": gm,
-               "ptc_iterations": ptc, "mean_dof": int(np.mean(dof_steps)),
+        rec = {"run_ms": round(ms, 1), "adapt_ms": round(t_adapt * 1e3, 1), "l2_error": err, "l2_error_rho": err_rho,
+               "gmres_iterations": gm, "ptc_iterations": ptc, "mean_dof": int(np.mean(dof_steps)),
                "final_degree_histogram_p1_to_p5": np.bincount(case.elem_p, minlength=6)[1:].tolist()}
-        print(f"[bench] g2 {'adaptive p_max' if adaptive else 'uniform p'} = {k}: {rec}", file=sys.stderr,
-              flush=True)
+        print(f"[bench] g2 scheme {scheme} {'uniform p' if scope is None else 'adaptive (scope %d) p_max' % scope}"
+              f" = {k}: {rec}", file=sys.stderr, flush=True)
         return rec
 
     out = {"study": "g2", "mesh": "50x50x2 periodic cubes on [-10,10]^2 x [0,0.8]", "dt": dt, "steps": steps,
-           "settings": {**common, **g}, "uniform": {}, "adaptive": {}}
-    run(2, False)  # warm-up: kernels and graph paths loaded once
-    for k in p_values:
-        out["uniform"][k] = run(k, False)
-        out["adaptive"][k] = run(k, True) if k > 1 else dict(out["uniform"][k])
-        out["adaptive"][k]["run_time_reduction"] = round(1.0 - out["adaptive"][k]["run_ms"] /
-                                                         out["uniform"][k]["run_ms"], 4)
+           "settings": {**common, **g}, "free_stream": "(rho, u, v, w) = (1, 1, 1, 0), Mach 0.5", "runs": {}}
+    run(2, frx.FR_ESDIRK2, None)  # warm-up: kernels and graph paths loaded once
+    for scheme, sname in ((frx.FR_ESDIRK2, "esdirk2"), (frx.FR_ESDIRK4, "esdirk4")):
+        res = {"uniform": {}, "adaptive_eta_max_all": {}, "adaptive_eta_max_same_degree": {}}
+        for k in p_values:
+            res["uniform"][k] = run(k, scheme, None)
+            for key, scope in (("adaptive_eta_max_all", frx.FR_ETA_MAX_ALL),
+                               ("adaptive_eta_max_same_degree", frx.FR_ETA_MAX_SAME_DEGREE)):
+                r = run(k, scheme, scope) if k > 1 else dict(res["uniform"][k])
+                r["run_time_reduction"] = round(1.0 - r["run_ms"] / res["uniform"][k]["run_ms"], 4)
+                # without the adaptations themselves (new context, graphs, projection)
+                r["solver_time_reduction"] = round(1.0 - (r["run_ms"] - r["adapt_ms"]) / res["uniform"][k]["run_ms"], 4)
+                res[key][k] = r
+        out["runs"][sname] = res
     return out
 
 

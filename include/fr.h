@@ -237,12 +237,17 @@ fr_status spectral_decay_indicator(fr_ctx ctx, const double* U, int32_t var, dou
  * p - 1 where eta < nu_min * eta_max (the paper: nu_max = 0.1,
  * nu_min = 0.001; decisions in float64), clamped to [p_min, p_max]; then
  * the lower side of every face whose degrees differ by more than one is
- * raised until no face does.  p_new: device int8 [n_elem], written in mesh
- * order.  FR_E_INVALID for 1 <= p_min <= p_max <= 5 violated, var outside
- * 0..4 or nu_max < nu_min.  To adapt, create a context for p_new and move the
- * state with fr_project. */
+ * raised until no face does.  The paper's eta_{k,max} is not defined beyond
+ * its name; eta_max_scope selects the reading: FR_ETA_MAX_ALL, the maximum
+ * over all elements, or FR_ETA_MAX_SAME_DEGREE, the maximum over the
+ * elements of the same degree as the element (so that elements are ranked
+ * among those whose indicator measures the same modes).  p_new: device int8
+ * [n_elem], written in mesh order.  FR_E_INVALID for 1 <= p_min <= p_max <= 5
+ * violated, var outside 0..4, nu_max < nu_min or an unknown scope.  To
+ * adapt, create a context for p_new and move the state with fr_project. */
+enum { FR_ETA_MAX_ALL = 0, FR_ETA_MAX_SAME_DEGREE = 1 };
 fr_status fr_select_degrees(fr_ctx ctx, const double* U, int32_t var, double nu_max, double nu_min, int32_t p_min,
-                            int32_t p_max, int8_t* p_new, void* stream);
+                            int32_t p_max, int32_t eta_max_scope, int8_t* p_new, void* stream);
 
 /* Moves a state between two contexts of the same mesh with different degree
  * fields (section 3.1: a lower degree takes the projection of the solution

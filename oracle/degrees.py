@@ -7,6 +7,9 @@ product path selects degrees on the device (fr_select_degrees).
   an element whose indicator exceeds nu_max times the largest indicator gets
   one degree more, one whose indicator is below nu_min times it one degree
   less; the result stays in [p_min, p_max].  Both inequalities are strict.
+  "The largest indicator" (the paper's eta_{k,max}) is read two ways:
+  scope "all", over every element, or scope "degree", over the elements of
+  the same degree as the element.
 * Limiter (section 3.1, neighbours differ by at most one degree): where a
   face joins degrees that differ by more than one, the lower side is raised
   (refinement wins) until no face does.  Boundary faces (negative neighbour
@@ -17,7 +20,24 @@ from __future__ import annotations
 import numpy as np
 
 
+def eta_maxima(p, eta, scope="all"):
+    """The reference maximum of every element: the largest eta of all
+    elements, or of the elements of the same degree."""
+    p = np.asarray(p, dtype=np.int64)
+    eta = np.asarray(eta, dtype=np.float64)
+    if scope == "all":
+        return np.full(len(p), eta.max() if len(eta) else 0.0)
+    if scope != "degree":
+        raise ValueError(scope)
+    out = np.zeros(len(p))
+    for k in np.unique(p):
+        sel = p == k
+        out[sel] = eta[sel].max()
+    return out
+
+
 def apply_criteria(p, eta, eta_max, nu_max=0.1, nu_min=0.001, p_min=1, p_max=5):
+    """eta_max: a number, or one reference maximum per element."""
     p = np.asarray(p, dtype=np.int64)
     eta = np.asarray(eta, dtype=np.float64)
     up = eta > nu_max * eta_max
@@ -42,12 +62,15 @@ def limit_jumps(p, elem_nbr, max_jump=1):
     return p
 
 
-def select_degrees(p, eta, eta_max, elem_nbr, nu_max=0.1, nu_min=0.001, p_min=1, p_max=5):
-    """Criteria, then the limiter: the degree field one adaptation chooses."""
-    return limit_jumps(apply_criteria(p, eta, eta_max, nu_max, nu_min, p_min, p_max), elem_nbr)
+def select_degrees(p, eta, eta_max, elem_nbr, nu_max=0.1, nu_min=0.001, p_min=1, p_max=5, scope="all"):
+    """Criteria, then the limiter: the degree field one adaptation chooses.
+    With scope "all" eta_max is the global maximum (as returned with eta); with
+    scope "degree" it is ignored and the per-degree maxima are used."""
+    ref = eta_max if scope == "all" else eta_maxima(p, eta, "degree")
+    return limit_jumps(apply_criteria(p, eta, ref, nu_max, nu_min, p_min, p_max), elem_nbr)
 
 
-def indicator_degree_field(make_case, indicator, p_max=5, p_min=1, nu_max=0.1, nu_min=0.001, sweeps=4):
+def indicator_degree_field(make_case, indicator, p_max=5, p_min=1, nu_max=0.1, nu_min=0.001, sweeps=4, scope="all"):
     """The degree field of an analytic workload: every element starts at p_max
     (the paper starts its adaptive runs at the highest degree); each sweep
     samples the field at the current degrees (``make_case(p)``), evaluates
@@ -59,7 +82,7 @@ def indicator_degree_field(make_case, indicator, p_max=5, p_min=1, nu_max=0.1, n
     for _ in range(sweeps):
         case = make_case(p.astype(np.int8))
         eta, mx = indicator(case)
-        pn = select_degrees(p, eta, mx, case.mesh["elem_nbr"], nu_max, nu_min, p_min, p_max)
+        pn = select_degrees(p, eta, mx, case.mesh["elem_nbr"], nu_max, nu_min, p_min, p_max, scope)
         hist.append(np.bincount(pn, minlength=p_max + 1)[1:].tolist())
         if np.array_equal(pn, p):
             break

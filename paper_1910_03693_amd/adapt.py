@@ -16,7 +16,7 @@ from __future__ import annotations
 import numpy as np
 
 
-def indicator_degree_field(make_case, p_max=5, p_min=1, nu_max=0.1, nu_min=0.001, sweeps=4, var=1):
+def indicator_degree_field(make_case, p_max=5, p_min=1, nu_max=0.1, nu_min=0.001, sweeps=4, var=1, eta_max_scope=0):
     """``make_case(elem_p)`` builds the workload at a degree field; returns the
     final degree field and the per-sweep histograms."""
     import torch
@@ -30,7 +30,7 @@ def indicator_degree_field(make_case, p_max=5, p_min=1, nu_max=0.1, nu_min=0.001
         case = make_case(p)
         ctx = frx.Context.from_case(case, max_restart=0)
         U = torch.tensor(case.U, device="cuda")
-        pn = ctx.select_degrees(U, var, nu_max, nu_min, p_min, p_max).cpu().numpy()
+        pn = ctx.select_degrees(U, var, nu_max, nu_min, p_min, p_max, eta_max_scope).cpu().numpy()
         ctx.close()
         hist.append(np.bincount(pn, minlength=p_max + 1)[1:].tolist())
         if np.array_equal(pn, p):
@@ -39,17 +39,22 @@ def indicator_degree_field(make_case, p_max=5, p_min=1, nu_max=0.1, nu_min=0.001
     return p, hist
 
 
-def adapt_step(case, ctx, U, nu_max=0.1, nu_min=0.001, p_min=1, p_max=5, var=1, reserve=None):
+def adapt_step(case, ctx, U, nu_max=0.1, nu_min=0.001, p_min=1, p_max=5, var=1, reserve=None, eta_max_scope=1,
+               fused=None):
     """One p-adaptation on the device: degrees from the indicator, criteria and
     face limiter (fr_select_degrees), a context for the new degree field (new
     degree buckets and face lists; ``reserve`` = the Context's max_restart /
-    graphs), the state projected onto it (fr_project).
+    graphs, ``fused`` its launch mode), the state projected onto it
+    (fr_project).  ``eta_max_scope``: the reading of the criteria's maximum
+    indicator (1, the default: over the elements of the same degree; 0: over
+    all elements, which on the isentropic vortex coarsens the vortex core to
+    p <= 2 whatever p_max).
     Returns (new case description, new context, new state)."""
     import dataclasses
 
     from . import frx
 
-    p_new = ctx.select_degrees(U, var, nu_max, nu_min, p_min, p_max).cpu().numpy()
+    p_new = ctx.select_degrees(U, var, nu_max, nu_min, p_min, p_max, eta_max_scope).cpu().numpy()
     new_case = dataclasses.replace(case, elem_p=p_new.astype(np.int8), U=None)
-    new_ctx = frx.Context.from_case(new_case, **(reserve or {}))
+    new_ctx = frx.Context.from_case(new_case, fused=fused, **(reserve or {}))
     return new_case, new_ctx, ctx.project_to(U, new_ctx)

@@ -79,7 +79,7 @@ struct MeshDev {
   int* flag = nullptr;
   int8_t* p_dev = nullptr;        // [E] degrees
   int* nbr = nullptr;             // [E][6] neighbours (negative: boundary)
-  double* eta_w = nullptr;        // [E + 1] indicator workspace of the degree selection
+  double* eta_w = nullptr;        // [E + 8] indicator workspace of the degree selection (eta, maxima)
   int8_t* psel = nullptr;         // [2 E] degree-selection ping-pong buffers
   ProfHook* prof = nullptr;
   bool fused = false;             // one launch per stage over all buckets
@@ -131,7 +131,7 @@ hipError_t launch_vjp(const MeshDev& M, const double* U, const double* w, double
 hipError_t launch_indicator(const MeshDev& M, const double* U, int var, double* eta, double* eta_max,
                             hipStream_t s);
 hipError_t launch_select_degrees(const MeshDev& M, const double* U, int var, double nu_max, double nu_min, int p_min,
-                                 int p_max, int8_t* p_new, hipStream_t s);
+                                 int p_max, int by_degree, int8_t* p_new, hipStream_t s);
 hipError_t launch_project(const MeshDev& Ms, const double* Us, const MeshDev& Md, double* Ud, hipStream_t s);
 // nodal polynomial filter of the elements of degree >= p_from (Uout may be U)
 hipError_t launch_filter(const MeshDev& M, const double* U, double* Uout, double alpha, int p_from, hipStream_t s);

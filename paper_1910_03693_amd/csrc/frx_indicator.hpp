@@ -101,6 +101,32 @@ __global__ void __launch_bounds__(256) k_max(const double* __restrict__ x, int n
   if (threadIdx.x == 0) *out = sh[0];
 }
 
+// out[n] = max of eta_e over the elements of size n = p + 1 (n = 2..6; 0 where
+// there is none), one block, fixed order
+__global__ void __launch_bounds__(256) k_max_by_degree(const double* __restrict__ x, const int8_t* __restrict__ p,
+                                                      int n, double* __restrict__ out) {
+  __shared__ double sh[NMAX + 1][256];
+  double m[NMAX + 1];
+#pragma unroll
+  for (int k = 0; k <= NMAX; ++k) m[k] = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const int k = p[i] + 1;
+#pragma unroll
+    for (int j = 2; j <= NMAX; ++j)
+      if (k == j) m[j] = fmax(m[j], x[i]);
+  }
+#pragma unroll
+  for (int k = 0; k <= NMAX; ++k) sh[k][threadIdx.x] = m[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+#pragma unroll
+      for (int k = 0; k <= NMAX; ++k) sh[k][threadIdx.x] = fmax(sh[k][threadIdx.x], sh[k][threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x <= NMAX) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
 }  // namespace frx
 
 namespace frx {
@@ -108,13 +134,15 @@ namespace frx {
 // ------------------------------------------------------- degree selection
 // Criteria of section 3.1 from the indicator: raise p by one where
 // eta > nu_max eta_max, lower it by one where eta < nu_min eta_max, clamped to
-// [p_min, p_max] (decided in float64).  One thread per element.
+// [p_min, p_max] (decided in float64).  eta_max is the maximum over all
+// elements (by_degree = 0: eta_max[0]) or over the elements of the same degree
+// (by_degree = 1: eta_max[p + 1]).  One thread per element.
 __global__ void __launch_bounds__(256) k_select(const double* __restrict__ eta, const double* __restrict__ eta_max,
-                                               const int8_t* __restrict__ p, int E, double nu_max, double nu_min,
-                                               int p_min, int p_max, int8_t* __restrict__ out) {
+                                               int by_degree, const int8_t* __restrict__ p, int E, double nu_max,
+                                               double nu_min, int p_min, int p_max, int8_t* __restrict__ out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= E) return;
-  const double m = *eta_max;
+  const double m = by_degree ? eta_max[p[e] + 1] : eta_max[0];
   int q = p[e] + (eta[e] > nu_max * m ? 1 : 0) - (eta[e] < nu_min * m ? 1 : 0);
   q = q < p_min ? p_min : (q > p_max ? p_max : q);
   out[e] = (int8_t)q;

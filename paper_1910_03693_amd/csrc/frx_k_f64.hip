@@ -58,16 +58,23 @@ hipError_t launch_indicator(const MeshDev& M, const double* U, int var, double* 
   return hipGetLastError();
 }
 hipError_t launch_select_degrees(const MeshDev& M, const double* U, int var, double nu_max, double nu_min, int p_min,
-                                 int p_max, int8_t* p_new, hipStream_t s) {
+                                 int p_max, int by_degree, int8_t* p_new, hipStream_t s) {
   double* eta = M.eta_w;
-  double* eta_max = M.eta_w + M.E;
+  double* eta_max = M.eta_w + M.E;  // [0]: over all elements; [n]: over the elements of size n
   hipError_t e = launch_indicator(M, U, var, eta, eta_max, s);
   if (e != hipSuccess) return e;
+  if (by_degree) {
+    hipLaunchKernelGGL(k_max_by_degree, dim3(1), dim3(256), 0, s, (const double*)eta, (const int8_t*)M.p_dev, M.E,
+                       eta_max + 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const int grid = (M.E + 255) / 256;
   int8_t* a = M.psel;
   int8_t* b = M.psel + M.E;
-  hipLaunchKernelGGL(k_select, dim3(grid), dim3(256), 0, s, (const double*)eta, (const double*)eta_max,
-                     (const int8_t*)M.p_dev, M.E, nu_max, nu_min, p_min, p_max, a);
+  // (k_max_by_degree writes eta_max[1 + n'] for n' = 0..6; k_select reads eta_max[p + 1])
+  hipLaunchKernelGGL(k_select, dim3(grid), dim3(256), 0, s, (const double*)eta,
+                     (const double*)(by_degree ? eta_max + 1 : eta_max), by_degree, (const int8_t*)M.p_dev, M.E,
+                     nu_max, nu_min, p_min, p_max, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   for (int it = 0; it < p_max - p_min; ++it) {
     hipLaunchKernelGGL(k_limit, dim3(grid), dim3(256), 0, s, (const int8_t*)a, (const int*)M.nbr, M.E, b);

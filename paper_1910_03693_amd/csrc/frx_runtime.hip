@@ -1156,7 +1156,7 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
     FRX_TRY(hipMemcpy(M.p_dev, d->elem_p, E, hipMemcpyHostToDevice));
     M.nbr = (int*)C->dalloc(sizeof(int) * 6L * E);
     FRX_TRY(hipMemcpy(M.nbr, d->elem_nbr, sizeof(int) * 6L * E, hipMemcpyHostToDevice));
-    M.eta_w = (double*)C->dalloc(sizeof(double) * (E + 1));
+    M.eta_w = (double*)C->dalloc(sizeof(double) * (E + 8));
     M.psel = (int8_t*)C->dalloc(2L * E);
     M.flag = (int*)C->dalloc(sizeof(int) * 4);
     FRX_TRY(hipMemset(M.flag, 0, sizeof(int) * 4));
@@ -1529,13 +1529,14 @@ fr_status spectral_decay_indicator(fr_ctx c, const double* U, int32_t var, doubl
 }
 
 fr_status fr_select_degrees(fr_ctx c, const double* U, int32_t var, double nu_max, double nu_min, int32_t p_min,
-                            int32_t p_max, int8_t* p_new, void* stream) {
+                            int32_t p_max, int32_t eta_max_scope, int8_t* p_new, void* stream) {
   if (!c) return FR_E_INVALID;
   if (!U || !p_new || var < 0 || var > 4 || p_min < 1 || p_max > 5 || p_min > p_max || !(nu_min >= 0.0) ||
-      !(nu_max >= nu_min))
+      !(nu_max >= nu_min) || (eta_max_scope != FR_ETA_MAX_ALL && eta_max_scope != FR_ETA_MAX_SAME_DEGREE))
     return fail(c, FR_E_INVALID, "fr_select_degrees: bad arguments");
   return guarded(c, [&]() -> fr_status {
-    FRX_TRY(launch_select_degrees(c->M, U, var, nu_max, nu_min, p_min, p_max, p_new, S(stream)));
+    FRX_TRY(launch_select_degrees(c->M, U, var, nu_max, nu_min, p_min, p_max,
+                                  eta_max_scope == FR_ETA_MAX_SAME_DEGREE ? 1 : 0, p_new, S(stream)));
     return FR_OK;
   });
 }

@@ -25,6 +25,7 @@ FR_GRAPHS_F64_EXACT, FR_GRAPHS_F32_EXACT, FR_GRAPHS_F64_FD, FR_GRAPHS_F64_FD_SCA
 FR_LAUNCH_PER_BUCKET, FR_LAUNCH_FUSED = 0, 1
 FR_LAUNCH_FACES_TWO_PASS, FR_LAUNCH_FACES_ONE_PASS = 4, 8
 FR_ESDIRK2, FR_ESDIRK4 = 0, 1
+FR_ETA_MAX_ALL, FR_ETA_MAX_SAME_DEGREE = 0, 1
 STATUS_NAMES = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_NOMEM", -3: "FR_E_HIP", -4: "FR_E_NOTCONVERGED",
                 -5: "FR_E_NONPHYSICAL", -6: "FR_E_UNSUPPORTED"}
 EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_reserve", "fr_residual", "fr_residual_noalloc", "fr_residual_jvp", "fr_jvp", "fr_vjp", "gmres_stage_solve",
@@ -95,7 +96,8 @@ def lib():
                                         C.POINTER(fr_gmres_stats), vp]
         L.esdirk_step.argtypes = [vp, vp, C.c_double, C.POINTER(fr_step_opts), C.POINTER(fr_step_stats), vp]
         L.spectral_decay_indicator.argtypes = [vp, vp, C.c_int32, vp, vp, vp]
-        L.fr_select_degrees.argtypes = [vp, vp, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32, vp, vp]
+        L.fr_select_degrees.argtypes = [vp, vp, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_int32,
+                                        vp, vp]
         L.fr_project.argtypes = [vp, vp, vp, vp, vp]
         L.fr_filter.argtypes = [vp, vp, vp, C.c_double, C.c_int32, vp]
         L.fr_autotune.argtypes = [vp, vp, vp]
@@ -268,10 +270,10 @@ def fr_residual_jvp(h, U, v, R, Jv, stream=None):
                                         _dev(Jv, torch.float64, n), _stream(stream)), h)
 
 
-def fr_select_degrees(h, U, var, nu_max, nu_min, p_min, p_max, p_new, stream=None):
+def fr_select_degrees(h, U, var, nu_max, nu_min, p_min, p_max, p_new, eta_max_scope=FR_ETA_MAX_ALL, stream=None):
     n, ne = _sizes(h)
     return _check(lib().fr_select_degrees(h, _dev(U, torch.float64, n), var, nu_max, nu_min, p_min, p_max,
-                                          _dev(p_new, torch.int8, ne), _stream(stream)), h)
+                                          eta_max_scope, _dev(p_new, torch.int8, ne), _stream(stream)), h)
 
 
 def fr_project(h_src, U_src, h_dst, U_dst, stream=None):
@@ -325,14 +327,17 @@ class Context:
 
     max_restart / graphs: the solver workspace and Arnoldi graph sets that
     fr_reserve makes at construction (max_restart=0 reserves nothing; the
-    solver calls then refuse to run until reserve() is called)."""
+    solver calls then refuse to run until reserve() is called); fused: the
+    launch mode, set before the graphs are captured (None keeps the default)."""
 
     def __init__(self, elem_xyz, elem_nbr, elem_p, physics=FR_EULER, flux=FR_RUSANOV, gamma=1.4, mu=0.0,
-                 prandtl=0.72, farfield=None, max_restart=40, graphs=0):
+                 prandtl=0.72, farfield=None, max_restart=40, graphs=0, fused=None):
         self.n_elem = len(elem_p)
         self.h = fr_create(elem_xyz, elem_nbr, elem_p, physics, flux, gamma, mu, prandtl, farfield)
         self.n_dof, self.sp_offset = fr_layout(self.h, self.n_elem)
         self.n_sp = self.n_dof // 5
+        if fused is not None:  # before the graphs are captured
+            self.set_launch(fused)
         if max_restart:
             fr_reserve(self.h, max_restart, graphs)
 
@@ -393,11 +398,11 @@ class Context:
         fr_residual_jvp(self.h, U, v, R, Jv)
         return R, Jv
 
-    def select_degrees(self, U, var=1, nu_max=0.1, nu_min=0.001, p_min=1, p_max=5):
+    def select_degrees(self, U, var=1, nu_max=0.1, nu_min=0.001, p_min=1, p_max=5, eta_max_scope=FR_ETA_MAX_ALL):
         """Device int8 tensor [n_elem] of the degrees chosen by the criteria
         and the face limiter of section 3.1."""
         p = torch.empty(self.n_elem, dtype=torch.int8, device=U.device)
-        fr_select_degrees(self.h, U, var, nu_max, nu_min, p_min, p_max, p)
+        fr_select_degrees(self.h, U, var, nu_max, nu_min, p_min, p_max, p, eta_max_scope)
         return p
 
     def project_to(self, U, dst):

@@ -73,3 +73,17 @@ def test_selection_is_criteria_then_limiter():
     eta = np.array([1.0, 1e-6, 1e-6, 0.05])
     # criteria: [5, 1, 1, 2]; limiter: [5, 4, 3, 2]
     assert D.select_degrees(p, eta, 1.0, m["elem_nbr"]).tolist() == [5, 4, 3, 2]
+
+
+def test_same_degree_maxima():
+    p = np.array([1, 1, 2, 2, 3])
+    eta = np.array([0.5, 1e-4, 0.01, 1e-7, 2e-3])
+    assert D.eta_maxima(p, eta, "all").tolist() == [0.5] * 5
+    assert D.eta_maxima(p, eta, "degree").tolist() == [0.5, 0.5, 0.01, 0.01, 2e-3]
+    # criteria against each reference, worked out by hand
+    assert D.apply_criteria(p, eta, D.eta_maxima(p, eta, "all")).tolist() == [2, 1, 2, 1, 3]
+    assert D.apply_criteria(p, eta, D.eta_maxima(p, eta, "degree")).tolist() == [2, 1, 3, 1, 4]
+    # through select_degrees, on elements that share no face
+    nbr = -np.ones((5, 6), dtype=np.int32)
+    assert D.select_degrees(p, eta, 0.5, nbr, scope="degree").tolist() == [2, 1, 3, 1, 4]
+    assert D.select_degrees(p, eta, 0.5, nbr, scope="all").tolist() == [2, 1, 2, 1, 3]

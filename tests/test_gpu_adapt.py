@@ -21,10 +21,11 @@ def frx():
     return F
 
 
-def oracle_degrees(oracle_mod, case, nu_max=0.1, nu_min=0.001, p_min=1, p_max=5):
+def oracle_degrees(oracle_mod, case, nu_max=0.1, nu_min=0.001, p_min=1, p_max=5, eta_max_scope=0):
     from oracle import degrees
     eta, mx = oracle_mod.Oracle.from_case(case).indicator(case.U, var=1)
-    return degrees.select_degrees(case.elem_p, eta, mx, case.mesh["elem_nbr"], nu_max, nu_min, p_min, p_max)
+    return degrees.select_degrees(case.elem_p, eta, mx, case.mesh["elem_nbr"], nu_max, nu_min, p_min, p_max,
+                                  "degree" if eta_max_scope else "all")
 
 
 def _mixed_case():
@@ -40,10 +41,14 @@ def _mixed_case():
     ("street_16x16x2_from_p5_nu", dict(nu_max=0.05, nu_min=0.01, p_min=2, p_max=4)),
     ("mixed_random_p", dict()),
     ("mixed_random_p_p1p2", dict(p_min=1, p_max=2)),
+    ("mixed_random_p_same_degree_max", dict(eta_max_scope=1)),
+    ("street_16x16x2_mixed_same_degree_max", dict(eta_max_scope=1)),
 ])
 def test_select_degrees_matches_oracle(frx, oracle_mod, kind, kw):
     print("case", kind, kw, flush=True)
-    if kind.startswith("street"):
+    if kind == "street_16x16x2_mixed_same_degree_max":
+        case = I.case_street(16, 16, 2, elem_p=I.draw_p(16 * 16 * 2, [1, 2, 3, 4, 5], [1, 1, 1, 1, 1], 77))
+    elif kind.startswith("street"):
         case = I.case_street(16, 16, 2, elem_p=np.full(16 * 16 * 2, 5, np.int8))
     else:
         case = _mixed_case()
@@ -97,7 +102,7 @@ def test_adapt_step_street(frx, oracle_mod):
     ctx = frx.Context.from_case(case)
     U = torch.tensor(case.U, device="cuda")
     new_case, new_ctx, U2 = adapt.adapt_step(case, ctx, U)
-    p_ref = oracle_degrees(oracle_mod, case)
+    p_ref = oracle_degrees(oracle_mod, case, eta_max_scope=1)  # adapt_step's default reading
     assert np.array_equal(new_case.elem_p.astype(np.int64), p_ref)
     ref = P.project(case.elem_p, case.U, new_case.elem_p)
     assert np.abs(U2.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
