@@ -101,6 +101,10 @@ typedef struct {
   double fd_eps;      /* finite-difference step along the unit direction (1e-6) */
   int32_t use_graph;  /* replay each Arnoldi cycle from the graphs that fr_reserve
                          captured for this (jv_mode, precision) */
+  int32_t precond;    /* 1: left preconditioning by the element-Jacobi
+                         preconditioner (section 2.3) built in this precision;
+                         the stop test and rel_res are then those of the
+                         preconditioned system; 0: none */
 } fr_gmres_opts;
 
 typedef struct {
@@ -152,14 +156,19 @@ enum {
   FR_GRAPHS_F32_EXACT = 2,
   FR_GRAPHS_F64_FD = 4,
   FR_GRAPHS_F64_FD_SCALED = 8,
-  FR_GRAPHS_ALL = 15
+  FR_GRAPHS_ALL = 15,
+  /* storage of the element-Jacobi preconditioner (one of the two): sum over
+   * elements of N_e^2 float64 or float32 entries, N_e = 5 (p_e + 1)^3 */
+  FR_RESERVE_PRECOND_F64 = 16,
+  FR_RESERVE_PRECOND_F32 = 32
 };
 
 /* Allocates the workspace of gmres_stage_solve and esdirk_step (section
  * 2.3): a Krylov basis of max_restart + 1 vectors of n_dof float64 entries
  * (float32 bases use half of it), the Hessenberg system and 11 n_dof float64
  * vectors of ESDIRK stages, and captures the Arnoldi graphs of every set in
- * graph_sets (or-ed FR_GRAPHS_* bits; sets reserved earlier are kept).  It
+ * graph_sets (or-ed FR_GRAPHS_* bits; sets reserved earlier are kept) and,
+ * with FR_RESERVE_PRECOND_F64 or _F32, the element-Jacobi blocks.  It
  * synchronises the device.  Later solver calls with restart <= max_restart
  * and use_graph on a reserved set allocate nothing; a larger restart, an
  * unreserved graph set or an esdirk_step before any fr_reserve returns
@@ -224,6 +233,26 @@ fr_status gmres_stage_solve(fr_ctx ctx, const double* U, double shift, const dou
  * or a context without fr_reserve. */
 fr_status esdirk_step(fr_ctx ctx, double* U, double dt, const fr_step_opts* opts, fr_step_stats* stats,
                       void* stream);
+
+/* The element-Jacobi preconditioner of section 2.3: the diagonal blocks of
+ * (sigma I - dR/dq(U)), one dense block of order N_e = 5 (p_e + 1)^3 per
+ * element, assembled from exact tangent products over a colouring of the
+ * elements (no two face neighbours share a colour; seeding one DOF of every
+ * element of a colour gives a column of each of their blocks), in the
+ * storage precision fr_reserve made (FR_F64: float64 tangents on U; FR_F32:
+ * float32 tangents on a float32 copy of U), then LU-factored with partial
+ * pivoting.  The paper evaluates it once at the start of each physical step
+ * with sigma = 1/(omega dt) + 1/dtau_max (esdirk_step does so when
+ * opts->gmres.precond is set).  U: device float64 [5][n_sp].  Synchronises the
+ * stream.  FR_E_INVALID for sigma <= 0 or a precision without storage;
+ * FR_E_NONPHYSICAL if a block is singular. */
+fr_status fr_precond_build(fr_ctx ctx, const double* U, double sigma, int32_t precision, void* stream);
+
+/* y = P^{-1} x with the preconditioner last built (permutation, forward and
+ * backward substitution per element).  x, y: device float64 [5][n_sp]; y may
+ * be x (in place), else they must not overlap.  FR_E_INVALID if none was
+ * built. */
+fr_status fr_precond_apply(fr_ctx ctx, const double* x, double* y, void* stream);
 
 /* Spectral-decay smoothness indicator of section 3.1 for variable `var`
  * (the paper uses 1 = rho u): eta[e] = ||s_p - s_{p-1}|| / ||s_p|| in the

@@ -19,6 +19,7 @@
 #include "../../include/fr.h"
 #include "frx_host.hpp"
 #include "frx_krylov.hpp"
+#include "frx_precond.hpp"
 
 using namespace frx;
 
@@ -311,6 +312,20 @@ struct fr_ctx_s {
   void* vjpw = nullptr;
   // this device's copy of the static scratch of fr_residual_noalloc
   void* scratch_dev = nullptr;
+  // element-Jacobi preconditioner (section 2.3): storage made by fr_reserve
+  // in one precision, built by fr_precond_build or at the start of a step
+  void* pc_blocks = nullptr;   // dense blocks, column-major, [sum_e N_e^2] of pc_prec
+  int pc_prec = -1;            // FR_F64 / FR_F32 storage, -1: none
+  bool pc_built = false;
+  int* pc_piv = nullptr;       // [sum_e N_e]
+  int4* pc_recs = nullptr;     // [E] (e, first solution point, n, 0)
+  long* pc_boff = nullptr;     // [E]
+  int* pc_poff = nullptr;      // [E]
+  int* pc_flag = nullptr;      // singular block met by the factorisation
+  std::vector<int4*> pc_crecs; // per colour: records of its elements
+  std::vector<int*> pc_cidx;   // per colour: their element ids
+  std::vector<int> pc_ccount;
+  int pc_nmax = 0;             // largest block order
 
   void* dalloc(size_t bytes) {
     void* p = nullptr;
@@ -453,6 +468,24 @@ GmresDev gdev(fr_ctx c) {
   return G;
 }
 
+// Element-Jacobi preconditioner (apply; the build follows the Arnoldi code)
+PcDev pc_dev(fr_ctx c) { return PcDev{c->pc_recs, c->pc_boff, c->pc_poff}; }
+
+// x <- P^{-1} x (if the preconditioner is switched on: ist[5] on the device);
+// nothing when the context has no preconditioner storage
+template <class TV>
+void pc_apply(fr_ctx c, TV* x, const int* done, hipStream_t s) {
+  if (!c->pc_blocks) return;
+  const int* on = c->ist + 5;
+  if (c->pc_prec == FR_F64)
+    hipLaunchKernelGGL((k_pc_apply<TV, double>), dim3(c->M.E), dim3(256), 0, s, x, c->M.nsp,
+                       (const double*)c->pc_blocks, pc_dev(c), (const int*)c->pc_piv, on, done);
+  else
+    hipLaunchKernelGGL((k_pc_apply<TV, float>), dim3(c->M.E), dim3(256), 0, s, x, c->M.nsp,
+                       (const float*)c->pc_blocks, pc_dev(c), (const int*)c->pc_piv, on, done);
+  FRX_TRY(hipGetLastError());
+}
+
 // The GMRES operator A x = sigma x - J(Ulin) x (sigma in sc[6], float copy in
 // sigf) applied to `in` (basis type) into `out` (basis type).
 template <class TV>
@@ -559,6 +592,7 @@ void arnoldi_step(fr_ctx c, int mode, int j, hipStream_t s) {
   double* h2 = h1 + (m + 1);
   double* nr = h2 + (m + 1);
   apply_A<TV>(c, mode, V + (size_t)j * n, w, done, s);
+  pc_apply<TV>(c, w, done, s);  // left preconditioning (a no-op unless switched on)
   const int nv = j + 1;
   if (nv <= 32) {
     gs_fused<TV>(c, G, j, h1, h2, nr, V + (size_t)(j + 1) * n, done, s);
@@ -658,6 +692,70 @@ void arnoldi_cycle(fr_ctx c, int mode, int m, bool use_graph, hipStream_t s) {
   }
 }
 
+// ------------------------------------------------ element-Jacobi preconditioner
+// Assembles the blocks sigma I - dR/dq(U)|_ee by coloured exact tangent
+// products (the tangent in the storage precision: float64 duals on U, or
+// float32 duals on a float32 copy of U) and factors them.
+void pc_build(fr_ctx c, const double* U, double sigma, hipStream_t s) {
+  if (!c->pc_blocks) throw StatusErr{FR_E_INVALID, "no preconditioner storage (fr_reserve with FR_RESERVE_PRECOND_*)"};
+  const long n = c->ndof;
+  const bool f64 = c->pc_prec == FR_F64;
+  if (!f64) {
+    hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, U, c->uf, n);
+    FRX_TRY(hipGetLastError());
+  }
+  // seed and product vectors: t0 and t1 (n doubles hold n floats as well)
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(KR_THREADS), 0, s, c->t0, n, 0.0);
+  FRX_TRY(hipGetLastError());
+  for (size_t col = 0; col < c->pc_crecs.size(); ++col) {
+    const int cnt = c->pc_ccount[col];
+    if (!cnt) continue;
+    for (int j = 0; j <= c->pc_nmax; ++j) {
+      const int jn = j < c->pc_nmax ? j : -1;  // the last pass only clears the seed
+      if (f64)
+        hipLaunchKernelGGL((k_pc_seed<double>), dim3((cnt + 255) / 256), dim3(256), 0, s, c->t0, c->M.nsp,
+                           (const int4*)c->pc_crecs[col], cnt, j - 1, jn);
+      else
+        hipLaunchKernelGGL((k_pc_seed<float>), dim3((cnt + 255) / 256), dim3(256), 0, s, (float*)c->t0, c->M.nsp,
+                           (const int4*)c->pc_crecs[col], cnt, j - 1, jn);
+      FRX_TRY(hipGetLastError());
+      if (jn < 0) break;
+      if (f64) {
+        ResCall<double> rc;
+        rc.U = U;
+        rc.V = c->t0;
+        rc.out = c->t1;
+        FRX_TRY(launch_residual_dual64(c->M, rc, s));
+        hipLaunchKernelGGL((k_pc_extract<double, double>), dim3(cnt), dim3(256), 0, s, (const double*)c->t1,
+                           c->M.nsp, (const int4*)c->pc_crecs[col], (const int*)c->pc_cidx[col], j, sigma,
+                           (const long*)c->pc_boff, (double*)c->pc_blocks);
+      } else {
+        ResCall<float> rc;
+        rc.U = c->uf;
+        rc.V = (const float*)c->t0;
+        rc.out = (float*)c->t1;
+        FRX_TRY(launch_residual_dual32(c->M, rc, s));
+        hipLaunchKernelGGL((k_pc_extract<float, float>), dim3(cnt), dim3(256), 0, s, (const float*)c->t1,
+                           c->M.nsp, (const int4*)c->pc_crecs[col], (const int*)c->pc_cidx[col], j, sigma,
+                           (const long*)c->pc_boff, (float*)c->pc_blocks);
+      }
+      FRX_TRY(hipGetLastError());
+    }
+  }
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->pc_flag, 0);
+  if (f64)
+    hipLaunchKernelGGL((k_pc_lu<double>), dim3(c->M.E), dim3(256), 0, s, (double*)c->pc_blocks, pc_dev(c),
+                       c->pc_piv, c->pc_flag);
+  else
+    hipLaunchKernelGGL((k_pc_lu<float>), dim3(c->M.E), dim3(256), 0, s, (float*)c->pc_blocks, pc_dev(c), c->pc_piv,
+                       c->pc_flag);
+  FRX_TRY(hipGetLastError());
+  FRX_TRY(hipMemcpyAsync(c->ipin + 16, c->pc_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  FRX_TRY(hipStreamSynchronize(s));
+  c->pc_built = c->ipin[16] == 0;
+  if (!c->pc_built) throw StatusErr{FR_E_NONPHYSICAL, "element-Jacobi preconditioner: a singular element block"};
+}
+
 // Iterations of the cycle just finished (read by gmres_run after its
 // synchronisation) sizes the first graph of the next cycle.
 void note_cycle(fr_ctx c, int mode, int prec_bytes, int iters) { c->cycle_iters[{mode, prec_bytes}] = iters; }
@@ -673,7 +771,15 @@ fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats*
   TV* w = (TV*)c->wv;
   TV* xv = (TV*)c->xv;
   // ||F|| (unless the caller has it), tolerance, budget
-  const double nF = nF_known >= 0.0 ? nF_known : norm2(c, c->Fb, s);
+  // left preconditioning: the Krylov space of P^-1 A, the right-hand side
+  // P^-1 F and the residual norms of the preconditioned system
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->ist + 5, o.precond ? 1 : 0);
+  FRX_TRY(hipGetLastError());
+  if (o.precond) {
+    FRX_TRY(hipMemcpyAsync(c->rb, c->Fb, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    pc_apply<double>(c, c->rb, nullptr, s);
+  }
+  const double nF = o.precond ? norm2(c, c->rb, s) : (nF_known >= 0.0 ? nF_known : norm2(c, c->Fb, s));
   hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(KR_THREADS), 0, s, x, n, 0.0);
   FRX_TRY(hipGetLastError());
   fr_gmres_stats stats{0, 0, 0.0, 1};
@@ -691,9 +797,9 @@ fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats*
   int total = 0, cycles = 0;
   bool conv = false;
   while (true) {
-    // restart residual r = F - A x (r = F at the start)
+    // restart residual r = F - A x (r = F at the start), preconditioned
     if (cycles == 0) {
-      FRX_TRY(hipMemcpyAsync(c->rb, c->Fb, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+      if (!o.precond) FRX_TRY(hipMemcpyAsync(c->rb, c->Fb, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     } else {
       hipLaunchKernelGGL((k_cast<double, TV>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const double*)x, xv, n);
       FRX_TRY(hipGetLastError());
@@ -701,6 +807,7 @@ fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats*
       hipLaunchKernelGGL((k_cast<TV, double>), dim3(grid_for(n)), dim3(KR_THREADS), 0, s, (const TV*)w, c->R1, n);
       FRX_TRY(hipGetLastError());
       lincomb(c, c->rb, 1.0, c->Fb, -1.0, c->R1, 0, nullptr, 0, nullptr, s);
+      if (o.precond) pc_apply<double>(c, c->rb, nullptr, s);
     }
     dot_to<double>(c, c->rb, nullptr, c->sc + 9, nullptr, s);
     hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(1), 0, s, G, (const double*)(c->sc + 9));
@@ -749,6 +856,8 @@ fr_status gmres_solve(fr_ctx c, const double* U, double shift, const double* F, 
                                       std::to_string(c->m_alloc) + "); call fr_reserve"};
   if (o.use_graph && !(c->graph_sets & graph_bit(o.jv_mode, o.precision)))
     throw StatusErr{FR_E_INVALID, "Arnoldi graphs of this mode and precision were not reserved (fr_reserve)"};
+  if (o.precond && (!c->pc_built || c->pc_prec != o.precision))
+    throw StatusErr{FR_E_INVALID, "no element-Jacobi preconditioner built in this precision (fr_precond_build)"};
   const long n = c->ndof;
   if (U != c->Ulin) FRX_TRY(hipMemcpyAsync(c->Ulin, U, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   if (F != c->Fb) FRX_TRY(hipMemcpyAsync(c->Fb, F, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
@@ -1134,6 +1243,61 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
     }
     for (int sk = 0; sk < SK_COUNT; ++sk) default_shapes(M, sk);
     build_fused_plans(C.get(), d, fmap, bmap);
+    // preconditioner records and a colouring of the elements in which no two
+    // face neighbours share a colour (greedy, in mesh order)
+    {
+      std::vector<int> colour(E, -1);
+      int ncol = 0;
+      for (int e = 0; e < E; ++e) {
+        unsigned used = 0;
+        for (int f = 0; f < 6; ++f) {
+          const int nb = d->elem_nbr[6 * e + f];
+          if (nb >= 0 && colour[nb] >= 0) used |= 1u << colour[nb];
+        }
+        int k = 0;
+        while (used & (1u << k)) ++k;
+        colour[e] = k;
+        ncol = std::max(ncol, k + 1);
+      }
+      std::vector<int4> recs(E);
+      std::vector<long> boff(E);
+      std::vector<int> poff(E);
+      long b = 0;
+      int pv = 0;
+      for (int e = 0; e < E; ++e) {
+        const int n = d->elem_p[e] + 1, N = 5 * n * n * n;
+        recs[e] = make_int4(e, sp[e], n, 0);
+        boff[e] = b;
+        poff[e] = pv;
+        b += (long)N * N;
+        pv += N;
+        C->pc_nmax = std::max(C->pc_nmax, N);
+      }
+      C->pc_recs = (int4*)C->dalloc(sizeof(int4) * E);
+      C->pc_boff = (long*)C->dalloc(sizeof(long) * E);
+      C->pc_poff = (int*)C->dalloc(sizeof(int) * E);
+      C->pc_piv = (int*)C->dalloc(sizeof(int) * std::max(1, pv));
+      C->pc_flag = (int*)C->dalloc(sizeof(int) * 4);
+      FRX_TRY(hipMemcpy(C->pc_recs, recs.data(), sizeof(int4) * E, hipMemcpyHostToDevice));
+      FRX_TRY(hipMemcpy(C->pc_boff, boff.data(), sizeof(long) * E, hipMemcpyHostToDevice));
+      FRX_TRY(hipMemcpy(C->pc_poff, poff.data(), sizeof(int) * E, hipMemcpyHostToDevice));
+      for (int k = 0; k < ncol; ++k) {
+        std::vector<int4> cr;
+        std::vector<int> ci;
+        for (int e = 0; e < E; ++e)
+          if (colour[e] == k) {
+            cr.push_back(recs[e]);
+            ci.push_back(e);
+          }
+        int4* crd = (int4*)C->dalloc(sizeof(int4) * std::max<size_t>(1, cr.size()));
+        int* cid = (int*)C->dalloc(sizeof(int) * std::max<size_t>(1, ci.size()));
+        FRX_TRY(hipMemcpy(crd, cr.data(), sizeof(int4) * cr.size(), hipMemcpyHostToDevice));
+        FRX_TRY(hipMemcpy(cid, ci.data(), sizeof(int) * ci.size(), hipMemcpyHostToDevice));
+        C->pc_crecs.push_back(crd);
+        C->pc_cidx.push_back(cid);
+        C->pc_ccount.push_back((int)cr.size());
+      }
+    }
     // gas
     const double kappa = d->mu * d->gamma / ((d->gamma - 1.0) * d->prandtl);
     M.gas_d.gamma = d->gamma;
@@ -1191,14 +1355,28 @@ fr_status fr_layout(fr_ctx c, int64_t* n_dof, int64_t* sp_offset) {
 
 fr_status fr_reserve(fr_ctx c, int32_t max_restart, int32_t graph_sets) {
   if (!c) return FR_E_INVALID;
-  if (max_restart < 1 || max_restart > 200 ||
-      (graph_sets & ~(FR_GRAPHS_F64_EXACT | FR_GRAPHS_F32_EXACT | FR_GRAPHS_F64_FD | FR_GRAPHS_F64_FD_SCALED)))
-    return fail(c, FR_E_INVALID, "fr_reserve: max_restart outside 1..200 or unknown graph-set bits");
+  const int gbits = FR_GRAPHS_F64_EXACT | FR_GRAPHS_F32_EXACT | FR_GRAPHS_F64_FD | FR_GRAPHS_F64_FD_SCALED;
+  const int pbits = FR_RESERVE_PRECOND_F64 | FR_RESERVE_PRECOND_F32;
+  if (max_restart < 1 || max_restart > 200 || (graph_sets & ~(gbits | pbits)) || (graph_sets & pbits) == pbits)
+    return fail(c, FR_E_INVALID, "fr_reserve: max_restart outside 1..200, unknown bits or two preconditioner precisions");
   return guarded(c, [&]() -> fr_status {
     FRX_TRY(hipDeviceSynchronize());
     ensure_krylov(c, max_restart);
     if (!c->es) c->es = (double*)c->dalloc(sizeof(double) * 11 * c->ndof);
-    c->graph_sets |= graph_sets;
+    const int want = (graph_sets & FR_RESERVE_PRECOND_F64) ? FR_F64 : ((graph_sets & FR_RESERVE_PRECOND_F32) ? FR_F32 : -1);
+    if (want >= 0 && want != c->pc_prec) {
+      // one block of N_e^2 entries per element, N_e = 5 (p_e + 1)^3
+      if (c->pc_blocks) c->dfree(c->pc_blocks);
+      long entries = 0;
+      for (int e = 0; e < c->M.E; ++e) {
+        const long N = 5L * (c->p[e] + 1) * (c->p[e] + 1) * (c->p[e] + 1);
+        entries += N * N;
+      }
+      c->pc_blocks = c->dalloc((size_t)entries * (want == FR_F64 ? sizeof(double) : sizeof(float)));
+      c->pc_prec = want;
+      c->pc_built = false;
+    }
+    c->graph_sets |= (graph_sets & gbits);
     instantiate_graphs(c);
     FRX_TRY(hipDeviceSynchronize());
     return FR_OK;
@@ -1446,6 +1624,13 @@ fr_status esdirk_step(fr_ctx c, double* U, double dt, const fr_step_opts* o, fr_
     fr_step_stats stats{0, 0, 0, 0, 0.0};
     FRX_TRY(hipMemcpyAsync(qn, U, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     FRX_TRY(hipMemcpyAsync(q, U, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    // the element-Jacobi preconditioner, evaluated once at the start of the
+    // step (section 2.3) with sigma = 1/(omega dt) + 1/dtau_max
+    if (o->gmres.precond) {
+      if (c->pc_prec != o->gmres.precision)
+        throw StatusErr{FR_E_INVALID, "esdirk_step: no preconditioner storage in the GMRES precision (fr_reserve)"};
+      pc_build(c, qn, 1.0 / (w * dt) + 1.0 / o->dtau_max, s);
+    }
     ResCall<double> rc;
     rc.U = qn;
     rc.out = Rs;
@@ -1814,6 +1999,34 @@ fr_status fr_profile(fr_ctx c, const double* U, int32_t op, int32_t reps, fr_ker
       (void)hipEventDestroy(R.b);
     }
     *n_out = k;
+    return FR_OK;
+  });
+}
+
+fr_status fr_precond_build(fr_ctx c, const double* U, double sigma, int32_t precision, void* stream) {
+  if (!c) return FR_E_INVALID;
+  if (!U || !(sigma > 0.0) || (precision != FR_F64 && precision != FR_F32))
+    return fail(c, FR_E_INVALID, "fr_precond_build: bad arguments");
+  if (c->pc_prec != precision)
+    return fail(c, FR_E_INVALID, "fr_precond_build: no preconditioner storage in this precision (fr_reserve)");
+  return guarded(c, [&]() -> fr_status {
+    c->pc_built = false;
+    pc_build(c, U, sigma, S(stream));
+    return FR_OK;
+  });
+}
+
+fr_status fr_precond_apply(fr_ctx c, const double* x, double* y, void* stream) {
+  if (!c) return FR_E_INVALID;
+  const size_t nb = sizeof(double) * c->ndof;
+  if (!x || !y || ((const void*)x != (const void*)y && overlap(x, nb, y, nb)))
+    return fail(c, FR_E_INVALID, "fr_precond_apply: bad arguments");
+  if (!c->pc_built) return fail(c, FR_E_INVALID, "fr_precond_apply: no preconditioner built (fr_precond_build)");
+  return guarded(c, [&]() -> fr_status {
+    hipStream_t s = S(stream);
+    if (x != y) FRX_TRY(hipMemcpyAsync(y, x, nb, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->ist + 5, 1);
+    pc_apply<double>(c, y, nullptr, s);
     return FR_OK;
   });
 }

@@ -22,6 +22,7 @@ FR_ROE, FR_RUSANOV = 0, 1
 FR_F64, FR_F32 = 0, 1
 FR_JV_EXACT, FR_JV_FD, FR_JV_FD_SCALED = 0, 1, 2
 FR_GRAPHS_F64_EXACT, FR_GRAPHS_F32_EXACT, FR_GRAPHS_F64_FD, FR_GRAPHS_F64_FD_SCALED, FR_GRAPHS_ALL = 1, 2, 4, 8, 15
+FR_RESERVE_PRECOND_F64, FR_RESERVE_PRECOND_F32 = 16, 32
 FR_LAUNCH_PER_BUCKET, FR_LAUNCH_FUSED = 0, 1
 FR_LAUNCH_FACES_TWO_PASS, FR_LAUNCH_FACES_ONE_PASS = 4, 8
 FR_ESDIRK2, FR_ESDIRK4 = 0, 1
@@ -30,7 +31,8 @@ STATUS_NAMES = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_NOMEM", -3: "FR_E_HIP"
                 -5: "FR_E_NONPHYSICAL", -6: "FR_E_UNSUPPORTED"}
 EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_reserve", "fr_residual", "fr_residual_noalloc", "fr_residual_jvp", "fr_jvp", "fr_vjp", "gmres_stage_solve",
             "esdirk_step", "spectral_decay_indicator", "fr_select_degrees", "fr_project", "fr_filter", "fr_autotune", "fr_profile",
-            "fr_set_launch", "fr_check", "fr_launch_shapes", "fr_last_error")
+            "fr_set_launch", "fr_check", "fr_launch_shapes", "fr_precond_build", "fr_precond_apply",
+            "fr_last_error")
 
 
 class FrError(RuntimeError):
@@ -47,7 +49,8 @@ class fr_mesh_desc(C.Structure):
 
 class fr_gmres_opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double), ("jv_mode", C.c_int32),
-                ("precision", C.c_int32), ("fd_eps", C.c_double), ("use_graph", C.c_int32)]
+                ("precision", C.c_int32), ("fd_eps", C.c_double), ("use_graph", C.c_int32),
+                ("precond", C.c_int32)]
 
 
 class fr_gmres_stats(C.Structure):
@@ -106,6 +109,8 @@ def lib():
         L.fr_profile.argtypes = [vp, vp, C.c_int32, C.c_int32, C.POINTER(fr_kernel_time), C.c_int32,
                                  C.POINTER(C.c_int32), vp]
         L.fr_launch_shapes.argtypes = [vp, C.c_int32, vp, C.c_int32, C.POINTER(C.c_int32)]
+        L.fr_precond_build.argtypes = [vp, vp, C.c_double, C.c_int32, vp]
+        L.fr_precond_apply.argtypes = [vp, vp, vp, vp]
         L.fr_last_error.restype = C.c_char_p
         L.fr_last_error.argtypes = [vp]
         for name in EXPORTED:
@@ -218,10 +223,10 @@ def fr_vjp(h, U, w, JTw, stream=None):
 
 
 def gmres_opts(restart=30, max_iter=100, tol=1e-1, jv_mode=FR_JV_EXACT, precision=FR_F64, fd_eps=1e-6,
-               use_graph=False):
+               use_graph=False, precond=False):
     o = fr_gmres_opts()
-    o.restart, o.max_iter, o.tol, o.jv_mode, o.precision, o.fd_eps, o.use_graph = (
-        restart, max_iter, tol, jv_mode, precision, fd_eps, int(bool(use_graph)))
+    o.restart, o.max_iter, o.tol, o.jv_mode, o.precision, o.fd_eps, o.use_graph, o.precond = (
+        restart, max_iter, tol, jv_mode, precision, fd_eps, int(bool(use_graph)), int(bool(precond)))
     return o
 
 
@@ -309,6 +314,16 @@ def fr_launch_shapes(h, kind):
     n = C.c_int32(0)
     _check(lib().fr_launch_shapes(h, int(kind), C.c_void_p(buf.ctypes.data), 256, C.byref(n)), h)
     return [tuple(int(x) for x in buf[3 * i:3 * i + 3]) for i in range(n.value)]
+
+
+def fr_precond_build(h, U, sigma, precision=FR_F64, stream=None):
+    return _check(lib().fr_precond_build(h, _dev(U, torch.float64, _ndof(h)), float(sigma), int(precision),
+                                         _stream(stream)), h)
+
+
+def fr_precond_apply(h, x, y, stream=None):
+    n = _ndof(h)
+    return _check(lib().fr_precond_apply(h, _dev(x, torch.float64, n), _dev(y, torch.float64, n), _stream(stream)), h)
 
 
 def fr_set_launch(h, mode):
@@ -430,6 +445,14 @@ class Context:
         if two_pass_faces is not None:
             mode |= FR_LAUNCH_FACES_TWO_PASS if two_pass_faces else FR_LAUNCH_FACES_ONE_PASS
         fr_set_launch(self.h, mode)
+
+    def precond_build(self, U, sigma, precision=FR_F64):
+        fr_precond_build(self.h, U, sigma, precision)
+
+    def precond_apply(self, x, out=None):
+        out = torch.empty_like(x) if out is None else out
+        fr_precond_apply(self.h, x, out)
+        return out
 
     def launch_shapes(self, kind=1):
         return fr_launch_shapes(self.h, kind)
