@@ -28,7 +28,7 @@ The same run reports, on that workload:
     thread and at every host thread.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-       python bench.py --study {c3,c5,c3adapt,g2}
+       python bench.py --study {c3,c5,c3adapt,g2,precond}
 """
 from __future__ import annotations
 
@@ -188,7 +188,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB five times (reference for the HBM byte counters)")
-    ap.add_argument("--study", choices=("c3", "c5", "c3adapt", "g2"), default=None,
+    ap.add_argument("--study", choices=("c3", "c5", "c3adapt", "g2", "precond"), default=None,
                     help="instead of the headline: implicit steps on the 64x64x8 vortex street (c3) or the "
                          "128x128x8 box (c5), the adaptive vortex-street loop (c3adapt), or the p / p_max "
                          "refinement study of the isentropic vortex, uniform against adaptive degrees (g2)")
@@ -202,6 +202,8 @@ def main():
             res = adaptive_study()
         elif args.study == "g2":
             res = g2_study()
+        elif args.study == "precond":
+            res = precond_study()
         else:
             res = step_study(args.study)
         print(json.dumps(res), flush=True)
@@ -581,6 +583,60 @@ def step_study(which):
         out[f"rel_diff_{name}_vs_f64_exact"] = (outs[name] - ref).norm().item() / ref.norm().item()
     out["speedup_mixed_vs_plain_scaled"] = round(out["plain_f64_fd_scaled"]["ms"] /
                                                  out["mixed_f32_exact_graph"]["ms"], 3)
+    return out
+
+
+def precond_study():
+    """The element-Jacobi preconditioner (section 2.3) against none, in the
+    mixed form (float32 exact tangent and basis, float32 blocks) and in
+    float64: on the 32x32x4 workload one full ESDIRK2 step at the paper's
+    settings (dt 0.005, dtau 5e-4 .. 5e-3, PTC to 1e-4, GMRES(30) to 1e-1);
+    on the 128x128x8 workload one implicit stage (dt 0.002, dtau 2e-4 .. 4e-3,
+    GMRES(30) to 1e-6).  The step builds the preconditioner at its start
+    (sigma = 1/(omega dt) + 1/dtau_max); its build time is also measured alone."""
+    import torch
+
+    from paper_1910_03693_amd import frx
+    from paper_1910_03693_amd import inputs as I
+
+    out = {"study": "precond"}
+    for name, k, dt, common, g in (
+            ("32x32x4", 2, 0.005, dict(dtau_init=5e-4, dtau_max=5e-3, tol_pseudo=1e-4, max_ptc_iter=50),
+             dict(restart=30, max_iter=100, tol=1e-1)),
+            ("128x128x8_stage", 5, 0.002, dict(dtau_init=2e-4, dtau_max=4e-3, tol_pseudo=1e-4, max_ptc_iter=50,
+                                               last_stage=2), dict(restart=30, max_iter=300, tol=1e-6))):
+        case = I.config(k)
+        res = {"dt": dt, "settings": {**common, **g}}
+        for prec, pname in ((frx.FR_F32, "mixed_f32"), (frx.FR_F64, "f64")):
+            if k == 5 and prec == frx.FR_F64:
+                continue  # float64 blocks of this workload take 94 GB; the float32 ones are timed
+            resv = (frx.FR_RESERVE_PRECOND_F32 if prec == frx.FR_F32 else frx.FR_RESERVE_PRECOND_F64) | \
+                (frx.FR_GRAPHS_F32_EXACT if prec == frx.FR_F32 else frx.FR_GRAPHS_F64_EXACT)
+            ctx = frx.Context.from_case(case, max_restart=30, graphs=resv, fused=True)
+            U = torch.tensor(case.U, device="cuda")
+            sigma = 1.0 / ((1.0 - 2 ** -0.5) * dt) + 1.0 / common["dtau_max"]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.precond_build(U, sigma, prec)
+            torch.cuda.synchronize()
+            t_build = (time.perf_counter() - t0) * 1e3
+            x = torch.tensor(I.random_direction(case.U.size, 4090).reshape(case.U.shape), device="cuda")
+            y = torch.empty_like(x)
+            t_apply, _ = median_ms(lambda: ctx.precond_apply(x, out=y), 5, 1, torch.cuda.current_stream(), torch)
+            for pc in (False, True):
+                gg = dict(g, precision=prec, use_graph=True, precond=pc)
+                Uw, ms, st = _timed_step(ctx, U, dt, torch, gmres=gg, **common)
+                key = f"{pname}_{'element_jacobi' if pc else 'none'}"
+                res[key] = {"ms": round(ms, 1), **st}
+                print(f"[bench] precond {name} {key}: {ms:.1f} ms {st}", file=sys.stderr, flush=True)
+            res[f"{pname}_build_ms"] = round(t_build, 1)
+            res[f"{pname}_apply_ms"] = round(t_apply, 3)
+            print(f"[bench] precond {name} {pname}: build {t_build:.1f} ms, apply {t_apply:.3f} ms", file=sys.stderr,
+                  flush=True)
+            ctx.close()
+            del U, x, y
+            torch.cuda.empty_cache()
+        out[name] = res
     return out
 
 

@@ -241,15 +241,17 @@ fr_status esdirk_step(fr_ctx ctx, double* U, double dt, const fr_step_opts* opts
  * element of a colour gives a column of each of their blocks), in the
  * storage precision fr_reserve made (FR_F64: float64 tangents on U; FR_F32:
  * float32 tangents on a float32 copy of U), then LU-factored with partial
- * pivoting.  The paper evaluates it once at the start of each physical step
+ * pivoting and inverted through the factors (as the paper does), in place.
+ * The paper evaluates it once at the start of each physical step
  * with sigma = 1/(omega dt) + 1/dtau_max (esdirk_step does so when
  * opts->gmres.precond is set).  U: device float64 [5][n_sp].  Synchronises the
  * stream.  FR_E_INVALID for sigma <= 0 or a precision without storage;
  * FR_E_NONPHYSICAL if a block is singular. */
 fr_status fr_precond_build(fr_ctx ctx, const double* U, double sigma, int32_t precision, void* stream);
 
-/* y = P^{-1} x with the preconditioner last built (permutation, forward and
- * backward substitution per element).  x, y: device float64 [5][n_sp]; y may
+/* y = P^{-1} x with the preconditioner last built (per element: the row
+ * permutation of the factorisation, then the product with the stored
+ * inverse).  x, y: device float64 [5][n_sp]; y may
  * be x (in place), else they must not overlap.  FR_E_INVALID if none was
  * built. */
 fr_status fr_precond_apply(fr_ctx ctx, const double* x, double* y, void* stream);

@@ -8,9 +8,10 @@
 // colour; seeding DOF j of every element of one colour gives, in those
 // elements' own rows, column j of their diagonal blocks (the residual of an
 // element depends on its own and its face neighbours' DOF only).
-// Factorisation: LU with partial pivoting, one 256-thread block per element,
-// the matrix column-major in device memory.  Apply: permutation, forward and
-// backward substitution, one block per element, in place.
+// Factorisation: blocked LU with partial pivoting, one 256-thread block per
+// element, the matrix column-major in device memory, then the inverse from
+// the factors in place (the block is inverted through its LU, as the paper
+// does).  Apply: the permutation and a dense product per element, in place.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -61,73 +62,306 @@ __global__ void __launch_bounds__(256) k_pc_extract(const TV* __restrict__ Jv, i
 }
 
 // LU factorisation with partial pivoting of every element block, in place:
-// P A = L U with unit lower L; piv[k] = the row swapped with row k at step k.
-// A zero pivot column (a singular block) sets *flag.
+// P A = L U with unit lower L; on return piv[i] = the row of A that is row i
+// of P A (during the factorisation it holds the row swapped with row k at step k).
+// Blocked, right-looking, one 256-thread block per element: a panel of PB
+// columns (rows k0..N-1) is factored in LDS (pivot search, row swaps within
+// the panel, scaling and the panel's own updates), written back, its swaps
+// applied to the other columns, the panel's rows of the trailing columns
+// solved with its unit lower triangle, and the trailing matrix updated once
+// per panel (each thread holds the panel's multipliers of its rows in
+// registers).  A zero pivot column (a singular block) sets *flag.
+constexpr int PC_NMAX = 5 * 6 * 6 * 6;            // largest block order (p = 5)
+constexpr int PC_ROWS = (PC_NMAX + 255) / 256;    // trailing rows per thread
+template <class TB> struct PcPanel { static constexpr int value = sizeof(TB) == 8 ? 8 : 16; };
+
 template <class TB>
 __global__ void __launch_bounds__(256) k_pc_lu(TB* __restrict__ blocks, PcDev pc, int* __restrict__ piv,
                                               int* __restrict__ flag) {
+  constexpr int PB = PcPanel<TB>::value;
+  __shared__ TB pan[PB * PC_NMAX];  // pan[c * nr + (r - k0)]: panel column c, rows k0..N-1
   __shared__ double red_v[256];
   __shared__ int red_i[256];
-  __shared__ TB rowk[5 * 6 * 6 * 6];
-  const int4 r = pc.recs[blockIdx.x];
-  const int N = pc_rows(r.z);
+  __shared__ int pv[PB];
+  const int4 rec = pc.recs[blockIdx.x];
+  const int N = pc_rows(rec.z);
   TB* A = blocks + pc.boff[blockIdx.x];
   int* P = piv + pc.poff[blockIdx.x];
   const int tid = threadIdx.x;
-  for (int k = 0; k < N; ++k) {
-    // pivot: the largest |a_ik|, i >= k (the smallest index among equals)
-    double best = -1.0;
-    int bi = k;
-    for (int i = k + tid; i < N; i += blockDim.x) {
-      const double v = fabs((double)A[i + (long)k * N]);
-      if (v > best) {
-        best = v;
-        bi = i;
-      }
+  for (int k0 = 0; k0 < N; k0 += PB) {
+    const int w = min(PB, N - k0), nr = N - k0;
+    // 1. the panel into LDS
+    for (int t = tid; t < w * nr; t += blockDim.x) {
+      const int c = t / nr, r = t - c * nr;
+      pan[c * nr + r] = A[(k0 + r) + (long)(k0 + c) * N];
     }
-    red_v[tid] = best;
-    red_i[tid] = bi;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) {
-        const double a = red_v[tid], b = red_v[tid + s];
-        if (b > a || (b == a && red_i[tid + s] < red_i[tid])) {
-          red_v[tid] = b;
-          red_i[tid] = red_i[tid + s];
+    // 2. unblocked LU of the panel
+    for (int c = 0; c < w; ++c) {
+      double best = -1.0;
+      int bi = c;
+      for (int r = c + tid; r < nr; r += blockDim.x) {
+        const double v = fabs((double)pan[c * nr + r]);
+        if (v > best) {
+          best = v;
+          bi = r;
         }
+      }
+      red_v[tid] = best;
+      red_i[tid] = bi;
+      __syncthreads();
+      for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+          const double a = red_v[tid], b = red_v[tid + s];
+          if (b > a || (b == a && red_i[tid + s] < red_i[tid])) {
+            red_v[tid] = b;
+            red_i[tid] = red_i[tid + s];
+          }
+        }
+        __syncthreads();
+      }
+      const int p = red_i[0];
+      const bool singular = !(red_v[0] > 0.0);
+      __syncthreads();
+      if (tid == 0) {
+        pv[c] = p;
+        P[k0 + c] = k0 + p;
+        if (singular) *flag = 1;
+      }
+      if (p != c && tid < w) {
+        const TB t = pan[tid * nr + c];
+        pan[tid * nr + c] = pan[tid * nr + p];
+        pan[tid * nr + p] = t;
+      }
+      __syncthreads();
+      const TB inv = singular ? TB(0) : TB(1) / pan[c * nr + c];
+      for (int r = c + 1 + tid; r < nr; r += blockDim.x) {
+        const TB l = pan[c * nr + r] * inv;
+        pan[c * nr + r] = l;
+        for (int cc = c + 1; cc < w; ++cc) pan[cc * nr + r] -= l * pan[cc * nr + c];
       }
       __syncthreads();
     }
-    const int p = red_i[0];
-    const bool singular = !(red_v[0] > 0.0);
-    __syncthreads();
-    if (tid == 0) {
-      P[k] = p;
-      if (singular) *flag = 1;
+    // 3. the panel back
+    for (int t = tid; t < w * nr; t += blockDim.x) {
+      const int c = t / nr, r = t - c * nr;
+      A[(k0 + r) + (long)(k0 + c) * N] = pan[c * nr + r];
     }
-    if (p != k)
-      for (int j = tid; j < N; j += blockDim.x) {
-        const TB t = A[k + (long)j * N];
-        A[k + (long)j * N] = A[p + (long)j * N];
-        A[p + (long)j * N] = t;
+    // 4. the panel's row swaps on the other columns, in order
+    for (int c = 0; c < w; ++c) {
+      const int p = pv[c];
+      if (p != c)
+        for (int j = tid; j < N; j += blockDim.x) {
+          if (j >= k0 && j < k0 + w) continue;
+          const TB t = A[(k0 + c) + (long)j * N];
+          A[(k0 + c) + (long)j * N] = A[(k0 + p) + (long)j * N];
+          A[(k0 + p) + (long)j * N] = t;
+        }
+      __syncthreads();
+    }
+    if (k0 + w >= N) break;
+    // 5. the panel's rows of the trailing columns: solve with its unit lower triangle
+    for (int j = k0 + w + tid; j < N; j += blockDim.x) {
+      TB u[PB];
+#pragma unroll
+      for (int r = 0; r < PB; ++r) u[r] = r < w ? A[(k0 + r) + (long)j * N] : TB(0);
+#pragma unroll
+      for (int r = 1; r < PB; ++r)
+#pragma unroll
+        for (int t = 0; t < PB; ++t)
+          if (t < r && r < w) u[r] -= pan[t * nr + r] * u[t];
+#pragma unroll
+      for (int r = 0; r < PB; ++r)
+        if (r < w) A[(k0 + r) + (long)j * N] = u[r];
+    }
+    __syncthreads();
+    // 6. trailing update A22 -= L21 U12, a thread per row (multipliers in registers)
+    TB l[PC_ROWS][PB];
+#pragma unroll
+    for (int q = 0; q < PC_ROWS; ++q) {
+      const int r = w + tid + q * (int)blockDim.x;
+#pragma unroll
+      for (int t = 0; t < PB; ++t) l[q][t] = (r < nr && t < w) ? pan[t * nr + r] : TB(0);
+    }
+    for (int j = k0 + w; j < N; ++j) {
+      TB u[PB];
+#pragma unroll
+      for (int t = 0; t < PB; ++t) u[t] = t < w ? A[(k0 + t) + (long)j * N] : TB(0);
+#pragma unroll
+      for (int q = 0; q < PC_ROWS; ++q) {
+        const int r = w + tid + q * (int)blockDim.x;
+        if (r < nr) {
+          TB acc = A[(k0 + r) + (long)j * N];
+#pragma unroll
+          for (int t = 0; t < PB; ++t) acc -= l[q][t] * u[t];
+          A[(k0 + r) + (long)j * N] = acc;
+        }
       }
+    }
     __syncthreads();
-    for (int j = k + 1 + tid; j < N; j += blockDim.x) rowk[j] = A[k + (long)j * N];
+  }
+  // the swaps as one gather: perm[i] = the row of the original vector that
+  // lands in row i after all of them (the swaps replayed on the identity,
+  // serially, in LDS), stored over the swap list
+  __syncthreads();
+  static_assert(sizeof(pan) >= 2 * PC_NMAX * sizeof(int), "the panel buffer holds the permutation");
+  int* perm = reinterpret_cast<int*>(pan);
+  int* sw = perm + PC_NMAX;
+  for (int i = tid; i < N; i += blockDim.x) {
+    perm[i] = i;
+    sw[i] = P[i];
+  }
+  __syncthreads();
+  if (tid == 0)
+    for (int k = 0; k < N; ++k) {
+      const int p = sw[k];
+      if (p != k) {
+        const int t = perm[k];
+        perm[k] = perm[p];
+        perm[p] = t;
+      }
+    }
+  __syncthreads();
+  for (int i = tid; i < N; i += blockDim.x) P[i] = perm[i];
+}
+
+// The inverse of every factored block, in place: from the L\U of P A left
+// by k_pc_lu, first U <- U^{-1} (column blocks of PB from the left: the
+// block's rows above the diagonal are multiplied by the already inverted
+// leading triangle and by minus the inverse of the block's own diagonal
+// triangle, which is then inverted), then X L = U^{-1} is solved for X =
+// (P A)^{-1} (column blocks from the right: the block's part of L is moved to
+// LDS and cleared, the columns to its right are subtracted through it, and the
+// block is solved with its unit lower triangle).  The block then holds
+// (P A)^{-1}, so that A^{-1} x = (P A)^{-1} (P x): the apply gathers x
+// through the permutation left in piv and multiplies.  One 256-thread block
+// per element; a thread owns rows tid + 256 q and holds PB partial sums of
+// each in registers; every loop over a column index reads a whole column
+// (coalesced) per step.
+template <class TB>
+__global__ void __launch_bounds__(256) k_pc_inv(TB* __restrict__ blocks, PcDev pc) {
+  constexpr int PB = PcPanel<TB>::value;
+  __shared__ __align__(16) TB wk[PB * PC_NMAX];  // the column block (above the diagonal, or its part of L), wk[row * PB + c]
+  __shared__ TB dg[PB * PB];       // diagonal triangle of the column block, dg[c * PB + r]
+  const int4 rec = pc.recs[blockIdx.x];
+  const int N = pc_rows(rec.z);
+  TB* A = blocks + pc.boff[blockIdx.x];
+  const int tid = threadIdx.x;
+  // 1. U <- U^{-1}
+  for (int j0 = 0; j0 < N; j0 += PB) {
+    const int jb = min(PB, N - j0);
+    for (int t = tid; t < PB * j0; t += blockDim.x) {
+      const int c = t / j0, r = t - c * j0;
+      wk[r * PB + c] = c < jb ? A[r + (long)(j0 + c) * N] : TB(0);
+    }
+    for (int t = tid; t < PB * PB; t += blockDim.x) {
+      const int c = t / PB, r = t - c * PB;
+      dg[t] = (r < jb && c < jb) ? A[(j0 + r) + (long)(j0 + c) * N] : TB(1);
+    }
     __syncthreads();
-    const TB pivot = A[k + (long)k * N];
-    const TB inv = singular ? TB(0) : TB(1) / pivot;
-    // multipliers and the rank-1 update of the trailing rows, a row per thread
-    for (int i = k + 1 + tid; i < N; i += blockDim.x) {
-      const TB l = A[i + (long)k * N] * inv;
-      A[i + (long)k * N] = l;
-      for (int j = k + 1; j < N; ++j) A[i + (long)j * N] -= l * rowk[j];
+#pragma unroll
+    for (int q = 0; q < PC_ROWS; ++q) {
+      const int base = (tid & ~63) + q * (int)blockDim.x;  // first row of this wave
+      if (base >= j0) break;
+      const int i = tid + q * (int)blockDim.x;
+      TB acc[PB];
+#pragma unroll
+      for (int c = 0; c < PB; ++c) acc[c] = TB(0);
+      for (int k = base; k < j0; ++k) {  // (U^{-1})[i, k] for k >= i, times the old column block
+        const TB u = (i < j0 && k >= i) ? A[i + (long)k * N] : TB(0);
+        const TB* w = wk + k * PB;
+#pragma unroll
+        for (int c = 0; c < PB; ++c) acc[c] += u * w[c];
+      }
+      // X D = -acc with D the block's upper diagonal triangle
+#pragma unroll
+      for (int c = 0; c < PB; ++c) {
+        TB v = -acc[c];
+#pragma unroll
+        for (int k = 0; k < PB; ++k)
+          if (k < c) v -= acc[k] * dg[c * PB + k];
+        acc[c] = v / dg[c * PB + c];
+      }
+      if (i < j0)
+#pragma unroll
+        for (int c = 0; c < PB; ++c)
+          if (c < jb) A[i + (long)(j0 + c) * N] = acc[c];
+    }
+    // the diagonal triangle's inverse, a row per thread
+    if (tid < jb) {
+      const int r = tid;
+      TB row[PB];
+#pragma unroll
+      for (int c = 0; c < PB; ++c) {
+        if (c < r || c >= jb) {
+          row[c] = TB(0);
+        } else if (c == r) {
+          row[c] = TB(1) / dg[c * PB + c];
+        } else {
+          TB v = TB(0);
+#pragma unroll
+          for (int k = 0; k < PB; ++k)
+            if (k >= r && k < c) v += row[k] * dg[c * PB + k];
+          row[c] = -v / dg[c * PB + c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < PB; ++c)
+        if (c >= r && c < jb) A[(j0 + r) + (long)(j0 + c) * N] = row[c];
+    }
+    __syncthreads();
+  }
+  // 2. X L = U^{-1}, column blocks from the right
+  for (int j0 = ((N - 1) / PB) * PB; j0 >= 0; j0 -= PB) {
+    const int jb = min(PB, N - j0), nw = N - j0;
+    for (int t = tid; t < PB * nw; t += blockDim.x) {
+      const int c = t / nw, r = t - c * nw;
+      TB* a = A + (j0 + r) + (long)(j0 + c) * N;
+      if (r > c && c < jb) {
+        wk[r * PB + c] = *a;
+        *a = TB(0);
+      } else {
+        wk[r * PB + c] = TB(0);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PC_ROWS; ++q) {
+      const int i = tid + q * (int)blockDim.x;
+      if (i - (tid & 63) >= N) break;  // the whole wave is past the last row
+      const bool own = i < N;
+      TB acc[PB];
+#pragma unroll
+      for (int c = 0; c < PB; ++c) acc[c] = (own && c < jb) ? A[i + (long)(j0 + c) * N] : TB(0);
+      for (int k = j0 + jb; k < N; ++k) {
+        const TB x = own ? A[i + (long)k * N] : TB(0);
+        const TB* w = wk + (k - j0) * PB;
+#pragma unroll
+        for (int c = 0; c < PB; ++c) acc[c] -= x * w[c];
+      }
+      // X Ld = acc with Ld the unit lower triangle of the block's L part
+#pragma unroll
+      for (int c = PB - 1; c >= 0; --c) {
+        TB v = acc[c];
+#pragma unroll
+        for (int k = 0; k < PB; ++k)
+          if (k > c && k < jb) v -= acc[k] * wk[k * PB + c];
+        acc[c] = v;
+      }
+      if (own)
+#pragma unroll
+        for (int c = 0; c < PB; ++c)
+          if (c < jb) A[i + (long)(j0 + c) * N] = acc[c];
     }
     __syncthreads();
   }
 }
 
-// x_e <- P_e^{-1} x_e for every element, in place (x: the Krylov vector, TV
-// storage; the substitution runs in TB).  *on == 0 leaves x unchanged (one
+// x_e <- A_e^{-1} x_e for every element, in place (x: the Krylov vector, TV
+// storage; the product runs in TB): x is gathered through the permutation
+// (z = P x, in LDS), then multiplied by the stored (P A)^{-1}.  Rows over the
+// threads; blocks of at most 128 rows split the columns over 2 or 4 groups of
+// threads and add the partial sums in LDS.  *on == 0 leaves x unchanged (one
 // captured graph serves the preconditioned and the plain solves); *done != 0
 // returns at once, as every kernel of a captured Arnoldi step.
 template <class TV, class TB>
@@ -135,39 +369,44 @@ __global__ void __launch_bounds__(256) k_pc_apply(TV* __restrict__ x, int nsp, c
                                                  const int* __restrict__ piv, const int* __restrict__ on,
                                                  const int* __restrict__ done) {
   if (!*on || (done && *done)) return;
-  __shared__ TB y[5 * 6 * 6 * 6];
+  __shared__ TB z[PC_NMAX];
+  __shared__ TB part[256];
   const int4 r = pc.recs[blockIdx.x];
   const int N = pc_rows(r.z);
   const TB* A = blocks + pc.boff[blockIdx.x];
   const int* P = piv + pc.poff[blockIdx.x];
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += blockDim.x) y[i] = (TB)x[pc_dof(i, r.z, r.y, nsp)];
+  for (int i = tid; i < N; i += blockDim.x) z[i] = (TB)x[pc_dof(P[i], r.z, r.y, nsp)];
   __syncthreads();
-  if (tid == 0)
-    for (int k = 0; k < N; ++k) {  // the row swaps, in the order of the factorisation
-      const int p = P[k];
-      if (p != k) {
-        const TB t = y[k];
-        y[k] = y[p];
-        y[p] = t;
-      }
+  const int slots = (N + 63) & ~63;  // rows padded to whole waves
+  if (slots <= 128) {
+    const int groups = 256 / slots, g = tid / slots, i = tid - g * slots;
+    const int k0 = g * N / groups, k1 = (g + 1) * N / groups;
+    TB acc = TB(0);
+    if (i < N)
+      for (int k = k0; k < k1; ++k) acc += A[i + (long)k * N] * z[k];
+    part[tid] = acc;
+    __syncthreads();
+    if (g == 0 && i < N) {
+      for (int h = 1; h < groups; ++h) acc += part[h * slots + i];
+      x[pc_dof(i, r.z, r.y, nsp)] = (TV)acc;
     }
-  __syncthreads();
-  // forward: L (unit diagonal), column by column
-  for (int k = 0; k < N - 1; ++k) {
-    const TB yk = y[k];
-    for (int i = k + 1 + tid; i < N; i += blockDim.x) y[i] -= A[i + (long)k * N] * yk;
-    __syncthreads();
+    return;
   }
-  // backward: U, column by column from the last
-  for (int k = N - 1; k >= 0; --k) {
-    if (tid == 0) y[k] /= A[k + (long)k * N];
-    __syncthreads();
-    const TB yk = y[k];
-    for (int i = tid; i < k; i += blockDim.x) y[i] -= A[i + (long)k * N] * yk;
-    __syncthreads();
+  for (int i0 = tid & ~63; i0 < N; i0 += blockDim.x) {
+    const int i = i0 + (tid & 63);
+    if (i >= N) break;
+    TB a0 = TB(0), a1 = TB(0), a2 = TB(0), a3 = TB(0);
+    int k = 0;
+    for (; k + 4 <= N; k += 4) {
+      a0 += A[i + (long)k * N] * z[k];
+      a1 += A[i + (long)(k + 1) * N] * z[k + 1];
+      a2 += A[i + (long)(k + 2) * N] * z[k + 2];
+      a3 += A[i + (long)(k + 3) * N] * z[k + 3];
+    }
+    for (; k < N; ++k) a0 += A[i + (long)k * N] * z[k];
+    x[pc_dof(i, r.z, r.y, nsp)] = (TV)((a0 + a1) + (a2 + a3));
   }
-  for (int i = tid; i < N; i += blockDim.x) x[pc_dof(i, r.z, r.y, nsp)] = (TV)y[i];
 }
 
 }  // namespace frx

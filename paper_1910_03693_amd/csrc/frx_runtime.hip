@@ -695,7 +695,7 @@ void arnoldi_cycle(fr_ctx c, int mode, int m, bool use_graph, hipStream_t s) {
 // ------------------------------------------------ element-Jacobi preconditioner
 // Assembles the blocks sigma I - dR/dq(U)|_ee by coloured exact tangent
 // products (the tangent in the storage precision: float64 duals on U, or
-// float32 duals on a float32 copy of U) and factors them.
+// float32 duals on a float32 copy of U), factors and inverts them.
 void pc_build(fr_ctx c, const double* U, double sigma, hipStream_t s) {
   if (!c->pc_blocks) throw StatusErr{FR_E_INVALID, "no preconditioner storage (fr_reserve with FR_RESERVE_PRECOND_*)"};
   const long n = c->ndof;
@@ -749,6 +749,11 @@ void pc_build(fr_ctx c, const double* U, double sigma, hipStream_t s) {
   else
     hipLaunchKernelGGL((k_pc_lu<float>), dim3(c->M.E), dim3(256), 0, s, (float*)c->pc_blocks, pc_dev(c), c->pc_piv,
                        c->pc_flag);
+  FRX_TRY(hipGetLastError());
+  if (f64)
+    hipLaunchKernelGGL((k_pc_inv<double>), dim3(c->M.E), dim3(256), 0, s, (double*)c->pc_blocks, pc_dev(c));
+  else
+    hipLaunchKernelGGL((k_pc_inv<float>), dim3(c->M.E), dim3(256), 0, s, (float*)c->pc_blocks, pc_dev(c));
   FRX_TRY(hipGetLastError());
   FRX_TRY(hipMemcpyAsync(c->ipin + 16, c->pc_flag, sizeof(int), hipMemcpyDeviceToHost, s));
   FRX_TRY(hipStreamSynchronize(s));

@@ -59,6 +59,38 @@ def test_precond_apply_matches_oracle(frx, small, prec, fused):
     assert err <= (1e-11 if prec == "f64" else 2e-4)
 
 
+@pytest.fixture(scope="module")
+def largest(oracle_mod):
+    """Blocks of the largest orders: one element of p = 5 (N = 1080, the
+    maximum) and one of p = 4 (N = 625, a ragged last panel in both
+    precisions), six of p = 1."""
+    from oracle import precond as PC
+    case = I.case_ns_mixed(2, 2, 2, k=91, lengths=(1.0, 0.7, 0.6), pvals=(1, 4, 5), pw=(6, 1, 1), re=200.0, ma=0.3,
+                           wall=True)
+    assert sorted(set(int(q) for q in case.elem_p)) == [1, 4, 5]
+    orc = oracle_mod.Oracle.from_case(case)
+    J = orc.jacobian(case.U)
+    dofs = PC.element_dofs(I.sp_offsets(case.elem_p), orc.n_sp)
+    return case, J, dofs
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_precond_apply_largest_blocks(frx, largest, prec):
+    from oracle import precond as PC
+    case, J, dofs = largest
+    p = frx.FR_F64 if prec == "f64" else frx.FR_F32
+    ctx = frx.Context.from_case(case, max_restart=4, graphs=_reserve(frx, p), fused=True)
+    U = torch.tensor(case.U, device="cuda")
+    sigma = 60.0
+    ctx.precond_build(U, sigma, p)
+    x = I.random_direction(case.U.size, 4084).reshape(case.U.shape)
+    y = ctx.precond_apply(torch.tensor(x, device="cuda")).cpu().numpy().ravel()
+    ref = PC.apply(PC.element_blocks(J, dofs, sigma), dofs, x.ravel())
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    print(prec, "p = 1, 4, 5: P^-1 x rel err", err)
+    assert err <= (1e-11 if prec == "f64" else 2e-4)
+
+
 @pytest.mark.parametrize("graph", [False, True])
 def test_preconditioned_gmres_fixed_iterations_parity(frx, small, graph):
     from oracle import precond as PC
