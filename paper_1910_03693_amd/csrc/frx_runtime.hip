@@ -926,6 +926,43 @@ int max_items(bool ns, int sk, int st, int code) {
   return k;
 }
 
+// XCD-aware order of a tile table.  Workgroup b of a launch runs on XCD
+// b mod 8 (the dispatcher deals workgroups to the XCDs round-robin), and each
+// XCD has its own L2.  The heavy-first list is cut into runs of one bucket
+// code; every run is split into 8 contiguous chunks, chunk x going to XCD x
+// (the larger chunks to the XCDs with the fewest tiles so far), and the table
+// interleaves the 8 sequences: entry 8 j + x is tile j of XCD x.  Each XCD so
+// walks contiguous pieces of every bucket, heaviest first, and tiles whose
+// face slots share cache lines meet in the same L2.  The sequences are padded
+// to one length with empty tiles (code 0), which the kernels skip.
+constexpr int N_XCD = 8;
+std::vector<int4> xcd_order(const std::vector<int4>& t) {
+  std::vector<std::vector<int4>> seq(N_XCD);
+  size_t i = 0;
+  while (i < t.size()) {
+    size_t j = i;
+    while (j < t.size() && t[j].x == t[i].x) ++j;
+    const size_t m = j - i, q = m / N_XCD, r = m % N_XCD;
+    std::vector<int> ord(N_XCD);
+    for (int x = 0; x < N_XCD; ++x) ord[x] = x;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return seq[a].size() < seq[b].size(); });
+    std::vector<size_t> len(N_XCD, q);
+    for (size_t k = 0; k < r; ++k) ++len[ord[k]];
+    size_t at = i;
+    for (int x = 0; x < N_XCD; ++x) {
+      seq[x].insert(seq[x].end(), t.begin() + at, t.begin() + at + len[x]);
+      at += len[x];
+    }
+    i = j;
+  }
+  size_t L = 0;
+  for (auto& v : seq) L = std::max(L, v.size());
+  std::vector<int4> out(N_XCD * L, make_int4(0, 0, 0, 0));
+  for (int x = 0; x < N_XCD; ++x)
+    for (size_t k = 0; k < seq[x].size(); ++k) out[N_XCD * k + x] = seq[x][k];
+  return out;
+}
+
 // (Re)builds the tile table of one stage of one scalar kind from the chosen
 // items per tile (c->shape), into the table allocated for the worst case.
 void plan_stage(fr_ctx c, int sk, int st) {
@@ -974,11 +1011,15 @@ void plan_stage(fr_ctx c, int sk, int st) {
     if (bx != by) return !bx;
     return x.first > y.first;
   });
-  std::vector<int4> t;
-  for (auto& x : tiles) t.push_back(x.second);
+  std::vector<int4> t_int, t_bnd;
+  for (auto& x : tiles) (x.second.x < 64 ? t_int : t_bnd).push_back(x.second);
+  std::vector<int4> t = xcd_order(t_int);
+  const int nint = (int)t.size();
+  if (!t_bnd.empty()) {
+    const std::vector<int4> tb = xcd_order(t_bnd);
+    t.insert(t.end(), tb.begin(), tb.end());
+  }
   if ((int)t.size() > c->plan_cap[st]) throw StatusErr{FR_E_INVALID, "tile table larger than its allocation"};
-  int nint = 0;
-  for (auto& x : t) nint += x.x < 64 ? 1 : 0;
   if (st == 1) P.n_interior = nint;
   P.count[st] = (int)t.size();
   P.lds[st] = lds;
@@ -1018,8 +1059,10 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
     FRX_TRY(hipMemcpy(M.all_faces, faces.data(), sizeof(int4) * faces.size(), hipMemcpyHostToDevice));
   const bool ns = d->physics == FR_NAVIER_STOKES;
   // tile tables sized for one item per tile, so that any shape fits
-  c->plan_cap[0] = c->plan_cap[2] = std::max(1, E);
-  c->plan_cap[1] = std::max<int>(1, (int)faces.size());
+  // (plus the padding of the XCD order: under 8 per run of one bucket code)
+  const int pad = N_XCD * (2 * (int)(erange.size() + frange.size()) + 2);
+  c->plan_cap[0] = c->plan_cap[2] = std::max(1, E) + pad;
+  c->plan_cap[1] = std::max<int>(1, (int)faces.size()) + pad;
   for (int sk = 0; sk < SK_COUNT; ++sk)
     for (int st = 0; st < 3; ++st) {
       M.plan[sk].tiles[st] = (int4*)c->dalloc(sizeof(int4) * c->plan_cap[st]);
@@ -1071,11 +1114,13 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
       if (bx != by) return !bx;
       return x.first > y.first;
     });
-    std::vector<int4> t;
-    for (auto& x : tiles) t.push_back(x.second);
-    if (st == 1) {
-      V.n_interior = 0;
-      for (auto& x : t) V.n_interior += x.x < 64 ? 1 : 0;
+    std::vector<int4> t_int, t_bnd;
+    for (auto& x : tiles) (x.second.x < 64 ? t_int : t_bnd).push_back(x.second);
+    std::vector<int4> t = xcd_order(t_int);
+    if (st == 1) V.n_interior = (int)t.size();
+    if (!t_bnd.empty()) {
+      const std::vector<int4> tb = xcd_order(t_bnd);
+      t.insert(t.end(), tb.begin(), tb.end());
     }
     V.count[st] = (int)t.size();
     V.lds[st] = lds;
@@ -1152,11 +1197,18 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
     for (int e = 0; e < E; ++e) {
       const int n = d->elem_p[e] + 1;
       sp[e] = (int)nsp;
-      fp[e] = (int)nfp;
       C->sp_off_h[e] = nsp;
       nsp += (long)n * n * n;
-      nfp += 6L * n * n;
     }
+    // face slots (internal) in the order of the fused element list: degree
+    // buckets from the highest, mesh order inside a bucket, so that the
+    // elements of a tile, and consecutive tiles, own contiguous slots
+    for (int n = NMAX; n >= 2; --n)
+      for (int e = 0; e < E; ++e)
+        if (d->elem_p[e] + 1 == n) {
+          fp[e] = (int)nfp;
+          nfp += 6L * n * n;
+        }
     C->sp_off_h[E] = nsp;
     C->fp_off_h = fp;
     // (30 nfp < 2^31 also keeps face-slot offsets below 2^28, as the packed
