@@ -70,23 +70,27 @@ __global__ void __launch_bounds__(256) k_pc_extract(const TV* __restrict__ Jv, i
 // applied to the other columns, the panel's rows of the trailing columns
 // solved with its unit lower triangle, and the trailing matrix updated once
 // per panel (each thread holds the panel's multipliers of its rows in
-// registers).  A zero pivot column (a singular block) sets *flag.
+// registers, U12 staged in LDS).  A zero pivot column (a singular block)
+// sets *flag.  Launched per degree bucket: ids lists the bucket's elements
+// (null: element = block index) and the dynamic LDS holds PB N scalars.
 constexpr int PC_NMAX = 5 * 6 * 6 * 6;            // largest block order (p = 5)
 constexpr int PC_ROWS = (PC_NMAX + 255) / 256;    // trailing rows per thread
 template <class TB> struct PcPanel { static constexpr int value = sizeof(TB) == 8 ? 8 : 16; };
 
 template <class TB>
-__global__ void __launch_bounds__(256) k_pc_lu(TB* __restrict__ blocks, PcDev pc, int* __restrict__ piv,
-                                              int* __restrict__ flag) {
+__global__ void __launch_bounds__(256) k_pc_lu(TB* __restrict__ blocks, PcDev pc, const int* __restrict__ ids,
+                                              int* __restrict__ piv, int* __restrict__ flag) {
   constexpr int PB = PcPanel<TB>::value;
-  __shared__ TB pan[PB * PC_NMAX];  // pan[c * nr + (r - k0)]: panel column c, rows k0..N-1
+  extern __shared__ __align__(16) unsigned char pc_lds[];
+  TB* pan = reinterpret_cast<TB*>(pc_lds);  // [PB N]: pan[c * nr + (r - k0)], panel column c, rows k0..N-1
   __shared__ double red_v[256];
   __shared__ int red_i[256];
   __shared__ int pv[PB];
-  const int4 rec = pc.recs[blockIdx.x];
+  const int el = ids ? ids[blockIdx.x] : (int)blockIdx.x;
+  const int4 rec = pc.recs[el];
   const int N = pc_rows(rec.z);
-  TB* A = blocks + pc.boff[blockIdx.x];
-  int* P = piv + pc.poff[blockIdx.x];
+  TB* A = blocks + pc.boff[el];
+  int* P = piv + pc.poff[el];
   const int tid = threadIdx.x;
   for (int k0 = 0; k0 < N; k0 += PB) {
     const int w = min(PB, N - k0), nr = N - k0;
@@ -183,19 +187,41 @@ __global__ void __launch_bounds__(256) k_pc_lu(TB* __restrict__ blocks, PcDev pc
 #pragma unroll
       for (int t = 0; t < PB; ++t) l[q][t] = (r < nr && t < w) ? pan[t * nr + r] : TB(0);
     }
-    for (int j = k0 + w; j < N; ++j) {
-      TB u[PB];
-#pragma unroll
-      for (int t = 0; t < PB; ++t) u[t] = t < w ? A[(k0 + t) + (long)j * N] : TB(0);
+    __syncthreads();  // the panel is no longer read: U12 goes over it
+    const int j0 = k0 + w, nt = N - j0;
+    TB* u12 = pan;  // u12[(j - j0) PB + t] = U(k0 + t, j)
+    for (int x = tid; x < nt * PB; x += blockDim.x) {
+      const int jj = x / PB, t = x - jj * PB;
+      u12[x] = t < w ? A[(k0 + t) + (long)(j0 + jj) * N] : TB(0);
+    }
+    __syncthreads();
+    // four columns per step: 4 PC_ROWS independent loads per thread in flight
+    for (int jj = 0; jj < nt; jj += 4) {
+      TB a4[PC_ROWS][4];
 #pragma unroll
       for (int q = 0; q < PC_ROWS; ++q) {
         const int r = w + tid + q * (int)blockDim.x;
-        if (r < nr) {
-          TB acc = A[(k0 + r) + (long)j * N];
 #pragma unroll
-          for (int t = 0; t < PB; ++t) acc -= l[q][t] * u[t];
-          A[(k0 + r) + (long)j * N] = acc;
-        }
+        for (int c = 0; c < 4; ++c)
+          a4[q][c] = (r < nr && jj + c < nt) ? A[(k0 + r) + (long)(j0 + jj + c) * N] : TB(0);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (jj + c >= nt) break;
+        TB u[PB];
+#pragma unroll
+        for (int t = 0; t < PB; ++t) u[t] = u12[(jj + c) * PB + t];
+#pragma unroll
+        for (int q = 0; q < PC_ROWS; ++q)
+#pragma unroll
+          for (int t = 0; t < PB; ++t) a4[q][c] -= l[q][t] * u[t];
+      }
+#pragma unroll
+      for (int q = 0; q < PC_ROWS; ++q) {
+        const int r = w + tid + q * (int)blockDim.x;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (r < nr && jj + c < nt) A[(k0 + r) + (long)(j0 + jj + c) * N] = a4[q][c];
       }
     }
     __syncthreads();
@@ -204,9 +230,9 @@ __global__ void __launch_bounds__(256) k_pc_lu(TB* __restrict__ blocks, PcDev pc
   // lands in row i after all of them (the swaps replayed on the identity,
   // serially, in LDS), stored over the swap list
   __syncthreads();
-  static_assert(sizeof(pan) >= 2 * PC_NMAX * sizeof(int), "the panel buffer holds the permutation");
+  static_assert(PB * sizeof(TB) >= 2 * sizeof(int), "the panel buffer holds the permutation");
   int* perm = reinterpret_cast<int*>(pan);
-  int* sw = perm + PC_NMAX;
+  int* sw = perm + N;
   for (int i = tid; i < N; i += blockDim.x) {
     perm[i] = i;
     sw[i] = P[i];
@@ -237,15 +263,18 @@ __global__ void __launch_bounds__(256) k_pc_lu(TB* __restrict__ blocks, PcDev pc
 // through the permutation left in piv and multiplies.  One 256-thread block
 // per element; a thread owns rows tid + 256 q and holds PB partial sums of
 // each in registers; every loop over a column index reads a whole column
-// (coalesced) per step.
+// (coalesced) per step.  Launched per degree bucket like k_pc_lu (ids, PB N
+// scalars of dynamic LDS).
 template <class TB>
-__global__ void __launch_bounds__(256) k_pc_inv(TB* __restrict__ blocks, PcDev pc) {
+__global__ void __launch_bounds__(256) k_pc_inv(TB* __restrict__ blocks, PcDev pc, const int* __restrict__ ids) {
   constexpr int PB = PcPanel<TB>::value;
-  __shared__ __align__(16) TB wk[PB * PC_NMAX];  // the column block (above the diagonal, or its part of L), wk[row * PB + c]
-  __shared__ TB dg[PB * PB];       // diagonal triangle of the column block, dg[c * PB + r]
-  const int4 rec = pc.recs[blockIdx.x];
+  extern __shared__ __align__(16) unsigned char pc_lds[];
+  TB* wk = reinterpret_cast<TB*>(pc_lds);  // [PB N] the column block (above the diagonal, or its part of L), wk[row * PB + c]
+  __shared__ TB dg[PB * PB];               // diagonal triangle of the column block, dg[c * PB + r]
+  const int el = ids ? ids[blockIdx.x] : (int)blockIdx.x;
+  const int4 rec = pc.recs[el];
   const int N = pc_rows(rec.z);
-  TB* A = blocks + pc.boff[blockIdx.x];
+  TB* A = blocks + pc.boff[el];
   const int tid = threadIdx.x;
   // 1. U <- U^{-1}
   for (int j0 = 0; j0 < N; j0 += PB) {
@@ -267,6 +296,7 @@ __global__ void __launch_bounds__(256) k_pc_inv(TB* __restrict__ blocks, PcDev p
       TB acc[PB];
 #pragma unroll
       for (int c = 0; c < PB; ++c) acc[c] = TB(0);
+#pragma unroll 4
       for (int k = base; k < j0; ++k) {  // (U^{-1})[i, k] for k >= i, times the old column block
         const TB u = (i < j0 && k >= i) ? A[i + (long)k * N] : TB(0);
         const TB* w = wk + k * PB;
@@ -333,6 +363,7 @@ __global__ void __launch_bounds__(256) k_pc_inv(TB* __restrict__ blocks, PcDev p
       TB acc[PB];
 #pragma unroll
       for (int c = 0; c < PB; ++c) acc[c] = (own && c < jb) ? A[i + (long)(j0 + c) * N] : TB(0);
+#pragma unroll 4
       for (int k = j0 + jb; k < N; ++k) {
         const TB x = own ? A[i + (long)k * N] : TB(0);
         const TB* w = wk + (k - j0) * PB;

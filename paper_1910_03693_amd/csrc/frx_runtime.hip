@@ -743,18 +743,26 @@ void pc_build(fr_ctx c, const double* U, double sigma, hipStream_t s) {
     }
   }
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->pc_flag, 0);
-  if (f64)
-    hipLaunchKernelGGL((k_pc_lu<double>), dim3(c->M.E), dim3(256), 0, s, (double*)c->pc_blocks, pc_dev(c),
-                       c->pc_piv, c->pc_flag);
-  else
-    hipLaunchKernelGGL((k_pc_lu<float>), dim3(c->M.E), dim3(256), 0, s, (float*)c->pc_blocks, pc_dev(c), c->pc_piv,
-                       c->pc_flag);
-  FRX_TRY(hipGetLastError());
-  if (f64)
-    hipLaunchKernelGGL((k_pc_inv<double>), dim3(c->M.E), dim3(256), 0, s, (double*)c->pc_blocks, pc_dev(c));
-  else
-    hipLaunchKernelGGL((k_pc_inv<float>), dim3(c->M.E), dim3(256), 0, s, (float*)c->pc_blocks, pc_dev(c));
-  FRX_TRY(hipGetLastError());
+  // factorisation and inverse per degree bucket, with LDS for that order
+  for (const ElemBucket& eb : c->M.eb) {
+    if (!eb.count) continue;
+    const int N = 5 * eb.n * eb.n * eb.n;
+    const size_t lds = (size_t)(f64 ? PcPanel<double>::value * 8 : PcPanel<float>::value * 4) * N;
+    if (f64) {
+      hipLaunchKernelGGL((k_pc_lu<double>), dim3(eb.count), dim3(256), lds, s, (double*)c->pc_blocks, pc_dev(c),
+                         (const int*)eb.elems, c->pc_piv, c->pc_flag);
+      FRX_TRY(hipGetLastError());
+      hipLaunchKernelGGL((k_pc_inv<double>), dim3(eb.count), dim3(256), lds, s, (double*)c->pc_blocks, pc_dev(c),
+                         (const int*)eb.elems);
+    } else {
+      hipLaunchKernelGGL((k_pc_lu<float>), dim3(eb.count), dim3(256), lds, s, (float*)c->pc_blocks, pc_dev(c),
+                         (const int*)eb.elems, c->pc_piv, c->pc_flag);
+      FRX_TRY(hipGetLastError());
+      hipLaunchKernelGGL((k_pc_inv<float>), dim3(eb.count), dim3(256), lds, s, (float*)c->pc_blocks, pc_dev(c),
+                         (const int*)eb.elems);
+    }
+    FRX_TRY(hipGetLastError());
+  }
   FRX_TRY(hipMemcpyAsync(c->ipin + 16, c->pc_flag, sizeof(int), hipMemcpyDeviceToHost, s));
   FRX_TRY(hipStreamSynchronize(s));
   c->pc_built = c->ipin[16] == 0;
