@@ -146,9 +146,10 @@ def measured_traffic(name):
         return None
 
 
-# sources that define the residual and tangent kernels: a counter summary is
-# used only while they hash to the value recorded in it
-KERNEL_SOURCES = ("frx_device.hpp", "frx_residual.hpp", "frx_launch.hpp", "frx_k_dual64.hip")
+# sources that define the residual and tangent kernels and their launch plans
+# (tile tables, face-slot order): a counter summary is used only while they
+# hash to the value recorded in it
+KERNEL_SOURCES = ("frx_device.hpp", "frx_residual.hpp", "frx_launch.hpp", "frx_k_dual64.hip", "frx_runtime.hip")
 TRAFFIC_PROFILE = "residual_jvp_dual64_ns_128x128x8_hbm_traffic.md"
 
 

@@ -154,3 +154,34 @@ def test_box_128x128x8_mixed_stage_against_float64_stage(frx):
     # both solutions satisfy the same stage equation to the PTC tolerance;
     # they agree far below the change the stage makes
     assert d <= 1e-6 and d <= 1e-3 * change
+
+
+def test_street_64x64x8_full_step_mixed_against_float64(frx, street_degrees):
+    """One full ESDIRK2 step (all three stages) of the vortex street on its
+    indicator degree field at the paper's settings (dt 0.05, dtau from dt/10
+    up to dt, PTC to 1e-4, GMRES(30) to 1e-1): the mixed form (float32 exact
+    tangent and basis, captured graphs) against the float64 exact form.  As
+    for the 128x128x8 stage, the reference is the float64 GPU path, whose
+    operators are checked against the oracle above; both forms take the same
+    pseudo-time path, so they agree to well below the GMRES tolerance's effect
+    on the step."""
+    case = I.case_street(elem_p=street_degrees[0])
+    ctx = frx.Context.from_case(case, max_restart=30, graphs=frx.FR_GRAPHS_F64_EXACT | frx.FR_GRAPHS_F32_EXACT)
+    ctx.set_launch(True)
+    U = torch.tensor(case.U, device="cuda")
+    dt = 0.05
+    kw = dict(dtau_init=dt / 10, dtau_max=dt, tol_pseudo=1e-4, max_ptc_iter=60)
+    out = {}
+    for name, prec in (("float64", frx.FR_F64), ("mixed", frx.FR_F32)):
+        Us = U.clone()
+        st = ctx.esdirk_step(Us, dt, gmres=dict(restart=30, max_iter=100, tol=1e-1, precision=prec, use_graph=True),
+                             **kw)
+        print("64x64x8 street step", name, st, flush=True)
+        assert st["status"] == frx.FR_OK and st["stages"] == 2
+        out[name] = (Us, st)
+    d = (torch.linalg.norm(out["mixed"][0] - out["float64"][0]) / torch.linalg.norm(out["float64"][0])).item()
+    change = (torch.linalg.norm(out["float64"][0] - U) / torch.linalg.norm(U)).item()
+    print(f"mixed vs float64 step: {d:.3e} relative (the step changes U by {change:.3e})")
+    assert out["mixed"][1]["ptc_iterations"] == out["float64"][1]["ptc_iterations"]
+    assert d <= 1e-6 and d <= 1e-3 * change
+    ctx.close()
