@@ -22,7 +22,9 @@ implicit ESDIRK2 stage (GMRES(30) to 1e-6, PTC to 1e-4) in the mixed form
 (float32 exact tangent and basis) is compared with the same stage in float64:
 the oracle cannot solve this stage in a test's time, so the reference is the
 float64 GPU path, whose operators are the ones checked against the oracle
-above.
+above.  The same holds for one full ESDIRK2 step of the vortex street on its
+indicator degree field (measured: 1.2e-8 relative, against a change of U by
+4.4e-3 over the step).
 """
 import numpy as np
 import pytest
