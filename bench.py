@@ -189,6 +189,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB five times (reference for the HBM byte counters)")
+    ap.add_argument("--forms", default=None,
+                    help="c3 / c5 studies: comma-separated subset of the step forms (f64_exact_graph, "
+                         "mixed_f32_exact_graph, mixed_f32_exact_graph_cgs1, plain_f64_fd_scaled, plain_f64_fd)")
     ap.add_argument("--study", choices=("c3", "c5", "c3adapt", "g2", "precond"), default=None,
                     help="instead of the headline: implicit steps on the 64x64x8 vortex street (c3) or the "
                          "128x128x8 box (c5), the adaptive vortex-street loop (c3adapt), or the p / p_max "
@@ -206,7 +209,7 @@ def main():
         elif args.study == "precond":
             res = precond_study()
         else:
-            res = step_study(args.study)
+            res = step_study(args.study, args.forms.split(",") if args.forms else None)
         print(json.dumps(res), flush=True)
         return
 
@@ -361,9 +364,10 @@ def _timed_step(ctx, U, dt, torch, **kw):
 def implicit_stage_c5(ctx, case, U, frx, torch):
     """The first implicit stage of an ESDIRK2 step (dt 0.002; PTC from
     dtau 2e-4 up to 4e-3, to 1e-4; GMRES(30) to 1e-6 relative, at most 300
-    products) in three forms: mixed (float32 exact tangent and basis, graph),
-    float64 exact (graph) and plain (float64 finite differences with the step
-    scaled to the state, per-bucket launches, no graph).  The plain form with
+    products) in the forms: mixed (float32 exact tangent and basis, graph;
+    Gram-Schmidt twice, and once as in PETSc's GMRES), float64 exact (graph)
+    and plain (float64 finite differences with the step scaled to the state,
+    per-bucket launches, no graph).  The plain form with
     the paper's absolute step (1e-6 along the unit direction, 29.6 M
     components) stagnates here: see the c5 study."""
     dt = 0.002
@@ -372,6 +376,8 @@ def implicit_stage_c5(ctx, case, U, frx, torch):
     res = {"dt": dt, "settings": {**common, **g}}
     outs = {}
     for name, gv, fused in (("mixed_f32_exact_graph", dict(g, precision=frx.FR_F32, use_graph=True), True),
+                            ("mixed_f32_exact_graph_cgs1", dict(g, precision=frx.FR_F32, use_graph=True,
+                                                                orthog=frx.FR_ORTHO_CGS), True),
                             ("f64_exact_graph", dict(g, precision=frx.FR_F64, use_graph=True), True),
                             ("plain_f64_fd_scaled", dict(g, jv_mode=frx.FR_JV_FD_SCALED, precision=frx.FR_F64),
                              False)):
@@ -382,10 +388,12 @@ def implicit_stage_c5(ctx, case, U, frx, torch):
         print(f"[bench] 128x128x8 stage {name}: {ms:.1f} ms {st}", file=sys.stderr, flush=True)
     ctx.set_launch(True)
     ref = outs["f64_exact_graph"]
-    for name in ("mixed_f32_exact_graph", "plain_f64_fd_scaled"):
+    for name in ("mixed_f32_exact_graph", "mixed_f32_exact_graph_cgs1", "plain_f64_fd_scaled"):
         res[f"rel_diff_{name}_vs_f64_exact"] = (outs[name] - ref).norm().item() / ref.norm().item()
     res["rel_change_of_stage"] = (ref - U).norm().item() / U.norm().item()
     res["speedup_mixed_vs_plain"] = round(res["plain_f64_fd_scaled"]["ms"] / res["mixed_f32_exact_graph"]["ms"], 3)
+    res["speedup_mixed_cgs1_vs_plain"] = round(res["plain_f64_fd_scaled"]["ms"] /
+                                               res["mixed_f32_exact_graph_cgs1"]["ms"], 3)
     return res
 
 
@@ -539,7 +547,7 @@ def adaptive_study(steps=4):
     return out
 
 
-def step_study(which):
+def step_study(which, forms=None):
     """Implicit steps on a larger workload (not the headline): c3 = 64x64x8
     vortex street with the degree field chosen by the spectral-decay indicator
     (one full ESDIRK2 step, GMRES(30) to 1e-1); c5 = the 128x128x8 box at
@@ -570,8 +578,12 @@ def step_study(which):
     out["settings"] = {**common, **g}
     variants = (("f64_exact_graph", dict(g, precision=frx.FR_F64, use_graph=True), True),
                 ("mixed_f32_exact_graph", dict(g, precision=frx.FR_F32, use_graph=True), True),
+                ("mixed_f32_exact_graph_cgs1", dict(g, precision=frx.FR_F32, use_graph=True,
+                                                    orthog=frx.FR_ORTHO_CGS), True),
                 ("plain_f64_fd_scaled", dict(g, jv_mode=frx.FR_JV_FD_SCALED, precision=frx.FR_F64), False),
                 ("plain_f64_fd", dict(g, jv_mode=frx.FR_JV_FD, precision=frx.FR_F64), False))
+    if forms:
+        variants = tuple(v for v in variants if v[0] in forms)
     outs = {}
     for name, gv, fused in variants:
         ctx.set_launch(fused)
@@ -579,11 +591,13 @@ def step_study(which):
         outs[name] = Uw
         out[name] = {"ms": round(ms, 1), **st, "launch": "fused" if fused else "per-bucket"}
         print(f"[bench] {which} {name}: {ms:.1f} ms {st}", file=sys.stderr, flush=True)
-    ref = outs["f64_exact_graph"]
-    for name in ("mixed_f32_exact_graph", "plain_f64_fd_scaled", "plain_f64_fd"):
-        out[f"rel_diff_{name}_vs_f64_exact"] = (outs[name] - ref).norm().item() / ref.norm().item()
-    out["speedup_mixed_vs_plain_scaled"] = round(out["plain_f64_fd_scaled"]["ms"] /
-                                                 out["mixed_f32_exact_graph"]["ms"], 3)
+    ref = outs.get("f64_exact_graph")
+    for name in ("mixed_f32_exact_graph", "mixed_f32_exact_graph_cgs1", "plain_f64_fd_scaled", "plain_f64_fd"):
+        if ref is not None and name in outs:
+            out[f"rel_diff_{name}_vs_f64_exact"] = (outs[name] - ref).norm().item() / ref.norm().item()
+    if "plain_f64_fd_scaled" in out and "mixed_f32_exact_graph" in out:
+        out["speedup_mixed_vs_plain_scaled"] = round(out["plain_f64_fd_scaled"]["ms"] /
+                                                     out["mixed_f32_exact_graph"]["ms"], 3)
     return out
 
 

@@ -105,7 +105,13 @@ typedef struct {
                          preconditioner (section 2.3) built in this precision;
                          the stop test and rel_res are then those of the
                          preconditioned system; 0: none */
+  int32_t orthog;     /* Gram-Schmidt of the Arnoldi step: FR_ORTHO_CGS2 (0,
+                         classical, twice) or FR_ORTHO_CGS (classical, once:
+                         the default of the PETSc GMRES the paper uses; needs
+                         restart <= 32) */
 } fr_gmres_opts;
+
+enum { FR_ORTHO_CGS2 = 0, FR_ORTHO_CGS = 1 };
 
 typedef struct {
   int32_t iterations;  /* operator products */

@@ -19,7 +19,7 @@ constexpr int NMAX = 6;  // n = p + 1 <= 6 (p <= 5)
 // SIMDs, so the target is also the number of blocks per CU: the kernel gets
 // the register budget of that many waves (amdgpu_waves_per_eu) and the fused
 // plan keeps every tile's LDS within 160 KB / waves (64 KB at most).
-constexpr int FRX_STAGE_WAVES[3][3] = {{4, 4, 3}, {4, 2, 3}, {4, 4, 3}};
+constexpr int FRX_STAGE_WAVES[3][3] = {{4, 4, 3}, {4, 2, 3}, {4, 4, 4}};
 
 // ------------------------------------------------------------------ scalars
 // Forward-mode dual number: value and directional derivative.  The residual

@@ -25,7 +25,7 @@ struct GmresDev {
   double* hbuf;   // [m+1] current multi-dot result
   double* sc;     // scalars: 0 beta, 1 ||F||, 2 tol, 3 residual estimate, 4 1/h_{j+1,j}, 5 sigma
   int* ist;       // ints: 0 done flag, 1 iterations of this cycle, 2 total iterations, 3 iteration budget,
-                  // 4 length of this cycle (<= m)
+                  // 4 length of this cycle (<= m), 5 preconditioner on, 6 one-pass Gram-Schmidt
   int m;          // leading dimension of H: the largest cycle the workspace holds
   int nblk;
 };
@@ -200,6 +200,8 @@ __global__ void k_givens(GmresDev G, int j, const double* __restrict__ h1, const
 //  MODE 1: w -= sum_i h_i V_i (stored as TV); sums V_i . w   (first pass
 //          update fused with the second pass dots)
 //  MODE 2: out = w - sum_i h_i V_i (stored as TV); sum |out|^2
+// With *one != 0 (one-pass classical Gram-Schmidt) MODE 1 does nothing and
+// MODE 2 subtracts h1 (the first pass coefficients, hx) instead of h.
 // Each block writes its partial sums to part[i * nblk + blockIdx.x];
 // k_gs_reduce adds them up in a fixed order.  (A last-block reduction inside
 // k_gs would need a device-scope fence per block, which costs an L2
@@ -207,14 +209,16 @@ __global__ void k_givens(GmresDev G, int j, const double* __restrict__ h1, const
 template <class TV, int NV, int MODE>
 __global__ void __launch_bounds__(KR_THREADS) k_gs(const TV* __restrict__ V, long ldv, const double* __restrict__ h,
                                                   TV* w, TV* __restrict__ out, long n, double* __restrict__ part,
-                                                  const int* __restrict__ done) {
+                                                  const int* __restrict__ done, const double* __restrict__ hx,
+                                                  const int* __restrict__ one) {
   if (done && *done) return;
+  if (MODE == 1 && one && *one) return;
   constexpr int NS = MODE == 2 ? 1 : NV;
   __shared__ double sh[KR_THREADS / 64][NS];
   __shared__ double hs[NV];
   const int nblk = gridDim.x;
   if (MODE != 0) {
-    if (threadIdx.x < NV) hs[threadIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < NV) hs[threadIdx.x] = (MODE == 2 && one && *one) ? hx[threadIdx.x] : h[threadIdx.x];
     __syncthreads();
   }
   double s[NS];
@@ -286,8 +290,13 @@ __global__ void __launch_bounds__(KR_THREADS) k_gs_reduce(const double* __restri
                                                          double* __restrict__ hout, int givens, GmresDev G, int j,
                                                          const double* __restrict__ h1,
                                                          const double* __restrict__ h2,
-                                                         const int* __restrict__ done) {
+                                                         const int* __restrict__ done,
+                                                         const int* __restrict__ zero) {
   if (done && *done) return;
+  if (zero && *zero) {  // the second pass skipped: its coefficients are 0
+    if (threadIdx.x == 0) hout[blockIdx.x] = 0.0;
+    return;
+  }
   __shared__ double sh[KR_THREADS / 64];
   double r = 0.0;
   for (int b = threadIdx.x; b < nblk; b += KR_THREADS) r += part[(long)blockIdx.x * nblk + b];

@@ -548,23 +548,26 @@ void gs_fused_n(fr_ctx c, const GmresDev& G, int j, double* h1, double* h2, doub
   // of its rows in registers and gets what stays resident of it at once
   constexpr int nb0 = 2048, nb1 = NV <= 8 ? 2048 : (NV <= 16 ? 1024 : 512);
   static_assert(NV * nb0 <= GS_PARTS && NV * nb1 <= GS_PARTS, "partials");
+  // (ist[6] set: one-pass classical Gram-Schmidt; the second pass is skipped
+  // and its coefficients read as 0)
+  const int* one = c->ist + 6;
   hipLaunchKernelGGL((k_gs<TV, NV, 0>), dim3(nb0), dim3(KR_THREADS), 0, s, V, n, (const double*)nullptr, w,
-                     (TV*)nullptr, n, c->part, done);
+                     (TV*)nullptr, n, c->part, done, (const double*)nullptr, (const int*)nullptr);
   FRX_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_gs_reduce, dim3(NV), dim3(KR_THREADS), 0, s, (const double*)c->part, nb0, h1, 0, G, j,
-                     (const double*)nullptr, (const double*)nullptr, done);
+                     (const double*)nullptr, (const double*)nullptr, done, (const int*)nullptr);
   FRX_TRY(hipGetLastError());
   hipLaunchKernelGGL((k_gs<TV, NV, 1>), dim3(nb1), dim3(KR_THREADS), 0, s, V, n, (const double*)h1, w,
-                     (TV*)nullptr, n, c->part, done);
+                     (TV*)nullptr, n, c->part, done, (const double*)nullptr, one);
   FRX_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_gs_reduce, dim3(NV), dim3(KR_THREADS), 0, s, (const double*)c->part, nb1, h2, 0, G, j,
-                     (const double*)nullptr, (const double*)nullptr, done);
+                     (const double*)nullptr, (const double*)nullptr, done, one);
   FRX_TRY(hipGetLastError());
   hipLaunchKernelGGL((k_gs<TV, NV, 2>), dim3(nb0), dim3(KR_THREADS), 0, s, V, n, (const double*)h2, w, vnext, n,
-                     c->part, done);
+                     c->part, done, (const double*)h1, one);
   FRX_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_gs_reduce, dim3(1), dim3(KR_THREADS), 0, s, (const double*)c->part, nb0, nr, 1, G, j,
-                     (const double*)h1, (const double*)h2, done);
+                     (const double*)h1, (const double*)h2, done, (const int*)nullptr);
   FRX_TRY(hipGetLastError());
 }
 
@@ -579,7 +582,8 @@ void gs_fused(fr_ctx c, const GmresDev& G, int j, double* h1, double* h2, double
   }
 }
 
-// One Arnoldi iteration j with CGS2 (all kernels skip once *done is set).
+// One Arnoldi iteration j with CGS2, or one-pass CGS when ist[6] is set (all
+// kernels skip once *done is set).
 template <class TV>
 void arnoldi_step(fr_ctx c, int mode, int j, hipStream_t s) {
   GmresDev G = gdev(c);
@@ -788,6 +792,8 @@ fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats*
   // P^-1 F and the residual norms of the preconditioned system
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->ist + 5, o.precond ? 1 : 0);
   FRX_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->ist + 6, o.orthog == FR_ORTHO_CGS ? 1 : 0);
+  FRX_TRY(hipGetLastError());
   if (o.precond) {
     FRX_TRY(hipMemcpyAsync(c->rb, c->Fb, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     pc_apply<double>(c, c->rb, nullptr, s);
@@ -860,8 +866,10 @@ fr_status gmres_solve(fr_ctx c, const double* U, double shift, const double* F, 
                       fr_gmres_stats* st, hipStream_t s, const double* R0_known, double nF_known = -1.0) {
   if (o.restart < 1 || o.max_iter < 1 || !(o.tol >= 0.0) || !(o.fd_eps >= 0.0) ||
       (o.jv_mode != FR_JV_EXACT && o.jv_mode != FR_JV_FD && o.jv_mode != FR_JV_FD_SCALED) ||
-      (o.precision != FR_F64 && o.precision != FR_F32))
+      (o.precision != FR_F64 && o.precision != FR_F32) || (o.orthog != FR_ORTHO_CGS2 && o.orthog != FR_ORTHO_CGS))
     throw StatusErr{FR_E_INVALID, "gmres options out of range"};
+  if (o.orthog == FR_ORTHO_CGS && o.restart > 32)
+    throw StatusErr{FR_E_INVALID, "one-pass Gram-Schmidt is built for restart <= 32"};
   if (o.precision == FR_F32 && o.jv_mode != FR_JV_EXACT)
     throw StatusErr{FR_E_UNSUPPORTED, "float32 GMRES needs the exact tangent"};
   if (o.restart > c->m_alloc)

@@ -27,6 +27,7 @@ FR_LAUNCH_PER_BUCKET, FR_LAUNCH_FUSED = 0, 1
 FR_LAUNCH_FACES_TWO_PASS, FR_LAUNCH_FACES_ONE_PASS = 4, 8
 FR_ESDIRK2, FR_ESDIRK4 = 0, 1
 FR_ETA_MAX_ALL, FR_ETA_MAX_SAME_DEGREE = 0, 1
+FR_ORTHO_CGS2, FR_ORTHO_CGS = 0, 1
 STATUS_NAMES = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_NOMEM", -3: "FR_E_HIP", -4: "FR_E_NOTCONVERGED",
                 -5: "FR_E_NONPHYSICAL", -6: "FR_E_UNSUPPORTED"}
 EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_reserve", "fr_residual", "fr_residual_noalloc", "fr_residual_jvp", "fr_jvp", "fr_vjp", "gmres_stage_solve",
@@ -50,7 +51,7 @@ class fr_mesh_desc(C.Structure):
 class fr_gmres_opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double), ("jv_mode", C.c_int32),
                 ("precision", C.c_int32), ("fd_eps", C.c_double), ("use_graph", C.c_int32),
-                ("precond", C.c_int32)]
+                ("precond", C.c_int32), ("orthog", C.c_int32)]
 
 
 class fr_gmres_stats(C.Structure):
@@ -223,10 +224,10 @@ def fr_vjp(h, U, w, JTw, stream=None):
 
 
 def gmres_opts(restart=30, max_iter=100, tol=1e-1, jv_mode=FR_JV_EXACT, precision=FR_F64, fd_eps=1e-6,
-               use_graph=False, precond=False):
+               use_graph=False, precond=False, orthog=FR_ORTHO_CGS2):
     o = fr_gmres_opts()
-    o.restart, o.max_iter, o.tol, o.jv_mode, o.precision, o.fd_eps, o.use_graph, o.precond = (
-        restart, max_iter, tol, jv_mode, precision, fd_eps, int(bool(use_graph)), int(bool(precond)))
+    o.restart, o.max_iter, o.tol, o.jv_mode, o.precision, o.fd_eps, o.use_graph, o.precond, o.orthog = (
+        restart, max_iter, tol, jv_mode, precision, fd_eps, int(bool(use_graph)), int(bool(precond)), int(orthog))
     return o
 
 

@@ -336,6 +336,41 @@ def test_gmres_fixed_iterations_parity(frx, oracle_mod):
         assert abs(sg["rel_res"] - so["rel_res"]) <= 1e-9 * max(so["rel_res"], 1e-300) + 1e-12
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_gmres_one_pass_gram_schmidt_parity(frx, oracle_mod, prec):
+    """One-pass classical Gram-Schmidt (FR_ORTHO_CGS, the PETSc default) spans
+    the same Krylov space as the oracle's modified Gram-Schmidt: 10 fixed
+    iterations of GMRES(30) (the fused Gram-Schmidt kernels up to 11 basis
+    vectors) agree with the oracle, with and without the captured graphs, and
+    match the CGS2 result of the same call."""
+    case = CASES["mixed_p1to5_ns_roe"]
+    orc, ctx, U = _pair(frx, oracle_mod, case, graphs=frx.FR_GRAPHS_ALL)
+    F = I.random_direction(case.U.size, 79).reshape(case.U.shape)
+    shift = 20.0
+    p = frx.FR_F64 if prec == "f64" else frx.FR_F32
+    xo, so = orc.gmres(case.U, shift, F, m=30, max_it=10, tol=0.0, jv_mode=0)
+    Ft = torch.tensor(F, device="cuda")
+    x2, s2 = ctx.gmres(U, shift, Ft, restart=30, max_iter=10, tol=0.0, precision=p)
+    for graph in (False, True):
+        xg, sg = ctx.gmres(U, shift, Ft, restart=30, max_iter=10, tol=0.0, use_graph=graph, precision=p,
+                           orthog=frx.FR_ORTHO_CGS)
+        assert sg["iterations"] == so["iterations"] == 10
+        err = np.linalg.norm(xg.cpu().numpy() - xo) / np.linalg.norm(xo)
+        d2 = (torch.linalg.norm(xg - x2) / torch.linalg.norm(x2)).item()
+        print(prec, "CGS gmres(10) rel diff to oracle", err, "to CGS2", d2, "graph", graph, sg["rel_res"], so["rel_res"])
+        assert err <= (1e-9 if p == frx.FR_F64 else 1e-4)
+        assert d2 <= (1e-10 if p == frx.FR_F64 else 1e-4)
+
+
+def test_gmres_one_pass_gram_schmidt_refusals(frx, oracle_mod):
+    case = CASES["mixed_p1to5_ns_roe"]
+    orc, ctx, U = _pair(frx, oracle_mod, case)
+    for kw in (dict(restart=33, orthog=frx.FR_ORTHO_CGS), dict(restart=8, orthog=2)):
+        with pytest.raises(frx.FrError) as ei:
+            ctx.gmres(U, 10.0, U, **kw)
+        assert ei.value.status == frx.FR_E_INVALID
+
+
 def test_gmres_long_cycle_parity(frx, oracle_mod):
     """GMRES(40), 36 iterations in one cycle: the fused Gram-Schmidt kernels
     (up to 32 basis vectors) and the split multi-dot / multi-axpy path beyond
