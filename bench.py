@@ -127,10 +127,11 @@ def stage_medians(ctx, U, op, reps=20):
     return out
 
 
-def measured_traffic(name):
+def measured_traffic(name, key="traffic_bytes"):
     """HBM bytes per call of an operator from a committed rocprofv3 counter
     summary under profiles/ (lines 'source_sha256: ...', 'traffic_bytes:
-    ...'), or None if there is none or the kernel sources changed since."""
+    ...', 'fetched_bytes: ...', 'written_bytes: ...'), or None if there is
+    none or the kernel sources changed since."""
     path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
@@ -141,7 +142,7 @@ def measured_traffic(name):
     if kv.get("source_sha256") != kernel_source_hash():
         return None
     try:
-        return float(kv["traffic_bytes"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
 
@@ -259,8 +260,18 @@ def main():
                           f"{W['residual_and_jvp']['bytes'] / n_dof:.2f} B/DOF (U, v, R, Jv + "
                           f"{MESH_BYTES_PER_ELEMENT} B/element)")
     roof["traffic"] = measured_traffic(TRAFFIC_PROFILE)
+    peaks = memory_peaks(torch)
+    roof["measured_memory_peaks_gbs"] = peaks
     if roof["traffic"] is not None:
         roof["traffic_over_algorithmic"] = round(roof["traffic"] / roof["algorithmic_bytes"], 2)
+        fetched = measured_traffic(TRAFFIC_PROFILE, "fetched_bytes")
+        written = measured_traffic(TRAFFIC_PROFILE, "written_bytes")
+        if fetched is not None and written is not None:
+            # the step's measured reads and writes at the measured read-only
+            # and write-only rates: the memory roof of this staged design
+            t_mem = fetched / (peaks["read"] * 1e9) + written / (peaks["write"] * 1e9)
+            roof["traffic_time_at_measured_peaks_ms"] = round(t_mem * 1e3, 4)
+            roof["frac_of_measured_memory_roof"] = round(t_mem / (ms_step * 1e-3), 4)
     print(f"[bench] roofline {roof}", file=sys.stderr, flush=True)
 
     reps = max(20, args.steps // 2)
@@ -331,6 +342,34 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds, value)
     print(json.dumps(out), flush=True)
+
+
+def memory_peaks(torch, mib=2048, reps=10):
+    """Achievable HBM rates on this GPU (GB/s), median of `reps`: read only
+    (a sum over a float64 buffer), write only (a fill) and copy (bytes read
+    plus bytes written), on 2 GiB buffers, far above the 256 MB Infinity
+    Cache."""
+    n = mib * 1024 * 1024 // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    out = {}
+    for name, fn, nbytes in (("read", lambda: x.sum(), 8 * n), ("write", lambda: y.fill_(0.5), 8 * n),
+                             ("copy", lambda: y.copy_(x), 16 * n)):
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            t.append(a.elapsed_time(b))
+        out[name] = round(nbytes / (float(np.median(t)) * 1e-3) / 1e9, 1)
+    del x, y
+    torch.cuda.empty_cache()
+    return out
 
 
 def copy_calibration(torch, mib):
