@@ -642,8 +642,9 @@ def step_study(which, forms=None):
 
 def precond_study():
     """The element-Jacobi preconditioner (section 2.3) against none, in the
-    mixed form (float32 exact tangent and basis, float32 blocks) and in
-    float64: on the 32x32x4 workload one full ESDIRK2 step at the paper's
+    mixed form (float32 exact tangent and basis, float32 blocks, and the same
+    with the inverse kept in float16) and in float64, GMRES with one-pass
+    Gram-Schmidt: on the 32x32x4 workload one full ESDIRK2 step at the paper's
     settings (dt 0.005, dtau 5e-4 .. 5e-3, PTC to 1e-4, GMRES(30) to 1e-1);
     on the 128x128x8 workload one full ESDIRK2 step (dt 0.002, dtau 2e-4 ..
     4e-3, GMRES(30) to 1e-6).  The step builds the preconditioner once at its
@@ -662,7 +663,8 @@ def precond_study():
              dict(restart=30, max_iter=300, tol=1e-6))):
         case = I.config(k)
         res = {"dt": dt, "settings": {**common, **g}}
-        for prec, pname in ((frx.FR_F32, "mixed_f32"), (frx.FR_F64, "f64")):
+        for prec, pname, form in ((frx.FR_F32, "mixed_f32", 1), (frx.FR_F32, "mixed_f32_inverse_f16", 2),
+                                  (frx.FR_F64, "f64", 1)):
             if k == 5 and prec == frx.FR_F64:
                 continue  # float64 blocks of this workload take 94 GB; the float32 ones are timed
             resv = (frx.FR_RESERVE_PRECOND_F32 if prec == frx.FR_F32 else frx.FR_RESERVE_PRECOND_F64) | \
@@ -672,14 +674,14 @@ def precond_study():
             sigma = 1.0 / ((1.0 - 2 ** -0.5) * dt) + 1.0 / common["dtau_max"]
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            ctx.precond_build(U, sigma, prec)
+            ctx.precond_build(U, sigma, frx.FR_PC_F16 if form == 2 else prec)
             torch.cuda.synchronize()
             t_build = (time.perf_counter() - t0) * 1e3
             x = torch.tensor(I.random_direction(case.U.size, 4090).reshape(case.U.shape), device="cuda")
             y = torch.empty_like(x)
             t_apply, _ = median_ms(lambda: ctx.precond_apply(x, out=y), 5, 1, torch.cuda.current_stream(), torch)
-            for pc in (False, True):
-                gg = dict(g, precision=prec, use_graph=True, precond=pc)
+            for pc in ((0, form) if form == 1 else (form,)):
+                gg = dict(g, precision=prec, use_graph=True, precond=pc, orthog=frx.FR_ORTHO_CGS)
                 Uw, ms, st = _timed_step(ctx, U, dt, torch, gmres=gg, **common)
                 key = f"{pname}_{'element_jacobi' if pc else 'none'}"
                 res[key] = {"ms": round(ms, 1), **st}

@@ -103,8 +103,10 @@ typedef struct {
                          captured for this (jv_mode, precision) */
   int32_t precond;    /* 1: left preconditioning by the element-Jacobi
                          preconditioner (section 2.3) built in this precision;
-                         the stop test and rel_res are then those of the
-                         preconditioned system; 0: none */
+                         2: the same with its inverse kept in float16
+                         (FR_PC_F16 build, float32 GMRES only); the stop test
+                         and rel_res are then those of the preconditioned
+                         system; 0: none */
   int32_t orthog;     /* Gram-Schmidt of the Arnoldi step: FR_ORTHO_CGS2 (0,
                          classical, twice) or FR_ORTHO_CGS (classical, once:
                          the default of the PETSc GMRES the paper uses; needs
@@ -239,6 +241,12 @@ fr_status gmres_stage_solve(fr_ctx ctx, const double* U, double shift, const dou
  * or a context without fr_reserve. */
 fr_status esdirk_step(fr_ctx ctx, double* U, double dt, const fr_step_opts* opts, fr_step_stats* stats,
                       void* stream);
+
+/* Preconditioner forms of fr_precond_build beside FR_F64 and FR_F32:
+ * FR_PC_F16 builds in float32 (float32 storage) and keeps sigma times the
+ * inverse of every block as float16 in place, which halves the bytes each
+ * application streams; it serves float32 GMRES with precond = 2. */
+enum { FR_PC_F16 = 2 };
 
 /* The element-Jacobi preconditioner of section 2.3: the diagonal blocks of
  * (sigma I - dR/dq(U)), one dense block of order N_e = 5 (p_e + 1)^3 per

@@ -388,20 +388,74 @@ __global__ void __launch_bounds__(256) k_pc_inv(TB* __restrict__ blocks, PcDev p
   }
 }
 
+// x_e <- A_e^{-1} x_e from the float16 copy of sigma (P A)^{-1} that
+// k_pc_to_half leaves: z = P x (float, LDS), the product accumulated in
+// float32 and scaled by sc = 1/sigma.  Called by k_pc_apply (float32
+// storage) when the device flag asks for it; shapes as there.
+template <class TV>
+__device__ void pc_apply_half(TV* __restrict__ x, int nsp, const float* __restrict__ blocks, const PcDev& pc,
+                              const int* __restrict__ piv, float sc, float* z, float* part) {
+  const int4 r = pc.recs[blockIdx.x];
+  const int N = pc_rows(r.z);
+  const _Float16* A = reinterpret_cast<const _Float16*>(blocks + pc.boff[blockIdx.x]);
+  const int* P = piv + pc.poff[blockIdx.x];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += blockDim.x) z[i] = (float)x[pc_dof(P[i], r.z, r.y, nsp)];
+  __syncthreads();
+  const int slots = (N + 63) & ~63;
+  if (slots <= 128) {
+    const int groups = 256 / slots, g = tid / slots, i = tid - g * slots;
+    const int k0 = g * N / groups, k1 = (g + 1) * N / groups;
+    float acc = 0.0f;
+    if (i < N)
+      for (int k = k0; k < k1; ++k) acc += (float)A[i + (long)k * N] * z[k];
+    part[tid] = acc;
+    __syncthreads();
+    if (g == 0 && i < N) {
+      for (int h = 1; h < groups; ++h) acc += part[h * slots + i];
+      x[pc_dof(i, r.z, r.y, nsp)] = (TV)(acc * sc);
+    }
+    return;
+  }
+  for (int i0 = tid & ~63; i0 < N; i0 += blockDim.x) {
+    const int i = i0 + (tid & 63);
+    if (i >= N) break;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    int k = 0;
+    for (; k + 4 <= N; k += 4) {
+      a0 += (float)A[i + (long)k * N] * z[k];
+      a1 += (float)A[i + (long)(k + 1) * N] * z[k + 1];
+      a2 += (float)A[i + (long)(k + 2) * N] * z[k + 2];
+      a3 += (float)A[i + (long)(k + 3) * N] * z[k + 3];
+    }
+    for (; k < N; ++k) a0 += (float)A[i + (long)k * N] * z[k];
+    x[pc_dof(i, r.z, r.y, nsp)] = (TV)(((a0 + a1) + (a2 + a3)) * sc);
+  }
+}
+
 // x_e <- A_e^{-1} x_e for every element, in place (x: the Krylov vector, TV
 // storage; the product runs in TB): x is gathered through the permutation
 // (z = P x, in LDS), then multiplied by the stored (P A)^{-1}.  Rows over the
 // threads; blocks of at most 128 rows split the columns over 2 or 4 groups of
-// threads and add the partial sums in LDS.  *on == 0 leaves x unchanged (one
-// captured graph serves the preconditioned and the plain solves); *done != 0
-// returns at once, as every kernel of a captured Arnoldi step.
+// threads and add the partial sums in LDS.  The device flag *on selects: 0
+// leaves x unchanged, 1 the stored inverse, 2 (float32 storage) its float16
+// copy with *isig = 1/sigma; so one captured graph serves the plain and both
+// preconditioned solves, whichever was built last.  *done != 0 returns at
+// once, as every kernel of a captured Arnoldi step.
 template <class TV, class TB>
 __global__ void __launch_bounds__(256) k_pc_apply(TV* __restrict__ x, int nsp, const TB* __restrict__ blocks, PcDev pc,
                                                  const int* __restrict__ piv, const int* __restrict__ on,
-                                                 const int* __restrict__ done) {
-  if (!*on || (done && *done)) return;
+                                                 const int* __restrict__ done, const double* __restrict__ isig) {
+  const int mode = *on;
+  if (!mode || (done && *done)) return;
   __shared__ TB z[PC_NMAX];
   __shared__ TB part[256];
+  if constexpr (sizeof(TB) == 4) {
+    if (mode == 2) {
+      pc_apply_half<TV>(x, nsp, (const float*)blocks, pc, piv, (float)*isig, (float*)z, (float*)part);
+      return;
+    }
+  }
   const int4 r = pc.recs[blockIdx.x];
   const int N = pc_rows(r.z);
   const TB* A = blocks + pc.boff[blockIdx.x];
@@ -437,6 +491,33 @@ __global__ void __launch_bounds__(256) k_pc_apply(TV* __restrict__ x, int nsp, c
     }
     for (; k < N; ++k) a0 += A[i + (long)k * N] * z[k];
     x[pc_dof(i, r.z, r.y, nsp)] = (TV)((a0 + a1) + (a2 + a3));
+  }
+}
+
+// Half-precision copy of the inverse for the apply (float32 build): every
+// element's float32 (P A)^{-1} is replaced, in place at the start of its own
+// block, by float16 values of sigma (P A)^{-1} (entries of order one, since
+// the blocks are sigma I minus the Jacobian block).  A chunk of 256 entries is
+// read, then written after a barrier: the float16 entries of a chunk cover
+// float32 entries of the same or earlier chunks only.  One 256-thread block
+// per element (blockDim.x = 256), per degree bucket (ids).
+__global__ void __launch_bounds__(256) k_pc_to_half(float* __restrict__ blocks, PcDev pc, const int* __restrict__ ids,
+                                                   double sigma) {
+  const int el = ids ? ids[blockIdx.x] : (int)blockIdx.x;
+  const int N = pc_rows(pc.recs[el].z);
+  float* A = blocks + pc.boff[el];
+  _Float16* H = reinterpret_cast<_Float16*>(A);
+  const long NN = (long)N * N;
+  const float sg = (float)sigma;
+  __shared__ float stage[256];
+  for (long k0 = 0; k0 < NN; k0 += blockDim.x) {
+    const long k = k0 + threadIdx.x;
+    // through LDS, so that every load of the chunk has returned (its value
+    // stored in LDS) before the barrier that precedes the overwriting stores
+    stage[threadIdx.x] = k < NN ? A[k] : 0.0f;
+    __syncthreads();
+    if (k < NN) H[k] = (_Float16)(sg * stage[threadIdx.x]);
+    __syncthreads();
   }
 }
 

@@ -317,6 +317,8 @@ struct fr_ctx_s {
   void* pc_blocks = nullptr;   // dense blocks, column-major, [sum_e N_e^2] of pc_prec
   int pc_prec = -1;            // FR_F64 / FR_F32 storage, -1: none
   bool pc_built = false;
+  bool pc_half = false;        // the built inverse is kept as float16 of sigma times it (float32 storage)
+  double* pc_isig = nullptr;   // device: 1 / sigma of the last build
   int* pc_piv = nullptr;       // [sum_e N_e]
   int4* pc_recs = nullptr;     // [E] (e, first solution point, n, 0)
   long* pc_boff = nullptr;     // [E]
@@ -476,13 +478,15 @@ PcDev pc_dev(fr_ctx c) { return PcDev{c->pc_recs, c->pc_boff, c->pc_poff}; }
 template <class TV>
 void pc_apply(fr_ctx c, TV* x, const int* done, hipStream_t s) {
   if (!c->pc_blocks) return;
-  const int* on = c->ist + 5;
+  const int* on = c->ist + 5;  // 0 off, 1 stored inverse, 2 its float16 copy (chosen on the device)
   if (c->pc_prec == FR_F64)
     hipLaunchKernelGGL((k_pc_apply<TV, double>), dim3(c->M.E), dim3(256), 0, s, x, c->M.nsp,
-                       (const double*)c->pc_blocks, pc_dev(c), (const int*)c->pc_piv, on, done);
+                       (const double*)c->pc_blocks, pc_dev(c), (const int*)c->pc_piv, on, done,
+                       (const double*)c->pc_isig);
   else
     hipLaunchKernelGGL((k_pc_apply<TV, float>), dim3(c->M.E), dim3(256), 0, s, x, c->M.nsp,
-                       (const float*)c->pc_blocks, pc_dev(c), (const int*)c->pc_piv, on, done);
+                       (const float*)c->pc_blocks, pc_dev(c), (const int*)c->pc_piv, on, done,
+                       (const double*)c->pc_isig);
   FRX_TRY(hipGetLastError());
 }
 
@@ -700,8 +704,10 @@ void arnoldi_cycle(fr_ctx c, int mode, int m, bool use_graph, hipStream_t s) {
 // Assembles the blocks sigma I - dR/dq(U)|_ee by coloured exact tangent
 // products (the tangent in the storage precision: float64 duals on U, or
 // float32 duals on a float32 copy of U), factors and inverts them.
-void pc_build(fr_ctx c, const double* U, double sigma, hipStream_t s) {
+void pc_build(fr_ctx c, const double* U, double sigma, hipStream_t s, bool half = false) {
   if (!c->pc_blocks) throw StatusErr{FR_E_INVALID, "no preconditioner storage (fr_reserve with FR_RESERVE_PRECOND_*)"};
+  if (half && c->pc_prec != FR_F32) throw StatusErr{FR_E_INVALID, "a float16 inverse needs float32 storage"};
+  c->pc_built = false;
   const long n = c->ndof;
   const bool f64 = c->pc_prec == FR_F64;
   if (!f64) {
@@ -764,12 +770,20 @@ void pc_build(fr_ctx c, const double* U, double sigma, hipStream_t s) {
       FRX_TRY(hipGetLastError());
       hipLaunchKernelGGL((k_pc_inv<float>), dim3(eb.count), dim3(256), lds, s, (float*)c->pc_blocks, pc_dev(c),
                          (const int*)eb.elems);
+      if (half) {
+        FRX_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_pc_to_half, dim3(eb.count), dim3(256), 0, s, (float*)c->pc_blocks, pc_dev(c),
+                           (const int*)eb.elems, sigma);
+      }
     }
     FRX_TRY(hipGetLastError());
   }
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(KR_THREADS), 0, s, c->pc_isig, 1L, 1.0 / sigma);
+  FRX_TRY(hipGetLastError());
   FRX_TRY(hipMemcpyAsync(c->ipin + 16, c->pc_flag, sizeof(int), hipMemcpyDeviceToHost, s));
   FRX_TRY(hipStreamSynchronize(s));
   c->pc_built = c->ipin[16] == 0;
+  c->pc_half = half;
   if (!c->pc_built) throw StatusErr{FR_E_NONPHYSICAL, "element-Jacobi preconditioner: a singular element block"};
 }
 
@@ -790,7 +804,7 @@ fr_status gmres_run(fr_ctx c, const fr_gmres_opts& o, double* x, fr_gmres_stats*
   // ||F|| (unless the caller has it), tolerance, budget
   // left preconditioning: the Krylov space of P^-1 A, the right-hand side
   // P^-1 F and the residual norms of the preconditioned system
-  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->ist + 5, o.precond ? 1 : 0);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->ist + 5, o.precond);
   FRX_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->ist + 6, o.orthog == FR_ORTHO_CGS ? 1 : 0);
   FRX_TRY(hipGetLastError());
@@ -877,8 +891,9 @@ fr_status gmres_solve(fr_ctx c, const double* U, double shift, const double* F, 
                                       std::to_string(c->m_alloc) + "); call fr_reserve"};
   if (o.use_graph && !(c->graph_sets & graph_bit(o.jv_mode, o.precision)))
     throw StatusErr{FR_E_INVALID, "Arnoldi graphs of this mode and precision were not reserved (fr_reserve)"};
-  if (o.precond && (!c->pc_built || c->pc_prec != o.precision))
-    throw StatusErr{FR_E_INVALID, "no element-Jacobi preconditioner built in this precision (fr_precond_build)"};
+  if (o.precond < 0 || o.precond > 2) throw StatusErr{FR_E_INVALID, "gmres options out of range"};
+  if (o.precond && (!c->pc_built || c->pc_prec != o.precision || c->pc_half != (o.precond == 2)))
+    throw StatusErr{FR_E_INVALID, "no element-Jacobi preconditioner built in this precision and form (fr_precond_build)"};
   const long n = c->ndof;
   if (U != c->Ulin) FRX_TRY(hipMemcpyAsync(c->Ulin, U, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   if (F != c->Fb) FRX_TRY(hipMemcpyAsync(c->Fb, F, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
@@ -1351,6 +1366,7 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
       C->pc_poff = (int*)C->dalloc(sizeof(int) * E);
       C->pc_piv = (int*)C->dalloc(sizeof(int) * std::max(1, pv));
       C->pc_flag = (int*)C->dalloc(sizeof(int) * 4);
+      C->pc_isig = (double*)C->dalloc(sizeof(double) * 2);
       FRX_TRY(hipMemcpy(C->pc_recs, recs.data(), sizeof(int4) * E, hipMemcpyHostToDevice));
       FRX_TRY(hipMemcpy(C->pc_boff, boff.data(), sizeof(long) * E, hipMemcpyHostToDevice));
       FRX_TRY(hipMemcpy(C->pc_poff, poff.data(), sizeof(int) * E, hipMemcpyHostToDevice));
@@ -1700,9 +1716,10 @@ fr_status esdirk_step(fr_ctx c, double* U, double dt, const fr_step_opts* o, fr_
     // the element-Jacobi preconditioner, evaluated once at the start of the
     // step (section 2.3) with sigma = 1/(omega dt) + 1/dtau_max
     if (o->gmres.precond) {
-      if (c->pc_prec != o->gmres.precision)
+      if (c->pc_prec != o->gmres.precision || o->gmres.precond < 0 || o->gmres.precond > 2 ||
+          (o->gmres.precond == 2 && c->pc_prec != FR_F32))
         throw StatusErr{FR_E_INVALID, "esdirk_step: no preconditioner storage in the GMRES precision (fr_reserve)"};
-      pc_build(c, qn, 1.0 / (w * dt) + 1.0 / o->dtau_max, s);
+      pc_build(c, qn, 1.0 / (w * dt) + 1.0 / o->dtau_max, s, o->gmres.precond == 2);
     }
     ResCall<double> rc;
     rc.U = qn;
@@ -2078,13 +2095,13 @@ fr_status fr_profile(fr_ctx c, const double* U, int32_t op, int32_t reps, fr_ker
 
 fr_status fr_precond_build(fr_ctx c, const double* U, double sigma, int32_t precision, void* stream) {
   if (!c) return FR_E_INVALID;
-  if (!U || !(sigma > 0.0) || (precision != FR_F64 && precision != FR_F32))
+  if (!U || !(sigma > 0.0) || (precision != FR_F64 && precision != FR_F32 && precision != FR_PC_F16))
     return fail(c, FR_E_INVALID, "fr_precond_build: bad arguments");
-  if (c->pc_prec != precision)
+  if (c->pc_prec != (precision == FR_PC_F16 ? FR_F32 : precision))
     return fail(c, FR_E_INVALID, "fr_precond_build: no preconditioner storage in this precision (fr_reserve)");
   return guarded(c, [&]() -> fr_status {
     c->pc_built = false;
-    pc_build(c, U, sigma, S(stream));
+    pc_build(c, U, sigma, S(stream), precision == FR_PC_F16);
     return FR_OK;
   });
 }
@@ -2098,7 +2115,7 @@ fr_status fr_precond_apply(fr_ctx c, const double* x, double* y, void* stream) {
   return guarded(c, [&]() -> fr_status {
     hipStream_t s = S(stream);
     if (x != y) FRX_TRY(hipMemcpyAsync(y, x, nb, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->ist + 5, 1);
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->ist + 5, c->pc_half ? 2 : 1);
     pc_apply<double>(c, y, nullptr, s);
     return FR_OK;
   });

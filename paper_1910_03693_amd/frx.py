@@ -28,6 +28,7 @@ FR_LAUNCH_FACES_TWO_PASS, FR_LAUNCH_FACES_ONE_PASS = 4, 8
 FR_ESDIRK2, FR_ESDIRK4 = 0, 1
 FR_ETA_MAX_ALL, FR_ETA_MAX_SAME_DEGREE = 0, 1
 FR_ORTHO_CGS2, FR_ORTHO_CGS = 0, 1
+FR_PC_F16 = 2
 STATUS_NAMES = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_NOMEM", -3: "FR_E_HIP", -4: "FR_E_NOTCONVERGED",
                 -5: "FR_E_NONPHYSICAL", -6: "FR_E_UNSUPPORTED"}
 EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_reserve", "fr_residual", "fr_residual_noalloc", "fr_residual_jvp", "fr_jvp", "fr_vjp", "gmres_stage_solve",
@@ -227,7 +228,7 @@ def gmres_opts(restart=30, max_iter=100, tol=1e-1, jv_mode=FR_JV_EXACT, precisio
                use_graph=False, precond=False, orthog=FR_ORTHO_CGS2):
     o = fr_gmres_opts()
     o.restart, o.max_iter, o.tol, o.jv_mode, o.precision, o.fd_eps, o.use_graph, o.precond, o.orthog = (
-        restart, max_iter, tol, jv_mode, precision, fd_eps, int(bool(use_graph)), int(bool(precond)), int(orthog))
+        restart, max_iter, tol, jv_mode, precision, fd_eps, int(bool(use_graph)), int(precond), int(orthog))
     return o
 
 

@@ -41,12 +41,21 @@ def _reserve(frx, prec):
     return frx.FR_RESERVE_PRECOND_F64 if prec == frx.FR_F64 else frx.FR_RESERVE_PRECOND_F32
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+def _prec(frx, name):
+    return {"f64": frx.FR_F64, "f32": frx.FR_F32, "f16": frx.FR_PC_F16}[name]
+
+
+# P^-1 x against the oracle's dense solves: float64 blocks, float32 blocks,
+# and the float16 copy of sigma times the float32 inverse (11-bit significand)
+APPLY_TOL = {"f64": 1e-11, "f32": 2e-4, "f16": 3e-3}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("fused", [True, False], ids=["fused", "per_bucket"])
 def test_precond_apply_matches_oracle(frx, small, prec, fused):
     from oracle import precond as PC
     case, orc, J, dofs = small
-    p = frx.FR_F64 if prec == "f64" else frx.FR_F32
+    p = _prec(frx, prec)
     ctx = frx.Context.from_case(case, max_restart=10, graphs=_reserve(frx, p), fused=fused)
     U = torch.tensor(case.U, device="cuda")
     sigma = 35.0
@@ -56,7 +65,7 @@ def test_precond_apply_matches_oracle(frx, small, prec, fused):
     ref = PC.apply(PC.element_blocks(J, dofs, sigma), dofs, x.ravel())
     err = np.abs(y - ref).max() / np.abs(ref).max()
     print(prec, "fused" if fused else "per-bucket", "P^-1 x rel err", err)
-    assert err <= (1e-11 if prec == "f64" else 2e-4)
+    assert err <= APPLY_TOL[prec]
 
 
 @pytest.fixture(scope="module")
@@ -74,11 +83,11 @@ def largest(oracle_mod):
     return case, J, dofs
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
 def test_precond_apply_largest_blocks(frx, largest, prec):
     from oracle import precond as PC
     case, J, dofs = largest
-    p = frx.FR_F64 if prec == "f64" else frx.FR_F32
+    p = _prec(frx, prec)
     ctx = frx.Context.from_case(case, max_restart=4, graphs=_reserve(frx, p), fused=True)
     U = torch.tensor(case.U, device="cuda")
     sigma = 60.0
@@ -88,7 +97,7 @@ def test_precond_apply_largest_blocks(frx, largest, prec):
     ref = PC.apply(PC.element_blocks(J, dofs, sigma), dofs, x.ravel())
     err = np.abs(y - ref).max() / np.abs(ref).max()
     print(prec, "p = 1, 4, 5: P^-1 x rel err", err)
-    assert err <= (1e-11 if prec == "f64" else 2e-4)
+    assert err <= APPLY_TOL[prec]
 
 
 @pytest.mark.parametrize("graph", [False, True])
@@ -113,7 +122,7 @@ def test_preconditioned_gmres_fixed_iterations_parity(frx, small, graph):
     assert abs(sg["rel_res"] - rr) <= 1e-8 * rr + 1e-14
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32_graph"])
+@pytest.mark.parametrize("prec", ["f64", "f32_graph", "f16_graph"])
 def test_preconditioned_gmres_converges_with_fewer_products(frx, small, prec):
     case, orc, J, dofs = small
     p = frx.FR_F64 if prec == "f64" else frx.FR_F32
@@ -122,11 +131,11 @@ def test_preconditioned_gmres_converges_with_fewer_products(frx, small, prec):
                                 fused=True)
     U = torch.tensor(case.U, device="cuda")
     shift = 8.0
-    ctx.precond_build(U, shift, p)
+    ctx.precond_build(U, shift, frx.FR_PC_F16 if prec.startswith("f16") else p)
     F = I.random_direction(case.U.size, 4083).reshape(case.U.shape)
     Ft = torch.tensor(F, device="cuda")
     kw = dict(restart=10, max_iter=600, tol=1e-6, precision=p, use_graph="graph" in prec)
-    xp, sp = ctx.gmres(U, shift, Ft, precond=True, **kw)
+    xp, sp = ctx.gmres(U, shift, Ft, precond=2 if prec.startswith("f16") else 1, **kw)
     x0, s0 = ctx.gmres(U, shift, Ft, precond=False, **kw)
     A = shift * np.eye(J.shape[0]) - J
     rel = np.linalg.norm(F.ravel() - A @ xp.cpu().numpy().ravel()) / np.linalg.norm(F)
@@ -173,4 +182,16 @@ def test_precond_refusals(frx):
     assert ei.value.status == frx.FR_E_INVALID
     with pytest.raises(frx.FrError) as ei:
         ctx.precond_build(U, -1.0, frx.FR_F32)
+    assert ei.value.status == frx.FR_E_INVALID
+    ctx.precond_build(U, 10.0, frx.FR_F32)
+    with pytest.raises(frx.FrError) as ei:
+        ctx.gmres(U, 10.0, U, restart=8, precision=frx.FR_F32, precond=2)  # built without the float16 copy
+    assert ei.value.status == frx.FR_E_INVALID
+    ctx.precond_build(U, 10.0, frx.FR_PC_F16)
+    with pytest.raises(frx.FrError) as ei:
+        ctx.gmres(U, 10.0, U, restart=8, precision=frx.FR_F32, precond=1)  # built as float16
+    assert ei.value.status == frx.FR_E_INVALID
+    ctx2 = frx.Context.from_case(case, max_restart=8, graphs=frx.FR_RESERVE_PRECOND_F64)
+    with pytest.raises(frx.FrError) as ei:
+        ctx2.precond_build(U, 10.0, frx.FR_PC_F16)  # float16 needs float32 storage
     assert ei.value.status == frx.FR_E_INVALID
