@@ -10,7 +10,7 @@ hipError_t upload_tables_dual32(const OpsTab<double>& d, const OpsTab<float>& f)
   return hipMemcpyToSymbol(HIP_SYMBOL(c_ops_f), &f, sizeof(f));
 }
 
-hipError_t launch_residual_dual32(const MeshDev& M, const ResCall<float>& c, hipStream_t s) {
-  return launch_residual_T<Dual<float>>(M, c, SK_DUAL32, s);
+hipError_t launch_residual_dual32(const MeshDev& M, const ResCall<float>& c, hipStream_t s, const FusedSubset* sub) {
+  return launch_residual_T<Dual<float>>(M, c, SK_DUAL32, s, sub);
 }
 }  // namespace frx

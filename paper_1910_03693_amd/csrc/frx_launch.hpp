@@ -190,23 +190,25 @@ hipError_t residual_stages(const ResArgs<T>& a, const MeshDev& M, int sk, hipStr
 // Face stage of the fused plan: interior-face tiles (one or two passes), then
 // the boundary-face tiles in a launch of their own.
 template <class T, bool NS, int FLUX>
-hipError_t face_stage_fused(const ResArgs<T>& a, const MeshDev& M, const FusedPlan& P, bool two_pass, hipStream_t s) {
+hipError_t face_stage_fused(const ResArgs<T>& a, const MeshDev& M, const FusedPlan& P, bool two_pass, hipStream_t s,
+                            const int4* faces = nullptr) {
   hipError_t e;
+  if (!faces) faces = M.all_faces;
   if (P.n_interior > 0) {
     if (two_pass) {
-      hipLaunchKernelGGL((k_face_split_fused<T, 0, FLUX>), dim3(P.n_interior), dim3(256), P.lds[1], s, a, M.all_faces,
+      hipLaunchKernelGGL((k_face_split_fused<T, 0, FLUX>), dim3(P.n_interior), dim3(256), P.lds[1], s, a, faces,
                          P.tiles[1]);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL((k_face_split_fused<T, 1, FLUX>), dim3(P.n_interior), dim3(256), P.lds[1], s, a, M.all_faces,
+      hipLaunchKernelGGL((k_face_split_fused<T, 1, FLUX>), dim3(P.n_interior), dim3(256), P.lds[1], s, a, faces,
                          P.tiles[1]);
     } else {
-      hipLaunchKernelGGL((k_face_fused<T, NS, FLUX>), dim3(P.n_interior), dim3(256), P.lds[1], s, a, M.all_faces,
+      hipLaunchKernelGGL((k_face_fused<T, NS, FLUX>), dim3(P.n_interior), dim3(256), P.lds[1], s, a, faces,
                          P.tiles[1]);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (P.count[1] > P.n_interior) {
-    hipLaunchKernelGGL((k_bface_fused<T, NS, FLUX>), dim3(P.count[1] - P.n_interior), dim3(256), 0, s, a, M.all_faces,
+    hipLaunchKernelGGL((k_bface_fused<T, NS, FLUX>), dim3(P.count[1] - P.n_interior), dim3(256), 0, s, a, faces,
                        P.tiles[1] + P.n_interior);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -214,22 +216,28 @@ hipError_t face_stage_fused(const ResArgs<T>& a, const MeshDev& M, const FusedPl
 }
 
 template <class T, bool NS>
-hipError_t residual_fused(const ResArgs<T>& a, const MeshDev& M, int sk, hipStream_t s) {
+hipError_t residual_fused(const ResArgs<T>& a, const MeshDev& M, int sk, hipStream_t s,
+                          const FusedSubset* sub = nullptr) {
   const FusedPlan& P = M.plan[sk];
+  const FusedPlan& Q = sub ? sub->plan[sk] : P;  // face and divergence stages
+  const int4* faces = sub ? sub->faces : M.all_faces;
+  const int4* elems2 = sub ? sub->elems : M.all_elems;
   ProfHook* H = M.prof;
   const char* names[3] = {"k_trace_fused", "k_face_fused", "k_div_fused"};
   hipError_t e;
   for (int st = 0; st < 3; ++st) {
-    if (!P.count[st]) continue;
-    if (H) H->begin(names[st], 0, 0, P.count[st], s);
+    const FusedPlan& X = st == 0 ? P : Q;
+    if (!X.count[st]) continue;
+    if (H) H->begin(names[st], 0, 0, X.count[st], s);
     if (st == 0)
       hipLaunchKernelGGL((k_trace_fused<T, NS>), dim3(P.count[0]), dim3(256), P.lds[0], s, a, M.all_elems, P.tiles[0]);
     else if (st == 1) {
       const bool two_pass = NS && M.split_faces[1][sk];
-      e = M.flux == 1 ? face_stage_fused<T, NS, 1>(a, M, P, two_pass, s) : face_stage_fused<T, NS, 0>(a, M, P, two_pass, s);
+      e = M.flux == 1 ? face_stage_fused<T, NS, 1>(a, M, Q, two_pass, s, faces)
+                      : face_stage_fused<T, NS, 0>(a, M, Q, two_pass, s, faces);
       if (e != hipSuccess) return e;
     } else
-      hipLaunchKernelGGL((k_div_fused<T, NS>), dim3(P.count[2]), dim3(256), P.lds[2], s, a, M.all_elems, P.tiles[2]);
+      hipLaunchKernelGGL((k_div_fused<T, NS>), dim3(Q.count[2]), dim3(256), Q.lds[2], s, a, elems2, Q.tiles[2]);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (H) H->end(s);
@@ -238,7 +246,8 @@ hipError_t residual_fused(const ResArgs<T>& a, const MeshDev& M, int sk, hipStre
 }
 
 template <class T>
-hipError_t launch_residual_T(const MeshDev& M, const ResCall<base_t<T>>& c, int sk, hipStream_t s) {
+hipError_t launch_residual_T(const MeshDev& M, const ResCall<base_t<T>>& c, int sk, hipStream_t s,
+                             const FusedSubset* sub = nullptr) {
   using B = base_t<T>;
   ResArgs<T> a;
   a.U = c.U;
@@ -265,7 +274,7 @@ hipError_t launch_residual_T(const MeshDev& M, const ResCall<base_t<T>>& c, int 
   a.flag = M.flag;
   a.skip = c.skip;
   if (M.fused)
-    return M.physics == 1 ? residual_fused<T, true>(a, M, sk, s) : residual_fused<T, false>(a, M, sk, s);
+    return M.physics == 1 ? residual_fused<T, true>(a, M, sk, s, sub) : residual_fused<T, false>(a, M, sk, s, sub);
   return M.physics == 1 ? residual_stages<T, true>(a, M, sk, s) : residual_stages<T, false>(a, M, sk, s);
 }
 

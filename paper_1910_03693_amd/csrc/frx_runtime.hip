@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -328,6 +329,12 @@ struct fr_ctx_s {
   std::vector<int*> pc_cidx;   // per colour: their element ids
   std::vector<int> pc_ccount;
   int pc_nmax = 0;             // largest block order
+  // per colour and n: the fused subset of the colour's elements of size >= n
+  // (the elements that a column j < 5 n^3 seeds), null entries where no
+  // element is that large
+  std::vector<std::array<std::unique_ptr<FusedSubset>, NMAX + 1>> pc_sub;  // built by fr_reserve
+  std::vector<int> pc_colour;  // colour of every element
+  std::vector<int4> faces_h;   // host copy of the concatenated face list (ranges in frange)
 
   void* dalloc(size_t bytes) {
     void* p = nullptr;
@@ -730,12 +737,17 @@ void pc_build(fr_ctx c, const double* U, double sigma, hipStream_t s, bool half 
                            (const int4*)c->pc_crecs[col], cnt, j - 1, jn);
       FRX_TRY(hipGetLastError());
       if (jn < 0) break;
+      // only the colour's elements of order N_e > j are seeded, and only
+      // their rows are read: their faces and divergence suffice
+      int nmin = 2;
+      while (nmin < NMAX && 5 * nmin * nmin * nmin <= j) ++nmin;
+      const FusedSubset* sub = c->M.fused ? c->pc_sub[col][nmin].get() : nullptr;
       if (f64) {
         ResCall<double> rc;
         rc.U = U;
         rc.V = c->t0;
         rc.out = c->t1;
-        FRX_TRY(launch_residual_dual64(c->M, rc, s));
+        FRX_TRY(launch_residual_dual64(c->M, rc, s, sub));
         hipLaunchKernelGGL((k_pc_extract<double, double>), dim3(cnt), dim3(256), 0, s, (const double*)c->t1,
                            c->M.nsp, (const int4*)c->pc_crecs[col], (const int*)c->pc_cidx[col], j, sigma,
                            (const long*)c->pc_boff, (double*)c->pc_blocks);
@@ -744,7 +756,7 @@ void pc_build(fr_ctx c, const double* U, double sigma, hipStream_t s, bool half 
         rc.U = c->uf;
         rc.V = (const float*)c->t0;
         rc.out = (float*)c->t1;
-        FRX_TRY(launch_residual_dual32(c->M, rc, s));
+        FRX_TRY(launch_residual_dual32(c->M, rc, s, sub));
         hipLaunchKernelGGL((k_pc_extract<float, float>), dim3(cnt), dim3(256), 0, s, (const float*)c->t1,
                            c->M.nsp, (const int4*)c->pc_crecs[col], (const int*)c->pc_cidx[col], j, sigma,
                            (const long*)c->pc_boff, (float*)c->pc_blocks);
@@ -994,20 +1006,25 @@ std::vector<int4> xcd_order(const std::vector<int4>& t) {
   return out;
 }
 
-// (Re)builds the tile table of one stage of one scalar kind from the chosen
-// items per tile (c->shape), into the table allocated for the worst case.
-void plan_stage(fr_ctx c, int sk, int st) {
+// The tile table of one stage of one scalar kind over element ranges er
+// (n -> first, count) or face ranges fr (code, first, count, nl), with the
+// chosen items per tile (c->shape; the defaults if use_shapes is false), in
+// the XCD order; *lds receives the largest tile's LDS and *nint the length
+// of the interior-face part.
+std::vector<int4> make_tiles(fr_ctx c, int sk, int st, const std::map<int, std::pair<int, int>>& er,
+                             const std::vector<std::tuple<int, int, int, int>>& fr, bool use_shapes, size_t* lds_out,
+                             int* nint_out) {
   MeshDev& M = c->M;
   const bool ns = M.physics == FR_NAVIER_STOKES;
-  FusedPlan& P = M.plan[sk];
   std::vector<std::pair<double, int4>> tiles;
   size_t lds = 0;
   auto items = [&](int code) {
+    if (!use_shapes) return max_items(ns, sk, st, code);
     auto it = c->shape[sk][st].find(code);
     return it != c->shape[sk][st].end() ? it->second : max_items(ns, sk, st, code);
   };
   if (st != 1) {
-    for (auto& kv : c->erange) {
+    for (auto& kv : er) {
       const int n = kv.first, first = kv.second.first, count = kv.second.second;
       const int epb = items(n);
       lds = std::max(lds, epb * item_lds(ns, scalar_bytes(sk), st, n));
@@ -1017,8 +1034,8 @@ void plan_stage(fr_ctx c, int sk, int st) {
       }
     }
   } else {
-    for (auto& fr : c->frange) {
-      const int code = std::get<0>(fr), first = std::get<1>(fr), count = std::get<2>(fr);
+    for (auto& f : fr) {
+      const int code = std::get<0>(f), first = std::get<1>(f), count = std::get<2>(f);
       if (code >= 64) {
         const int n = code - 64, per = std::max(1, 256 / (n * n));
         for (int i = 0; i < count; i += per)
@@ -1045,11 +1062,22 @@ void plan_stage(fr_ctx c, int sk, int st) {
   std::vector<int4> t_int, t_bnd;
   for (auto& x : tiles) (x.second.x < 64 ? t_int : t_bnd).push_back(x.second);
   std::vector<int4> t = xcd_order(t_int);
-  const int nint = (int)t.size();
+  *nint_out = (int)t.size();
   if (!t_bnd.empty()) {
     const std::vector<int4> tb = xcd_order(t_bnd);
     t.insert(t.end(), tb.begin(), tb.end());
   }
+  *lds_out = lds;
+  return t;
+}
+
+// (Re)builds the tile table of one stage of one scalar kind from the chosen
+// items per tile (c->shape), into the table allocated for the worst case.
+void plan_stage(fr_ctx c, int sk, int st) {
+  FusedPlan& P = c->M.plan[sk];
+  size_t lds = 0;
+  int nint = 0;
+  const std::vector<int4> t = make_tiles(c, sk, st, c->erange, c->frange, true, &lds, &nint);
   if ((int)t.size() > c->plan_cap[st]) throw StatusErr{FR_E_INVALID, "tile table larger than its allocation"};
   if (st == 1) P.n_interior = nint;
   P.count[st] = (int)t.size();
@@ -1085,6 +1113,7 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
   for (int e : all) all_recs.push_back(make_int4(e, (int)c->sp_off_h[e], c->fp_off_h[e], 0));
   M.all_elems = (int4*)c->dalloc(sizeof(int4) * std::max<size_t>(1, all_recs.size()));
   FRX_TRY(hipMemcpy(M.all_elems, all_recs.data(), sizeof(int4) * all_recs.size(), hipMemcpyHostToDevice));
+  c->faces_h = faces;
   M.all_faces = (int4*)c->dalloc(sizeof(int4) * std::max<size_t>(1, faces.size()));
   if (!faces.empty())
     FRX_TRY(hipMemcpy(M.all_faces, faces.data(), sizeof(int4) * faces.size(), hipMemcpyHostToDevice));
@@ -1158,6 +1187,64 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
     V.tiles[st] = (int4*)c->dalloc(sizeof(int4) * std::max<size_t>(1, t.size()));
     if (!t.empty()) FRX_TRY(hipMemcpy(V.tiles[st], t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice));
   }
+}
+
+// The fused subsets of the preconditioner assembly (see pc_sub): per colour
+// k and size n, the elements of colour k with n_e >= n by degree bucket, the
+// interior faces with a side among them and their boundary faces, both in
+// the order of the full face list, and the face and divergence tiles of
+// every scalar kind with the default items per tile.  Built once, by
+// fr_reserve with preconditioner storage.
+void build_pc_subsets(fr_ctx c) {
+  const int E = c->M.E;
+  const std::vector<int>& colour = c->pc_colour;
+  for (size_t k = 0; k < c->pc_sub.size(); ++k)
+    for (int nmin = 2; nmin <= NMAX; ++nmin) {
+      if (c->pc_sub[k][nmin]) continue;
+      auto in = [&](int e) { return colour[e] == (int)k && c->p[e] + 1 >= nmin; };
+      std::vector<int4> recs;
+      std::map<int, std::pair<int, int>> er;
+      for (int n = NMAX; n >= nmin; --n) {
+        const int first = (int)recs.size();
+        for (int e = 0; e < E; ++e)
+          if (colour[e] == (int)k && c->p[e] + 1 == n)
+            recs.push_back(make_int4(e, (int)c->sp_off_h[e], c->fp_off_h[e], 0));
+        if ((int)recs.size() > first) er[n] = {first, (int)recs.size() - first};
+      }
+      if (recs.empty()) continue;
+      std::vector<int4> faces;
+      std::vector<std::tuple<int, int, int, int>> fr;
+      for (auto& f : c->frange) {
+        const int code = std::get<0>(f), first0 = std::get<1>(f), count0 = std::get<2>(f);
+        const int first = (int)faces.size();
+        for (int i = first0; i < first0 + count0; ++i) {
+          const int4 F = c->faces_h[i];
+          // interior record (L, R, ...), boundary record (e, f, bc, slot)
+          if (in(F.x) || (code < 64 && in(F.y))) faces.push_back(F);
+        }
+        if ((int)faces.size() > first) fr.emplace_back(code, first, (int)faces.size() - first, std::get<3>(f));
+      }
+      auto S = std::make_unique<FusedSubset>();
+      int4* de = (int4*)c->dalloc(sizeof(int4) * recs.size());
+      FRX_TRY(hipMemcpy(de, recs.data(), sizeof(int4) * recs.size(), hipMemcpyHostToDevice));
+      S->elems = de;
+      int4* df = (int4*)c->dalloc(sizeof(int4) * std::max<size_t>(1, faces.size()));
+      if (!faces.empty()) FRX_TRY(hipMemcpy(df, faces.data(), sizeof(int4) * faces.size(), hipMemcpyHostToDevice));
+      S->faces = df;
+      for (int sk = 0; sk < SK_COUNT; ++sk)
+        for (int st = 1; st < 3; ++st) {
+          size_t lds = 0;
+          int nint = 0;
+          const std::vector<int4> t = make_tiles(c, sk, st, er, fr, false, &lds, &nint);
+          FusedPlan& P = S->plan[sk];
+          if (st == 1) P.n_interior = nint;
+          P.count[st] = (int)t.size();
+          P.lds[st] = lds;
+          P.tiles[st] = (int4*)c->dalloc(sizeof(int4) * std::max<size_t>(1, t.size()));
+          if (!t.empty()) FRX_TRY(hipMemcpy(P.tiles[st], t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice));
+        }
+      c->pc_sub[k][nmin] = std::move(S);
+    }
 }
 
 void validate_desc(const fr_mesh_desc* d) {
@@ -1386,6 +1473,8 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
         C->pc_cidx.push_back(cid);
         C->pc_ccount.push_back((int)cr.size());
       }
+      C->pc_colour = colour;
+      C->pc_sub.resize(ncol);
     }
     // gas
     const double kappa = d->mu * d->gamma / ((d->gamma - 1.0) * d->prandtl);
@@ -1465,6 +1554,7 @@ fr_status fr_reserve(fr_ctx c, int32_t max_restart, int32_t graph_sets) {
       c->pc_prec = want;
       c->pc_built = false;
     }
+    if (want >= 0) build_pc_subsets(c);
     c->graph_sets |= (graph_sets & gbits);
     instantiate_graphs(c);
     FRX_TRY(hipDeviceSynchronize());
