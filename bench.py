@@ -48,31 +48,47 @@ HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6
 FP32_VECTOR_TFLOPS = 157.3
 MESH_BYTES_PER_ELEMENT = 217  # 8 vertices (192 B), 6 neighbour ids (24 B), the degree (1 B)
-TANGENT_FLOP_FACTOR = 2.25    # dual-number pass / residual (value and derivative parts)
+# counted floating-point operations of the method (the oracle's residual on
+# counted scalars), written by tests/golden/make_flop_counts.py
+FLOP_COUNTS = os.path.join(ROOT, "tests", "golden", "flop_counts.json")
+HEADLINE_SAMPLE = "navier_stokes_128x128x8_slab_4x128x8"
 
 
-def residual_flops_per_dof(n, ns=True):
-    """Sum-factorised flops per DOF of the float64 residual at n = p + 1:
-    about 60 n^4 per element for the gradient and divergence contractions,
-    plus pointwise flux, metric and correction work per solution point and
-    Riemann / viscous work per face point (planning model, per DOF)."""
-    return (12.0 * n + 165.0 + 200.0 / n) if ns else (6.0 * n + 60.0 + 100.0 / n)
+def planning_flops_per_dof(n):
+    """The planning estimate of the Navier-Stokes residual's flops per DOF at
+    n = p + 1 (about 60 n^4 per element of contractions plus pointwise and
+    face work), kept beside the counted work for reference."""
+    return 12.0 * n + 165.0 + 200.0 / n
 
 
-def work_model(elem_p, ns=True):
-    """Per-DOF algorithmic work of the hot path on a degree field:
-    bytes (compulsory HBM traffic) and flops of each operator."""
+def work_model(elem_p, sample=None):
+    """Algorithmic work of the hot path on a degree field: bytes (compulsory
+    HBM traffic: U, v read, R, Jv written, mesh data) and flops of each
+    operator.  Flops are counted operations of the method per DOF: those of a
+    sample of the same workload (mortar faces included) if one is named, else
+    per degree from uniform periodic boxes.  The residual costs the counted
+    residual; the tangents and the one-pass step cost the counted
+    forward-mode dual evaluation (value and derivative)."""
+    with open(FLOP_COUNTS) as f:
+        counts = json.load(f)
     n = elem_p.astype(np.int64) + 1
     dof = 5 * n ** 3
     n_dof, E = float(dof.sum()), float(len(n))
-    fres = float((dof * np.array([residual_flops_per_dof(k, ns) for k in n])).sum())
+    if sample:
+        fres = counts[sample]["residual_per_dof"] * n_dof
+        fdual = counts[sample]["dual_per_dof"] * n_dof
+    else:
+        tab = counts["uniform_4x4x4_navier_stokes"]
+        fres = float(sum(dof[n == k].sum() * tab[str(k - 1)]["residual_per_dof"] for k in set(n.tolist())))
+        fdual = float(sum(dof[n == k].sum() * tab[str(k - 1)]["dual_per_dof"] for k in set(n.tolist())))
     mesh = MESH_BYTES_PER_ELEMENT * E
     return {
         "n_dof": n_dof,
         "residual": {"bytes": 16 * n_dof + mesh, "flops": fres},
-        "jvp_f64": {"bytes": 24 * n_dof + mesh, "flops": TANGENT_FLOP_FACTOR * fres},
-        "jvp_f32": {"bytes": 12 * n_dof + mesh, "flops": TANGENT_FLOP_FACTOR * fres},
-        "residual_and_jvp": {"bytes": 32 * n_dof + mesh, "flops": TANGENT_FLOP_FACTOR * fres},
+        "jvp_f64": {"bytes": 24 * n_dof + mesh, "flops": fdual},
+        "jvp_f32": {"bytes": 12 * n_dof + mesh, "flops": fdual},
+        "residual_and_jvp": {"bytes": 32 * n_dof + mesh, "flops": fdual},
+        "planning_residual_flops": float((dof * np.array([planning_flops_per_dof(k) for k in n])).sum()),
     }
 
 
@@ -247,7 +263,7 @@ def main():
     print(f"[bench] residual + exact Jv (one pass): median {ms_step:.4f} ms/step (mean {ms_mean:.4f}), "
           f"{value:.3f} GDOF/s", file=sys.stderr, flush=True)
 
-    W = work_model(case.elem_p)
+    W = work_model(case.elem_p, sample=HEADLINE_SAMPLE)
     W["residual_and_jvp"]["n_dof"] = n_dof
     roof = roofline(W["residual_and_jvp"], ms_step * 1e-3)
     stages = stage_medians(ctx, U, op=3)
@@ -255,8 +271,11 @@ def main():
                       " (Dual<double>, navier-stokes, roe)")
     roof["launch_ms"] = round(ms_step, 5)
     roof["stages"] = [dict(s, share=round(s["ms"] / sum(x["ms"] for x in stages), 3)) for s in stages]
-    roof["work_model"] = (f"{W['residual_and_jvp']['flops'] / n_dof:.1f} flop/DOF "
-                          f"({TANGENT_FLOP_FACTOR} x the residual's 12n + 165 + 200/n), "
+    roof["work_model"] = (f"{W['residual_and_jvp']['flops'] / n_dof:.1f} flop/DOF (the oracle's counted "
+                          f"forward-mode dual evaluation on a 4x128x8 slab of this workload, "
+                          f"tests/golden/flop_counts.json; the residual alone "
+                          f"{W['residual']['flops'] / n_dof:.1f}, the planning estimate 12n + 165 + 200/n "
+                          f"{W['planning_residual_flops'] / n_dof:.1f}), "
                           f"{W['residual_and_jvp']['bytes'] / n_dof:.2f} B/DOF (U, v, R, Jv + "
                           f"{MESH_BYTES_PER_ELEMENT} B/element)")
     roof["traffic"] = measured_traffic(TRAFFIC_PROFILE)

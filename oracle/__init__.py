@@ -50,6 +50,8 @@ def lib():
         for name in ("oracle_residual", "oracle_residual_ld"):
             getattr(L, name).argtypes = [C.c_void_p, dp, dp]
         L.oracle_residual_terms.argtypes = [C.c_void_p, dp, dp, dp]
+        L.oracle_count_flops.restype = C.c_longlong
+        L.oracle_count_flops.argtypes = [C.c_void_p, dp, dp, C.c_int, dp]
         L.oracle_threads.restype = C.c_int
         L.oracle_set_threads.argtypes = [C.c_int]
         L.oracle_jvp_cs.argtypes = [C.c_void_p, dp, dp, dp]
@@ -195,6 +197,21 @@ class Oracle:
         R = np.zeros(self.shape)
         lib().oracle_residual(self.h, _p(U), _p(R))
         return R
+
+    def count_flops(self, U, v=None):
+        """Floating-point operations of one residual evaluation at U (v None)
+        or of one residual-and-tangent evaluation along v in forward-mode dual
+        arithmetic, counted operation by operation on the oracle's own code
+        (one per +, -, *, / and square root; the dual operations at their cost
+        in that arithmetic).  Returns (flops, R or J v)."""
+        U = self._vec(U)
+        out = np.zeros_like(U)
+        if v is None:
+            f = lib().oracle_count_flops(self.h, _p(U), _p(U), 0, _p(out))
+        else:
+            v = self._vec(v)
+            f = lib().oracle_count_flops(self.h, _p(U), _p(v), 1, _p(out))
+        return int(f), out
 
     def residual_terms(self, U):
         """(R, T): the residual and, per solution point, the sum of the

@@ -52,6 +52,69 @@ inline double ssqrt(double x) { return std::sqrt(x); }
 inline long double ssqrt(long double x) { return std::sqrt(x); }
 inline cplx ssqrt(const cplx& x) { return std::sqrt(x); }
 
+// ------------------------------------------------------- operation counting
+// Scalars that count the floating-point operations of the code that runs on
+// them (one per +, -, *, / and square root; a sign change or a comparison is
+// none), for the work model of the measured kernels.  Cnt is a counted real;
+// DCnt is a counted forward-mode dual number (value and derivative), with
+// each operation charged what it costs in that arithmetic: a product 3 (+1
+// for the value), a quotient 4, a square root 3, an operation with a plain
+// double half of that or less.  The counter is global: the counting entry
+// points run their residual with one thread.
+static long long g_flops = 0;
+struct Cnt {
+  double v;
+  Cnt() : v(0.0) {}
+  Cnt(double x) : v(x) {}
+};
+inline Cnt operator+(Cnt a, Cnt b) { ++g_flops; return Cnt(a.v + b.v); }
+inline Cnt operator-(Cnt a, Cnt b) { ++g_flops; return Cnt(a.v - b.v); }
+inline Cnt operator*(Cnt a, Cnt b) { ++g_flops; return Cnt(a.v * b.v); }
+inline Cnt operator/(Cnt a, Cnt b) { ++g_flops; return Cnt(a.v / b.v); }
+inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
+inline Cnt& operator+=(Cnt& a, Cnt b) { a = a + b; return a; }
+inline Cnt& operator-=(Cnt& a, Cnt b) { a = a - b; return a; }
+inline Cnt& operator*=(Cnt& a, Cnt b) { a = a * b; return a; }
+inline double re(const Cnt& x) { return x.v; }
+inline Cnt ssqrt(const Cnt& x) { ++g_flops; return Cnt(std::sqrt(x.v)); }
+
+struct DCnt {
+  double v, d;
+  DCnt() : v(0.0), d(0.0) {}
+  DCnt(double x) : v(x), d(0.0) {}
+  DCnt(double x, double y) : v(x), d(y) {}
+};
+inline DCnt operator+(DCnt a, DCnt b) { g_flops += 2; return DCnt(a.v + b.v, a.d + b.d); }
+inline DCnt operator-(DCnt a, DCnt b) { g_flops += 2; return DCnt(a.v - b.v, a.d - b.d); }
+inline DCnt operator*(DCnt a, DCnt b) { g_flops += 4; return DCnt(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline DCnt operator/(DCnt a, DCnt b) {
+  g_flops += 4;
+  const double q = a.v / b.v;
+  return DCnt(q, (a.d - q * b.d) / b.v);
+}
+inline DCnt operator+(DCnt a, double b) { g_flops += 1; return DCnt(a.v + b, a.d); }
+inline DCnt operator+(double a, DCnt b) { g_flops += 1; return DCnt(a + b.v, b.d); }
+inline DCnt operator-(DCnt a, double b) { g_flops += 1; return DCnt(a.v - b, a.d); }
+inline DCnt operator-(double a, DCnt b) { g_flops += 1; return DCnt(a - b.v, -b.d); }
+inline DCnt operator*(DCnt a, double b) { g_flops += 2; return DCnt(a.v * b, a.d * b); }
+inline DCnt operator*(double a, DCnt b) { g_flops += 2; return DCnt(a * b.v, a * b.d); }
+inline DCnt operator/(DCnt a, double b) { g_flops += 2; return DCnt(a.v / b, a.d / b); }
+inline DCnt operator/(double a, DCnt b) {
+  g_flops += 4;
+  const double q = a / b.v;
+  return DCnt(q, -q * b.d / b.v);
+}
+inline DCnt operator-(DCnt a) { return DCnt(-a.v, -a.d); }
+inline DCnt& operator+=(DCnt& a, DCnt b) { a = a + b; return a; }
+inline DCnt& operator-=(DCnt& a, DCnt b) { a = a - b; return a; }
+inline DCnt& operator*=(DCnt& a, DCnt b) { a = a * b; return a; }
+inline double re(const DCnt& x) { return x.v; }
+inline DCnt ssqrt(const DCnt& x) {
+  g_flops += 3;
+  const double r = std::sqrt(x.v);
+  return DCnt(r, x.d / (2.0 * r));
+}
+
 // ------------------------------------------------------- 1-D polynomial tools
 // Legendre P_k(x) and P_k'(x) for k = 0..K by the three-term recurrence.
 template <class R> static void legendre(int K, R x, R* P, R* dP) {
@@ -766,6 +829,36 @@ void oracle_residual(void* h, const double* U, double* R) { residual<double>(*(M
 // the terms it adds up, over |J| (see residual()).
 void oracle_residual_terms(void* h, const double* U, double* R, double* T) {
   residual<double>(*(Mesh*)h, U, R, nullptr, T);
+}
+
+// Floating-point operations of one residual evaluation (mode 0, counted
+// reals) or of one residual-and-tangent evaluation in forward-mode dual
+// arithmetic along v (mode 1), at the state U: the work model of the
+// measured kernels.  R receives the residual (mode 0) or the tangent (mode
+// 1).  Runs with one thread (the counter is global).
+long long oracle_count_flops(void* h, const double* U, const double* v, int mode, double* R) {
+  Mesh& M = *(Mesh*)h;
+  const long N = 5 * M.n_sp;
+#ifdef _OPENMP
+  const int nt = omp_get_max_threads();
+  omp_set_num_threads(1);
+#endif
+  g_flops = 0;
+  if (mode == 0) {
+    std::vector<Cnt> Uc(U, U + N), Rc(N);
+    residual<Cnt>(M, Uc.data(), Rc.data());
+    for (long i = 0; i < N; ++i) R[i] = Rc[i].v;
+  } else {
+    std::vector<DCnt> Uc(N), Rc(N);
+    for (long i = 0; i < N; ++i) Uc[i] = DCnt(U[i], v[i]);
+    residual<DCnt>(M, Uc.data(), Rc.data());
+    for (long i = 0; i < N; ++i) R[i] = Rc[i].d;
+  }
+  const long long f = g_flops;
+#ifdef _OPENMP
+  omp_set_num_threads(nt);
+#endif
+  return f;
 }
 
 // Threads an OpenMP region of the oracle uses (1 without OpenMP).
