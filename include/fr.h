@@ -151,7 +151,12 @@ typedef struct {
  * residual workspace.  Returns FR_E_INVALID for a non-conforming or
  * inconsistent description. */
 fr_status fr_create(const fr_mesh_desc* desc, fr_ctx* out);
+/* Releases a context.  Its device blocks and pinned host buffers go back to a
+ * per-device cache of the library, which later fr_create / fr_reserve calls
+ * reuse (a p-adaptation replaces a context by one of nearly the same sizes);
+ * fr_trim frees the cached blocks of every device. */
 fr_status fr_destroy(fr_ctx ctx);
+fr_status fr_trim(void);
 
 /* Number of degrees of freedom (5 x solution points) and, if sp_offset is not
  * NULL, the first solution point of every element (host [n_elem + 1]). */

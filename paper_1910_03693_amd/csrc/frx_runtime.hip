@@ -265,6 +265,83 @@ inline int graph_bit(int mode, int prec) {
                              : (mode == FR_JV_FD ? FR_GRAPHS_F64_FD : FR_GRAPHS_F64_FD_SCALED);
 }
 
+// Device memory of the contexts comes from, and goes back to, a cache of
+// freed blocks per device.  A p-adaptation replaces a context by one of
+// nearly the same sizes (Krylov basis, face slots, stage vectors), so the
+// new context takes the blocks the old one returned instead of unmapping and
+// mapping hundreds of MB.  A request takes the smallest cached block of at
+// least its size if that block is at most 1/8 larger; a miss allocates, and
+// an allocation failure empties the device's cache and tries once more.
+// Returned blocks beyond 16 GB of cache per device are freed.  fr_trim
+// empties the caches.  The same holds for the two small pinned host buffers
+// of every context.
+namespace {
+struct BlockCache {
+  std::mutex mu;
+  std::map<int, std::multimap<size_t, void*>> dev_free;  // device -> (size, block)
+  std::map<int, size_t> dev_bytes;
+  std::vector<void*> host_free;                          // pinned host blocks of HOST_BLOCK bytes
+};
+BlockCache& block_cache() {
+  static BlockCache* c = new BlockCache;  // never destroyed: blocks may be returned at process exit
+  return *c;
+}
+constexpr size_t CACHE_CAP = 16ull << 30;
+constexpr size_t HOST_BLOCK = 64 * sizeof(double);
+
+void* cache_take(int dev, size_t bytes, size_t* got) {
+  BlockCache& C = block_cache();
+  std::lock_guard<std::mutex> lock(C.mu);
+  auto& m = C.dev_free[dev];
+  auto it = m.lower_bound(bytes);
+  if (it == m.end() || it->first > bytes + bytes / 8) return nullptr;
+  void* p = it->second;
+  *got = it->first;
+  C.dev_bytes[dev] -= it->first;
+  m.erase(it);
+  return p;
+}
+void cache_give(int dev, void* p, size_t bytes) {
+  BlockCache& C = block_cache();
+  {
+    std::lock_guard<std::mutex> lock(C.mu);
+    if (C.dev_bytes[dev] + bytes <= CACHE_CAP) {
+      C.dev_free[dev].emplace(bytes, p);
+      C.dev_bytes[dev] += bytes;
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
+void cache_empty(int dev) {
+  BlockCache& C = block_cache();
+  std::lock_guard<std::mutex> lock(C.mu);
+  for (auto& kv : C.dev_free[dev]) (void)hipFree(kv.second);
+  C.dev_free[dev].clear();
+  C.dev_bytes[dev] = 0;
+}
+void* host_take() {
+  BlockCache& C = block_cache();
+  {
+    std::lock_guard<std::mutex> lock(C.mu);
+    if (!C.host_free.empty()) {
+      void* p = C.host_free.back();
+      C.host_free.pop_back();
+      return p;
+    }
+  }
+  void* p = nullptr;
+  FRX_TRY(hipHostMalloc(&p, HOST_BLOCK, 0));
+  return p;
+}
+void host_give(void* p) {
+  if (!p) return;
+  BlockCache& C = block_cache();
+  std::lock_guard<std::mutex> lock(C.mu);
+  C.host_free.push_back(p);
+}
+}  // namespace
+
 struct fr_ctx_s {
   MeshDev M;
   int dev = 0;
@@ -273,7 +350,7 @@ struct fr_ctx_s {
   std::vector<int8_t> p;
   std::vector<int64_t> sp_off_h;
   std::vector<int> fp_off_h;      // first face slot of each element
-  std::vector<void*> allocs;
+  std::vector<std::pair<void*, size_t>> allocs;  // device blocks and their sizes (from the block cache)
   hipStream_t cap = nullptr;  // private stream for graph capture
   // scratch for fr_jvp / operators
   double* t0 = nullptr;   // ndof
@@ -337,24 +414,36 @@ struct fr_ctx_s {
   std::vector<int4> faces_h;   // host copy of the concatenated face list (ranges in frange)
 
   void* dalloc(size_t bytes) {
-    void* p = nullptr;
-    if (bytes == 0) bytes = 8;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) throw StatusErr{FR_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
-    allocs.push_back(p);
+    bytes = (std::max<size_t>(bytes, 8) + 255) / 256 * 256;
+    size_t got = 0;
+    void* p = cache_take(dev, bytes, &got);
+    if (!p) {
+      got = bytes;
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        cache_empty(dev);
+        e = hipMalloc(&p, bytes);
+      }
+      if (e != hipSuccess) throw StatusErr{FR_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    }
+    allocs.emplace_back(p, got);
     return p;
   }
+  // (callers synchronise the device before they free: the block may be
+  // handed to another context at once)
   void dfree(void* p) {
     if (!p) return;
-    auto it = std::find(allocs.begin(), allocs.end(), p);
-    if (it != allocs.end()) allocs.erase(it);
-    (void)hipFree(p);
+    auto it = std::find_if(allocs.begin(), allocs.end(), [&](const std::pair<void*, size_t>& a) { return a.first == p; });
+    if (it == allocs.end()) return;
+    cache_give(dev, it->first, it->second);
+    allocs.erase(it);
   }
   ~fr_ctx_s() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
-    for (void* p : allocs) (void)hipFree(p);
-    if (hpin) (void)hipHostFree(hpin);
-    if (ipin) (void)hipHostFree(ipin);
+    for (auto& a : allocs) cache_give(dev, a.first, a.second);
+    host_give(hpin);
+    host_give(ipin);
     if (cap) (void)hipStreamDestroy(cap);
   }
 };
@@ -1506,8 +1595,8 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
     C->t1 = (double*)C->dalloc(sizeof(double) * C->ndof);
     C->t2 = (double*)C->dalloc(sizeof(double) * C->ndof);
     C->uf = (float*)C->dalloc(sizeof(float) * C->ndof);
-    FRX_TRY(hipHostMalloc((void**)&C->hpin, 64 * sizeof(double), 0));
-    FRX_TRY(hipHostMalloc((void**)&C->ipin, 64 * sizeof(int), 0));
+    C->hpin = (double*)host_take();
+    C->ipin = (int*)host_take();
     ensure_krylov(C.get(), 1);
     FRX_TRY(hipDeviceSynchronize());
     c = C.release();
@@ -1515,6 +1604,19 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
   });
   if (st == FR_OK) *out = c;
   return st;
+}
+
+fr_status fr_trim(void) {
+  BlockCache& C = block_cache();
+  std::lock_guard<std::mutex> lock(C.mu);
+  for (auto& dv : C.dev_free) {
+    for (auto& kv : dv.second) (void)hipFree(kv.second);
+    dv.second.clear();
+  }
+  for (auto& kv : C.dev_bytes) kv.second = 0;
+  for (void* p : C.host_free) (void)hipHostFree(p);
+  C.host_free.clear();
+  return FR_OK;
 }
 
 fr_status fr_destroy(fr_ctx c) {

@@ -34,7 +34,7 @@ STATUS_NAMES = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_NOMEM", -3: "FR_E_HIP"
 EXPORTED = ("fr_create", "fr_destroy", "fr_layout", "fr_reserve", "fr_residual", "fr_residual_noalloc", "fr_residual_jvp", "fr_jvp", "fr_vjp", "gmres_stage_solve",
             "esdirk_step", "spectral_decay_indicator", "fr_select_degrees", "fr_project", "fr_filter", "fr_autotune", "fr_profile",
             "fr_set_launch", "fr_check", "fr_launch_shapes", "fr_precond_build", "fr_precond_apply",
-            "fr_last_error")
+            "fr_trim", "fr_last_error")
 
 
 class FrError(RuntimeError):
@@ -113,6 +113,7 @@ def lib():
         L.fr_launch_shapes.argtypes = [vp, C.c_int32, vp, C.c_int32, C.POINTER(C.c_int32)]
         L.fr_precond_build.argtypes = [vp, vp, C.c_double, C.c_int32, vp]
         L.fr_precond_apply.argtypes = [vp, vp, vp, vp]
+        L.fr_trim.argtypes = []
         L.fr_last_error.restype = C.c_char_p
         L.fr_last_error.argtypes = [vp]
         for name in EXPORTED:
@@ -316,6 +317,12 @@ def fr_launch_shapes(h, kind):
     n = C.c_int32(0)
     _check(lib().fr_launch_shapes(h, int(kind), C.c_void_p(buf.ctypes.data), 256, C.byref(n)), h)
     return [tuple(int(x) for x in buf[3 * i:3 * i + 3]) for i in range(n.value)]
+
+
+def fr_trim():
+    """Frees the device blocks that destroyed contexts returned to the
+    library's cache."""
+    return lib().fr_trim()
 
 
 def fr_precond_build(h, U, sigma, precision=FR_F64, stream=None):
