@@ -595,7 +595,8 @@ def adaptive_study(steps=4):
                                          fused=True, eta_max_scope=frx.FR_ETA_MAX_SAME_DEGREE)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        ctx.close()
+        if ctx2 is not ctx:
+            ctx.close()
         ctx = ctx2
         rec = {"step_ms": round((t1 - t0) * 1e3, 1), "adapt_ms": round((t2 - t1) * 1e3, 1), **st,
                "n_dof_after": int(ctx.n_dof),
@@ -777,6 +778,7 @@ def g2_study(p_values=(1, 2, 3, 4, 5), steps=60):
         gm = ptc = 0
         dof_steps = []
         t_adapt = 0.0
+        n_new = 0  # adaptations that changed the degree field (a new context)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -790,14 +792,17 @@ def g2_study(p_values=(1, 2, 3, 4, 5), steps=60):
                 ta = time.perf_counter()
                 case, ctx2, U = adapt.adapt_step(case, ctx, U, p_min=1, p_max=k, reserve=reserve, fused=True,
                                                  eta_max_scope=scope)
-                ctx.close()
+                if ctx2 is not ctx:
+                    ctx.close()
+                    n_new += 1
                 ctx = ctx2
                 t_adapt += time.perf_counter() - ta
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
         err, err_rho = _vortex_l2_error(case, U.cpu().numpy(), steps * dt, uinf, period)
         ctx.close()
-        rec = {"run_ms": round(ms, 1), "adapt_ms": round(t_adapt * 1e3, 1), "l2_error": err, "l2_error_rho": err_rho,
+        rec = {"run_ms": round(ms, 1), "adapt_ms": round(t_adapt * 1e3, 1), "new_contexts": n_new,
+               "l2_error": err, "l2_error_rho": err_rho,
                "gmres_iterations": gm, "ptc_iterations": ptc, "mean_dof": int(np.mean(dof_steps)),
                "final_degree_histogram_p1_to_p5": np.bincount(case.elem_p, minlength=6)[1:].tolist()}
         print(f"[bench] g2 scheme {scheme} {'uniform p' if scope is None else 'adaptive (scope %d) p_max' % scope}"

@@ -49,12 +49,15 @@ def adapt_step(case, ctx, U, nu_max=0.1, nu_min=0.001, p_min=1, p_max=5, var=1, 
     indicator (1, the default: over the elements of the same degree; 0: over
     all elements, which on the isentropic vortex coarsens the vortex core to
     p <= 2 whatever p_max).
-    Returns (new case description, new context, new state)."""
+    Returns (new case description, new context, new state); when no degree
+    changes these are the given case, context and state themselves."""
     import dataclasses
 
     from . import frx
 
     p_new = ctx.select_degrees(U, var, nu_max, nu_min, p_min, p_max, eta_max_scope).cpu().numpy()
+    if np.array_equal(p_new.astype(np.int8), np.asarray(case.elem_p, np.int8)):
+        return case, ctx, U
     new_case = dataclasses.replace(case, elem_p=p_new.astype(np.int8), U=None)
     new_ctx = frx.Context.from_case(new_case, fused=fused, **(reserve or {}))
     return new_case, new_ctx, ctx.project_to(U, new_ctx)
