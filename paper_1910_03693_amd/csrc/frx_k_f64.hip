@@ -19,17 +19,15 @@ hipError_t launch_face_geometry(const MeshDev& M, hipStream_t s) {
     if (!b.count) continue;
     const long tot = (long)b.count * b.nh * b.nh;
     const dim3 grid((unsigned)((tot + 255) / 256));
-    hipLaunchKernelGGL(k_face_geo<double>, grid, dim3(256), 0, s, M.geo_d, b.faces, b.count, b.nl, b.nh, M.fgeo_d,
-                       M.nfp);
-    hipLaunchKernelGGL(k_face_geo<float>, grid, dim3(256), 0, s, M.geo_f, b.faces, b.count, b.nl, b.nh, M.fgeo_f,
-                       M.nfp);
+    hipLaunchKernelGGL(k_face_geo<double>, grid, dim3(256), 0, s, M.geo_d, b.faces, b.count, b.nl, b.nh, M.fgeo_d);
+    hipLaunchKernelGGL(k_face_geo<float>, grid, dim3(256), 0, s, M.geo_f, b.faces, b.count, b.nl, b.nh, M.fgeo_f);
   }
   for (const BFaceBucket& b : M.bb) {
     if (!b.count) continue;
     const long tot = (long)b.count * b.n * b.n;
     const dim3 grid((unsigned)((tot + 255) / 256));
-    hipLaunchKernelGGL(k_bface_geo<double>, grid, dim3(256), 0, s, M.geo_d, b.faces, b.count, b.n, M.fgeo_d, M.nfp);
-    hipLaunchKernelGGL(k_bface_geo<float>, grid, dim3(256), 0, s, M.geo_f, b.faces, b.count, b.n, M.fgeo_f, M.nfp);
+    hipLaunchKernelGGL(k_bface_geo<double>, grid, dim3(256), 0, s, M.geo_d, b.faces, b.count, b.n, M.fgeo_d);
+    hipLaunchKernelGGL(k_bface_geo<float>, grid, dim3(256), 0, s, M.geo_f, b.faces, b.count, b.n, M.fgeo_f);
   }
   return hipGetLastError();
 }

@@ -53,11 +53,12 @@ template <class T> struct ResArgs {
   const int* sp_off;   // [E] first solution point of each element
   const int* fp_off;   // [E] first face-slot point (6 n^2 per element)
   const B* geo;        // [E][24] trilinear monomial coefficients
-  const B* fgeo;       // [5][nfp] face-point geometry (k_face_geo)
-  T* QF;               // [5][nfp]  q traces
-  T* GF;               // [15][nfp] gradient traces (Navier-Stokes)
-  T* DQ;               // [5][nfp]  q_com - q at own face points
-  T* FS;               // [5][nfp]  f_com . S at own face points
+  // face-slot buffers, nv values per slot laid out by fslot()
+  const B* fgeo;       // nv 5: face-point geometry (k_face_geo)
+  T* QF;               // nv 5: q traces
+  T* GF;               // nv 15: gradient traces (Navier-Stokes)
+  T* DQ;               // nv 5: q_com - q at own face points
+  T* FS;               // nv 5: f_com . S at own face points
   Gas<B> gas;
   int* flag;           // set to 1 on a non-physical state (rho <= 0 or p <= 0)
   const int* skip;     // if set and nonzero the kernels return at once
@@ -86,6 +87,14 @@ __device__ __forceinline__ FaceRec face_rec(const int4 F) {
   r.d = (F.w >> 28) & 3;
   r.low_is_R = (F.w >> 30) & 1;
   return r;
+}
+
+// Face-slot buffers hold nv values per slot.  A face side (first slot fs,
+// n2 points) keeps its values as one [nv][n2] block at nv fs, so that the
+// variables of a face point share cache lines, and an element's six sides,
+// whose slots are consecutive, form one [6][nv][n2] block.
+__device__ __forceinline__ long fslot(int nv, long fs, int n2, int v, int pt) {
+  return (long)nv * fs + (v * n2 + pt);
 }
 
 // ---------------------------------------------------------------- trace stage
@@ -127,7 +136,7 @@ __device__ __forceinline__ void trace_body_rounds(const ResArgs<T>& a, const int
     const int f = rem / N2, pt = rem - f * N2;
     const int s2 = blk * epb + l2;
     if (s2 >= nel) continue;
-    const long o = elems[s2].z + f * N2 + pt;
+    const long fs = elems[s2].z + f * N2;
     const int d = f >> 1, fa = pt % N, fb = pt / N;
     const B* lf = (f & 1) ? O.lp[N] : O.lm[N];
     const T* q = sq + l2 * 5 * N3;
@@ -136,7 +145,7 @@ __device__ __forceinline__ void trace_body_rounds(const ResArgs<T>& a, const int
       T s = T(B(0));
 #pragma unroll
       for (int m = 0; m < N; ++m) s = fmab(lf[m], q[v * N3 + line_pt<N>(d, fa, fb, m)], s);
-      a.QF[(long)v * a.nfp + o] = s;
+      a.QF[fslot(5, fs, N2, v, pt)] = s;
     }
   }
   if (!NS) return;
@@ -175,14 +184,14 @@ __device__ __forceinline__ void trace_body_rounds(const ResArgs<T>& a, const int
       const int f = fp / N2, pt = fp - f * N2;
       const int s2 = blk * epb + l2;
       if (s2 >= nel) continue;
-      const long o = elems[s2].z + f * N2 + pt;
+      const long fs = elems[s2].z + f * N2;
       const int d = f >> 1;
       const B* lf = (f & 1) ? O.lp[N] : O.lm[N];
       const T* g = sq + (l2 * 5 + c) * N3;
       T s = T(B(0));
 #pragma unroll
       for (int m = 0; m < N; ++m) s = fmab(lf[m], g[line_pt<N>(d, pt % N, pt / N, m)], s);
-      a.GF[(long)(v * 3 + c) * a.nfp + o] = s;
+      a.GF[fslot(15, fs, N2, v * 3 + c, pt)] = s;
     }
   }
 }
@@ -243,7 +252,7 @@ __device__ __forceinline__ void trace_body(const ResArgs<T>& a, const int4* __re
     if (s2 >= nel) continue;
     const int f = fp / N2, pt = fp - f * N2;
     const int d = f >> 1, fa = pt % N, fb = pt / N;
-    const int o = elems[s2].z + fp;
+    const long fs = elems[s2].z + f * N2;
     const B* lf = (f & 1) ? O.lp[N] : O.lm[N];
     // start and stride of the normal line through (fa, fb)
     const int base = d == 0 ? N * (fa + N * fb) : (d == 1 ? fa + N2 * fb : fa + N * fb);
@@ -257,8 +266,8 @@ __device__ __forceinline__ void trace_body(const ResArgs<T>& a, const int4* __re
       T s = T(B(0));
 #pragma unroll
       for (int m = 0; m < N; ++m) s = fmab(w[m], src[v * N3 + m * stride], s);
-      if (v < 5) a.QF[v * a.nfp + o] = s;
-      else a.GF[(v - 5) * a.nfp + o] = s;
+      if (v < 5) a.QF[fslot(5, fs, N2, v, pt)] = s;
+      else a.GF[fslot(15, fs, N2, v - 5, pt)] = s;
     }
   }
 }
@@ -311,8 +320,8 @@ __device__ __forceinline__ void face_gather(const ResArgs<T>& a, const int4* __r
       const int f2 = blk * fpb + l2;
       if (f2 >= nf) continue;
       const FaceRec G2 = face_rec(faces[f2]);
-      const long o = (G2.low_is_R ? G2.oR : G2.oL) + p2;
-      slow[it] = vv < 5 ? a.QF[(long)vv * a.nfp + o] : a.GF[(long)(vv - 5) * a.nfp + o];
+      const long fs = G2.low_is_R ? G2.oR : G2.oL;
+      slow[it] = vv < 5 ? a.QF[fslot(5, fs, NL2, vv, p2)] : a.GF[fslot(15, fs, NL2, vv - 5, p2)];
     }
     __syncthreads();
   }
@@ -343,24 +352,24 @@ __device__ __forceinline__ void face_gather(const ResArgs<T>& a, const int4* __r
         else P.g[(vv - 5) / 3][(vv - 5) % 3] += acc;
       }
     } else {
-      const long o = (s ? F.oR : F.oL) + pt;
+      const long fs = s ? F.oR : F.oL;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) P.q[s][v] = a.QF[(long)v * a.nfp + o];
+      for (int v = 0; v < 5; ++v) P.q[s][v] = a.QF[fslot(5, fs, NH2, v, pt)];
       if (NS) {
 #pragma unroll
-        for (int vc = 0; vc < 15; ++vc) P.g[vc / 3][vc % 3] += a.GF[(long)vc * a.nfp + o];
+        for (int vc = 0; vc < 15; ++vc) P.g[vc / 3][vc % 3] += a.GF[fslot(15, fs, NH2, vc, pt)];
       }
     }
   }
   // geometry at the face point, kept at the high side's slot
-  const long og = (P.lowL ? F.oR : F.oL) + pt;
-  P.S[0] = a.fgeo[og];
-  P.S[1] = a.fgeo[a.nfp + og];
-  P.S[2] = a.fgeo[2L * a.nfp + og];
+  const long og = P.lowL ? F.oR : F.oL;
+  P.S[0] = a.fgeo[fslot(5, og, NH2, 0, pt)];
+  P.S[1] = a.fgeo[fslot(5, og, NH2, 1, pt)];
+  P.S[2] = a.fgeo[fslot(5, og, NH2, 2, pt)];
   P.cL = P.cR = B(0);
   if (NS) {
-    P.cL = a.fgeo[3L * a.nfp + og];
-    P.cR = a.fgeo[4L * a.nfp + og];
+    P.cL = a.fgeo[fslot(5, og, NH2, 3, pt)];
+    P.cR = a.fgeo[fslot(5, og, NH2, 4, pt)];
   }
 }
 
@@ -377,19 +386,17 @@ __device__ __forceinline__ void face_scatter(const ResArgs<T>& a, const int4* __
     T jL[5], jR[5];
     face_jumps<T, B>(P.q[0], P.q[1], jL, jR);
     if (!P.lowL) {
-      const long o = P.oL + pt;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        a.FS[(long)v * a.nfp + o] = fS[v];
-        a.DQ[(long)v * a.nfp + o] = jL[v];
+        a.FS[fslot(5, P.oL, NH2, v, pt)] = fS[v];
+        a.DQ[fslot(5, P.oL, NH2, v, pt)] = jL[v];
       }
     }
     if (!P.lowR) {
-      const long o = P.oR + pt;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        a.FS[(long)v * a.nfp + o] = fS[v];
-        a.DQ[(long)v * a.nfp + o] = jR[v];
+        a.FS[fslot(5, P.oR, NH2, v, pt)] = fS[v];
+        a.DQ[fslot(5, P.oR, NH2, v, pt)] = jR[v];
       }
     }
     if (MIX) {
@@ -409,7 +416,7 @@ __device__ __forceinline__ void face_scatter(const ResArgs<T>& a, const int4* __
       const int f2 = blk * fpb + l2;
       if (f2 >= nf) continue;
       const FaceRec G2 = face_rec(faces[f2]);
-      const long o = (G2.low_is_R ? G2.oR : G2.oL) + p2;
+      const long fs = G2.low_is_R ? G2.oR : G2.oL;
       const int aa = p2 % NL, bb = p2 / NL;
       const T* src = sout + l2 * 10 * NH2;
       for (int vv = 0; vv < 10; ++vv) {
@@ -421,8 +428,8 @@ __device__ __forceinline__ void face_scatter(const ResArgs<T>& a, const int4* __
           for (int A = 0; A < NH; ++A) row = fmab(O.P[NL - 2][NH - 2][aa][A], src[vv * NH2 + A + NH * Bq], row);
           acc = fmab(O.P[NL - 2][NH - 2][bb][Bq], row, acc);
         }
-        if (vv < 5) a.FS[(long)vv * a.nfp + o] = acc;
-        else a.DQ[(long)(vv - 5) * a.nfp + o] = acc;
+        if (vv < 5) a.FS[fslot(5, fs, NL2, vv, p2)] = acc;
+        else a.DQ[fslot(5, fs, NL2, vv - 5, p2)] = acc;
       }
     }
   }
@@ -450,22 +457,22 @@ __device__ __forceinline__ void bface_body(const ResArgs<T>& a, const int4* __re
   const int fi = gid / N2, pt = gid - fi * N2;
   const int4 F = faces[fi];
   const int bc = F.z, side = F.y & 1;
-  const long o = F.w + pt;
+  const long fs = F.w;
   T q[5], g[5][3];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) q[v] = a.QF[(long)v * a.nfp + o];
+  for (int v = 0; v < 5; ++v) q[v] = a.QF[fslot(5, fs, N2, v, pt)];
   if (NS) {
 #pragma unroll
-    for (int vc = 0; vc < 15; ++vc) g[vc / 3][vc % 3] = a.GF[(long)vc * a.nfp + o];
+    for (int vc = 0; vc < 15; ++vc) g[vc / 3][vc % 3] = a.GF[fslot(15, fs, N2, vc, pt)];
   }
-  const B S[3] = {a.fgeo[o], a.fgeo[a.nfp + o], a.fgeo[2L * a.nfp + o]};
-  const B cf = a.fgeo[3L * a.nfp + o];
+  const B S[3] = {a.fgeo[fslot(5, fs, N2, 0, pt)], a.fgeo[fslot(5, fs, N2, 1, pt)], a.fgeo[fslot(5, fs, N2, 2, pt)]};
+  const B cf = a.fgeo[fslot(5, fs, N2, 3, pt)];
   T fS[5], jmp[5];
   bface_fn<NS, T, B, FLUX>(q, g, S, cf, bc, side, a.gas, a.flux, fS, jmp);
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    a.FS[(long)v * a.nfp + o] = fS[v];
-    a.DQ[(long)v * a.nfp + o] = jmp[v];
+    a.FS[fslot(5, fs, N2, v, pt)] = fS[v];
+    a.DQ[fslot(5, fs, N2, v, pt)] = jmp[v];
   }
 }
 
@@ -477,10 +484,10 @@ __device__ __forceinline__ void bface_body(const ResArgs<T>& a, const int4* __re
 // S from L's map at r_d = +1 and the BR2 lifting coefficients
 // cL = g_R'(+1)/J_L = n_L^2/(2 J_L) > 0, cR = g_L'(-1)/J_R = -n_R^2/(2 J_R);
 // boundary face point: S and c = +-n^2/(2 J) (+ on the +xi^d face).
-// Layout [5][nfp]: S_x, S_y, S_z, cL (or c), cR.
+// Values (fslot, nv 5): S_x, S_y, S_z, cL (or c), cR.
 template <class B>
 __global__ void k_face_geo(const B* __restrict__ geo, const int4* __restrict__ faces, int nf, int nl, int nh,
-                           B* __restrict__ fg, int nfp) {
+                           B* __restrict__ fg) {
   const int nh2 = nh * nh;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (long)nf * nh2) return;
@@ -493,16 +500,16 @@ __global__ void k_face_geo(const B* __restrict__ geo, const int4* __restrict__ f
   face_geom<B>(geo + 24L * F.L, F.d, B(1), ta, tb, S, JL);
   face_geom<B>(geo + 24L * F.R, F.d, B(-1), ta, tb, SR, JR);
   const int nL = lowL ? nl : nh, nR = lowR ? nl : nh;
-  const long o = (lowL ? F.oR : F.oL) + pt;
-  fg[o] = S[0];
-  fg[nfp + o] = S[1];
-  fg[2L * nfp + o] = S[2];
-  fg[3L * nfp + o] = B(0.5) * B(nL * nL) / JL;
-  fg[4L * nfp + o] = -B(0.5) * B(nR * nR) / JR;
+  const long fs = lowL ? F.oR : F.oL;
+  fg[fslot(5, fs, nh2, 0, pt)] = S[0];
+  fg[fslot(5, fs, nh2, 1, pt)] = S[1];
+  fg[fslot(5, fs, nh2, 2, pt)] = S[2];
+  fg[fslot(5, fs, nh2, 3, pt)] = B(0.5) * B(nL * nL) / JL;
+  fg[fslot(5, fs, nh2, 4, pt)] = -B(0.5) * B(nR * nR) / JR;
 }
 template <class B>
 __global__ void k_bface_geo(const B* __restrict__ geo, const int4* __restrict__ faces, int nf, int n,
-                            B* __restrict__ fg, int nfp) {
+                            B* __restrict__ fg) {
   const int n2 = n * n;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (long)nf * n2) return;
@@ -512,12 +519,12 @@ __global__ void k_bface_geo(const B* __restrict__ geo, const int4* __restrict__ 
   const OpsTab<B>& O = ops<B>();
   B S[3], J;
   face_geom<B>(geo + 24L * e, d, side ? B(1) : B(-1), O.x[n][pt % n], O.x[n][pt / n], S, J);
-  const long o = F.w + pt;
-  fg[o] = S[0];
-  fg[nfp + o] = S[1];
-  fg[2L * nfp + o] = S[2];
-  fg[3L * nfp + o] = (side ? B(0.5) : B(-0.5)) * B(n2) / J;
-  fg[4L * nfp + o] = B(0);
+  const long fs = F.w;
+  fg[fslot(5, fs, n2, 0, pt)] = S[0];
+  fg[fslot(5, fs, n2, 1, pt)] = S[1];
+  fg[fslot(5, fs, n2, 2, pt)] = S[2];
+  fg[fslot(5, fs, n2, 3, pt)] = (side ? B(0.5) : B(-0.5)) * B(n2) / J;
+  fg[fslot(5, fs, n2, 4, pt)] = B(0);
 }
 
 // ------------------------------------------------- viscous face correction
@@ -553,8 +560,8 @@ __device__ __forceinline__ void face_visc_body(const ResArgs<T>& a, const int4* 
       const int f2 = blk * fpb + l2;
       if (f2 >= nf) continue;
       const FaceRec G2 = face_rec(faces[f2]);
-      const long o = (G2.low_is_R ? G2.oR : G2.oL) + p2;
-      slow[it] = vv < 5 ? a.QF[(long)vv * a.nfp + o] : a.GF[(long)(vv - 5) * a.nfp + o];
+      const long fs = G2.low_is_R ? G2.oR : G2.oL;
+      slow[it] = vv < 5 ? a.QF[fslot(5, fs, NL2, vv, p2)] : a.GF[fslot(15, fs, NL2, vv - 5, p2)];
     }
     __syncthreads();
   }
@@ -583,17 +590,18 @@ __device__ __forceinline__ void face_visc_body(const ResArgs<T>& a, const int4* 
           else g[(vv - 5) / 3][(vv - 5) % 3] += acc;
         }
       } else {
-        const long o = (s ? F.oR : F.oL) + pt;
+        const long fs = s ? F.oR : F.oL;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) q[s][v] = a.QF[(long)v * a.nfp + o];
+        for (int v = 0; v < 5; ++v) q[s][v] = a.QF[fslot(5, fs, NH2, v, pt)];
 #pragma unroll
-        for (int vc = 0; vc < 15; ++vc) g[vc / 3][vc % 3] += a.GF[(long)vc * a.nfp + o];
+        for (int vc = 0; vc < 15; ++vc) g[vc / 3][vc % 3] += a.GF[fslot(15, fs, NH2, vc, pt)];
       }
     }
-    const long og = (lowL ? F.oR : F.oL) + pt;
-    const B S[3] = {a.fgeo[og], a.fgeo[a.nfp + og], a.fgeo[2L * a.nfp + og]};
-    const B cL = a.fgeo[3L * a.nfp + og];
-    const B cR = a.fgeo[4L * a.nfp + og];
+    const long og = lowL ? F.oR : F.oL;
+    const B S[3] = {a.fgeo[fslot(5, og, NH2, 0, pt)], a.fgeo[fslot(5, og, NH2, 1, pt)],
+                    a.fgeo[fslot(5, og, NH2, 2, pt)]};
+    const B cL = a.fgeo[fslot(5, og, NH2, 3, pt)];
+    const B cR = a.fgeo[fslot(5, og, NH2, 4, pt)];
     // common solution and the BR2 common gradient from the jumps
     // q_com - q^- = (q^+ - q^-)/2, q_com - q^+ = -(q^+ - q^-)/2
     T qc[5], Gc[5][3];
@@ -611,14 +619,18 @@ __device__ __forceinline__ void face_visc_body(const ResArgs<T>& a, const int4* 
     for (int c = 0; c < 3; ++c) fv[c] = tau[c][0] * S[0] + tau[c][1] * S[1] + tau[c][2] * S[2];
     fv[3] = e[0] * S[0] + e[1] * S[1] + e[2] * S[2];
     if (!lowL) {
-      const long o = F.oL + pt;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) a.FS[(long)(1 + c) * a.nfp + o] = a.FS[(long)(1 + c) * a.nfp + o] - fv[c];
+      for (int c = 0; c < 4; ++c) {
+        const long o = fslot(5, F.oL, NH2, 1 + c, pt);
+        a.FS[o] = a.FS[o] - fv[c];
+      }
     }
     if (!lowR) {
-      const long o = F.oR + pt;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) a.FS[(long)(1 + c) * a.nfp + o] = a.FS[(long)(1 + c) * a.nfp + o] - fv[c];
+      for (int c = 0; c < 4; ++c) {
+        const long o = fslot(5, F.oR, NH2, 1 + c, pt);
+        a.FS[o] = a.FS[o] - fv[c];
+      }
     }
     if (MIX) {
       T* dst = sout + lf * 4 * NH2;
@@ -633,7 +645,7 @@ __device__ __forceinline__ void face_visc_body(const ResArgs<T>& a, const int4* 
       const int f2 = blk * fpb + l2;
       if (f2 >= nf) continue;
       const FaceRec G2 = face_rec(faces[f2]);
-      const long o = (G2.low_is_R ? G2.oR : G2.oL) + p2;
+      const long fs = G2.low_is_R ? G2.oR : G2.oL;
       const int aa = p2 % NL, bb = p2 / NL;
       const T* src = sout + l2 * 4 * NH2;
       for (int c = 0; c < 4; ++c) {
@@ -645,7 +657,8 @@ __device__ __forceinline__ void face_visc_body(const ResArgs<T>& a, const int4* 
           for (int A2 = 0; A2 < NH; ++A2) row = fmab(O.P[NL - 2][NH - 2][aa][A2], src[c * NH2 + A2 + NH * Bq2], row);
           acc = fmab(O.P[NL - 2][NH - 2][bb][Bq2], row, acc);
         }
-        a.FS[(long)(1 + c) * a.nfp + o] = a.FS[(long)(1 + c) * a.nfp + o] - acc;
+        const long o = fslot(5, fs, NL2, 1 + c, p2);
+        a.FS[o] = a.FS[o] - acc;
       }
     }
   }
@@ -677,13 +690,11 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int4* __rest
   }
   if (NS) {
     for (int it = tid; it < epb * 30 * N2; it += blockDim.x) {
-      // (element, variable, face, point): contiguous 6 n^2 runs per variable
+      // (element, face, variable, point): Y has the element's slot block layout
       const int l2 = it / (30 * N2), rem = it - l2 * 30 * N2;
-      const int v = rem / (6 * N2), fp = rem - v * 6 * N2;
-      const int f = fp / N2, p2 = fp - f * N2;
       const int s2 = blk * epb + l2;
       if (s2 >= nel) continue;
-      sY[(l2 * 30 + f * 5 + v) * N2 + p2] = a.DQ[(long)v * a.nfp + elems[s2].z + fp];
+      sY[it] = a.DQ[5L * elems[s2].z + rem];
     }
   }
   __syncthreads();
@@ -742,10 +753,8 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int4* __rest
       fsr[q] = T(B(0));
       if (it < items) {
         const int l2 = it / (10 * N2), rem = it - l2 * 10 * N2;
-        const int v = rem / (2 * N2), sp2 = rem - v * 2 * N2;
-        const int side = sp2 / N2, p2 = sp2 - side * N2, f = 2 * d + side;
         const int s2 = blk * epb + l2;
-        if (s2 < nel) fsr[q] = a.FS[(long)v * a.nfp + elems[s2].z + f * N2 + p2];
+        if (s2 < nel) fsr[q] = a.FS[5L * elems[s2].z + 10 * d * N2 + rem];
       }
     }
     __syncthreads();  // X (q or the previous direction) and Y are no longer read
@@ -766,14 +775,14 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int4* __rest
         }
     }
     // flux jumps f_com . S - f_loc on the two faces of direction d
-    // (element, variable, side, point): the two faces are contiguous slots
+    // (element, side, variable, point): the two faces are one contiguous block
 #pragma unroll
     for (int q = 0; q < FIT; ++q) {
       const int it = tid + q * (int)blockDim.x;
       if (it >= items) continue;
       const int l2 = it / (10 * N2), rem = it - l2 * 10 * N2;
-      const int v = rem / (2 * N2), sp2 = rem - v * 2 * N2;
-      const int side = sp2 / N2, p2 = sp2 - side * N2, f = 2 * d + side;
+      const int side = rem / (5 * N2), vp2 = rem - side * 5 * N2;
+      const int v = vp2 / N2, p2 = vp2 - v * N2, f = 2 * d + side;
       const int s2 = blk * epb + l2;
       if (s2 >= nel) continue;
       const B* lf = side ? O.lp[N] : O.lm[N];
@@ -787,8 +796,8 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int4* __rest
     // launchers do not make)
     for (int it = tid + FIT * (int)blockDim.x; it < items; it += blockDim.x) {
       const int l2 = it / (10 * N2), rem = it - l2 * 10 * N2;
-      const int v = rem / (2 * N2), sp2 = rem - v * 2 * N2;
-      const int side = sp2 / N2, p2 = sp2 - side * N2, f = 2 * d + side;
+      const int side = rem / (5 * N2), vp2 = rem - side * 5 * N2;
+      const int v = vp2 / N2, p2 = vp2 - v * N2, f = 2 * d + side;
       const int s2 = blk * epb + l2;
       if (s2 >= nel) continue;
       const B* lf = side ? O.lp[N] : O.lm[N];
@@ -796,7 +805,7 @@ __device__ __forceinline__ void div_body(const ResArgs<T>& a, const int4* __rest
       T floc = T(B(0));
 #pragma unroll
       for (int m = 0; m < N; ++m) floc = fmab(lf[m], X[line_pt<N>(d, p2 % N, p2 / N, m)], floc);
-      sY[(l2 * 30 + f * 5 + v) * N2 + p2] = a.FS[(long)v * a.nfp + elems[s2].z + f * N2 + p2] - floc;
+      sY[(l2 * 30 + f * 5 + v) * N2 + p2] = a.FS[5L * elems[s2].z + 10 * d * N2 + rem] - floc;
     }
     __syncthreads();
     if (act) {

@@ -27,7 +27,8 @@ struct VjpArgs {
   const int* sp_off;
   const int* fp_off;
   const double* geo;
-  const double* fgeo;  // [5][nfp] face-point geometry (k_face_geo)
+  // face-slot buffers, nv values per slot laid out by fslot()
+  const double* fgeo;  // nv 5: face-point geometry (k_face_geo)
   double* QF;  // forward q traces, then their adjoints
   double* GF;  // forward gradient traces, then their adjoints
   double* DQ;  // forward solution jumps, then their adjoints
@@ -192,11 +193,9 @@ __device__ __forceinline__ void div_rev_body(const VjpArgs& a, const int* __rest
   if (NS) {
     for (int it = tid; it < epb * 30 * N2; it += blockDim.x) {
       const int l2 = it / (30 * N2), rem = it - l2 * 30 * N2;
-      const int fv = rem / N2, p2 = rem - fv * N2;
       const int s2 = blk * epb + l2;
       if (s2 >= nel) continue;
-      const int f = fv / 5, v = fv - f * 5;
-      sY[it] = a.DQ[(long)v * a.nfp + a.fp_off[elems[s2]] + f * N2 + p2];
+      sY[it] = a.DQ[5L * a.fp_off[elems[s2]] + rem];  // the element's [6][5][n^2] block
     }
   }
   __syncthreads();
@@ -253,7 +252,7 @@ __device__ __forceinline__ void div_rev_body(const VjpArgs& a, const int* __rest
 #pragma unroll
     for (int m = 0; m < N; ++m) s = fma(gf[m], X[line_pt<N>(d, p2 % N, p2 / N, m)], s);
     sY[it] = s;
-    a.FS[(long)v * a.nfp + a.fp_off[elems[s2]] + f * N2 + p2] = s;
+    a.FS[5L * a.fp_off[elems[s2]] + rem] = s;
   }
   __syncthreads();
   double Ub[5];
@@ -312,13 +311,13 @@ __device__ __forceinline__ void div_rev_body(const VjpArgs& a, const int* __rest
         const int sv = rem / N2, p2 = rem - sv * N2;
         const int s2 = blk * epb + l2;
         if (s2 >= nel) continue;
-        const int side = sv / 5, v = sv - side * 5, f = 2 * i + side;
+        const int side = sv / 5, v = sv - side * 5;
         const double* gf = side ? O.gR[N] : O.gL[N];
         const double* X = sX + (l2 * 5 + v) * N3;
         double s = 0.0;
 #pragma unroll
         for (int m = 0; m < N; ++m) s = fma(gf[m], X[line_pt<N>(i, p2 % N, p2 / N, m)], s);
-        a.DQ[(long)v * a.nfp + a.fp_off[elems[s2]] + f * N2 + p2] = s;
+        a.DQ[5L * a.fp_off[elems[s2]] + 10 * i * N2 + rem] = s;
       }
     }
   }
@@ -373,12 +372,12 @@ __device__ __forceinline__ void face_rev_gather(const VjpArgs& a, const int4* __
       const int f2 = blk * fpb + l2;
       if (f2 >= nf) continue;
       const FaceRec G2 = face_rec(faces[f2]);
-      const long o = (G2.low_is_R ? G2.oR : G2.oL) + p2;
+      const long fs = G2.low_is_R ? G2.oR : G2.oL;
       double val;
-      if (vv < 5) val = a.QF[(long)vv * a.nfp + o];
-      else if (vv < NV) val = a.GF[(long)(vv - 5) * a.nfp + o];
-      else if (vv < NV + 5) val = a.FS[(long)(vv - NV) * a.nfp + o];
-      else val = a.DQ[(long)(vv - NV - 5) * a.nfp + o];
+      if (vv < 5) val = a.QF[fslot(5, fs, NL2, vv, p2)];
+      else if (vv < NV) val = a.GF[fslot(15, fs, NL2, vv - 5, p2)];
+      else if (vv < NV + 5) val = a.FS[fslot(5, fs, NL2, vv - NV, p2)];
+      else val = a.DQ[fslot(5, fs, NL2, vv - NV - 5, p2)];
       if (vv < NV) slow[(l2 * NV + vv) * NL2 + p2] = val;
       else sadj[(l2 * 10 + vv - NV) * NL2 + p2] = val;
     }
@@ -412,26 +411,26 @@ __device__ __forceinline__ void face_rev_gather(const VjpArgs& a, const int4* __
         else P.jb[s][w - 5] = NS ? acc : 0.0;
       }
     } else {
-      const long o = (s ? F.oR : F.oL) + pt;
+      const long fs = s ? F.oR : F.oL;
       for (int v = 0; v < 5; ++v) {
-        P.q[s][v] = a.QF[(long)v * a.nfp + o];
-        P.fSb[v] += a.FS[(long)v * a.nfp + o];
-        P.jb[s][v] = NS ? a.DQ[(long)v * a.nfp + o] : 0.0;  // Euler: jumps do not enter R
+        P.q[s][v] = a.QF[fslot(5, fs, NH2, v, pt)];
+        P.fSb[v] += a.FS[fslot(5, fs, NH2, v, pt)];
+        P.jb[s][v] = NS ? a.DQ[fslot(5, fs, NH2, v, pt)] : 0.0;  // Euler: jumps do not enter R
       }
       if (NS) {
-        for (int vc = 0; vc < 15; ++vc) P.g[s][vc / 3][vc % 3] = a.GF[(long)vc * a.nfp + o];
+        for (int vc = 0; vc < 15; ++vc) P.g[s][vc / 3][vc % 3] = a.GF[fslot(15, fs, NH2, vc, pt)];
       } else {
         for (int vc = 0; vc < 15; ++vc) P.g[s][vc / 3][vc % 3] = 0.0;
       }
     }
   }
   // geometry of the face point, kept at the high side's slot
-  const long og = (P.lowL ? F.oR : F.oL) + pt;
-  P.S[0] = a.fgeo[og];
-  P.S[1] = a.fgeo[a.nfp + og];
-  P.S[2] = a.fgeo[2L * a.nfp + og];
-  P.cL = NS ? a.fgeo[3L * a.nfp + og] : 0.0;
-  P.cR = NS ? a.fgeo[4L * a.nfp + og] : 0.0;
+  const long og = P.lowL ? F.oR : F.oL;
+  P.S[0] = a.fgeo[fslot(5, og, NH2, 0, pt)];
+  P.S[1] = a.fgeo[fslot(5, og, NH2, 1, pt)];
+  P.S[2] = a.fgeo[fslot(5, og, NH2, 2, pt)];
+  P.cL = NS ? a.fgeo[fslot(5, og, NH2, 3, pt)] : 0.0;
+  P.cR = NS ? a.fgeo[fslot(5, og, NH2, 4, pt)] : 0.0;
 }
 
 template <int NL, int NH, bool NS>
@@ -448,10 +447,10 @@ __device__ __forceinline__ void face_rev_scatter(const VjpArgs& a, const int4* _
     for (int s = 0; s < 2; ++s) {
       const bool low = s ? P.lowR : P.lowL;
       if (!low) {
-        const long o = (s ? P.oR : P.oL) + pt;
-        for (int v = 0; v < 5; ++v) a.QF[(long)v * a.nfp + o] = qb[s][v];
+        const long fs = s ? P.oR : P.oL;
+        for (int v = 0; v < 5; ++v) a.QF[fslot(5, fs, NH2, v, pt)] = qb[s][v];
         if (NS)
-          for (int vc = 0; vc < 15; ++vc) a.GF[(long)vc * a.nfp + o] = gb[s][vc / 3][vc % 3];
+          for (int vc = 0; vc < 15; ++vc) a.GF[fslot(15, fs, NH2, vc, pt)] = gb[s][vc / 3][vc % 3];
       } else {
         double* dst = sres + P.lf * NV * NH2;
         for (int v = 0; v < 5; ++v) dst[v * NH2 + pt] = qb[s][v];
@@ -468,7 +467,7 @@ __device__ __forceinline__ void face_rev_scatter(const VjpArgs& a, const int4* _
       const int f2 = blk * fpb + l2;
       if (f2 >= nf) continue;
       const FaceRec G2 = face_rec(faces[f2]);
-      const long o = (G2.low_is_R ? G2.oR : G2.oL) + p2;
+      const long fs = G2.low_is_R ? G2.oR : G2.oL;
       const int aa = p2 % NL, bb = p2 / NL;
       const double* src = sres + l2 * NV * NH2;
       for (int vv = 0; vv < NV; ++vv) {
@@ -476,8 +475,8 @@ __device__ __forceinline__ void face_rev_scatter(const VjpArgs& a, const int4* _
         for (int Bq = 0; Bq < NH; ++Bq)
           for (int A = 0; A < NH; ++A)
             acc += O.I[NL - 2][NH - 2][A][aa] * O.I[NL - 2][NH - 2][Bq][bb] * src[vv * NH2 + A + NH * Bq];
-        if (vv < 5) a.QF[(long)vv * a.nfp + o] = acc;
-        else a.GF[(long)(vv - 5) * a.nfp + o] = acc;
+        if (vv < 5) a.QF[fslot(5, fs, NL2, vv, p2)] = acc;
+        else a.GF[fslot(15, fs, NL2, vv - 5, p2)] = acc;
       }
     }
   }
@@ -510,14 +509,14 @@ __device__ __forceinline__ void bface_rev_body(const VjpArgs& a, const int4* __r
   const int4 F = faces[fi];
   const int e = F.x, f = F.y, bc = F.z, d = f >> 1, side = f & 1;
   const OpsTab<double>& O = ops<double>();
-  const long o = F.w + pt;
+  const long fs = F.w;
   double q[5], g[5][3], fSb[5], jb[5];
   for (int v = 0; v < 5; ++v) {
-    q[v] = a.QF[(long)v * a.nfp + o];
-    fSb[v] = a.FS[(long)v * a.nfp + o];
-    jb[v] = NS ? a.DQ[(long)v * a.nfp + o] : 0.0;
+    q[v] = a.QF[fslot(5, fs, N2, v, pt)];
+    fSb[v] = a.FS[fslot(5, fs, N2, v, pt)];
+    jb[v] = NS ? a.DQ[fslot(5, fs, N2, v, pt)] : 0.0;
   }
-  for (int vc = 0; vc < 15; ++vc) g[vc / 3][vc % 3] = NS ? a.GF[(long)vc * a.nfp + o] : 0.0;
+  for (int vc = 0; vc < 15; ++vc) g[vc / 3][vc % 3] = NS ? a.GF[fslot(15, fs, N2, vc, pt)] : 0.0;
   double S[3], J;
   face_geom<double>(a.geo + 24L * e, d, side ? 1.0 : -1.0, O.x[N][pt % N], O.x[N][pt / N], S, J);
   const double cf = (side ? 0.5 : -0.5) * (double)(N * N) / J;
@@ -536,9 +535,9 @@ __device__ __forceinline__ void bface_rev_body(const VjpArgs& a, const int4* __r
     if (j < 5) qb[j] = s;
     else gb[(j - 5) / 3][(j - 5) % 3] = s;
   }
-  for (int v = 0; v < 5; ++v) a.QF[(long)v * a.nfp + o] = qb[v];
+  for (int v = 0; v < 5; ++v) a.QF[fslot(5, fs, N2, v, pt)] = qb[v];
   if (NS)
-    for (int vc = 0; vc < 15; ++vc) a.GF[(long)vc * a.nfp + o] = gb[vc / 3][vc % 3];
+    for (int vc = 0; vc < 15; ++vc) a.GF[fslot(15, fs, N2, vc, pt)] = gb[vc / 3][vc % 3];
 }
 template <int N, bool NS>
 __global__ void __launch_bounds__(256) k_bface_rev(VjpArgs a, const int4* __restrict__ faces, int nf) {
@@ -575,17 +574,17 @@ __device__ __forceinline__ void trace_rev_body(const VjpArgs& a, const int* __re
 #pragma unroll
     for (int dd = 0; dd < 3; ++dd) {
       const int fp = dd == 0 ? i1 + N * i2 : (dd == 1 ? i0 + N * i2 : i0 + N * i1);
-      const long om = fb + (2 * dd) * N2 + fp, op = fb + (2 * dd + 1) * N2 + fp;
+      const long fm = fb + (2 * dd) * N2, fq = fb + (2 * dd + 1) * N2;
       const double wm = O.lm[N][id[dd]], wp = O.lp[N][id[dd]];
 #pragma unroll
       for (int v = 0; v < 5; ++v)
-        Ub[v] += wm * a.QF[(long)v * a.nfp + om] + wp * a.QF[(long)v * a.nfp + op];
+        Ub[v] += wm * a.QF[fslot(5, fm, N2, v, fp)] + wp * a.QF[fslot(5, fq, N2, v, fp)];
       if (NS) {
 #pragma unroll
         for (int v = 0; v < 5; ++v)
 #pragma unroll
           for (int c = 0; c < 3; ++c)
-            gbar[v][c] += wm * a.GF[(long)(v * 3 + c) * a.nfp + om] + wp * a.GF[(long)(v * 3 + c) * a.nfp + op];
+            gbar[v][c] += wm * a.GF[fslot(15, fm, N2, v * 3 + c, fp)] + wp * a.GF[fslot(15, fq, N2, v * 3 + c, fp)];
       }
     }
     if (NS) {
