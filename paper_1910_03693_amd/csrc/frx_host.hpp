@@ -109,23 +109,25 @@ template <class B> struct ResCall {
   const int* skip = nullptr;  // device flag: skip all work when nonzero
 };
 
-// The face and divergence stages of the fused launch restricted to a subset
-// of the elements: the divergence over them, the face stage over the faces
-// with a side among them (their residual rows need no other face).  The
-// trace stage still runs over every element from the full plan.
+// The stages of the fused launch restricted to a subset of the elements:
+// the divergence over them, the face stage over the faces with a side among
+// them (their residual rows need no other face), the trace stage over them.
 struct FusedSubset {
   const int4* elems = nullptr;  // records of the subset's elements, by degree bucket
   const int4* faces = nullptr;  // interior faces with a side in the subset, then its boundary faces
-  FusedPlan plan[SK_COUNT];     // tiles of stages 1 (faces) and 2 (divergence) per scalar kind
+  FusedPlan plan[SK_COUNT];     // tiles of the three stages per scalar kind
 };
 
-// residual (SK_F64) or residual-and-tangent (duals) on a stream; with a
-// subset (fused launch mode only) R and Jv are written for its elements only
+// residual (SK_F64) or residual-and-tangent (duals) on a stream.  Fused
+// launch mode only: with a subset `sub` R and Jv are written for its elements
+// only; with a trace subset `tsub` the trace stage runs over its elements
+// only, and the face slots of every other element must already hold its
+// traces (of the same U and v) from an earlier pass.
 hipError_t launch_residual_f64(const MeshDev& M, const ResCall<double>& c, hipStream_t s);
 hipError_t launch_residual_dual64(const MeshDev& M, const ResCall<double>& c, hipStream_t s,
-                                  const FusedSubset* sub = nullptr);
+                                  const FusedSubset* sub = nullptr, const FusedSubset* tsub = nullptr);
 hipError_t launch_residual_dual32(const MeshDev& M, const ResCall<float>& c, hipStream_t s,
-                                  const FusedSubset* sub = nullptr);
+                                  const FusedSubset* sub = nullptr, const FusedSubset* tsub = nullptr);
 
 // operator tables into each translation unit's constant memory
 hipError_t upload_tables_f64(const OpsTab<double>& d, const OpsTab<float>& f);

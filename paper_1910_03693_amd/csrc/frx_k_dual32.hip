@@ -10,7 +10,8 @@ hipError_t upload_tables_dual32(const OpsTab<double>& d, const OpsTab<float>& f)
   return hipMemcpyToSymbol(HIP_SYMBOL(c_ops_f), &f, sizeof(f));
 }
 
-hipError_t launch_residual_dual32(const MeshDev& M, const ResCall<float>& c, hipStream_t s, const FusedSubset* sub) {
-  return launch_residual_T<Dual<float>>(M, c, SK_DUAL32, s, sub);
+hipError_t launch_residual_dual32(const MeshDev& M, const ResCall<float>& c, hipStream_t s, const FusedSubset* sub,
+                                  const FusedSubset* tsub) {
+  return launch_residual_T<Dual<float>>(M, c, SK_DUAL32, s, sub, tsub);
 }
 }  // namespace frx

@@ -217,9 +217,10 @@ hipError_t face_stage_fused(const ResArgs<T>& a, const MeshDev& M, const FusedPl
 
 template <class T, bool NS>
 hipError_t residual_fused(const ResArgs<T>& a, const MeshDev& M, int sk, hipStream_t s,
-                          const FusedSubset* sub = nullptr) {
-  const FusedPlan& P = M.plan[sk];
-  const FusedPlan& Q = sub ? sub->plan[sk] : P;  // face and divergence stages
+                          const FusedSubset* sub = nullptr, const FusedSubset* tsub = nullptr) {
+  const FusedPlan& P = tsub ? tsub->plan[sk] : M.plan[sk];  // trace stage
+  const FusedPlan& Q = sub ? sub->plan[sk] : M.plan[sk];    // face and divergence stages
+  const int4* elems0 = tsub ? tsub->elems : M.all_elems;
   const int4* faces = sub ? sub->faces : M.all_faces;
   const int4* elems2 = sub ? sub->elems : M.all_elems;
   ProfHook* H = M.prof;
@@ -230,7 +231,7 @@ hipError_t residual_fused(const ResArgs<T>& a, const MeshDev& M, int sk, hipStre
     if (!X.count[st]) continue;
     if (H) H->begin(names[st], 0, 0, X.count[st], s);
     if (st == 0)
-      hipLaunchKernelGGL((k_trace_fused<T, NS>), dim3(P.count[0]), dim3(256), P.lds[0], s, a, M.all_elems, P.tiles[0]);
+      hipLaunchKernelGGL((k_trace_fused<T, NS>), dim3(P.count[0]), dim3(256), P.lds[0], s, a, elems0, P.tiles[0]);
     else if (st == 1) {
       const bool two_pass = NS && M.split_faces[1][sk];
       e = M.flux == 1 ? face_stage_fused<T, NS, 1>(a, M, Q, two_pass, s, faces)
@@ -247,7 +248,7 @@ hipError_t residual_fused(const ResArgs<T>& a, const MeshDev& M, int sk, hipStre
 
 template <class T>
 hipError_t launch_residual_T(const MeshDev& M, const ResCall<base_t<T>>& c, int sk, hipStream_t s,
-                             const FusedSubset* sub = nullptr) {
+                             const FusedSubset* sub = nullptr, const FusedSubset* tsub = nullptr) {
   using B = base_t<T>;
   ResArgs<T> a;
   a.U = c.U;
@@ -274,7 +275,8 @@ hipError_t launch_residual_T(const MeshDev& M, const ResCall<base_t<T>>& c, int 
   a.flag = M.flag;
   a.skip = c.skip;
   if (M.fused)
-    return M.physics == 1 ? residual_fused<T, true>(a, M, sk, s, sub) : residual_fused<T, false>(a, M, sk, s, sub);
+    return M.physics == 1 ? residual_fused<T, true>(a, M, sk, s, sub, tsub)
+                          : residual_fused<T, false>(a, M, sk, s, sub, tsub);
   return M.physics == 1 ? residual_stages<T, true>(a, M, sk, s) : residual_stages<T, false>(a, M, sk, s);
 }
 

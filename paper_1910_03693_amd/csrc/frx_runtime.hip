@@ -816,6 +816,13 @@ void pc_build(fr_ctx c, const double* U, double sigma, hipStream_t s, bool half 
   for (size_t col = 0; col < c->pc_crecs.size(); ++col) {
     const int cnt = c->pc_ccount[col];
     if (!cnt) continue;
+    // Traces of an element depend on its own U and v only.  The first product
+    // of a colour traces every element; each later one traces the elements
+    // seeded in the previous product (a superset of its own seeded elements):
+    // that gives the newly seeded tangents and clears those of the elements
+    // that dropped out, so every other element's slots keep their values and
+    // a zero tangent.
+    const FusedSubset* prev = nullptr;
     for (int j = 0; j <= c->pc_nmax; ++j) {
       const int jn = j < c->pc_nmax ? j : -1;  // the last pass only clears the seed
       if (f64)
@@ -831,12 +838,13 @@ void pc_build(fr_ctx c, const double* U, double sigma, hipStream_t s, bool half 
       int nmin = 2;
       while (nmin < NMAX && 5 * nmin * nmin * nmin <= j) ++nmin;
       const FusedSubset* sub = c->M.fused ? c->pc_sub[col][nmin].get() : nullptr;
+      if (c->M.fused && !sub) continue;  // no element of the colour has N_e > j
       if (f64) {
         ResCall<double> rc;
         rc.U = U;
         rc.V = c->t0;
         rc.out = c->t1;
-        FRX_TRY(launch_residual_dual64(c->M, rc, s, sub));
+        FRX_TRY(launch_residual_dual64(c->M, rc, s, sub, prev));
         hipLaunchKernelGGL((k_pc_extract<double, double>), dim3(cnt), dim3(256), 0, s, (const double*)c->t1,
                            c->M.nsp, (const int4*)c->pc_crecs[col], (const int*)c->pc_cidx[col], j, sigma,
                            (const long*)c->pc_boff, (double*)c->pc_blocks);
@@ -845,12 +853,13 @@ void pc_build(fr_ctx c, const double* U, double sigma, hipStream_t s, bool half 
         rc.U = c->uf;
         rc.V = (const float*)c->t0;
         rc.out = (float*)c->t1;
-        FRX_TRY(launch_residual_dual32(c->M, rc, s, sub));
+        FRX_TRY(launch_residual_dual32(c->M, rc, s, sub, prev));
         hipLaunchKernelGGL((k_pc_extract<float, float>), dim3(cnt), dim3(256), 0, s, (const float*)c->t1,
                            c->M.nsp, (const int4*)c->pc_crecs[col], (const int*)c->pc_cidx[col], j, sigma,
                            (const long*)c->pc_boff, (float*)c->pc_blocks);
       }
       FRX_TRY(hipGetLastError());
+      prev = sub;
     }
   }
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->pc_flag, 0);
@@ -1281,7 +1290,7 @@ void build_fused_plans(fr_ctx c, const fr_mesh_desc* d, const std::map<std::pair
 // The fused subsets of the preconditioner assembly (see pc_sub): per colour
 // k and size n, the elements of colour k with n_e >= n by degree bucket, the
 // interior faces with a side among them and their boundary faces, both in
-// the order of the full face list, and the face and divergence tiles of
+// the order of the full face list, and the tiles of the three stages of
 // every scalar kind with the default items per tile.  Built once, by
 // fr_reserve with preconditioner storage.
 void build_pc_subsets(fr_ctx c) {
@@ -1321,7 +1330,7 @@ void build_pc_subsets(fr_ctx c) {
       if (!faces.empty()) FRX_TRY(hipMemcpy(df, faces.data(), sizeof(int4) * faces.size(), hipMemcpyHostToDevice));
       S->faces = df;
       for (int sk = 0; sk < SK_COUNT; ++sk)
-        for (int st = 1; st < 3; ++st) {
+        for (int st = 0; st < 3; ++st) {
           size_t lds = 0;
           int nint = 0;
           const std::vector<int4> t = make_tiles(c, sk, st, er, fr, false, &lds, &nint);
