@@ -171,7 +171,8 @@ enum {
   FR_GRAPHS_F64_FD_SCALED = 8,
   FR_GRAPHS_ALL = 15,
   /* storage of the element-Jacobi preconditioner (one of the two): sum over
-   * elements of N_e^2 float64 or float32 entries, N_e = 5 (p_e + 1)^3 */
+   * elements of N_e^2 float64 or float32 entries (each block rounded up to a
+   * multiple of 32 entries), N_e = 5 (p_e + 1)^3 */
   FR_RESERVE_PRECOND_F64 = 16,
   FR_RESERVE_PRECOND_F32 = 32
 };

@@ -25,6 +25,12 @@ struct PcDev {
 };
 
 __device__ __forceinline__ int pc_rows(int n) { return 5 * n * n * n; }
+// Entries reserved per block of order N: N^2 rounded up to 32, so that every
+// block starts on a 128-byte boundary (float32 storage).
+__host__ __device__ inline long pc_block_size(int N) { return ((long)N * N + 31) & ~31L; }
+// Column stride of the float16 copy of a block (k_pc_to_half): N rounded up to
+// 8, so that every column starts on a 16-byte boundary.
+__host__ __device__ inline int pc_ld_half(int N) { return (N + 7) & ~7; }
 // DOF j of an element (variable-major inside the element: j = v n^3 + k) in
 // the state layout U[v][sp]
 __device__ __forceinline__ long pc_dof(int j, int n, int sp0, int nsp) {
@@ -392,44 +398,45 @@ __global__ void __launch_bounds__(256) k_pc_inv(TB* __restrict__ blocks, PcDev p
 // k_pc_to_half leaves: z = P x (float, LDS), the product accumulated in
 // float32 and scaled by sc = 1/sigma.  Called by k_pc_apply (float32
 // storage) when the device flag asks for it; shapes as there.
+// The float16 copy has column stride pc_ld_half(N): a thread owns 8
+// consecutive rows and reads them with one 16-byte load per column; the
+// columns are split over blockDim.x / (LD / 8) groups of threads, whose
+// partial sums meet in LDS (part: at least 8 blockDim.x floats).
 template <class TV>
 __device__ void pc_apply_half(TV* __restrict__ x, int nsp, const float* __restrict__ blocks, const PcDev& pc,
                               const int* __restrict__ piv, float sc, float* z, float* part) {
   const int4 r = pc.recs[blockIdx.x];
-  const int N = pc_rows(r.z);
+  const int N = pc_rows(r.z), LD = pc_ld_half(N);
   const _Float16* A = reinterpret_cast<const _Float16*>(blocks + pc.boff[blockIdx.x]);
   const int* P = piv + pc.poff[blockIdx.x];
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += blockDim.x) z[i] = (float)x[pc_dof(P[i], r.z, r.y, nsp)];
   __syncthreads();
-  const int slots = (N + 63) & ~63;
-  if (slots <= 128) {
-    const int groups = 256 / slots, g = tid / slots, i = tid - g * slots;
-    const int k0 = g * N / groups, k1 = (g + 1) * N / groups;
-    float acc = 0.0f;
-    if (i < N)
-      for (int k = k0; k < k1; ++k) acc += (float)A[i + (long)k * N] * z[k];
-    part[tid] = acc;
-    __syncthreads();
-    if (g == 0 && i < N) {
-      for (int h = 1; h < groups; ++h) acc += part[h * slots + i];
-      x[pc_dof(i, r.z, r.y, nsp)] = (TV)(acc * sc);
+  const int nrg = LD / 8;                           // row groups, at most PC_NMAX / 8 = 135
+  const int ncg = (int)blockDim.x / nrg;            // column groups, at least 1
+  const int rg = tid % nrg, cg = tid / nrg;
+  if (cg < ncg) {
+    float acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
+    const int k0 = cg * N / ncg, k1 = (cg + 1) * N / ncg;
+    const _Float16* col = A + 8 * rg;
+#pragma unroll 4
+    for (int k = k0; k < k1; ++k) {
+      const uint4 w = *reinterpret_cast<const uint4*>(col + (long)k * LD);
+      const _Float16* h = reinterpret_cast<const _Float16*>(&w);
+      const float zk = z[k];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] += (float)h[q] * zk;
     }
-    return;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) part[cg * LD + 8 * rg + q] = acc[q];
   }
-  for (int i0 = tid & ~63; i0 < N; i0 += blockDim.x) {
-    const int i = i0 + (tid & 63);
-    if (i >= N) break;
-    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
-    int k = 0;
-    for (; k + 4 <= N; k += 4) {
-      a0 += (float)A[i + (long)k * N] * z[k];
-      a1 += (float)A[i + (long)(k + 1) * N] * z[k + 1];
-      a2 += (float)A[i + (long)(k + 2) * N] * z[k + 2];
-      a3 += (float)A[i + (long)(k + 3) * N] * z[k + 3];
-    }
-    for (; k < N; ++k) a0 += (float)A[i + (long)k * N] * z[k];
-    x[pc_dof(i, r.z, r.y, nsp)] = (TV)(((a0 + a1) + (a2 + a3)) * sc);
+  __syncthreads();
+  for (int i = tid; i < N; i += blockDim.x) {
+    float s = 0.0f;
+    for (int g = 0; g < ncg; ++g) s += part[g * LD + i];
+    x[pc_dof(i, r.z, r.y, nsp)] = (TV)(s * sc);
   }
 }
 
@@ -449,7 +456,7 @@ __global__ void __launch_bounds__(256) k_pc_apply(TV* __restrict__ x, int nsp, c
   const int mode = *on;
   if (!mode || (done && *done)) return;
   __shared__ TB z[PC_NMAX];
-  __shared__ TB part[256];
+  __shared__ TB part[sizeof(TB) == 4 ? 8 * 256 : 256];  // float32 storage: also the float16 path's partial sums
   if constexpr (sizeof(TB) == 4) {
     if (mode == 2) {
       pc_apply_half<TV>(x, nsp, (const float*)blocks, pc, piv, (float)*isig, (float*)z, (float*)part);
@@ -497,10 +504,14 @@ __global__ void __launch_bounds__(256) k_pc_apply(TV* __restrict__ x, int nsp, c
 // Half-precision copy of the inverse for the apply (float32 build): every
 // element's float32 (P A)^{-1} is replaced, in place at the start of its own
 // block, by float16 values of sigma (P A)^{-1} (entries of order one, since
-// the blocks are sigma I minus the Jacobian block).  A chunk of 256 entries is
-// read, then written after a barrier: the float16 entries of a chunk cover
-// float32 entries of the same or earlier chunks only.  One 256-thread block
-// per element (blockDim.x = 256), per degree bucket (ids).
+// the blocks are sigma I minus the Jacobian block), column-major with column
+// stride LD = pc_ld_half(N) and zero pad rows.  A chunk of 256 entries is
+// read, then written after a barrier: float32 entry k = c N + r ends at byte
+// 4 (k + 1), its float16 value (and, for r = N - 1, the pad of column c) ends
+// at byte 2 (c LD + r + 1) <= 4 (k + 1) (or 2 (c + 1) LD <= 4 (k + 1)), as
+// LD <= 2 N: a chunk's float16 values cover float32 entries of the same or
+// earlier chunks only.  One 256-thread block per element (blockDim.x = 256),
+// per degree bucket (ids).
 __global__ void __launch_bounds__(256) k_pc_to_half(float* __restrict__ blocks, PcDev pc, const int* __restrict__ ids,
                                                    double sigma) {
   const int el = ids ? ids[blockIdx.x] : (int)blockIdx.x;
@@ -508,6 +519,7 @@ __global__ void __launch_bounds__(256) k_pc_to_half(float* __restrict__ blocks, 
   float* A = blocks + pc.boff[el];
   _Float16* H = reinterpret_cast<_Float16*>(A);
   const long NN = (long)N * N;
+  const int LD = pc_ld_half(N);
   const float sg = (float)sigma;
   __shared__ float stage[256];
   for (long k0 = 0; k0 < NN; k0 += blockDim.x) {
@@ -516,7 +528,12 @@ __global__ void __launch_bounds__(256) k_pc_to_half(float* __restrict__ blocks, 
     // stored in LDS) before the barrier that precedes the overwriting stores
     stage[threadIdx.x] = k < NN ? A[k] : 0.0f;
     __syncthreads();
-    if (k < NN) H[k] = (_Float16)(sg * stage[threadIdx.x]);
+    if (k < NN) {
+      const int c = (int)(k / N), r = (int)(k - (long)c * N);
+      H[(long)c * LD + r] = (_Float16)(sg * stage[threadIdx.x]);
+      if (r == N - 1)
+        for (int q = N; q < LD; ++q) H[(long)c * LD + q] = (_Float16)0.0f;
+    }
     __syncthreads();
   }
 }

@@ -392,7 +392,7 @@ struct fr_ctx_s {
   void* scratch_dev = nullptr;
   // element-Jacobi preconditioner (section 2.3): storage made by fr_reserve
   // in one precision, built by fr_precond_build or at the start of a step
-  void* pc_blocks = nullptr;   // dense blocks, column-major, [sum_e N_e^2] of pc_prec
+  void* pc_blocks = nullptr;   // dense blocks, column-major, [sum_e pc_block_size(N_e)] of pc_prec
   int pc_prec = -1;            // FR_F64 / FR_F32 storage, -1: none
   bool pc_built = false;
   bool pc_half = false;        // the built inverse is kept as float16 of sigma times it (float32 storage)
@@ -1542,7 +1542,7 @@ fr_status fr_create(const fr_mesh_desc* d, fr_ctx* out) {
         recs[e] = make_int4(e, sp[e], n, 0);
         boff[e] = b;
         poff[e] = pv;
-        b += (long)N * N;
+        b += pc_block_size(N);
         pv += N;
         C->pc_nmax = std::max(C->pc_nmax, N);
       }
@@ -1657,10 +1657,7 @@ fr_status fr_reserve(fr_ctx c, int32_t max_restart, int32_t graph_sets) {
       // one block of N_e^2 entries per element, N_e = 5 (p_e + 1)^3
       if (c->pc_blocks) c->dfree(c->pc_blocks);
       long entries = 0;
-      for (int e = 0; e < c->M.E; ++e) {
-        const long N = 5L * (c->p[e] + 1) * (c->p[e] + 1) * (c->p[e] + 1);
-        entries += N * N;
-      }
+      for (int e = 0; e < c->M.E; ++e) entries += pc_block_size(5 * (c->p[e] + 1) * (c->p[e] + 1) * (c->p[e] + 1));
       c->pc_blocks = c->dalloc((size_t)entries * (want == FR_F64 ? sizeof(double) : sizeof(float)));
       c->pc_prec = want;
       c->pc_built = false;
