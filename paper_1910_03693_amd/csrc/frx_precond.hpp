@@ -77,16 +77,17 @@ __global__ void __launch_bounds__(256) k_pc_extract(const TV* __restrict__ Jv, i
 // solved with its unit lower triangle, and the trailing matrix updated once
 // per panel (each thread holds the panel's multipliers of its rows in
 // registers, U12 staged in LDS).  A zero pivot column (a singular block)
-// sets *flag.  Launched per degree bucket: ids lists the bucket's elements
-// (null: element = block index) and the dynamic LDS holds PB N scalars.
+// sets *flag.  Launched per degree bucket (pc_lu_launch): ids lists the
+// bucket's elements (null: element = block index), R (rows per thread,
+// 256 R >= N), the panel width PB and the columns per trailing step CG are
+// chosen by the block order, and the dynamic LDS holds PB N scalars.
 constexpr int PC_NMAX = 5 * 6 * 6 * 6;            // largest block order (p = 5)
-constexpr int PC_ROWS = (PC_NMAX + 255) / 256;    // trailing rows per thread
+constexpr int PC_ROWS = (PC_NMAX + 255) / 256;    // rows per thread for every order
 template <class TB> struct PcPanel { static constexpr int value = sizeof(TB) == 8 ? 8 : 16; };
 
-template <class TB>
+template <class TB, int R, int PB, int CG>
 __global__ void __launch_bounds__(256) k_pc_lu(TB* __restrict__ blocks, PcDev pc, const int* __restrict__ ids,
                                               int* __restrict__ piv, int* __restrict__ flag) {
-  constexpr int PB = PcPanel<TB>::value;
   extern __shared__ __align__(16) unsigned char pc_lds[];
   TB* pan = reinterpret_cast<TB*>(pc_lds);  // [PB N]: pan[c * nr + (r - k0)], panel column c, rows k0..N-1
   __shared__ double red_v[256];
@@ -186,9 +187,9 @@ __global__ void __launch_bounds__(256) k_pc_lu(TB* __restrict__ blocks, PcDev pc
     }
     __syncthreads();
     // 6. trailing update A22 -= L21 U12, a thread per row (multipliers in registers)
-    TB l[PC_ROWS][PB];
+    TB l[R][PB];
 #pragma unroll
-    for (int q = 0; q < PC_ROWS; ++q) {
+    for (int q = 0; q < R; ++q) {
       const int r = w + tid + q * (int)blockDim.x;
 #pragma unroll
       for (int t = 0; t < PB; ++t) l[q][t] = (r < nr && t < w) ? pan[t * nr + r] : TB(0);
@@ -201,32 +202,32 @@ __global__ void __launch_bounds__(256) k_pc_lu(TB* __restrict__ blocks, PcDev pc
       u12[x] = t < w ? A[(k0 + t) + (long)(j0 + jj) * N] : TB(0);
     }
     __syncthreads();
-    // four columns per step: 4 PC_ROWS independent loads per thread in flight
-    for (int jj = 0; jj < nt; jj += 4) {
-      TB a4[PC_ROWS][4];
+    // CG columns per step: CG R independent loads per thread in flight
+    for (int jj = 0; jj < nt; jj += CG) {
+      TB a4[R][CG];
 #pragma unroll
-      for (int q = 0; q < PC_ROWS; ++q) {
+      for (int q = 0; q < R; ++q) {
         const int r = w + tid + q * (int)blockDim.x;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < CG; ++c)
           a4[q][c] = (r < nr && jj + c < nt) ? A[(k0 + r) + (long)(j0 + jj + c) * N] : TB(0);
       }
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < CG; ++c) {
         if (jj + c >= nt) break;
         TB u[PB];
 #pragma unroll
         for (int t = 0; t < PB; ++t) u[t] = u12[(jj + c) * PB + t];
 #pragma unroll
-        for (int q = 0; q < PC_ROWS; ++q)
+        for (int q = 0; q < R; ++q)
 #pragma unroll
           for (int t = 0; t < PB; ++t) a4[q][c] -= l[q][t] * u[t];
       }
 #pragma unroll
-      for (int q = 0; q < PC_ROWS; ++q) {
+      for (int q = 0; q < R; ++q) {
         const int r = w + tid + q * (int)blockDim.x;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < CG; ++c)
           if (r < nr && jj + c < nt) A[(k0 + r) + (long)(j0 + jj + c) * N] = a4[q][c];
       }
     }
@@ -255,6 +256,29 @@ __global__ void __launch_bounds__(256) k_pc_lu(TB* __restrict__ blocks, PcDev pc
     }
   __syncthreads();
   for (int i = tid; i < N; i += blockDim.x) P[i] = perm[i];
+}
+
+// The LU of `count` blocks of order N (one degree bucket): rows per thread as
+// few as the order allows, which leaves the registers for a wider panel (the
+// trailing matrix is read and written once per panel: 24 float32 or 12
+// float64 columns against 16 or 8, an 8 % shorter build at 128x128x8, where
+// 32 float32 columns, with 2 trailing columns per step to stay in registers,
+// gained less); blocks of order 1080 (p = 5) keep 5 rows and a narrow panel.
+template <class TB, int R, int PB, int CG>
+hipError_t pc_lu_shape(TB* blocks, const PcDev& pc, const int* ids, int count, int N, int* piv, int* flag,
+                       hipStream_t s) {
+  hipLaunchKernelGGL((k_pc_lu<TB, R, PB, CG>), dim3(count), dim3(256), (size_t)PB * N * sizeof(TB), s, blocks, pc,
+                     ids, piv, flag);
+  return hipGetLastError();
+}
+template <class TB>
+hipError_t pc_lu_launch(TB* blocks, const PcDev& pc, const int* ids, int count, int N, int* piv, int* flag,
+                        hipStream_t s) {
+  constexpr int PB = sizeof(TB) == 8 ? 12 : 24;  // about 60 KB of LDS per block at N = 625
+  if (N <= 256) return pc_lu_shape<TB, 1, PB, 4>(blocks, pc, ids, count, N, piv, flag, s);
+  if (N <= 512) return pc_lu_shape<TB, 2, PB, 4>(blocks, pc, ids, count, N, piv, flag, s);
+  if (N <= 768) return pc_lu_shape<TB, 3, PB, 4>(blocks, pc, ids, count, N, piv, flag, s);
+  return pc_lu_shape<TB, PC_ROWS, PcPanel<TB>::value, 4>(blocks, pc, ids, count, N, piv, flag, s);
 }
 
 // The inverse of every factored block, in place: from the L\U of P A left
