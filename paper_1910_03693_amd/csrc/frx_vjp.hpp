@@ -38,13 +38,50 @@ struct VjpArgs {
 
 using D64 = Dual<double>;
 
+// Adjoint of viscous_terms with respect to the gradient Gq at fixed q: the
+// stress and energy flux are linear in Gq, so G-bar follows from the
+// adjoints of tau[a][c] (taub, as the consumers read tau; viscous_terms
+// stores one value in tau[a][c] and tau[c][a]) and of e[c] (eb) through the
+// transposed chain: e -> (tau, dT), tau -> du, dT -> (dE, du), du and dE -> Gq.
+__device__ __forceinline__ void visc_grad_adjoint(const double q[5], const double taub[3][3], const double eb[3],
+                                                  const Gas<double>& gas, double Gb[5][3]) {
+  const double ir = 1.0 / q[0];
+  const double u[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
+  const double E = q[4] * ir;
+  double T[3][3];  // adjoint of tau[a][c] including e[c] = u_a tau[a][c] + ...
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) T[a][c] = taub[a][c] + u[a] * eb[c];
+  const double tr = T[0][0] + T[1][1] + T[2][2];
+  double dub[3][3];  // adjoint of du[a][c] = d u_a / d x_c
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dub[a][c] = gas.mu * (T[a][c] + T[c][a]) - (a == c ? (2.0 / 3.0) * gas.mu * tr : 0.0);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double dTb = gas.kappa * eb[c];
+    const double dEb = gas.gm1 * dTb;
+    double g0 = -E * dEb * ir;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double d = dub[a][c] - gas.gm1 * u[a] * dTb;
+      Gb[1 + a][c] = d * ir;
+      g0 -= u[a] * d * ir;
+    }
+    Gb[4][c] = dEb * ir;
+    Gb[0][c] = g0;
+  }
+}
+
 // q-bar, G-bar of Ft = volume_flux(q, G, Ja) for the output adjoint Fb
 template <bool NS>
 __device__ void volume_flux_vjp(const double q[5], const double G[5][3], const double Ja[3][3], const Gas<double>& gas,
                                 const double Fb[3][5], double qb[5], double Gb[5][3]) {
-  constexpr int NI = NS ? 20 : 5;
+  // q-bar: one forward sweep per state component, the gradient held fixed
 #pragma unroll 1
-  for (int j = 0; j < NI; ++j) {
+  for (int j = 0; j < 5; ++j) {
     D64 qd[5], Gd[5][3];
 #pragma unroll
     for (int v = 0; v < 5; ++v) qd[v] = D64(q[v], j == v ? 1.0 : 0.0);
@@ -52,7 +89,7 @@ __device__ void volume_flux_vjp(const double q[5], const double G[5][3], const d
 #pragma unroll
       for (int v = 0; v < 5; ++v)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Gd[v][c] = D64(G[v][c], j == 5 + v * 3 + c ? 1.0 : 0.0);
+        for (int c = 0; c < 3; ++c) Gd[v][c] = D64(G[v][c]);
     }
     D64 Ft[3][5];
     volume_flux<D64, double, NS>(qd, Gd, Ja, gas, Ft);
@@ -66,15 +103,22 @@ __device__ void volume_flux_vjp(const double q[5], const double G[5][3], const d
 #pragma unroll
     for (int v = 0; v < 5; ++v)
       if (j == v) qb[v] = s;
-    if (NS) {
-#pragma unroll
-      for (int vc = 0; vc < 15; ++vc)
-        if (j == 5 + vc) Gb[vc / 3][vc % 3] = s;
-    }
   }
-  if (!NS)
+  if (NS) {
+    // G-bar: Ft^i -= Ja^i . tau and Ja^i . e, linear in G
+    double taub[3][3], eb[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      eb[c] = -(Fb[0][4] * Ja[0][c] + Fb[1][4] * Ja[1][c] + Fb[2][4] * Ja[2][c]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        taub[a][c] = -(Fb[0][1 + a] * Ja[0][c] + Fb[1][1 + a] * Ja[1][c] + Fb[2][1 + a] * Ja[2][c]);
+    }
+    visc_grad_adjoint(q, taub, eb, gas, Gb);
+  } else {
     for (int v = 0; v < 5; ++v)
       for (int c = 0; c < 3; ++c) Gb[v][c] = 0.0;
+  }
 }
 
 // viscous part of the common flux dotted with S: (0, tau . S, e . S)
@@ -128,23 +172,33 @@ __device__ void face_fn_vjp(const double qL[5], const double qR[5], const double
 #pragma unroll
       for (int c = 0; c < 3; ++c) Gc[v][c] = 0.5 * (gL[v][c] + gR[v][c] + S[c] * lift);
     }
-    double Gcb[5][3];
+    // q_com-bar: one forward sweep per component at fixed G_com
 #pragma unroll 1
-    for (int j = 0; j < 20; ++j) {
+    for (int j = 0; j < 5; ++j) {
       D64 a[5], G[5][3], o[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) a[v] = D64(qc[v], j == v ? 1.0 : 0.0);
 #pragma unroll
       for (int v = 0; v < 5; ++v)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) G[v][c] = D64(Gc[v][c], j == 5 + v * 3 + c ? 1.0 : 0.0);
+        for (int c = 0; c < 3; ++c) G[v][c] = D64(Gc[v][c]);
       visc_dot_S(a, G, S, gas, o);
       double s = 0.0;
 #pragma unroll
       for (int v = 0; v < 5; ++v) s -= o[v].d * fSb[v];  // fS = Riemann - visc
-      if (j < 5) qcb[j] += s;
-      else Gcb[(j - 5) / 3][(j - 5) % 3] = s;
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        if (j == v) qcb[v] += s;
     }
+    // G_com-bar: the viscous flux (tau . S, e . S) is linear in G_com
+    double taub[3][3], eb[3], Gcb[5][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      eb[c] = -fSb[4] * S[c];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) taub[a][c] = -fSb[1 + a] * S[c];
+    }
+    visc_grad_adjoint(qc, taub, eb, gas, Gcb);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       double sg = 0.0;
@@ -385,15 +439,20 @@ __device__ __forceinline__ void face_rev_gather(const VjpArgs& a, const int4* __
   }
   if (!P.act) return;
   const int pt = P.pt, A = pt % NH, Bq = pt / NH;
+#pragma unroll
   for (int v = 0; v < 5; ++v) P.fSb[v] = 0.0;
+#pragma unroll
   for (int s = 0; s < 2; ++s) {
     const bool low = s ? P.lowR : P.lowL;
     if (low) {
       const double* src = slow + P.lf * NV * NL2;
+#pragma unroll
       for (int vv = 0; vv < NV; ++vv) {
         double acc = 0.0;
+#pragma unroll
         for (int b = 0; b < NL; ++b) {
           double row = 0.0;
+#pragma unroll
           for (int aa = 0; aa < NL; ++aa) row = fma(O.I[NL - 2][NH - 2][A][aa], src[vv * NL2 + aa + NL * b], row);
           acc = fma(O.I[NL - 2][NH - 2][Bq][b], row, acc);
         }
@@ -402,9 +461,12 @@ __device__ __forceinline__ void face_rev_gather(const VjpArgs& a, const int4* __
       }
       // transposed projection of the low side's adjoints
       const double* adj = sadj + P.lf * 10 * NL2;
+#pragma unroll
       for (int w = 0; w < 10; ++w) {
         double acc = 0.0;
+#pragma unroll
         for (int b = 0; b < NL; ++b)
+#pragma unroll
           for (int aa = 0; aa < NL; ++aa)
             acc += O.P[NL - 2][NH - 2][aa][A] * O.P[NL - 2][NH - 2][b][Bq] * adj[w * NL2 + aa + NL * b];
         if (w < 5) P.fSb[w] += acc;
@@ -412,14 +474,17 @@ __device__ __forceinline__ void face_rev_gather(const VjpArgs& a, const int4* __
       }
     } else {
       const long fs = s ? F.oR : F.oL;
+#pragma unroll
       for (int v = 0; v < 5; ++v) {
         P.q[s][v] = a.QF[fslot(5, fs, NH2, v, pt)];
         P.fSb[v] += a.FS[fslot(5, fs, NH2, v, pt)];
         P.jb[s][v] = NS ? a.DQ[fslot(5, fs, NH2, v, pt)] : 0.0;  // Euler: jumps do not enter R
       }
       if (NS) {
+#pragma unroll
         for (int vc = 0; vc < 15; ++vc) P.g[s][vc / 3][vc % 3] = a.GF[fslot(15, fs, NH2, vc, pt)];
       } else {
+#pragma unroll
         for (int vc = 0; vc < 15; ++vc) P.g[s][vc / 3][vc % 3] = 0.0;
       }
     }
@@ -444,17 +509,22 @@ __device__ __forceinline__ void face_rev_scatter(const VjpArgs& a, const int4* _
   const OpsTab<double>& O = ops<double>();
   const int tid = threadIdx.x, pt = P.pt;
   if (P.act) {
+#pragma unroll
     for (int s = 0; s < 2; ++s) {
       const bool low = s ? P.lowR : P.lowL;
       if (!low) {
         const long fs = s ? P.oR : P.oL;
+#pragma unroll
         for (int v = 0; v < 5; ++v) a.QF[fslot(5, fs, NH2, v, pt)] = qb[s][v];
         if (NS)
+#pragma unroll
           for (int vc = 0; vc < 15; ++vc) a.GF[fslot(15, fs, NH2, vc, pt)] = gb[s][vc / 3][vc % 3];
       } else {
         double* dst = sres + P.lf * NV * NH2;
+#pragma unroll
         for (int v = 0; v < 5; ++v) dst[v * NH2 + pt] = qb[s][v];
         if (NS)
+#pragma unroll
           for (int vc = 0; vc < 15; ++vc) dst[(5 + vc) * NH2 + pt] = gb[s][vc / 3][vc % 3];
       }
     }
@@ -660,8 +730,8 @@ __global__ void __launch_bounds__(256) k_elem_rev_fused(VjpArgs a, const int* __
 // Interior-face tiles (the plan puts them first); boundary-face tiles go to
 // k_bface_rev_fused.
 template <bool NS, int FLUX>
-__global__ void __launch_bounds__(256) k_face_rev_fused(VjpArgs a, const int4* __restrict__ faces,
-                                                        const int4* __restrict__ tiles) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_face_rev_fused(VjpArgs a, const int4* __restrict__ faces, const int4* __restrict__ tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int4 t = tiles[blockIdx.x];
   FaceRevPt P;
