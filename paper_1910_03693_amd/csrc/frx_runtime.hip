@@ -244,8 +244,11 @@ struct GraphKey {
   }
 };
 // Captured Arnoldi graphs, all instantiated by fr_reserve for the reserved
-// restart M: "heads" cover iterations [0, h) for h in {3, 6, 12, ...} below M
-// and h = M; "chunks" cover [3i, min(3i + 3, M)).  A cycle replays the largest
+// restart M: "heads" cover iterations [0, h) for h in {3, 6, 12} below M,
+// and h = M when M <= 12; "chunks" cover [3i, min(3i + 3, M)).  (Longer heads
+// would save a few host round trips per long cycle, and doubled the capture
+// work of every new context, which the p-adaptation makes at every step.)
+// A cycle replays the largest
 // head not above the iterations that the previous cycle of the same (mode,
 // precision) needed, then chunks.  Between two graphs the host reads the
 // device's converged flag, so a converged cycle stops early instead of
@@ -253,10 +256,11 @@ struct GraphKey {
 // the finite-difference step are read from device memory, so one graph set
 // serves every restart <= M and every step size.
 constexpr int ARNOLDI_CHUNK = 3;
+constexpr int ARNOLDI_HEAD_MAX = 12;
 std::vector<int> arnoldi_heads(int M) {
   std::vector<int> h;
-  for (int k = ARNOLDI_CHUNK; k < M; k *= 2) h.push_back(k);
-  h.push_back(M);
+  for (int k = ARNOLDI_CHUNK; k < M && k <= ARNOLDI_HEAD_MAX; k *= 2) h.push_back(k);
+  if (M <= ARNOLDI_HEAD_MAX) h.push_back(M);
   return h;
 }
 // graph-set bits of fr_reserve for (jv mode, precision)
