@@ -21,6 +21,18 @@ constexpr int NMAX = 6;  // n = p + 1 <= 6 (p <= 5)
 // plan keeps every tile's LDS within 160 KB / waves (64 KB at most).
 constexpr int FRX_STAGE_WAVES[3][3] = {{4, 4, 3}, {4, 2, 3}, {4, 4, 4}};
 
+// LDS scalars per element of the trace stage for Navier-Stokes (ns) at n
+// points per direction and sb bytes per scalar: q and the uncorrected
+// gradient (20 n^3) up to FRX_TRACE_LDS_ALL bytes, else q alone with the
+// gradient passed through it one variable at a time (5 n^3); Euler: q (5 n^3).
+// (The one-variable rounds double the elements per CU at p = 3 and 4, and
+// were slower there: the 128x128x8 float64-dual trace took 0.92 ms with a
+// 32 KB limit and 1.05 ms with 16 KB, against 0.84 ms.)
+constexpr int FRX_TRACE_LDS_ALL = 65536;
+__host__ __device__ constexpr int trace_lds_vals(bool ns, int n, int sb) {
+  return (ns && 20 * n * n * n * sb > FRX_TRACE_LDS_ALL) ? 5 : (ns ? 20 : 5);
+}
+
 // ------------------------------------------------------------------ scalars
 // Forward-mode dual number: value and directional derivative.  The residual
 // kernels instantiated with Dual<B> compute R(U) and J(U) v in one sweep.

@@ -23,9 +23,7 @@ inline int round64(int t) { return (t + 63) / 64 * 64; }
 inline bool block_ok(int threads) { return threads >= 1 && threads <= FRX_MAX_THREADS; }
 
 // LDS scalars per element of the trace stage (see trace_in_rounds)
-inline int trace_vals_host(int n, bool ns, size_t sb) {
-  return (ns && 20 * n * n * n * sb > 65536) ? 5 : (ns ? 20 : 5);
-}
+inline int trace_vals_host(int n, bool ns, size_t sb) { return trace_lds_vals(ns, n, (int)sb); }
 template <class T> size_t trace_lds(int n, int epb, bool ns) {
   return (size_t)epb * trace_vals_host(n, ns, sizeof(T)) * n * n * n * sizeof(T);
 }

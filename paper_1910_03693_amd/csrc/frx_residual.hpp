@@ -102,10 +102,10 @@ __device__ __forceinline__ long fslot(int nv, long fs, int n2, int v, int pt) {
 // element: q (5 N^3) and, for Navier-Stokes, the uncorrected physical
 // gradient (15 N^3).  After one barrier every face item (element, face,
 // point) extrapolates all of its values along the face-normal line.  Where
-// 20 N^3 scalars of one element exceed 64 KB (n = 6 with float64 duals) the
-// gradient goes through a 5 N^3 region one variable at a time instead.
+// 20 N^3 scalars of one element exceed FRX_TRACE_LDS_ALL bytes the gradient
+// goes through a 5 N^3 region one variable at a time instead.
 template <class T, int N, bool NS> __host__ __device__ constexpr bool trace_in_rounds() {
-  return NS && 20 * N * N * N * (int)sizeof(T) > 65536;
+  return trace_lds_vals(NS, N, (int)sizeof(T)) == 5 && NS;
 }
 template <class T, int N, bool NS> __host__ __device__ constexpr int trace_vals() {
   return trace_in_rounds<T, N, NS>() ? 5 : (NS ? 20 : 5);

@@ -193,7 +193,7 @@ void default_shapes(MeshDev& M, int sk) {
   const size_t cap = 64 * 1024;
   for (ElemBucket& b : M.eb) {
     const int n = b.n, n3 = n * n * n;
-    const int tv = (M.physics == 1 && 20 * n3 * sb > 65536) ? 5 : (M.physics == 1 ? 20 : 5);
+    const int tv = trace_lds_vals(M.physics == 1, n, (int)sb);
     int e = std::max(1, 256 / n3);
     while (e > 1 && (size_t)e * tv * n3 * sb > cap) --e;
     b.epb_trace[sk] = e;
@@ -1052,7 +1052,7 @@ fr_status gmres_solve(fr_ctx c, const double* U, double shift, const double* F, 
 size_t item_lds(bool ns, size_t sb, int st, int code) {
   if (st != 1) {
     const int n = code, n3 = n * n * n;
-    const int tv = (ns && 20 * n3 * sb > 65536) ? 5 : (ns ? 20 : 5);
+    const int tv = trace_lds_vals(ns, n, (int)sb);
     return st == 0 ? (size_t)tv * n3 * sb : (size_t)(5 * n3 + 30 * n * n) * sb;
   }
   const int nl = code / 8, nh = code % 8;
@@ -2137,7 +2137,7 @@ fr_status fr_autotune(fr_ctx c, const double* U, void* stream) {
           int best = *slot;
           float tbest = timed(sk);
           for (int e : cands) {
-            const int tv = (c->M.physics == 1 && 20 * n3 * sb > 65536) ? 5 : (c->M.physics == 1 ? 20 : 5);
+            const int tv = trace_lds_vals(c->M.physics == 1, b.n, (int)sb);
             const size_t lds = kind == 0 ? (size_t)e * tv * n3 * sb : (size_t)e * (5 * n3 + 30 * b.n * b.n) * sb;
             if (e == best || e * n3 > FRX_MAX_THREADS || lds > lds_cap || e > 2 * b.count) continue;
             *slot = e;
