@@ -132,6 +132,162 @@ __device__ __forceinline__ void visc_dot_S(const D64 q[5], const D64 G[5][3], co
   out[4] = e[0] * S[0] + e[1] * S[1] + e[2] * S[2];
 }
 
+// Adjoint of the normal inviscid flux (f . S, normal_flux) of one state: the
+// output adjoint fb to the state adjoint qb (accumulated).
+__device__ __forceinline__ void normal_flux_vjp(const double q[5], const double S[3], const Gas<double>& gas,
+                                                const double fb[5], double qb[5]) {
+  const double i0 = 1.0 / q[0];
+  const double m2 = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+  const double mS = q[1] * S[0] + q[2] * S[1] + q[3] * S[2];
+  const double un = mS * i0;
+  const double p = gas.gm1 * (q[4] - 0.5 * m2 * i0);
+  const double unb = fb[0] * q[0] + fb[1] * q[1] + fb[2] * q[2] + fb[3] * q[3] + fb[4] * (q[4] + p);
+  const double pb = fb[1] * S[0] + fb[2] * S[1] + fb[3] * S[2] + fb[4] * un;
+  double i0b = unb * mS - gas.gm1 * pb * 0.5 * m2;
+  qb[0] += fb[0] * un;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) qb[1 + a] += fb[1 + a] * un + unb * i0 * S[a] - gas.gm1 * pb * q[1 + a] * i0;
+  qb[4] += fb[4] * un + gas.gm1 * pb;
+  qb[0] -= i0b * i0 * i0;
+}
+
+// Adjoint of the Roe flux of riemann (flux 0) in closed form: given the
+// adjoint ob of f_com . S, the adjoints of both states.  The forward
+// quantities are recomputed, then the chain is walked back: dissipation ->
+// (wave strengths, |lambda|, Roe averages) -> (pressures, velocities, rho^1/2)
+// -> states; the normal fluxes' adjoints are added by normal_flux_vjp.  |x|
+// takes the derivative sign as sabs does (+1 at 0).
+__device__ __forceinline__ void roe_vjp(const double qL[5], const double qR[5], const double S[3],
+                                        const Gas<double>& gas, const double ob[5], double qLb[5], double qRb[5]) {
+  const double gm1 = gas.gm1;
+  const double area = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+  const double n[3] = {S[0] / area, S[1] / area, S[2] / area};
+  const double iL = 1.0 / qL[0], iR = 1.0 / qR[0];
+  const double pL = gm1 * (qL[4] - 0.5 * (qL[1] * qL[1] + qL[2] * qL[2] + qL[3] * qL[3]) * iL);
+  const double pR = gm1 * (qR[4] - 0.5 * (qR[1] * qR[1] + qR[2] * qR[2] + qR[3] * qR[3]) * iR);
+  const double sL = sqrt(qL[0]), sR = sqrt(qR[0]), D = sL + sR;
+  const double wL = sL / D, wR = sR / D;
+  double uL[3], uR[3], ut[3], du[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    uL[a] = qL[1 + a] * iL;
+    uR[a] = qR[1 + a] * iR;
+    ut[a] = wL * uL[a] + wR * uR[a];
+    du[a] = uR[a] - uL[a];
+  }
+  const double hL = (qL[4] + pL) * iL, hR = (qR[4] + pR) * iR;
+  const double Ht = wL * hL + wR * hR, rt = sL * sR;
+  const double k2 = 0.5 * (ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+  const double c2 = gm1 * (Ht - k2), c = sqrt(c2);
+  const double un = ut[0] * n[0] + ut[1] * n[1] + ut[2] * n[2];
+  const double dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+  const double dp = pR - pL;
+  const double a1 = (dp - rt * c * dun) / (2.0 * c2), a3 = (dp + rt * c * dun) / (2.0 * c2);
+  const double a2 = (qR[0] - qL[0]) - dp / c2;
+  const double s1 = (un - c) < 0.0 ? -1.0 : 1.0, s2 = un < 0.0 ? -1.0 : 1.0, s3 = (un + c) < 0.0 ? -1.0 : 1.0;
+  const double l1 = s1 * (un - c), l2 = s2 * un, l3 = s3 * (un + c);
+  const double As = l1 * a1 + l3 * a3, Aa = (l3 * a3 - l1 * a1) * c;
+  const double ud = ut[0] * du[0] + ut[1] * du[1] + ut[2] * du[2];
+  // out = (fL + fR)/2 - area/2 diss
+  double db[5], fb[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    fb[v] = 0.5 * ob[v];
+    db[v] = -0.5 * area * ob[v];
+  }
+  const double dbu = db[1] * ut[0] + db[2] * ut[1] + db[3] * ut[2];
+  const double dbn = db[1] * n[0] + db[2] * n[1] + db[3] * n[2];
+  const double Asb = db[0] + dbu + db[4] * Ht;
+  const double Aab = dbn + db[4] * un;
+  double l2b = db[0] * a2 + db[4] * (a2 * k2 + rt * (ud - un * dun));
+  double rtb = db[4] * l2 * (ud - un * dun);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    l2b += db[1 + a] * (a2 * ut[a] + rt * (du[a] - dun * n[a]));
+    rtb += db[1 + a] * l2 * (du[a] - dun * n[a]);
+  }
+  const double a2b = l2 * (db[0] + dbu + db[4] * k2);
+  double dunb = -l2 * rt * (dbn + db[4] * un);
+  double Htb = db[4] * As;
+  double unb = db[4] * (Aa - l2 * rt * dun);
+  double k2b = db[4] * l2 * a2;
+  const double udb = db[4] * l2 * rt;
+  double utb[3], dub[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    utb[a] = db[1 + a] * (As + l2 * a2) + udb * du[a];
+    dub[a] = db[1 + a] * l2 * rt + udb * ut[a];
+  }
+  const double l1b = Asb * a1 - Aab * a1 * c, l3b = Asb * a3 + Aab * a3 * c;
+  const double a1b = Asb * l1 - Aab * l1 * c, a3b = Asb * l3 + Aab * l3 * c;
+  double cb = Aab * (l3 * a3 - l1 * a1);
+  unb += l1b * s1 + l2b * s2 + l3b * s3;
+  cb += -l1b * s1 + l3b * s3;
+  // wave strengths
+  double q0b_R = a2b, q0b_L = -a2b;
+  double dpb = -a2b / c2;
+  double c2b = a2b * dp / (c2 * c2);
+  const double t1 = a1b / (2.0 * c2), t3 = a3b / (2.0 * c2);
+  dpb += t1 + t3;
+  rtb += (t3 - t1) * c * dun;
+  cb += (t3 - t1) * rt * dun;
+  dunb += (t3 - t1) * rt * c;
+  c2b -= (a1b * a1 + a3b * a3) / c2;
+  double pRb = dpb, pLb = -dpb;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    dub[a] += dunb * n[a];
+    utb[a] += unb * n[a];
+  }
+  c2b += cb / (2.0 * c);
+  Htb += gm1 * c2b;
+  k2b -= gm1 * c2b;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) utb[a] += k2b * ut[a];
+  double sLb = rtb * sR, sRb = rtb * sL;
+  double wLb = Htb * hL, wRb = Htb * hR;
+  const double hLb = Htb * wL, hRb = Htb * wR;
+  double qLb4 = hLb * iL, qRb4 = hRb * iR;
+  pLb += hLb * iL;
+  pRb += hRb * iR;
+  double iLb = hLb * (qL[4] + pL), iRb = hRb * (qR[4] + pR);
+  double qLbm[3], qRbm[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double uLb = -dub[a] + utb[a] * wL, uRb = dub[a] + utb[a] * wR;
+    wLb += utb[a] * uL[a];
+    wRb += utb[a] * uR[a];
+    qLbm[a] = uLb * iL;
+    qRbm[a] = uRb * iR;
+    iLb += uLb * qL[1 + a];
+    iRb += uRb * qR[1 + a];
+  }
+  q0b_L -= iLb * iL * iL;
+  q0b_R -= iRb * iR * iR;
+  sLb += (wLb - wRb) * sR / (D * D);
+  sRb += (wRb - wLb) * sL / (D * D);
+  q0b_L += sLb / (2.0 * sL);
+  q0b_R += sRb / (2.0 * sR);
+  // pressures p = gm1 (q4 - |m|^2 / (2 q0))
+  const double m2L = qL[1] * qL[1] + qL[2] * qL[2] + qL[3] * qL[3];
+  const double m2R = qR[1] * qR[1] + qR[2] * qR[2] + qR[3] * qR[3];
+  qLb4 += gm1 * pLb;
+  qRb4 += gm1 * pRb;
+  q0b_L += gm1 * pLb * 0.5 * m2L * iL * iL;
+  q0b_R += gm1 * pRb * 0.5 * m2R * iR * iR;
+  qLb[0] = q0b_L;
+  qRb[0] = q0b_R;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    qLb[1 + a] = qLbm[a] - gm1 * pLb * qL[1 + a] * iL;
+    qRb[1 + a] = qRbm[a] - gm1 * pRb * qR[1 + a] * iR;
+  }
+  qLb[4] = qLb4;
+  qRb[4] = qRb4;
+  normal_flux_vjp(qL, S, gas, fb, qLb);
+  normal_flux_vjp(qR, S, gas, fb, qRb);
+}
+
 // Adjoint of face_fn at one point: given fSb, jLb, jRb return qLb, qRb, gLb, gRb.
 // FLUX >= 0 fixes the Riemann solver at compile time (as in riemann).
 template <bool NS, int FLUX = -1>
@@ -139,21 +295,26 @@ __device__ void face_fn_vjp(const double qL[5], const double qR[5], const double
                             const double S[3], double cL, double cR, const Gas<double>& gas, int flux,
                             const double fSb[5], const double jLb[5], const double jRb[5], double qLb[5],
                             double qRb[5], double gLb[5][3], double gRb[5][3]) {
-  // Riemann part: 10 sweeps
+  // Riemann part: the Roe flux's adjoint in closed form; Rusanov by 10
+  // forward sweeps
+  if ((FLUX < 0 ? flux : FLUX) == 0) {
+    roe_vjp(qL, qR, S, gas, fSb, qLb, qRb);
+  } else {
 #pragma unroll 1
-  for (int j = 0; j < 10; ++j) {
-    D64 a[5], b[5], o[5];
+    for (int j = 0; j < 10; ++j) {
+      D64 a[5], b[5], o[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      a[v] = D64(qL[v], j == v ? 1.0 : 0.0);
-      b[v] = D64(qR[v], j == 5 + v ? 1.0 : 0.0);
+      for (int v = 0; v < 5; ++v) {
+        a[v] = D64(qL[v], j == v ? 1.0 : 0.0);
+        b[v] = D64(qR[v], j == 5 + v ? 1.0 : 0.0);
+      }
+      riemann<D64, double, (FLUX < 0 ? 1 : FLUX)>(a, b, S, gas, flux, o);
+      double s = 0.0;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) s += o[v].d * fSb[v];
+      if (j < 5) qLb[j] = s;
+      else qRb[j - 5] = s;
     }
-    riemann<D64, double, FLUX>(a, b, S, gas, flux, o);
-    double s = 0.0;
-#pragma unroll
-    for (int v = 0; v < 5; ++v) s += o[v].d * fSb[v];
-    if (j < 5) qLb[j] = s;
-    else qRb[j - 5] = s;
   }
   double jl[5], jr[5], qcb[5];
 #pragma unroll
