@@ -89,8 +89,11 @@ hipError_t face_rev_n(const VjpArgs& va, const FaceBucket& b, hipStream_t s) {
   }
 }
 
-// The fused path: forward traces and faces with the fused forward kernels of
-// the float64 plan, then one launch per reverse stage.
+// The fused path: forward traces with the fused forward kernel of the float64
+// plan, and for Navier-Stokes the solution jumps (the interior faces' jumps
+// alone, the boundary faces' full face function), then one launch per reverse
+// stage.  The reverse stages read the forward traces, and the jumps for the
+// corrected gradient; the common fluxes are recomputed by face_rev.
 template <bool NS>
 hipError_t vjp_fused(const ResArgs<double>& fa, const VjpArgs& va, const MeshDev& M, hipStream_t s) {
   const FusedPlan& P = M.plan[SK_F64];
@@ -101,10 +104,19 @@ hipError_t vjp_fused(const ResArgs<double>& fa, const VjpArgs& va, const MeshDev
                        P.tiles[0]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if (P.count[1]) {
-    e = M.flux == 1 ? face_stage_fused<double, NS, 1>(fa, M, P, false, s)
-                    : face_stage_fused<double, NS, 0>(fa, M, P, false, s);
-    if (e != hipSuccess) return e;
+  if (NS && P.n_interior > 0) {
+    hipLaunchKernelGGL((k_face_jumps_fused<double>), dim3(P.n_interior), dim3(256), P.lds[1], s, fa, M.all_faces,
+                       P.tiles[1]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (NS && P.count[1] > P.n_interior) {
+    if (M.flux == 1)
+      hipLaunchKernelGGL((k_bface_fused<double, NS, 1>), dim3(P.count[1] - P.n_interior), dim3(256), 0, s, fa,
+                         M.all_faces, P.tiles[1] + P.n_interior);
+    else
+      hipLaunchKernelGGL((k_bface_fused<double, NS, 0>), dim3(P.count[1] - P.n_interior), dim3(256), 0, s, fa,
+                         M.all_faces, P.tiles[1] + P.n_interior);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (V.count[2]) {
     hipLaunchKernelGGL((k_elem_rev_fused<NS, false>), dim3(V.count[2]), dim3(256), V.lds[2], s, va,

@@ -373,7 +373,8 @@ __device__ __forceinline__ void face_gather(const ResArgs<T>& a, const int4* __r
   }
 }
 
-template <int NL, int NH, class T>
+// FS_OUT false: the jumps alone (fS unused, no common flux written).
+template <int NL, int NH, class T, bool FS_OUT = true>
 __device__ __forceinline__ void face_scatter(const ResArgs<T>& a, const int4* __restrict__ faces, int nf, int fpb,
                                              int blk, unsigned char* smem, const FacePt<T>& P, const T fS[5],
                                              int nv_low) {
@@ -388,14 +389,14 @@ __device__ __forceinline__ void face_scatter(const ResArgs<T>& a, const int4* __
     if (!P.lowL) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        a.FS[fslot(5, P.oL, NH2, v, pt)] = fS[v];
+        if (FS_OUT) a.FS[fslot(5, P.oL, NH2, v, pt)] = fS[v];
         a.DQ[fslot(5, P.oL, NH2, v, pt)] = jL[v];
       }
     }
     if (!P.lowR) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        a.FS[fslot(5, P.oR, NH2, v, pt)] = fS[v];
+        if (FS_OUT) a.FS[fslot(5, P.oR, NH2, v, pt)] = fS[v];
         a.DQ[fslot(5, P.oR, NH2, v, pt)] = jR[v];
       }
     }
@@ -428,8 +429,8 @@ __device__ __forceinline__ void face_scatter(const ResArgs<T>& a, const int4* __
           for (int A = 0; A < NH; ++A) row = fmab(O.P[NL - 2][NH - 2][aa][A], src[vv * NH2 + A + NH * Bq], row);
           acc = fmab(O.P[NL - 2][NH - 2][bb][Bq], row, acc);
         }
-        if (vv < 5) a.FS[fslot(5, fs, NL2, vv, p2)] = acc;
-        else a.DQ[fslot(5, fs, NL2, vv - 5, p2)] = acc;
+        if (vv >= 5) a.DQ[fslot(5, fs, NL2, vv - 5, p2)] = acc;
+        else if (FS_OUT) a.FS[fslot(5, fs, NL2, vv, p2)] = acc;
       }
     }
   }
@@ -939,6 +940,35 @@ __global__ void __launch_bounds__(FRX_MAX_THREADS) __attribute__((amdgpu_waves_p
   }
   T fS[5];
   if (P.act) face_fn<NS, T, B, FLUX>(P.q[0], P.q[1], P.g, P.S, P.cL, P.cR, a.gas, a.flux, fS);
+  switch (t.x) {
+    FRX_FLIST(FRX_SCASE)
+    default: break;
+  }
+}
+#undef FRX_GCASE
+#undef FRX_SCASE
+
+// The solution jumps q_com - q alone at the interior faces' own face points
+// (eq. com_q; the low side of a mixed face receives their L2 projection), for
+// the forward recomputation of the adjoint: its reverse stages read the
+// forward traces and these jumps, not the common fluxes.  The q traces are
+// gathered as for Euler; same tiles and LDS as k_face_fused.
+#define FRX_GCASE(NL, NH) \
+  case 8 * NL + NH: face_gather<NL, NH, T, false>(a, faces + t.y, t.z, t.w, 0, smem, P); break;
+#define FRX_SCASE(NL, NH) \
+  case 8 * NL + NH: face_scatter<NL, NH, T, false>(a, faces + t.y, t.z, t.w, 0, smem, P, fS, 5); break;
+template <class T>
+__global__ void __launch_bounds__(FRX_MAX_THREADS) k_face_jumps_fused(ResArgs<T> a, const int4* __restrict__ faces,
+                                                                    const int4* __restrict__ tiles) {
+  using B = base_t<T>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int4 t = tiles[blockIdx.x];
+  FacePt<T> P;
+  switch (t.x) {
+    FRX_FLIST(FRX_GCASE)
+    default: return;
+  }
+  const T fS[5] = {T(B(0)), T(B(0)), T(B(0)), T(B(0)), T(B(0))};
   switch (t.x) {
     FRX_FLIST(FRX_SCASE)
     default: break;
