@@ -75,35 +75,99 @@ __device__ __forceinline__ void visc_grad_adjoint(const double q[5], const doubl
   }
 }
 
+// q-bar of Ft = volume_flux(q, G, Ja) at fixed G for the output adjoint Fb,
+// in closed form: the inviscid contravariant flux through Uc = Ja^i . u, p and
+// h = E + p, and for Navier-Stokes the state dependence of tau and e (through
+// u = m / rho, E / rho and 1 / rho in the velocity and energy gradients).
+template <bool NS>
+__device__ __forceinline__ void volume_flux_q_adjoint(const double q[5], const double G[5][3], const double Ja[3][3],
+                                                      const Gas<double>& gas, const double Fb[3][5], double qb[5]) {
+  const double gm1 = gas.gm1, ir = 1.0 / q[0];
+  const double u[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
+  const double p = gm1 * (q[4] - 0.5 * (q[1] * u[0] + q[2] * u[1] + q[3] * u[2]));
+  const double h = q[4] + p;
+  double ub[3] = {0.0, 0.0, 0.0}, irb = 0.0, pb = 0.0, hb = 0.0;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) qb[v] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double Uc = Ja[i][0] * u[0] + Ja[i][1] * u[1] + Ja[i][2] * u[2];
+    const double Ucb = Fb[i][0] * q[0] + Fb[i][1] * q[1] + Fb[i][2] * q[2] + Fb[i][3] * q[3] + Fb[i][4] * h;
+    qb[0] += Fb[i][0] * Uc;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      qb[1 + a] += Fb[i][1 + a] * Uc;
+      pb += Fb[i][1 + a] * Ja[i][a];
+      ub[a] += Ucb * Ja[i][a];
+    }
+    hb += Fb[i][4] * Uc;
+  }
+  qb[4] += hb;
+  pb += hb;
+  qb[4] += gm1 * pb;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    qb[1 + a] -= gm1 * pb * 0.5 * u[a];
+    ub[a] -= gm1 * pb * 0.5 * q[1 + a];
+  }
+  if (NS) {
+    double du[3][3], taub[3][3], eb[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) du[a][c] = (G[1 + a][c] - u[a] * G[0][c]) * ir;
+    const double dil = du[0][0] + du[1][1] + du[2][2];
+    const double E = q[4] * ir;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      eb[c] = -(Fb[0][4] * Ja[0][c] + Fb[1][4] * Ja[1][c] + Fb[2][4] * Ja[2][c]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) taub[a][c] = -(Fb[0][1 + a] * Ja[0][c] + Fb[1][1 + a] * Ja[1][c] + Fb[2][1 + a] * Ja[2][c]);
+    }
+    double T[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) T[a][c] = taub[a][c] + u[a] * eb[c];
+    const double tr = T[0][0] + T[1][1] + T[2][2];
+    // e = u_a tau[a][c] + kappa dT: u-bar from the stress
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double tau = gas.mu * (du[a][c] + du[c][a]) - (a == c ? (2.0 / 3.0) * gas.mu * dil : 0.0);
+        ub[a] += tau * eb[c];
+      }
+    double Eb = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double dTb = gas.kappa * eb[c];
+      const double dEb = gm1 * dTb;
+      Eb -= dEb * G[0][c] * ir;
+      irb += dEb * (G[4][c] - E * G[0][c]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double dub = gas.mu * (T[a][c] + T[c][a]) - (a == c ? (2.0 / 3.0) * gas.mu * tr : 0.0) - gm1 * u[a] * dTb;
+        ub[a] -= gm1 * dTb * du[a][c] + dub * G[0][c] * ir;
+        irb += dub * (G[1 + a][c] - u[a] * G[0][c]);
+      }
+    }
+    qb[4] += Eb * ir;
+    irb += Eb * q[4];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    qb[1 + a] += ub[a] * ir;
+    irb += ub[a] * q[1 + a];
+  }
+  qb[0] -= irb * ir * ir;
+}
+
 // q-bar, G-bar of Ft = volume_flux(q, G, Ja) for the output adjoint Fb
 template <bool NS>
 __device__ void volume_flux_vjp(const double q[5], const double G[5][3], const double Ja[3][3], const Gas<double>& gas,
                                 const double Fb[3][5], double qb[5], double Gb[5][3]) {
-  // q-bar: one forward sweep per state component, the gradient held fixed
-#pragma unroll 1
-  for (int j = 0; j < 5; ++j) {
-    D64 qd[5], Gd[5][3];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) qd[v] = D64(q[v], j == v ? 1.0 : 0.0);
-    if (NS) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) Gd[v][c] = D64(G[v][c]);
-    }
-    D64 Ft[3][5];
-    volume_flux<D64, double, NS>(qd, Gd, Ja, gas, Ft);
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int v = 0; v < 5; ++v) s += Ft[i][v].d * Fb[i][v];
-    // (stores by compare and select: an index by the loop counter would put
-    // the arrays in scratch)
-#pragma unroll
-    for (int v = 0; v < 5; ++v)
-      if (j == v) qb[v] = s;
-  }
+  volume_flux_q_adjoint<NS>(q, G, Ja, gas, Fb, qb);
   if (NS) {
     // G-bar: Ft^i -= Ja^i . tau and Ja^i . e, linear in G
     double taub[3][3], eb[3];
