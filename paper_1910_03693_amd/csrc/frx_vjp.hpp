@@ -75,6 +75,59 @@ __device__ __forceinline__ void visc_grad_adjoint(const double q[5], const doubl
   }
 }
 
+// Adjoint of viscous_terms with respect to the state q at fixed Gq: given the
+// adjoints taub (of tau[a][c], as in visc_grad_adjoint) and eb (of e[c]),
+// adds q-bar through u = m / rho, E / rho and 1 / rho in the velocity and
+// energy gradients and in e = u . tau + kappa grad T.
+__device__ __forceinline__ void visc_q_adjoint(const double q[5], const double G[5][3], const double taub[3][3],
+                                               const double eb[3], const Gas<double>& gas, double qb[5]) {
+  const double gm1 = gas.gm1, ir = 1.0 / q[0];
+  const double u[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
+  const double E = q[4] * ir;
+  double du[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) du[a][c] = (G[1 + a][c] - u[a] * G[0][c]) * ir;
+  const double dil = du[0][0] + du[1][1] + du[2][2];
+  double T[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) T[a][c] = taub[a][c] + u[a] * eb[c];
+  const double tr = T[0][0] + T[1][1] + T[2][2];
+  double ub[3] = {0.0, 0.0, 0.0}, irb = 0.0, Eb = 0.0;
+  // e = u_a tau[a][c] + kappa dT: u-bar from the stress
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double tau = gas.mu * (du[a][c] + du[c][a]) - (a == c ? (2.0 / 3.0) * gas.mu * dil : 0.0);
+      ub[a] += tau * eb[c];
+    }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double dTb = gas.kappa * eb[c];
+    const double dEb = gm1 * dTb;
+    Eb -= dEb * G[0][c] * ir;
+    irb += dEb * (G[4][c] - E * G[0][c]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double dub = gas.mu * (T[a][c] + T[c][a]) - (a == c ? (2.0 / 3.0) * gas.mu * tr : 0.0) - gm1 * u[a] * dTb;
+      ub[a] -= gm1 * dTb * du[a][c] + dub * G[0][c] * ir;
+      irb += dub * (G[1 + a][c] - u[a] * G[0][c]);
+    }
+  }
+  qb[4] += Eb * ir;
+  irb += Eb * q[4];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    qb[1 + a] += ub[a] * ir;
+    irb += ub[a] * q[1 + a];
+  }
+  qb[0] -= irb * ir * ir;
+}
+
 // q-bar of Ft = volume_flux(q, G, Ja) at fixed G for the output adjoint Fb,
 // in closed form: the inviscid contravariant flux through Uc = Ja^i . u, p and
 // h = E + p, and for Navier-Stokes the state dependence of tau and e (through
@@ -86,7 +139,7 @@ __device__ __forceinline__ void volume_flux_q_adjoint(const double q[5], const d
   const double u[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
   const double p = gm1 * (q[4] - 0.5 * (q[1] * u[0] + q[2] * u[1] + q[3] * u[2]));
   const double h = q[4] + p;
-  double ub[3] = {0.0, 0.0, 0.0}, irb = 0.0, pb = 0.0, hb = 0.0;
+  double ub[3] = {0.0, 0.0, 0.0}, irb = 0.0, pb = 0.0, hb = 0.0;  // inviscid part
 #pragma unroll
   for (int v = 0; v < 5; ++v) qb[v] = 0.0;
 #pragma unroll
@@ -110,57 +163,22 @@ __device__ __forceinline__ void volume_flux_q_adjoint(const double q[5], const d
     qb[1 + a] -= gm1 * pb * 0.5 * u[a];
     ub[a] -= gm1 * pb * 0.5 * q[1 + a];
   }
-  if (NS) {
-    double du[3][3], taub[3][3], eb[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) du[a][c] = (G[1 + a][c] - u[a] * G[0][c]) * ir;
-    const double dil = du[0][0] + du[1][1] + du[2][2];
-    const double E = q[4] * ir;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      eb[c] = -(Fb[0][4] * Ja[0][c] + Fb[1][4] * Ja[1][c] + Fb[2][4] * Ja[2][c]);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) taub[a][c] = -(Fb[0][1 + a] * Ja[0][c] + Fb[1][1 + a] * Ja[1][c] + Fb[2][1 + a] * Ja[2][c]);
-    }
-    double T[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) T[a][c] = taub[a][c] + u[a] * eb[c];
-    const double tr = T[0][0] + T[1][1] + T[2][2];
-    // e = u_a tau[a][c] + kappa dT: u-bar from the stress
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double tau = gas.mu * (du[a][c] + du[c][a]) - (a == c ? (2.0 / 3.0) * gas.mu * dil : 0.0);
-        ub[a] += tau * eb[c];
-      }
-    double Eb = 0.0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double dTb = gas.kappa * eb[c];
-      const double dEb = gm1 * dTb;
-      Eb -= dEb * G[0][c] * ir;
-      irb += dEb * (G[4][c] - E * G[0][c]);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const double dub = gas.mu * (T[a][c] + T[c][a]) - (a == c ? (2.0 / 3.0) * gas.mu * tr : 0.0) - gm1 * u[a] * dTb;
-        ub[a] -= gm1 * dTb * du[a][c] + dub * G[0][c] * ir;
-        irb += dub * (G[1 + a][c] - u[a] * G[0][c]);
-      }
-    }
-    qb[4] += Eb * ir;
-    irb += Eb * q[4];
-  }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     qb[1 + a] += ub[a] * ir;
     irb += ub[a] * q[1 + a];
   }
   qb[0] -= irb * ir * ir;
+  if (NS) {
+    double taub[3][3], eb[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      eb[c] = -(Fb[0][4] * Ja[0][c] + Fb[1][4] * Ja[1][c] + Fb[2][4] * Ja[2][c]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) taub[a][c] = -(Fb[0][1 + a] * Ja[0][c] + Fb[1][1 + a] * Ja[1][c] + Fb[2][1 + a] * Ja[2][c]);
+    }
+    visc_q_adjoint(q, G, taub, eb, gas, qb);
+  }
 }
 
 // q-bar, G-bar of Ft = volume_flux(q, G, Ja) for the output adjoint Fb
@@ -183,17 +201,6 @@ __device__ void volume_flux_vjp(const double q[5], const double G[5][3], const d
     for (int v = 0; v < 5; ++v)
       for (int c = 0; c < 3; ++c) Gb[v][c] = 0.0;
   }
-}
-
-// viscous part of the common flux dotted with S: (0, tau . S, e . S)
-__device__ __forceinline__ void visc_dot_S(const D64 q[5], const D64 G[5][3], const double S[3], const Gas<double>& gas,
-                                           D64 out[5]) {
-  D64 tau[3][3], e[3];
-  viscous_terms<D64, double>(q, G, gas, tau, e);
-  out[0] = D64(0.0);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) out[1 + a] = tau[a][0] * S[0] + tau[a][1] * S[1] + tau[a][2] * S[2];
-  out[4] = e[0] * S[0] + e[1] * S[1] + e[2] * S[2];
 }
 
 // Adjoint of the normal inviscid flux (f . S, normal_flux) of one state: the
@@ -397,25 +404,8 @@ __device__ void face_fn_vjp(const double qL[5], const double qR[5], const double
 #pragma unroll
       for (int c = 0; c < 3; ++c) Gc[v][c] = 0.5 * (gL[v][c] + gR[v][c] + S[c] * lift);
     }
-    // q_com-bar: one forward sweep per component at fixed G_com
-#pragma unroll 1
-    for (int j = 0; j < 5; ++j) {
-      D64 a[5], G[5][3], o[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) a[v] = D64(qc[v], j == v ? 1.0 : 0.0);
-#pragma unroll
-      for (int v = 0; v < 5; ++v)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) G[v][c] = D64(Gc[v][c]);
-      visc_dot_S(a, G, S, gas, o);
-      double s = 0.0;
-#pragma unroll
-      for (int v = 0; v < 5; ++v) s -= o[v].d * fSb[v];  // fS = Riemann - visc
-#pragma unroll
-      for (int v = 0; v < 5; ++v)
-        if (j == v) qcb[v] += s;
-    }
-    // G_com-bar: the viscous flux (tau . S, e . S) is linear in G_com
+    // the viscous flux (tau . S, e . S) of fS = Riemann - visc: adjoints of
+    // tau and e, then q_com-bar at fixed G_com and G_com-bar (linear in it)
     double taub[3][3], eb[3], Gcb[5][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -423,6 +413,7 @@ __device__ void face_fn_vjp(const double qL[5], const double qR[5], const double
 #pragma unroll
       for (int a = 0; a < 3; ++a) taub[a][c] = -fSb[1 + a] * S[c];
     }
+    visc_q_adjoint(qc, Gc, taub, eb, gas, qcb);
     visc_grad_adjoint(qc, taub, eb, gas, Gcb);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
