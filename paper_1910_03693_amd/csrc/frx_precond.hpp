@@ -90,9 +90,10 @@ __global__ void __launch_bounds__(256) k_pc_lu(TB* __restrict__ blocks, PcDev pc
                                               int* __restrict__ piv, int* __restrict__ flag) {
   extern __shared__ __align__(16) unsigned char pc_lds[];
   TB* pan = reinterpret_cast<TB*>(pc_lds);  // [PB N]: pan[c * nr + (r - k0)], panel column c, rows k0..N-1
-  __shared__ double red_v[256];
-  __shared__ int red_i[256];
+  __shared__ double red_v[4];  // one per wave of the 256-thread block
+  __shared__ int red_i[4];
   __shared__ int pv[PB];
+  __shared__ int mv_dst[2 * PB], mv_src[2 * PB], mv_cnt;
   const int el = ids ? ids[blockIdx.x] : (int)blockIdx.x;
   const int4 rec = pc.recs[el];
   const int N = pc_rows(rec.z);
@@ -118,22 +119,33 @@ __global__ void __launch_bounds__(256) k_pc_lu(TB* __restrict__ blocks, PcDev pc
           bi = r;
         }
       }
-      red_v[tid] = best;
-      red_i[tid] = bi;
-      __syncthreads();
-      for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) {
-          const double a = red_v[tid], b = red_v[tid + s];
-          if (b > a || (b == a && red_i[tid + s] < red_i[tid])) {
-            red_v[tid] = b;
-            red_i[tid] = red_i[tid + s];
-          }
+      // the largest |value|, the lowest row among equal ones: within each
+      // wave by shuffles, then over the waves' results in LDS
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
         }
-        __syncthreads();
       }
-      const int p = red_i[0];
-      const bool singular = !(red_v[0] > 0.0);
+      if ((tid & 63) == 0) {
+        red_v[tid >> 6] = best;
+        red_i[tid >> 6] = bi;
+      }
       __syncthreads();
+      best = red_v[0];
+      bi = red_i[0];
+      for (int wv = 1; wv < (int)(blockDim.x >> 6); ++wv) {
+        const double ob = red_v[wv];
+        const int oi = red_i[wv];
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      const int p = bi;
+      const bool singular = !(best > 0.0);
       if (tid == 0) {
         pv[c] = p;
         P[k0 + c] = k0 + p;
@@ -158,18 +170,50 @@ __global__ void __launch_bounds__(256) k_pc_lu(TB* __restrict__ blocks, PcDev pc
       const int c = t / nr, r = t - c * nr;
       A[(k0 + r) + (long)(k0 + c) * N] = pan[c * nr + r];
     }
-    // 4. the panel's row swaps on the other columns, in order
-    for (int c = 0; c < w; ++c) {
-      const int p = pv[c];
-      if (p != c)
-        for (int j = tid; j < N; j += blockDim.x) {
-          if (j >= k0 && j < k0 + w) continue;
-          const TB t = A[(k0 + c) + (long)j * N];
-          A[(k0 + c) + (long)j * N] = A[(k0 + p) + (long)j * N];
-          A[(k0 + p) + (long)j * N] = t;
+    // 4. the panel's row swaps on the other columns.  Their product is a
+    // permutation of at most 2 w rows: replayed once on the row indices
+    // (mv_dst[i] receives the old row mv_src[i], panel-relative), it moves
+    // each column's rows with independent loads and then stores.
+    if (tid == 0) {
+      int cnt = 0;
+      for (int c = 0; c < w; ++c) {
+        const int p = pv[c];
+        if (p == c) continue;
+        int ic = -1, ip = -1;
+        for (int i = 0; i < cnt; ++i) {
+          if (mv_dst[i] == c) ic = i;
+          if (mv_dst[i] == p) ip = i;
         }
-      __syncthreads();
+        if (ic < 0) {
+          ic = cnt++;
+          mv_dst[ic] = mv_src[ic] = c;
+        }
+        if (ip < 0) {
+          ip = cnt++;
+          mv_dst[ip] = mv_src[ip] = p;
+        }
+        const int t = mv_src[ic];
+        mv_src[ic] = mv_src[ip];
+        mv_src[ip] = t;
+      }
+      mv_cnt = cnt;
     }
+    __syncthreads();
+    {
+      const int cnt = mv_cnt;
+      for (int j = tid; j < N; j += blockDim.x) {
+        if (j >= k0 && j < k0 + w) continue;
+        TB* col = A + k0 + (long)j * N;
+        TB mv[2 * PB];
+#pragma unroll
+        for (int i = 0; i < 2 * PB; ++i)
+          if (i < cnt) mv[i] = col[mv_src[i]];
+#pragma unroll
+        for (int i = 0; i < 2 * PB; ++i)
+          if (i < cnt && mv_src[i] != mv_dst[i]) col[mv_dst[i]] = mv[i];
+      }
+    }
+    __syncthreads();
     if (k0 + w >= N) break;
     // 5. the panel's rows of the trailing columns: solve with its unit lower triangle
     for (int j = k0 + w + tid; j < N; j += blockDim.x) {
