@@ -58,7 +58,7 @@ def test_precond_apply_matches_oracle(frx, small, prec, fused):
     p = _prec(frx, prec)
     ctx = frx.Context.from_case(case, max_restart=10, graphs=_reserve(frx, p), fused=fused)
     U = torch.tensor(case.U, device="cuda")
-    sigma = 35.0
+    sigma = 35.0  # partial pivoting swaps 8-145 rows of each of these blocks (orders 40-320)
     ctx.precond_build(U, sigma, p)
     x = I.random_direction(case.U.size, 4081).reshape(case.U.shape)
     y = ctx.precond_apply(torch.tensor(x, device="cuda")).cpu().numpy().ravel()
