@@ -335,11 +335,13 @@ hipError_t pc_lu_launch(TB* blocks, const PcDev& pc, const int* ids, int count, 
 // block is solved with its unit lower triangle).  The block then holds
 // (P A)^{-1}, so that A^{-1} x = (P A)^{-1} (P x): the apply gathers x
 // through the permutation left in piv and multiplies.  One 256-thread block
-// per element; a thread owns rows tid + 256 q and holds PB partial sums of
-// each in registers; every loop over a column index reads a whole column
-// (coalesced) per step.  Launched per degree bucket like k_pc_lu (ids, PB N
+// per element; a thread owns the R rows tid + 256 q (256 R >= N) and holds PB
+// partial sums of each in registers, all R rows in one pass over the column
+// index, so that one LDS value serves R rows and R loads are in flight per step;
+// every loop over a column index reads a whole column (coalesced) per step.
+// Launched per degree bucket (pc_inv_launch: ids, R by the block order, PB N
 // scalars of dynamic LDS).
-template <class TB>
+template <class TB, int R>
 __global__ void __launch_bounds__(256) k_pc_inv(TB* __restrict__ blocks, PcDev pc, const int* __restrict__ ids) {
   constexpr int PB = PcPanel<TB>::value;
   extern __shared__ __align__(16) unsigned char pc_lds[];
@@ -350,6 +352,7 @@ __global__ void __launch_bounds__(256) k_pc_inv(TB* __restrict__ blocks, PcDev p
   const int N = pc_rows(rec.z);
   TB* A = blocks + pc.boff[el];
   const int tid = threadIdx.x;
+  const int base = tid & ~63;  // first row of this wave
   // 1. U <- U^{-1}
   for (int j0 = 0; j0 < N; j0 += PB) {
     const int jb = min(PB, N - j0);
@@ -362,34 +365,45 @@ __global__ void __launch_bounds__(256) k_pc_inv(TB* __restrict__ blocks, PcDev p
       dg[t] = (r < jb && c < jb) ? A[(j0 + r) + (long)(j0 + c) * N] : TB(1);
     }
     __syncthreads();
+    if (base < j0) {  // rows above the block in this wave (their rows i >= base)
+      TB acc[R][PB];
 #pragma unroll
-    for (int q = 0; q < PC_ROWS; ++q) {
-      const int base = (tid & ~63) + q * (int)blockDim.x;  // first row of this wave
-      if (base >= j0) break;
-      const int i = tid + q * (int)blockDim.x;
-      TB acc[PB];
+      for (int q = 0; q < R; ++q)
 #pragma unroll
-      for (int c = 0; c < PB; ++c) acc[c] = TB(0);
+        for (int c = 0; c < PB; ++c) acc[q][c] = TB(0);
 #pragma unroll 4
       for (int k = base; k < j0; ++k) {  // (U^{-1})[i, k] for k >= i, times the old column block
-        const TB u = (i < j0 && k >= i) ? A[i + (long)k * N] : TB(0);
+        TB u[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int i = tid + q * (int)blockDim.x;
+          u[q] = (i < j0 && k >= i) ? A[i + (long)k * N] : TB(0);
+        }
         const TB* w = wk + k * PB;
 #pragma unroll
-        for (int c = 0; c < PB; ++c) acc[c] += u * w[c];
+        for (int c = 0; c < PB; ++c) {
+          const TB wc = w[c];
+#pragma unroll
+          for (int q = 0; q < R; ++q) acc[q][c] += u[q] * wc;
+        }
       }
-      // X D = -acc with D the block's upper diagonal triangle
 #pragma unroll
-      for (int c = 0; c < PB; ++c) {
-        TB v = -acc[c];
+      for (int q = 0; q < R; ++q) {
+        const int i = tid + q * (int)blockDim.x;
+        // X D = -acc with D the block's upper diagonal triangle
 #pragma unroll
-        for (int k = 0; k < PB; ++k)
-          if (k < c) v -= acc[k] * dg[c * PB + k];
-        acc[c] = v / dg[c * PB + c];
+        for (int c = 0; c < PB; ++c) {
+          TB v = -acc[q][c];
+#pragma unroll
+          for (int k = 0; k < PB; ++k)
+            if (k < c) v -= acc[q][k] * dg[c * PB + k];
+          acc[q][c] = v / dg[c * PB + c];
+        }
+        if (i < j0)
+#pragma unroll
+          for (int c = 0; c < PB; ++c)
+            if (c < jb) A[i + (long)(j0 + c) * N] = acc[q][c];
       }
-      if (i < j0)
-#pragma unroll
-        for (int c = 0; c < PB; ++c)
-          if (c < jb) A[i + (long)(j0 + c) * N] = acc[c];
     }
     // the diagonal triangle's inverse, a row per thread
     if (tid < jb) {
@@ -429,37 +443,66 @@ __global__ void __launch_bounds__(256) k_pc_inv(TB* __restrict__ blocks, PcDev p
       }
     }
     __syncthreads();
+    if (base < N) {
+      TB acc[R][PB];
 #pragma unroll
-    for (int q = 0; q < PC_ROWS; ++q) {
-      const int i = tid + q * (int)blockDim.x;
-      if (i - (tid & 63) >= N) break;  // the whole wave is past the last row
-      const bool own = i < N;
-      TB acc[PB];
+      for (int q = 0; q < R; ++q) {
+        const int i = tid + q * (int)blockDim.x;
 #pragma unroll
-      for (int c = 0; c < PB; ++c) acc[c] = (own && c < jb) ? A[i + (long)(j0 + c) * N] : TB(0);
+        for (int c = 0; c < PB; ++c) acc[q][c] = (i < N && c < jb) ? A[i + (long)(j0 + c) * N] : TB(0);
+      }
 #pragma unroll 4
       for (int k = j0 + jb; k < N; ++k) {
-        const TB x = own ? A[i + (long)k * N] : TB(0);
+        TB x[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int i = tid + q * (int)blockDim.x;
+          x[q] = i < N ? A[i + (long)k * N] : TB(0);
+        }
         const TB* w = wk + (k - j0) * PB;
 #pragma unroll
-        for (int c = 0; c < PB; ++c) acc[c] -= x * w[c];
+        for (int c = 0; c < PB; ++c) {
+          const TB wc = w[c];
+#pragma unroll
+          for (int q = 0; q < R; ++q) acc[q][c] -= x[q] * wc;
+        }
       }
-      // X Ld = acc with Ld the unit lower triangle of the block's L part
 #pragma unroll
-      for (int c = PB - 1; c >= 0; --c) {
-        TB v = acc[c];
+      for (int q = 0; q < R; ++q) {
+        const int i = tid + q * (int)blockDim.x;
+        // X Ld = acc with Ld the unit lower triangle of the block's L part
 #pragma unroll
-        for (int k = 0; k < PB; ++k)
-          if (k > c && k < jb) v -= acc[k] * wk[k * PB + c];
-        acc[c] = v;
+        for (int c = PB - 1; c >= 0; --c) {
+          TB v = acc[q][c];
+#pragma unroll
+          for (int k = 0; k < PB; ++k)
+            if (k > c && k < jb) v -= acc[q][k] * wk[k * PB + c];
+          acc[q][c] = v;
+        }
+        if (i < N)
+#pragma unroll
+          for (int c = 0; c < PB; ++c)
+            if (c < jb) A[i + (long)(j0 + c) * N] = acc[q][c];
       }
-      if (own)
-#pragma unroll
-        for (int c = 0; c < PB; ++c)
-          if (c < jb) A[i + (long)(j0 + c) * N] = acc[c];
     }
     __syncthreads();
   }
+}
+
+// The inverse of `count` factored blocks of order N (one degree bucket): rows
+// per thread as few as the order allows.
+template <class TB>
+hipError_t pc_inv_launch(TB* blocks, const PcDev& pc, const int* ids, int count, int N, hipStream_t s) {
+  const size_t lds = (size_t)PcPanel<TB>::value * N * sizeof(TB);
+  if (N <= 256)
+    hipLaunchKernelGGL((k_pc_inv<TB, 1>), dim3(count), dim3(256), lds, s, blocks, pc, ids);
+  else if (N <= 512)
+    hipLaunchKernelGGL((k_pc_inv<TB, 2>), dim3(count), dim3(256), lds, s, blocks, pc, ids);
+  else if (N <= 768)
+    hipLaunchKernelGGL((k_pc_inv<TB, 3>), dim3(count), dim3(256), lds, s, blocks, pc, ids);
+  else
+    hipLaunchKernelGGL((k_pc_inv<TB, PC_ROWS>), dim3(count), dim3(256), lds, s, blocks, pc, ids);
+  return hipGetLastError();
 }
 
 // x_e <- A_e^{-1} x_e from the float16 copy of sigma (P A)^{-1} that

@@ -871,18 +871,14 @@ void pc_build(fr_ctx c, const double* U, double sigma, hipStream_t s, bool half 
   for (const ElemBucket& eb : c->M.eb) {
     if (!eb.count) continue;
     const int N = 5 * eb.n * eb.n * eb.n;
-    // the inverse's LDS: PB N scalars
-    const size_t lds = (size_t)(f64 ? PcPanel<double>::value * 8 : PcPanel<float>::value * 4) * N;
     if (f64) {
       FRX_TRY(pc_lu_launch<double>((double*)c->pc_blocks, pc_dev(c), (const int*)eb.elems, eb.count, N, c->pc_piv,
                                    c->pc_flag, s));
-      hipLaunchKernelGGL((k_pc_inv<double>), dim3(eb.count), dim3(256), lds, s, (double*)c->pc_blocks, pc_dev(c),
-                         (const int*)eb.elems);
+      FRX_TRY(pc_inv_launch<double>((double*)c->pc_blocks, pc_dev(c), (const int*)eb.elems, eb.count, N, s));
     } else {
       FRX_TRY(pc_lu_launch<float>((float*)c->pc_blocks, pc_dev(c), (const int*)eb.elems, eb.count, N, c->pc_piv,
                                   c->pc_flag, s));
-      hipLaunchKernelGGL((k_pc_inv<float>), dim3(eb.count), dim3(256), lds, s, (float*)c->pc_blocks, pc_dev(c),
-                         (const int*)eb.elems);
+      FRX_TRY(pc_inv_launch<float>((float*)c->pc_blocks, pc_dev(c), (const int*)eb.elems, eb.count, N, s));
       if (half) {
         FRX_TRY(hipGetLastError());
         hipLaunchKernelGGL(k_pc_to_half, dim3(eb.count), dim3(256), 0, s, (float*)c->pc_blocks, pc_dev(c),
